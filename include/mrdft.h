@@ -1,0 +1,160 @@
+/*
+ * mrdft.h — multiresolution discrete Fourier transform (MrDFT) on AMD Instinct
+ * MI355X (gfx950).  C ABI: plain pointers and sizes, no C++ or framework types.
+ *
+ * The transform (Section 2, eq. (1), with the level block read as
+ * I_{2^{m-i}} (x) E_{2^i} so that every level is N x N): for a signal
+ * x[0..N-1], N = 2^m, and every level i = 1..m,
+ *
+ *     Y^(i)[w*2^i + k] = sum_{n < 2^i} x[w*2^i + n] * exp(-j*2*pi*n*k / 2^i),
+ *
+ * windows w = 0..N/2^i-1 in time order, bins k = 0..2^i-1 in natural order,
+ * no normalisation.  The output of one signal is the m*N values
+ * [Y^(1); Y^(2); ...; Y^(m)] (level 1 first), complex64.
+ *
+ * It is computed with the rationalised recurrence of Section 3, eq. (4): the
+ * even bins of level i are sums of adjacent level-(i-1) windows (U^(i), eq. (2))
+ * and the odd bins are a half-length FFT of the twiddled window difference
+ * (V^(i), eq. (3), D^(i), F^(i)).
+ *
+ * Conventions common to every entry point
+ *   - Memory: every x / Y / gY / gx / z / num_den / L / gL pointer is DEVICE
+ *     memory owned by the caller; the plan owns its twiddle tables, tile
+ *     tables and workspace.  `offsets` in mrdft_plan_create is HOST memory,
+ *     copied during the call.
+ *   - Layout: complex64 = interleaved (re, im) float32; real input = float32.
+ *     Uniform batches are contiguous: x[b][N], Y[b][m][N].  Ragged batches:
+ *     signal j occupies samples [off[j], off[j+1]) of x and the m_j*N_j
+ *     outputs starting at O_j = sum_{j'<j} m_j' * N_j' of Y (level-major).
+ *   - Pointers must be non-NULL and 16-byte aligned (8 for float32 inputs).
+ *   - Asynchrony: every call enqueues work on `stream` (0 = the null stream)
+ *     and returns without synchronising.  A plan is immutable after creation;
+ *     concurrent calls on the same plan from different streams are NOT
+ *     supported (they share one workspace).
+ *   - Errors: a non-zero mrdft_status is returned and mrdft_last_error()
+ *     gives a thread-local message.  No call aborts or throws.
+ */
+#ifndef MRDFT_H
+#define MRDFT_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mrdft_plan* mrdft_plan_t;
+
+typedef enum {
+    MRDFT_OK = 0,
+    MRDFT_E_INVALID_ARG = 1, /* bad order, length, offsets, pointer, alignment or dtype */
+    MRDFT_E_UNSUPPORTED = 2, /* valid request this build does not handle */
+    MRDFT_E_ALLOC = 3,       /* device or host allocation failed */
+    MRDFT_E_HIP = 4          /* a HIP runtime call failed (message has the HIP error) */
+} mrdft_status;
+
+typedef enum {
+    MRDFT_C64 = 0, /* complex64 input */
+    MRDFT_R32 = 1  /* real float32 input (treated as complex with zero imaginary part) */
+} mrdft_dtype;
+
+/* Largest supported order m (N = 2^m samples per signal). */
+#define MRDFT_MAX_ORDER 28
+
+/* Plan flags */
+#define MRDFT_FLAG_NONE 0u
+
+/*
+ * Create a plan.  Section 2 (problem statement of eq. (1)).
+ *   plan    : out, receives the handle.
+ *   m       : order of every signal of a uniform batch, 1 <= m <= MRDFT_MAX_ORDER.
+ *             Must be 0 when `offsets` is given.
+ *   batch   : number of signals, >= 1.
+ *   offsets : NULL for a uniform batch; otherwise host int64[batch+1] sample
+ *             offsets, offsets[0] = 0, each length offsets[j+1]-offsets[j] a
+ *             power of two 2^m_j with 1 <= m_j <= MRDFT_MAX_ORDER.
+ *   dtype   : element type of x (MRDFT_C64 or MRDFT_R32).
+ *   flags   : MRDFT_FLAG_NONE.
+ *   stream  : stream used for the plan's one-time uploads (synchronised
+ *             before return).
+ * Errors: MRDFT_E_INVALID_ARG for any violated rule, MRDFT_E_ALLOC, MRDFT_E_HIP.
+ */
+mrdft_status mrdft_plan_create(mrdft_plan_t* plan, int m, int64_t batch, const int64_t* offsets,
+                               mrdft_dtype dtype, unsigned flags, hipStream_t stream);
+
+/*
+ * Output offsets of a plan, in complex elements: host int64[batch+1],
+ * out[j] = O_j (start of signal j's levels in Y), out[batch] = total outputs.
+ */
+mrdft_status mrdft_plan_output_offsets(mrdft_plan_t plan, int64_t* out);
+
+/* Total number of input samples and of complex outputs of the plan. */
+mrdft_status mrdft_plan_sizes(mrdft_plan_t plan, int64_t* n_in, int64_t* n_out);
+
+/*
+ * Forward MrDFT, eq. (1) computed by eq. (4).
+ *   x : device, plan dtype, n_in elements.
+ *   Y : device, complex64, n_out elements (see layout above); fully overwritten.
+ */
+mrdft_status mrdft_forward(mrdft_plan_t plan, const void* x, void* Y, hipStream_t stream);
+
+/*
+ * Adjoint (conjugate transpose of eq. (1)): gx = sum_i (I (x) E_{2^i})^H gY^(i),
+ * i.e. gx[w*2^i + n] += sum_k gY^(i)[w*2^i + k] * exp(+j*2*pi*n*k/2^i), summed
+ * over levels.  For real plans gx receives the real part (the gradient of a
+ * real loss with respect to a real input).
+ *   gY : device, complex64, n_out elements.
+ *   gx : device, plan dtype, n_in elements; fully overwritten.
+ */
+mrdft_status mrdft_adjoint(mrdft_plan_t plan, const void* gY, void* gx, hipStream_t stream);
+
+/*
+ * Multi-resolution spectral loss, uniform real (MRDFT_R32) plans only:
+ *   num_i = || Y^(i)(x) - Y^(i)(z) ||^2,  den_i = || Y^(i)(z) ||^2,
+ *   L_b = (1/m) sum_i num_i / den_i,  L = sum_b L_b.
+ *   x, z    : device float32 [batch][N].
+ *   num_den : device double [batch][m][2] receives (num_i, den_i).
+ *   L       : device float, receives L.
+ * den_i = 0 (z = 0 on a whole signal) gives an infinite or NaN loss.
+ */
+mrdft_status mrdft_spectral_loss_fwd(mrdft_plan_t plan, const float* x, const float* z, double* num_den,
+                                     float* L, hipStream_t stream);
+
+/*
+ * Gradient of the spectral loss with respect to x, scaled by *gL:
+ *   gx = Re( sum_i A_i^H [ gL * 2 (Y^(i)(x) - Y^(i)(z)) / (m * den_i) ] ),
+ * with A_i^H the level-i adjoint above.  The level spectra are recomputed from
+ * x and z (nothing of the forward is stored).
+ *   num_den : device double [batch][m][2] from mrdft_spectral_loss_fwd.
+ *   gL      : device float, upstream gradient of L.
+ *   gx      : device float32 [batch][N], overwritten.
+ */
+mrdft_status mrdft_spectral_loss_bwd(mrdft_plan_t plan, const float* x, const float* z, const double* num_den,
+                                     const float* gL, float* gx, hipStream_t stream);
+
+/*
+ * Opt-in kernel timing (instrumentation, not part of the transform).  When
+ * enabled, every kernel launch of the plan is bracketed by two HIP events
+ * recorded on the launch stream.  mrdft_plan_read_profile waits for the
+ * recorded events, writes per kind the summed duration in milliseconds and
+ * the number of launches (arrays of nkinds entries), and clears the record.
+ * Kinds: */
+#define MRDFT_KERNEL_TILE_FWD 0 /* on-chip tile levels, forward */
+#define MRDFT_KERNEL_PASS_FWD 1 /* global pass of a level above the tile, forward */
+#define MRDFT_KERNEL_TILE_ADJ 2 /* on-chip tile levels, adjoint */
+#define MRDFT_KERNEL_PASS_ADJ 3 /* global pass, adjoint */
+#define MRDFT_KERNEL_KINDS 4
+mrdft_status mrdft_plan_set_profiling(mrdft_plan_t plan, int enable);
+mrdft_status mrdft_plan_read_profile(mrdft_plan_t plan, int nkinds, double* total_ms, int64_t* launches);
+
+/* Destroy a plan (NULL is accepted).  The handle must not be used afterwards. */
+mrdft_status mrdft_plan_destroy(mrdft_plan_t plan);
+
+/* Thread-local message of the last failing call on this thread ("" if none). */
+const char* mrdft_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MRDFT_H */

@@ -1,0 +1,545 @@
+// Host side of the C ABI declared in include/mrdft.h: plan creation and
+// validation, FP64 twiddle generation, tile tables, launch sequencing.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "../../include/mrdft.h"
+#include "mrdft_device.h"
+#include "mrdft_internal.h"
+#include "mrdft_loss.h"
+
+using namespace mrdft;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+// Live plans, so that a destroyed or foreign handle is rejected instead of
+// being dereferenced.
+std::mutex g_plans_mu;
+std::set<const void*> g_plans;
+
+mrdft_status fail(mrdft_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess) return fail(MRDFT_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+int ilog2_exact(int64_t v) {
+    if (v <= 0 || (v & (v - 1))) return -1;
+    int r = 0;
+    while ((int64_t(1) << r) < v) ++r;
+    return r;
+}
+
+// Signals of one order share the global passes of their upper levels.
+struct Group {
+    int order = 0;
+    int64_t count = 0;
+    int64_t* d_in_sig = nullptr;    // x offset of each signal (ragged only)
+    int64_t* d_out_sig = nullptr;   // Y offset of each signal (ragged only)
+};
+
+// Bit split of the passes for a window of 2^lg points (each pass radix <= 2^8,
+// first pass radix >= 2^4).
+std::vector<int> pass_bits(int lg) {
+    const int np = (lg + kPassMaxLog - 1) / kPassMaxLog;
+    std::vector<int> b(np, lg / np);
+    for (int p = 0; p < lg % np; ++p) b[p] += 1;
+    return b;
+}
+
+}  // namespace
+
+struct mrdft_plan {
+    int m = 0;
+    int64_t batch = 0;
+    mrdft_dtype dtype = MRDFT_C64;
+    bool ragged = false;
+    std::vector<int64_t> in_off, out_off;   // [batch+1]
+    std::vector<int> orders;
+    int64_t n_in = 0, n_out = 0;
+    int max_order = 0;
+    TileJob* d_jobs = nullptr;
+    int64_t njobs = 0;
+    std::vector<Group> groups;
+    float2* d_tw_tile = nullptr;
+    double2* d_tw_hi = nullptr;
+    double2* d_tw_lo = nullptr;
+    float2* d_s[2] = {nullptr, nullptr};    // pass ping-pong scratch
+    // spectral loss workspace
+    float* d_v = nullptr;
+    float2* d_Yv = nullptr;
+    float2* d_Yz = nullptr;
+    double* d_part = nullptr;
+    // opt-in kernel timing: events recorded around every launch on its stream
+    bool profiling = false;
+    struct Rec {
+        int kind;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> event_pool;
+
+    Twiddles tw() const { return Twiddles{d_tw_tile, d_tw_hi, d_tw_lo}; }
+};
+
+namespace {
+
+void dfree(void* ptr) {
+    if (ptr) (void)hipFree(ptr);
+}
+
+void free_plan(mrdft_plan* p) {
+    if (!p) return;
+    for (auto& r : p->recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (auto e : p->event_pool) (void)hipEventDestroy(e);
+    dfree(p->d_jobs);
+    for (auto& g : p->groups) {
+        dfree(g.d_in_sig);
+        dfree(g.d_out_sig);
+    }
+    dfree(p->d_tw_tile);
+    dfree(p->d_tw_hi);
+    dfree(p->d_tw_lo);
+    dfree(p->d_s[0]);
+    dfree(p->d_s[1]);
+    dfree(p->d_v);
+    dfree(p->d_Yv);
+    dfree(p->d_Yz);
+    dfree(p->d_part);
+    delete p;
+}
+
+mrdft_status upload_twiddles(mrdft_plan* p, hipStream_t s) {
+    std::vector<float2> tile(kTileMax);
+    for (int e = 0; e < kTileMax; ++e) {
+        const double a = 2.0 * M_PI * (double)e / (double)kTileMax;
+        tile[e] = make_float2((float)std::cos(a), (float)(-std::sin(a)));
+    }
+    const int nf = 1 << kTwFineLog;
+    std::vector<double2> hi(nf), lo(nf);
+    for (int e = 0; e < nf; ++e) {
+        const double ah = 2.0 * M_PI * (double)e / (double)nf;                       // a * 2^14 / 2^28
+        const double al = 2.0 * M_PI * (double)e / (double)(int64_t(1) << kMaxOrder);
+        hi[e] = make_double2(std::cos(ah), -std::sin(ah));
+        lo[e] = make_double2(std::cos(al), -std::sin(al));
+    }
+    if (hipMalloc(&p->d_tw_tile, sizeof(float2) * kTileMax) != hipSuccess ||
+        hipMalloc(&p->d_tw_hi, sizeof(double2) * nf) != hipSuccess ||
+        hipMalloc(&p->d_tw_lo, sizeof(double2) * nf) != hipSuccess)
+        return fail(MRDFT_E_ALLOC, "twiddle table allocation failed");
+    HIP_TRY(hipMemcpyAsync(p->d_tw_tile, tile.data(), sizeof(float2) * kTileMax, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(p->d_tw_hi, hi.data(), sizeof(double2) * nf, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(p->d_tw_lo, lo.data(), sizeof(double2) * nf, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return MRDFT_OK;
+}
+
+mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
+    std::vector<TileJob> jobs;
+    std::vector<std::vector<int64_t>> gin(kMaxOrder + 1), gout(kMaxOrder + 1);
+    for (int64_t j = 0; j < p->batch; ++j) {
+        const int mj = p->orders[j];
+        const int64_t N = int64_t(1) << mj;
+        const int t = mj < kTileMaxLog ? mj : kTileMaxLog;
+        const int64_t T = int64_t(1) << t;
+        for (int64_t tau = 0; tau < N / T; ++tau) {
+            TileJob jb;
+            jb.in_off = p->in_off[j] + tau * T;
+            jb.out_off = p->out_off[j] + tau * T;
+            jb.level_stride = N;
+            jb.t = t;
+            jb.pad = 0;
+            jobs.push_back(jb);
+        }
+        if (mj > kTileMaxLog) {
+            gin[mj].push_back(p->in_off[j]);
+            gout[mj].push_back(p->out_off[j]);
+        }
+    }
+    p->njobs = (int64_t)jobs.size();
+    if (hipMalloc(&p->d_jobs, sizeof(TileJob) * jobs.size()) != hipSuccess)
+        return fail(MRDFT_E_ALLOC, "tile table allocation failed (%zu bytes)", sizeof(TileJob) * jobs.size());
+    HIP_TRY(hipMemcpyAsync(p->d_jobs, jobs.data(), sizeof(TileJob) * jobs.size(), hipMemcpyHostToDevice, s));
+    int64_t scratch = 0;
+    for (int o = kTileMaxLog + 1; o <= kMaxOrder; ++o) {
+        if (gin[o].empty()) continue;
+        Group g;
+        g.order = o;
+        g.count = (int64_t)gin[o].size();
+        if (p->ragged) {
+            if (hipMalloc(&g.d_in_sig, sizeof(int64_t) * g.count) != hipSuccess ||
+                hipMalloc(&g.d_out_sig, sizeof(int64_t) * g.count) != hipSuccess) {
+                p->groups.push_back(g);
+                return fail(MRDFT_E_ALLOC, "signal table allocation failed");
+            }
+            p->groups.push_back(g);
+            HIP_TRY(hipMemcpyAsync(g.d_in_sig, gin[o].data(), sizeof(int64_t) * g.count, hipMemcpyHostToDevice, s));
+            HIP_TRY(hipMemcpyAsync(g.d_out_sig, gout[o].data(), sizeof(int64_t) * g.count, hipMemcpyHostToDevice, s));
+        } else {
+            p->groups.push_back(g);
+        }
+        const int64_t need = g.count << o;
+        if (need > scratch) scratch = need;
+    }
+    if (scratch > 0) {
+        if (hipMalloc(&p->d_s[0], sizeof(float2) * scratch) != hipSuccess ||
+            hipMalloc(&p->d_s[1], sizeof(float2) * scratch) != hipSuccess)
+            return fail(MRDFT_E_ALLOC, "pass workspace allocation failed (2 x %lld complex)", (long long)scratch);
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    return MRDFT_OK;
+}
+
+hipEvent_t take_event(mrdft_plan* p) {
+    if (!p->event_pool.empty()) {
+        hipEvent_t e = p->event_pool.back();
+        p->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Scoped timing of one launch (no-op unless profiling is enabled).
+struct ProfScope {
+    mrdft_plan* p;
+    hipStream_t s;
+    int kind;
+    hipEvent_t a = nullptr;
+    ProfScope(mrdft_plan* p_, int kind_, hipStream_t s_) : p(p_), s(s_), kind(kind_) {
+        if (p->profiling) {
+            a = take_event(p);
+            if (a) (void)hipEventRecord(a, s);
+        }
+    }
+    ~ProfScope() {
+        if (a) {
+            hipEvent_t b = take_event(p);
+            if (b) {
+                (void)hipEventRecord(b, s);
+                p->recs.push_back({kind, a, b});
+            } else {
+                p->event_pool.push_back(a);
+            }
+        }
+    }
+};
+
+// Forward transform of all levels of every signal (x of the plan dtype, or an
+// explicit override of kind `in_kind`).
+mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, hipStream_t s) {
+    const Twiddles tw = p->tw();
+    {
+        ProfScope ps(p, MRDFT_KERNEL_TILE_FWD, s);
+        HIP_TRY(launch_tile_fwd(in_kind == IN_R32, x, Y, p->d_jobs, p->njobs, tw, s));
+    }
+    for (const Group& g : p->groups) {
+        const int64_t N = int64_t(1) << g.order;
+        for (int i = kTileMaxLog + 1; i <= g.order; ++i) {
+            const std::vector<int> bits = pass_bits(i);
+            int ns = 0;
+            for (size_t q = 0; q < bits.size(); ++q) {
+                const bool first = q == 0, last = q + 1 == bits.size();
+                PassGeom geo;
+                geo.lg = i;
+                geo.r_log = bits[q];
+                geo.ns_log = ns;
+                geo.nwin = g.count * (N >> i);
+                geo.wps = N >> i;
+                geo.in_sig = first ? g.d_in_sig : nullptr;
+                geo.in_stride = N;
+                geo.out_sig = last ? g.d_out_sig : nullptr;
+                geo.out_stride = last ? (int64_t)g.order * N : N;
+                const void* in = first ? x : (const void*)p->d_s[(q - 1) & 1];
+                void* out = last ? (void*)(Y + (int64_t)(i - 1) * N) : (void*)p->d_s[q & 1];
+                ProfScope ps(p, MRDFT_KERNEL_PASS_FWD, s);
+                HIP_TRY(launch_pass(false, first ? in_kind : IN_C64, OUT_STORE, in, out, geo, tw, s));
+                ns += bits[q];
+            }
+        }
+    }
+    return MRDFT_OK;
+}
+
+mrdft_status run_adjoint(mrdft_plan* p, const float2* gY, void* gx, bool real_out, hipStream_t s) {
+    const Twiddles tw = p->tw();
+    {
+        ProfScope ps(p, MRDFT_KERNEL_TILE_ADJ, s);
+        HIP_TRY(launch_tile_adj(real_out, gY, gx, p->d_jobs, p->njobs, tw, s));
+    }
+    for (const Group& g : p->groups) {
+        const int64_t N = int64_t(1) << g.order;
+        for (int i = kTileMaxLog + 1; i <= g.order; ++i) {
+            const std::vector<int> bits = pass_bits(i);
+            int ns = 0;
+            for (size_t q = 0; q < bits.size(); ++q) {
+                const bool first = q == 0, last = q + 1 == bits.size();
+                PassGeom geo;
+                geo.lg = i;
+                geo.r_log = bits[q];
+                geo.ns_log = ns;
+                geo.nwin = g.count * (N >> i);
+                geo.wps = N >> i;
+                geo.in_sig = first ? g.d_out_sig : nullptr;
+                geo.in_stride = first ? (int64_t)g.order * N : N;
+                geo.out_sig = last ? g.d_in_sig : nullptr;
+                geo.out_stride = N;
+                const void* in = first ? (const void*)(gY + (int64_t)(i - 1) * N) : (const void*)p->d_s[(q - 1) & 1];
+                void* out = last ? gx : (void*)p->d_s[q & 1];
+                const int ok = last ? (real_out ? OUT_ADD_R32 : OUT_ADD_C64) : OUT_STORE;
+                ProfScope ps(p, MRDFT_KERNEL_PASS_ADJ, s);
+                HIP_TRY(launch_pass(true, IN_C64, ok, in, out, geo, tw, s));
+                ns += bits[q];
+            }
+        }
+    }
+    return MRDFT_OK;
+}
+
+bool misaligned(const void* ptr, size_t a) { return (reinterpret_cast<uintptr_t>(ptr) & (a - 1)) != 0; }
+
+mrdft_status check_plan(mrdft_plan_t plan) {
+    if (!plan) return fail(MRDFT_E_INVALID_ARG, "plan is NULL");
+    std::lock_guard<std::mutex> lk(g_plans_mu);
+    if (!g_plans.count(plan)) return fail(MRDFT_E_INVALID_ARG, "plan handle is not live (destroyed or invalid)");
+    return MRDFT_OK;
+}
+
+mrdft_status ensure_loss_workspace(mrdft_plan* p) {
+    if (p->d_Yv) return MRDFT_OK;
+    const int64_t rows = p->batch * p->m;
+    const int64_t N = int64_t(1) << p->m;
+    const int nch = loss_chunks(N);
+    if (hipMalloc(&p->d_v, sizeof(float) * p->n_in) != hipSuccess ||
+        hipMalloc(&p->d_Yv, sizeof(float2) * p->n_out) != hipSuccess ||
+        hipMalloc(&p->d_Yz, sizeof(float2) * p->n_out) != hipSuccess ||
+        hipMalloc(&p->d_part, sizeof(double) * 2 * rows * nch) != hipSuccess) {
+        dfree(p->d_v);
+        dfree(p->d_Yv);
+        dfree(p->d_Yz);
+        dfree(p->d_part);
+        p->d_v = nullptr;
+        p->d_Yv = p->d_Yz = nullptr;
+        p->d_part = nullptr;
+        return fail(MRDFT_E_ALLOC, "spectral-loss workspace allocation failed");
+    }
+    return MRDFT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mrdft_last_error(void) { return g_last_error.c_str(); }
+
+mrdft_status mrdft_plan_create(mrdft_plan_t* plan, int m, int64_t batch, const int64_t* offsets, mrdft_dtype dtype,
+                               unsigned flags, hipStream_t stream) {
+    if (!plan) return fail(MRDFT_E_INVALID_ARG, "plan output pointer is NULL");
+    *plan = nullptr;
+    if (batch < 1) return fail(MRDFT_E_INVALID_ARG, "batch must be >= 1 (got %lld)", (long long)batch);
+    if (dtype != MRDFT_C64 && dtype != MRDFT_R32) return fail(MRDFT_E_INVALID_ARG, "unknown dtype %d", (int)dtype);
+    if (flags != MRDFT_FLAG_NONE) return fail(MRDFT_E_INVALID_ARG, "unknown flags 0x%x", flags);
+    mrdft_plan* p = new (std::nothrow) mrdft_plan();
+    if (!p) return fail(MRDFT_E_ALLOC, "host allocation failed");
+    p->batch = batch;
+    p->dtype = dtype;
+    p->in_off.resize(batch + 1);
+    p->out_off.resize(batch + 1);
+    p->orders.resize(batch);
+    if (offsets) {
+        if (m != 0) {
+            delete p;
+            return fail(MRDFT_E_INVALID_ARG, "m must be 0 for a ragged plan (got %d)", m);
+        }
+        if (offsets[0] != 0) {
+            delete p;
+            return fail(MRDFT_E_INVALID_ARG, "offsets[0] must be 0 (got %lld)", (long long)offsets[0]);
+        }
+        p->ragged = true;
+        for (int64_t j = 0; j < batch; ++j) {
+            const int64_t len = offsets[j + 1] - offsets[j];
+            const int o = ilog2_exact(len);
+            if (o < 1 || o > MRDFT_MAX_ORDER) {
+                delete p;
+                return fail(MRDFT_E_INVALID_ARG,
+                            "signal %lld has length %lld: lengths must be 2^m with 1 <= m <= %d",
+                            (long long)j, (long long)len, MRDFT_MAX_ORDER);
+            }
+            p->orders[j] = o;
+        }
+    } else {
+        if (m < 1 || m > MRDFT_MAX_ORDER) {
+            delete p;
+            return fail(MRDFT_E_INVALID_ARG, "m must be in [1, %d] (got %d)", MRDFT_MAX_ORDER, m);
+        }
+        for (int64_t j = 0; j < batch; ++j) p->orders[j] = m;
+    }
+    p->in_off[0] = p->out_off[0] = 0;
+    for (int64_t j = 0; j < batch; ++j) {
+        const int64_t N = int64_t(1) << p->orders[j];
+        p->in_off[j + 1] = p->in_off[j] + N;
+        p->out_off[j + 1] = p->out_off[j] + (int64_t)p->orders[j] * N;
+        if (p->orders[j] > p->max_order) p->max_order = p->orders[j];
+    }
+    p->m = offsets ? 0 : m;
+    p->n_in = p->in_off[batch];
+    p->n_out = p->out_off[batch];
+    mrdft_status st = upload_twiddles(p, stream);
+    if (st == MRDFT_OK) st = build_tables(p, stream);
+    if (st != MRDFT_OK) {
+        free_plan(p);
+        return st;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_plans_mu);
+        g_plans.insert(p);
+    }
+    *plan = p;
+    return MRDFT_OK;
+}
+
+mrdft_status mrdft_plan_output_offsets(mrdft_plan_t plan, int64_t* out) {
+    mrdft_status st = check_plan(plan);
+    if (st) return st;
+    if (!out) return fail(MRDFT_E_INVALID_ARG, "out is NULL");
+    std::memcpy(out, plan->out_off.data(), sizeof(int64_t) * (plan->batch + 1));
+    return MRDFT_OK;
+}
+
+mrdft_status mrdft_plan_sizes(mrdft_plan_t plan, int64_t* n_in, int64_t* n_out) {
+    mrdft_status st = check_plan(plan);
+    if (st) return st;
+    if (!n_in || !n_out) return fail(MRDFT_E_INVALID_ARG, "size output pointer is NULL");
+    *n_in = plan->n_in;
+    *n_out = plan->n_out;
+    return MRDFT_OK;
+}
+
+mrdft_status mrdft_forward(mrdft_plan_t plan, const void* x, void* Y, hipStream_t stream) {
+    mrdft_status st = check_plan(plan);
+    if (st) return st;
+    if (!x || !Y) return fail(MRDFT_E_INVALID_ARG, "x and Y must be non-NULL");
+    if (misaligned(Y, 16) || misaligned(x, plan->dtype == MRDFT_C64 ? 16 : 8))
+        return fail(MRDFT_E_INVALID_ARG, "x or Y is not sufficiently aligned");
+    return run_forward(plan, x, plan->dtype == MRDFT_R32 ? IN_R32 : IN_C64, (float2*)Y, stream);
+}
+
+mrdft_status mrdft_adjoint(mrdft_plan_t plan, const void* gY, void* gx, hipStream_t stream) {
+    mrdft_status st = check_plan(plan);
+    if (st) return st;
+    if (!gY || !gx) return fail(MRDFT_E_INVALID_ARG, "gY and gx must be non-NULL");
+    if (misaligned(gY, 16) || misaligned(gx, plan->dtype == MRDFT_C64 ? 16 : 8))
+        return fail(MRDFT_E_INVALID_ARG, "gY or gx is not sufficiently aligned");
+    return run_adjoint(plan, (const float2*)gY, gx, plan->dtype == MRDFT_R32, stream);
+}
+
+mrdft_status mrdft_spectral_loss_fwd(mrdft_plan_t plan, const float* x, const float* z, double* num_den, float* L,
+                                     hipStream_t stream) {
+    mrdft_status st = check_plan(plan);
+    if (st) return st;
+    if (plan->ragged || plan->dtype != MRDFT_R32)
+        return fail(MRDFT_E_UNSUPPORTED, "the spectral loss needs a uniform real (MRDFT_R32) plan");
+    if (!x || !z || !num_den || !L) return fail(MRDFT_E_INVALID_ARG, "x, z, num_den and L must be non-NULL");
+    if (misaligned(x, 16) || misaligned(z, 16) || misaligned(num_den, 8) || misaligned(L, 4))
+        return fail(MRDFT_E_INVALID_ARG, "x or z is not 16-byte aligned");
+    st = ensure_loss_workspace(plan);
+    if (st) return st;
+    const int64_t N = int64_t(1) << plan->m;
+    const int64_t rows = plan->batch * plan->m;
+    const int nch = loss_chunks(N);
+    HIP_TRY(launch_sub_real(x, z, plan->d_v, plan->n_in, stream));
+    st = run_forward(plan, plan->d_v, IN_R32, plan->d_Yv, stream);
+    if (st) return st;
+    st = run_forward(plan, z, IN_R32, plan->d_Yz, stream);
+    if (st) return st;
+    HIP_TRY(launch_sumsq(plan->d_Yv, plan->d_part, rows, N, stream));
+    HIP_TRY(launch_sumsq(plan->d_Yz, plan->d_part + rows * nch, rows, N, stream));
+    HIP_TRY(launch_finalize(plan->d_part, plan->d_part + rows * nch, num_den, L, plan->batch, plan->m, N, stream));
+    return MRDFT_OK;
+}
+
+mrdft_status mrdft_spectral_loss_bwd(mrdft_plan_t plan, const float* x, const float* z, const double* num_den,
+                                     const float* gL, float* gx, hipStream_t stream) {
+    mrdft_status st = check_plan(plan);
+    if (st) return st;
+    if (plan->ragged || plan->dtype != MRDFT_R32)
+        return fail(MRDFT_E_UNSUPPORTED, "the spectral loss needs a uniform real (MRDFT_R32) plan");
+    if (!x || !z || !num_den || !gL || !gx) return fail(MRDFT_E_INVALID_ARG, "null pointer argument");
+    if (misaligned(x, 16) || misaligned(z, 16) || misaligned(gx, 16))
+        return fail(MRDFT_E_INVALID_ARG, "x, z or gx is not 16-byte aligned");
+    st = ensure_loss_workspace(plan);
+    if (st) return st;
+    const int64_t N = int64_t(1) << plan->m;
+    const int64_t rows = plan->batch * plan->m;
+    HIP_TRY(launch_sub_real(x, z, plan->d_v, plan->n_in, stream));
+    st = run_forward(plan, plan->d_v, IN_R32, plan->d_Yv, stream);
+    if (st) return st;
+    HIP_TRY(launch_scale_levels(plan->d_Yv, num_den, gL, plan->m, N, rows, stream));
+    return run_adjoint(plan, plan->d_Yv, gx, true, stream);
+}
+
+mrdft_status mrdft_plan_set_profiling(mrdft_plan_t plan, int enable) {
+    mrdft_status st = check_plan(plan);
+    if (st) return st;
+    plan->profiling = enable != 0;
+    return MRDFT_OK;
+}
+
+mrdft_status mrdft_plan_read_profile(mrdft_plan_t plan, int nkinds, double* total_ms, int64_t* launches) {
+    mrdft_status st = check_plan(plan);
+    if (st) return st;
+    if (nkinds < 0 || (nkinds > 0 && (!total_ms || !launches)))
+        return fail(MRDFT_E_INVALID_ARG, "bad profile output arrays");
+    for (int k = 0; k < nkinds; ++k) {
+        total_ms[k] = 0.0;
+        launches[k] = 0;
+    }
+    for (auto& r : plan->recs) {
+        HIP_TRY(hipEventSynchronize(r.b));
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, r.a, r.b));
+        if (r.kind < nkinds) {
+            total_ms[r.kind] += ms;
+            launches[r.kind] += 1;
+        }
+        plan->event_pool.push_back(r.a);
+        plan->event_pool.push_back(r.b);
+    }
+    plan->recs.clear();
+    return MRDFT_OK;
+}
+
+mrdft_status mrdft_plan_destroy(mrdft_plan_t plan) {
+    if (!plan) return MRDFT_OK;
+    {
+        std::lock_guard<std::mutex> lk(g_plans_mu);
+        if (!g_plans.erase(plan)) return fail(MRDFT_E_INVALID_ARG, "plan handle is not live (destroyed twice?)");
+    }
+    free_plan(plan);
+    return MRDFT_OK;
+}
+
+}  // extern "C"

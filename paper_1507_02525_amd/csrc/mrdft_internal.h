@@ -1,0 +1,47 @@
+// Internal declarations shared by the host API and the kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mrdft {
+
+// One on-chip tile of 2^t consecutive samples of one signal.
+struct TileJob {
+    int64_t in_off;        // element offset of the tile's first sample in x
+    int64_t out_off;       // element offset in Y of level 1 at that sample
+    int64_t level_stride;  // distance in Y between two levels of this signal (= N)
+    int32_t t;             // levels 1..t are computed on chip
+    int32_t pad;
+};
+
+// Geometry of one global Stockham pass over all windows of one level.
+struct PassGeom {
+    int lg;              // window order: windows hold L = 2^lg points
+    int r_log;           // radix of this pass, 2^r_log points per column FFT
+    int ns_log;          // span before this pass (log2)
+    int64_t nwin;        // number of windows processed
+    int64_t wps;         // windows per signal
+    // input element offset of window g = (b, W):  in_sig ? in_sig[b] : b*in_stride, + W*L
+    const int64_t* in_sig;
+    int64_t in_stride;
+    const int64_t* out_sig;
+    int64_t out_stride;
+};
+
+enum InKind { IN_C64 = 0, IN_R32 = 1 };
+enum OutKind { OUT_STORE = 0, OUT_ADD_C64 = 1, OUT_ADD_R32 = 2 };
+
+struct Twiddles {
+    const float2* tile;   // w_{4096}^e, e < 4096 (FP32, rounded once from FP64)
+    const double2* hi;    // w_{2^28}^{a*2^14}, a < 2^14 (FP64)
+    const double2* lo;    // w_{2^28}^{b}, b < 2^14 (FP64)
+};
+
+hipError_t launch_tile_fwd(bool real_in, const void* x, float2* Y, const TileJob* jobs, int64_t njobs,
+                           const Twiddles& tw, hipStream_t s);
+hipError_t launch_tile_adj(bool real_out, const float2* gY, void* gx, const TileJob* jobs, int64_t njobs,
+                           const Twiddles& tw, hipStream_t s);
+hipError_t launch_pass(bool inv, int in_kind, int out_kind, const void* in, void* out, const PassGeom& g,
+                       const Twiddles& tw, hipStream_t s);
+
+}  // namespace mrdft

@@ -1,0 +1,131 @@
+// Global Stockham passes for the levels whose windows exceed the on-chip tile.
+//
+// Level i (window L = 2^i) is the L-point DFT of every window (Section 2,
+// eq. (1)).  A window larger than the tile is transformed by a few passes over
+// HBM; pass p has radix r = 2^r_log and span Ns (product of earlier radices):
+// column j in [0, L/r) gathers the r inputs j + s*L/r, multiplies input s by
+// w_{Ns*r}^{(j mod Ns)*s}, runs an r-point DFT in LDS and writes output s to
+// (j / Ns)*Ns*r + (j mod Ns) + s*Ns.  The last pass leaves every window in
+// natural bin order, i.e. already permuted as Gamma asks.
+//
+// A workgroup handles 16 consecutive columns, so every global load and store
+// touches 16 consecutive complex64 values (128 bytes); the first pass radix is
+// at least 16 so later passes keep that property.  Twiddles of large windows
+// come from two FP64 tables (coarse and fine exponent), multiplied in FP64 and
+// rounded once.  With INV the conjugate kernel is used (adjoint), and the last
+// pass can accumulate into the gradient instead of storing.
+#include "mrdft_internal.h"
+#include "mrdft_lds_fft.h"
+
+namespace mrdft {
+
+constexpr int kColStride(int r) { return r + 1; }   // LDS padding against bank conflicts
+
+template <bool INV>
+__device__ __forceinline__ void column_fft(float2* B, int rl, const float2* __restrict__ tab, int tid) {
+    const int fst = kColStride(1 << rl);
+    int lgNs = 0;
+    const int rem = rl & 3;
+    if (rem == 1) { lds_step<2, 1, INV>(B, rl, 0, fst, 1, kPassCols, tab, tid, kPassThreads); lgNs = 1; }
+    else if (rem == 2) { lds_step<4, 1, INV>(B, rl, 0, fst, 1, kPassCols, tab, tid, kPassThreads); lgNs = 2; }
+    else if (rem == 3) { lds_step<8, 1, INV>(B, rl, 0, fst, 1, kPassCols, tab, tid, kPassThreads); lgNs = 3; }
+    while (lgNs < rl) {
+        lds_step<16, 1, INV>(B, rl, lgNs, fst, 1, kPassCols, tab, tid, kPassThreads);
+        lgNs += 4;
+    }
+}
+
+template <bool INV, int IN_KIND, int OUT_KIND>
+__global__ __launch_bounds__(kPassThreads) void pass_kernel(const void* __restrict__ in, void* __restrict__ out,
+                                                            PassGeom g, const float2* __restrict__ tab,
+                                                            const double2* __restrict__ hi,
+                                                            const double2* __restrict__ lo) {
+    __shared__ float2 B[kPassCols * ((1 << kPassMaxLog) + 1)];
+    const int rl = g.r_log;
+    const int r = 1 << rl;
+    const int fst = kColStride(r);
+    const int64_t L = (int64_t)1 << g.lg;
+    const int64_t cols = L >> rl;                      // columns j per window
+    const int64_t jblocks = cols / kPassCols;
+    const int64_t blk = blockIdx.x;
+    const int64_t gwin = blk / jblocks;
+    const int64_t j0 = (blk - gwin * jblocks) * kPassCols;
+    const int64_t b = gwin / g.wps, W = gwin - b * g.wps;
+    const int64_t ib = (g.in_sig ? g.in_sig[b] : b * g.in_stride) + W * L;
+    const int64_t ob = (g.out_sig ? g.out_sig[b] : b * g.out_stride) + W * L;
+    const int tid = threadIdx.x;
+    const int ns_log = g.ns_log;
+    const int64_t nsm = ((int64_t)1 << ns_log) - 1;
+    const int nval = r * kPassCols;
+
+    for (int e = tid; e < nval; e += kPassThreads) {
+        const int jj = e & (kPassCols - 1), s = e >> 4;
+        const int64_t j = j0 + jj;
+        const int64_t idx = ib + j + (int64_t)s * cols;
+        float2 v;
+        if constexpr (IN_KIND == IN_R32) v = make_float2(((const float*)in)[idx], 0.0f);
+        else v = ((const float2*)in)[idx];
+        if (ns_log > 0 && s > 0) {
+            const float2 w = tw_big(hi, lo, ns_log + rl, (j & nsm) * s);
+            v = INV ? cmulc(v, w) : cmul(v, w);
+        }
+        B[jj * fst + s] = v;
+    }
+    __syncthreads();
+    column_fft<INV>(B, rl, tab, tid);
+
+    for (int e = tid; e < nval; e += kPassThreads) {
+        int jj, s;
+        int64_t o;
+        if (ns_log == 0) {          // outputs of column j are the r consecutive values j*r + s
+            jj = e >> rl;
+            s = e & (r - 1);
+            o = ob + (j0 + jj) * r + s;
+        } else {                    // 16 consecutive columns -> 16 consecutive outputs per s
+            jj = e & (kPassCols - 1);
+            s = e >> 4;
+            const int64_t j = j0 + jj;
+            o = ob + ((j >> ns_log) << (ns_log + rl)) + (j & nsm) + ((int64_t)s << ns_log);
+        }
+        const float2 v = B[jj * fst + s];
+        if constexpr (OUT_KIND == OUT_STORE) {
+            ((float2*)out)[o] = v;
+        } else if constexpr (OUT_KIND == OUT_ADD_C64) {
+            float2* p = (float2*)out + o;
+            *p = cadd(*p, v);
+        } else {
+            float* p = (float*)out + o;
+            *p += v.x;
+        }
+    }
+}
+
+template <bool INV>
+static hipError_t launch_pass_t(int in_kind, int out_kind, const void* in, void* out, const PassGeom& g,
+                                const Twiddles& tw, hipStream_t s) {
+    const int64_t cols = ((int64_t)1 << g.lg) >> g.r_log;
+    const int64_t nblk = g.nwin * (cols / kPassCols);
+    if (nblk <= 0) return hipSuccess;
+    dim3 grid((unsigned)nblk), block(kPassThreads);
+#define MRDFT_PASS(IK, OK) \
+    hipLaunchKernelGGL((pass_kernel<INV, IK, OK>), grid, block, 0, s, in, out, g, tw.tile, tw.hi, tw.lo)
+    if (in_kind == IN_R32) {
+        if (out_kind == OUT_STORE) MRDFT_PASS(IN_R32, OUT_STORE);
+        else if (out_kind == OUT_ADD_C64) MRDFT_PASS(IN_R32, OUT_ADD_C64);
+        else MRDFT_PASS(IN_R32, OUT_ADD_R32);
+    } else {
+        if (out_kind == OUT_STORE) MRDFT_PASS(IN_C64, OUT_STORE);
+        else if (out_kind == OUT_ADD_C64) MRDFT_PASS(IN_C64, OUT_ADD_C64);
+        else MRDFT_PASS(IN_C64, OUT_ADD_R32);
+    }
+#undef MRDFT_PASS
+    return hipGetLastError();
+}
+
+hipError_t launch_pass(bool inv, int in_kind, int out_kind, const void* in, void* out, const PassGeom& g,
+                       const Twiddles& tw, hipStream_t s) {
+    return inv ? launch_pass_t<true>(in_kind, out_kind, in, out, g, tw, s)
+               : launch_pass_t<false>(in_kind, out_kind, in, out, g, tw, s);
+}
+
+}  // namespace mrdft

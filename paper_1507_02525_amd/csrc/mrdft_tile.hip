@@ -1,0 +1,459 @@
+// On-chip tile kernels: levels 1..t of a 2^t-sample tile (t <= 12).
+//
+// Forward (Section 3, eq. (4)).  With every level kept in natural bin order,
+// the factors of eq. (4) reduce to, for level i (window L = 2^i, M = L/2):
+//   even bins  Y^(i)[w][2k]   = Y^(i-1)[2w][k] + Y^(i-1)[2w+1][k]          (U^(i), eq. (2))
+//   odd bins   Y^(i)[w][2k+1] = DFT_M( (x[wL+q] - x[wL+q+M]) * w_L^q )[k]   (V^(i), eq. (3),
+//                                                                            then D^(i), F^(i))
+// so each level reuses the level below for half of its bins and runs one
+// half-length FFT of the twiddled window difference for the other half.  The
+// permutation Gamma is absorbed by the natural-order (Stockham) FFT.
+//
+// Levels 1..min(t,4) run in registers on 16-sample chunks; higher levels keep
+// x and the previous level in LDS and run the odd-bin FFT as radix-2/4/8
+// Stockham steps.  Every level is streamed to HBM with 16-byte stores.
+//
+// Adjoint: the transpose of the same recurrence, top level first.  The odd-bin
+// gradient goes through the conjugate FFT and the conjugate twiddles into x
+// (added at q, subtracted at q + M); the even-bin gradient is added to both
+// child windows of the level below.
+#include "mrdft_internal.h"
+#include "mrdft_lds_fft.h"
+
+namespace mrdft {
+
+template <bool REAL>
+struct XType {
+    using T = float2;
+};
+template <>
+struct XType<true> {
+    using T = float;
+};
+
+__device__ __forceinline__ float2 to_c(float v) { return make_float2(v, 0.0f); }
+__device__ __forceinline__ float2 to_c(float2 v) { return v; }
+
+// ---------------------------------------------------------------------------
+// Register phase, forward: levels 2..LC of a chunk of C = 2^LC samples.
+// ---------------------------------------------------------------------------
+template <int I, int LC>
+struct LocalFwd {
+    static __device__ __forceinline__ void run(const float2* xv, float2* pv, float2* y, int64_t ls) {
+        if constexpr (I <= LC) {
+            constexpr int C = 1 << LC, L = 1 << I, M = L / 2;
+            float2 nv[C];
+#pragma unroll
+            for (int w = 0; w < C / L; ++w) {
+                float2 d[M];
+#pragma unroll
+                for (int q = 0; q < M; ++q)
+                    d[q] = twiddle_small<false>(csub(xv[w * L + q], xv[w * L + q + M]), q, L);
+                dft_reg<M, false>(d);
+#pragma unroll
+                for (int k = 0; k < M; ++k) {
+                    nv[w * L + 2 * k] = cadd(pv[w * L + k], pv[w * L + M + k]);
+                    nv[w * L + 2 * k + 1] = d[k];
+                }
+            }
+            float4* yo = (float4*)(y + (int64_t)(I - 1) * ls);
+#pragma unroll
+            for (int e = 0; e < C; ++e) pv[e] = nv[e];
+#pragma unroll
+            for (int e = 0; e < C / 2; ++e)
+                yo[e] = make_float4(pv[2 * e].x, pv[2 * e].y, pv[2 * e + 1].x, pv[2 * e + 1].y);
+            LocalFwd<I + 1, LC>::run(xv, pv, y, ls);
+        }
+    }
+};
+
+template <int LC, bool REAL>
+__device__ __forceinline__ void fwd_local(const typename XType<REAL>::T* __restrict__ xin, float2* y, int64_t ls,
+                                          typename XType<REAL>::T* Xs, float2* Ps, bool keep) {
+    constexpr int C = 1 << LC;
+    float2 xv[C], pv[C];
+    if constexpr (REAL) {
+        // 8-byte loads: ragged real signals are only guaranteed 8-byte aligned.
+#pragma unroll
+        for (int e = 0; e < C / 2; ++e) {
+            float2 a = ((const float2*)xin)[e];
+            xv[2 * e] = to_c(a.x);
+            xv[2 * e + 1] = to_c(a.y);
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < C / 2; ++e) {
+            float4 a = ((const float4*)xin)[e];
+            xv[2 * e] = make_float2(a.x, a.y);
+            xv[2 * e + 1] = make_float2(a.z, a.w);
+        }
+    }
+    // Level 1: A^(1) = I (x) H_2 (D^(1) multiplies by w_2^0 = 1).
+#pragma unroll
+    for (int b = 0; b < C / 2; ++b) {
+        pv[2 * b] = cadd(xv[2 * b], xv[2 * b + 1]);
+        pv[2 * b + 1] = csub(xv[2 * b], xv[2 * b + 1]);
+    }
+    float4* yo = (float4*)y;
+#pragma unroll
+    for (int e = 0; e < C / 2; ++e)
+        yo[e] = make_float4(pv[2 * e].x, pv[2 * e].y, pv[2 * e + 1].x, pv[2 * e + 1].y);
+    LocalFwd<2, LC>::run(xv, pv, y, ls);
+    if (keep) {
+#pragma unroll
+        for (int e = 0; e < C; ++e) {
+            if constexpr (REAL) Xs[e] = xv[e].x; else Xs[e] = xv[e];
+            Ps[e] = pv[e];
+        }
+    }
+}
+
+// First Stockham step of the odd-bin FFT at level i: its inputs are the
+// twiddled window differences (x[wL+q] - x[wL+q+M]) * w_L^q read from LDS.
+template <int R, int JPT, typename XT>
+__device__ __forceinline__ void first_load_fwd(const XT* Xs, int i, int nw, const float2* __restrict__ tab,
+                                               float2* v, int tid) {
+    constexpr int lgR = Log2<R>::v;
+    const int lgM = i - 1, M = 1 << lgM, L = 2 * M;
+    const int lgper = lgM - lgR, per = 1 << lgper;
+    const int jobs = nw << lgper;
+#pragma unroll
+    for (int c = 0; c < JPT; ++c) {
+        const int J = tid + c * kTileThreads;
+        if (J < jobs) {
+            const int w = J >> lgper, j = J & (per - 1);
+#pragma unroll
+            for (int s = 0; s < R; ++s) {
+                const int q = j + s * per;
+                float2 d = csub(to_c(Xs[w * L + q]), to_c(Xs[w * L + q + M]));
+                v[c * R + s] = cmul(d, tw_tile(tab, i, q));
+            }
+            dft_reg<R, false>(&v[c * R]);
+        }
+    }
+}
+
+template <bool REAL>
+__global__ __launch_bounds__(kTileThreads) void tile_fwd_kernel(const void* __restrict__ x, float2* __restrict__ Y,
+                                                                const TileJob* __restrict__ jobs,
+                                                                const float2* __restrict__ tab) {
+    using XT = typename XType<REAL>::T;
+    __shared__ XT Xs[kTileMax];
+    __shared__ float4 Ps4[kTileMax / 2];
+    __shared__ float2 Fs[kTileMax / 2];
+    float2* Ps = (float2*)Ps4;
+
+    const TileJob jb = jobs[blockIdx.x];
+    const int t = jb.t;
+    const int T = 1 << t;
+    const int tid = threadIdx.x;
+    const XT* xin = (const XT*)x + jb.in_off;
+    float2* y = Y + jb.out_off;
+    const int64_t ls = jb.level_stride;
+
+    const int lc = t < 4 ? t : 4;
+    const bool keep = t > 4;
+    if (tid < (T >> lc)) {
+        const int c0 = tid << lc;
+        switch (lc) {
+            case 1: fwd_local<1, REAL>(xin + c0, y + c0, ls, Xs + c0, Ps + c0, keep); break;
+            case 2: fwd_local<2, REAL>(xin + c0, y + c0, ls, Xs + c0, Ps + c0, keep); break;
+            case 3: fwd_local<3, REAL>(xin + c0, y + c0, ls, Xs + c0, Ps + c0, keep); break;
+            default: fwd_local<4, REAL>(xin + c0, y + c0, ls, Xs + c0, Ps + c0, keep); break;
+        }
+    }
+    if (!keep) return;
+    __syncthreads();
+
+    for (int i = 5; i <= t; ++i) {
+        const int lgM = i - 1, M = 1 << lgM, L = 2 * M;
+        const int nw = T >> i;
+        const int rem = lgM % 3;
+        int lgNs;
+        // First step: V^(i) and D^(i) folded into the loads.
+        if (rem == 1) {
+            float2 v[8];
+            first_load_fwd<2, 4>(Xs, i, nw, tab, v, tid);
+            step_store<2, 4>(Fs, lgM, 0, M, 1, nw, v, tid, kTileThreads);
+            lgNs = 1;
+        } else if (rem == 2) {
+            float2 v[8];
+            first_load_fwd<4, 2>(Xs, i, nw, tab, v, tid);
+            step_store<4, 2>(Fs, lgM, 0, M, 1, nw, v, tid, kTileThreads);
+            lgNs = 2;
+        } else {
+            float2 v[8];
+            first_load_fwd<8, 1>(Xs, i, nw, tab, v, tid);
+            step_store<8, 1>(Fs, lgM, 0, M, 1, nw, v, tid, kTileThreads);
+            lgNs = 3;
+        }
+        __syncthreads();
+        // Middle radix-8 steps of R^(i).
+        while (lgNs + 3 < lgM) {
+            lds_step<8, 1, false>(Fs, lgM, lgNs, M, 1, nw, tab, tid, kTileThreads);
+            lgNs += 3;
+        }
+        // Last radix-8 step: outputs stay in registers, k = j + s*Ns.
+        float2 o[8];
+        step_load<8, 1, false>(Fs, lgM, lgNs, M, 1, nw, tab, o, tid, kTileThreads);
+        const int lgper = lgM - 3;
+        const int jobs_last = nw << lgper;
+        float2 sv[8];
+        int w = 0, j = 0;
+        if (tid < jobs_last) {
+            w = tid >> lgper;
+            j = tid & ((1 << lgper) - 1);
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                const int k = j + (s << lgper);
+                sv[s] = cadd(Ps[w * L + k], Ps[w * L + M + k]);     // U^(i): even bins
+            }
+        }
+        __syncthreads();
+        if (tid < jobs_last) {
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                const int k = j + (s << lgper);
+                Ps4[(w * L + 2 * k) >> 1] = make_float4(sv[s].x, sv[s].y, o[s].x, o[s].y);
+            }
+        }
+        __syncthreads();
+        float4* yo = (float4*)(y + (int64_t)(i - 1) * ls);
+        for (int e = tid; e < T / 2; e += kTileThreads) yo[e] = Ps4[e];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint
+// ---------------------------------------------------------------------------
+template <int I>
+struct LocalAdj {
+    // G: level-I gradient (natural order) for a chunk of C values; gx accumulates.
+    template <int C>
+    static __device__ __forceinline__ void run(float2* G, float2* gx, const float2* __restrict__ gy, int64_t ls) {
+        if constexpr (I >= 2) {
+            constexpr int L = 1 << I, M = L / 2;
+            float2 gn[C];
+            const float4* gl = (const float4*)(gy + (int64_t)(I - 2) * ls);   // gY^(I-1) chunk
+#pragma unroll
+            for (int e = 0; e < C / 2; ++e) {
+                float4 a = gl[e];
+                gn[2 * e] = make_float2(a.x, a.y);
+                gn[2 * e + 1] = make_float2(a.z, a.w);
+            }
+#pragma unroll
+            for (int w = 0; w < C / L; ++w) {
+                float2 z[M];
+#pragma unroll
+                for (int k = 0; k < M; ++k) z[k] = G[w * L + 2 * k + 1];
+                dft_reg<M, true>(z);
+#pragma unroll
+                for (int q = 0; q < M; ++q) {
+                    const float2 zz = twiddle_small<true>(z[q], q, L);
+                    gx[w * L + q] = cadd(gx[w * L + q], zz);
+                    gx[w * L + q + M] = csub(gx[w * L + q + M], zz);
+                }
+#pragma unroll
+                for (int k = 0; k < M; ++k) {
+                    const float2 ge = G[w * L + 2 * k];
+                    gn[w * L + k] = cadd(gn[w * L + k], ge);
+                    gn[w * L + M + k] = cadd(gn[w * L + M + k], ge);
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < C; ++e) G[e] = gn[e];
+            LocalAdj<I - 1>::template run<C>(G, gx, gy, ls);
+        } else {
+            // Level 1: transpose of I (x) H_2.
+#pragma unroll
+            for (int b = 0; b < C / 2; ++b) {
+                const float2 g0 = G[2 * b], g1 = G[2 * b + 1];
+                gx[2 * b] = cadd(gx[2 * b], cadd(g0, g1));
+                gx[2 * b + 1] = cadd(gx[2 * b + 1], csub(g0, g1));
+            }
+        }
+    }
+};
+
+template <int LC, bool REAL>
+__device__ __forceinline__ void adj_local(const float2* __restrict__ gy, int64_t ls, typename XType<REAL>::T* gout,
+                                          const float2* Gs /* LDS level-LC gradient or null */,
+                                          const typename XType<REAL>::T* Xs /* LDS partial gx or null */) {
+    constexpr int C = 1 << LC;
+    float2 G[C], gx[C];
+    if (Gs) {
+#pragma unroll
+        for (int e = 0; e < C; ++e) G[e] = Gs[e];
+    } else {
+        const float4* gl = (const float4*)(gy + (int64_t)(LC - 1) * ls);
+#pragma unroll
+        for (int e = 0; e < C / 2; ++e) {
+            float4 a = gl[e];
+            G[2 * e] = make_float2(a.x, a.y);
+            G[2 * e + 1] = make_float2(a.z, a.w);
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < C; ++e) {
+        if (Xs) gx[e] = to_c(Xs[e]);
+        else gx[e] = make_float2(0.0f, 0.0f);
+    }
+    LocalAdj<LC>::template run<C>(G, gx, gy, ls);
+    if constexpr (REAL) {
+#pragma unroll
+        for (int e = 0; e < C / 2; ++e) ((float2*)gout)[e] = make_float2(gx[2 * e].x, gx[2 * e + 1].x);
+    } else {
+#pragma unroll
+        for (int e = 0; e < C / 2; ++e)
+            ((float4*)gout)[e] = make_float4(gx[2 * e].x, gx[2 * e].y, gx[2 * e + 1].x, gx[2 * e + 1].y);
+    }
+}
+
+// First step of the conjugate odd-bin FFT: inputs are the odd bins of G.
+template <int R, int JPT>
+__device__ __forceinline__ void first_load_adj(const float2* Ps, int i, int nw, float2* v, int tid) {
+    constexpr int lgR = Log2<R>::v;
+    const int lgM = i - 1, L = 2 << lgM;
+    const int lgper = lgM - lgR, per = 1 << lgper;
+    const int jobs = nw << lgper;
+#pragma unroll
+    for (int c = 0; c < JPT; ++c) {
+        const int J = tid + c * kTileThreads;
+        if (J < jobs) {
+            const int w = J >> lgper, j = J & (per - 1);
+#pragma unroll
+            for (int s = 0; s < R; ++s) v[c * R + s] = Ps[w * L + 2 * (j + s * per) + 1];
+            dft_reg<R, true>(&v[c * R]);
+        }
+    }
+}
+
+template <bool REAL>
+__global__ __launch_bounds__(kTileThreads) void tile_adj_kernel(const float2* __restrict__ gY, void* __restrict__ gx,
+                                                                const TileJob* __restrict__ jobs,
+                                                                const float2* __restrict__ tab) {
+    using XT = typename XType<REAL>::T;
+    __shared__ XT Xs[kTileMax];            // gx accumulator (real part only for real x)
+    __shared__ float4 Ps4[kTileMax / 2];   // current level gradient G
+    __shared__ float2 Fs[kTileMax / 2];
+    float2* Ps = (float2*)Ps4;
+
+    const TileJob jb = jobs[blockIdx.x];
+    const int t = jb.t;
+    const int T = 1 << t;
+    const int tid = threadIdx.x;
+    const float2* gy = gY + jb.out_off;
+    XT* gout = (XT*)gx + jb.in_off;
+    const int64_t ls = jb.level_stride;
+
+    if (t > 4) {
+        const float4* g4 = (const float4*)(gy + (int64_t)(t - 1) * ls);
+        for (int e = tid; e < T / 2; e += kTileThreads) Ps4[e] = g4[e];
+        for (int e = tid; e < T; e += kTileThreads) {
+            if constexpr (REAL) Xs[e] = 0.0f; else Xs[e] = make_float2(0.0f, 0.0f);
+        }
+        __syncthreads();
+        for (int i = t; i >= 5; --i) {
+            const int lgM = i - 1, M = 1 << lgM, L = 2 * M;
+            const int nw = T >> i;
+            const int rem = lgM % 3;
+            int lgNs;
+            // Even-bin gradient of level i, read before G is overwritten.
+            float2 ge[8];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const int e = tid + c * kTileThreads;          // e = w*M + k
+                if (e < T / 2) {
+                    const int w = e >> lgM, k = e & (M - 1);
+                    ge[c] = Ps[w * L + 2 * k];
+                }
+            }
+            if (rem == 1) {
+                float2 v[8];
+                first_load_adj<2, 4>(Ps, i, nw, v, tid);
+                step_store<2, 4>(Fs, lgM, 0, M, 1, nw, v, tid, kTileThreads);
+                lgNs = 1;
+            } else if (rem == 2) {
+                float2 v[8];
+                first_load_adj<4, 2>(Ps, i, nw, v, tid);
+                step_store<4, 2>(Fs, lgM, 0, M, 1, nw, v, tid, kTileThreads);
+                lgNs = 2;
+            } else {
+                float2 v[8];
+                first_load_adj<8, 1>(Ps, i, nw, v, tid);
+                step_store<8, 1>(Fs, lgM, 0, M, 1, nw, v, tid, kTileThreads);
+                lgNs = 3;
+            }
+            __syncthreads();
+            while (lgNs + 3 < lgM) {
+                lds_step<8, 1, true>(Fs, lgM, lgNs, M, 1, nw, tab, tid, kTileThreads);
+                lgNs += 3;
+            }
+            float2 z[8];
+            step_load<8, 1, true>(Fs, lgM, lgNs, M, 1, nw, tab, z, tid, kTileThreads);
+            const int lgper = lgM - 3;
+            if (tid < (nw << lgper)) {
+                const int w = tid >> lgper, j = tid & ((1 << lgper) - 1);
+#pragma unroll
+                for (int s = 0; s < 8; ++s) {
+                    const int q = j + (s << lgper);
+                    const float2 zz = cmulc(z[s], tw_tile(tab, i, q));   // conj(D^(i))
+                    if constexpr (REAL) {
+                        Xs[w * L + q] += zz.x;
+                        Xs[w * L + q + M] -= zz.x;
+                    } else {
+                        Xs[w * L + q] = cadd(Xs[w * L + q], zz);
+                        Xs[w * L + q + M] = csub(Xs[w * L + q + M], zz);
+                    }
+                }
+            }
+            // Push the even-bin gradient to both children (transpose of U^(i)),
+            // adding the level i-1 input gradient.
+            const float2* gl = gy + (int64_t)(i - 2) * ls;
+            __syncthreads();
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const int e = tid + c * kTileThreads;
+                if (e < T / 2) {
+                    const int w = e >> lgM, k = e & (M - 1);
+                    const int p0 = w * L + k, p1 = p0 + M;
+                    Ps[p0] = cadd(ge[c], gl[p0]);
+                    Ps[p1] = cadd(ge[c], gl[p1]);
+                }
+            }
+            __syncthreads();
+        }
+    }
+    const int lc = t < 4 ? t : 4;
+    if (tid < (T >> lc)) {
+        const int c0 = tid << lc;
+        const float2* Gs = (t > 4) ? Ps + c0 : nullptr;
+        const XT* Xp = (t > 4) ? Xs + c0 : nullptr;
+        switch (lc) {
+            case 1: adj_local<1, REAL>(gy + c0, ls, gout + c0, Gs, Xp); break;
+            case 2: adj_local<2, REAL>(gy + c0, ls, gout + c0, Gs, Xp); break;
+            case 3: adj_local<3, REAL>(gy + c0, ls, gout + c0, Gs, Xp); break;
+            default: adj_local<4, REAL>(gy + c0, ls, gout + c0, Gs, Xp); break;
+        }
+    }
+}
+
+hipError_t launch_tile_fwd(bool real_in, const void* x, float2* Y, const TileJob* jobs, int64_t njobs,
+                           const Twiddles& tw, hipStream_t s) {
+    if (njobs <= 0) return hipSuccess;
+    dim3 grid((unsigned)njobs), block(kTileThreads);
+    if (real_in) hipLaunchKernelGGL(tile_fwd_kernel<true>, grid, block, 0, s, x, Y, jobs, tw.tile);
+    else hipLaunchKernelGGL(tile_fwd_kernel<false>, grid, block, 0, s, x, Y, jobs, tw.tile);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_adj(bool real_out, const float2* gY, void* gx, const TileJob* jobs, int64_t njobs,
+                           const Twiddles& tw, hipStream_t s) {
+    if (njobs <= 0) return hipSuccess;
+    dim3 grid((unsigned)njobs), block(kTileThreads);
+    if (real_out) hipLaunchKernelGGL(tile_adj_kernel<true>, grid, block, 0, s, gY, gx, jobs, tw.tile);
+    else hipLaunchKernelGGL(tile_adj_kernel<false>, grid, block, 0, s, gY, gx, jobs, tw.tile);
+    return hipGetLastError();
+}
+
+}  // namespace mrdft
