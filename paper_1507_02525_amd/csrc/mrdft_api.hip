@@ -83,6 +83,7 @@ struct mrdft_plan {
     float2* d_tw_tile = nullptr;
     double2* d_tw_hi = nullptr;
     double2* d_tw_lo = nullptr;
+    float2* d_tw16 = nullptr;
     float2* d_s[2] = {nullptr, nullptr};    // pass ping-pong scratch
     // spectral loss workspace
     float* d_v = nullptr;
@@ -98,7 +99,7 @@ struct mrdft_plan {
     std::vector<Rec> recs;
     std::vector<hipEvent_t> event_pool;
 
-    Twiddles tw() const { return Twiddles{d_tw_tile, d_tw_hi, d_tw_lo}; }
+    Twiddles tw() const { return Twiddles{d_tw_tile, d_tw16, d_tw_hi, d_tw_lo}; }
 };
 
 namespace {
@@ -122,6 +123,7 @@ void free_plan(mrdft_plan* p) {
     dfree(p->d_tw_tile);
     dfree(p->d_tw_hi);
     dfree(p->d_tw_lo);
+    dfree(p->d_tw16);
     dfree(p->d_s[0]);
     dfree(p->d_s[1]);
     dfree(p->d_v);
@@ -145,6 +147,22 @@ mrdft_status upload_twiddles(mrdft_plan* p, hipStream_t s) {
         hi[e] = make_double2(std::cos(ah), -std::sin(ah));
         lo[e] = make_double2(std::cos(al), -std::sin(al));
     }
+    // Row twiddles w_{2^l}^{n1*k2} (n1 < 1024, k2 < 2^(l-10)) of the single-pass
+    // levels l = 11..16, each block laid out [k2][n1].
+    const int64_t nrow = row_twiddle_entries();
+    std::vector<float2> rt(nrow);
+    for (int l = 11; l <= kUpperMaxLevel; ++l) {
+        const int64_t off = row_twiddle_offset(l);
+        const int64_t Ll = int64_t(1) << l;
+        for (int64_t k2 = 0; k2 < (Ll >> 10); ++k2)
+            for (int64_t n1 = 0; n1 < 1024; ++n1) {
+                const double a = 2.0 * M_PI * (double)((n1 * k2) % Ll) / (double)Ll;
+                rt[off + k2 * 1024 + n1] = make_float2((float)std::cos(a), (float)(-std::sin(a)));
+            }
+    }
+    if (hipMalloc(&p->d_tw16, sizeof(float2) * nrow) != hipSuccess)
+        return fail(MRDFT_E_ALLOC, "twiddle table allocation failed");
+    HIP_TRY(hipMemcpyAsync(p->d_tw16, rt.data(), sizeof(float2) * nrow, hipMemcpyHostToDevice, s));
     if (hipMalloc(&p->d_tw_tile, sizeof(float2) * kTileMax) != hipSuccess ||
         hipMalloc(&p->d_tw_hi, sizeof(double2) * nf) != hipSuccess ||
         hipMalloc(&p->d_tw_lo, sizeof(double2) * nf) != hipSuccess)
@@ -259,6 +277,21 @@ mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, h
     for (const Group& g : p->groups) {
         const int64_t N = int64_t(1) << g.order;
         for (int i = kTileMaxLog + 1; i <= g.order; ++i) {
+            if (i <= kUpperMaxLevel) {
+                PassGeom geo;
+                geo.lg = i;
+                geo.r_log = 0;
+                geo.ns_log = 0;
+                geo.nwin = g.count * (N >> i);
+                geo.wps = N >> i;
+                geo.in_sig = g.d_in_sig;
+                geo.in_stride = N;
+                geo.out_sig = g.d_out_sig;
+                geo.out_stride = (int64_t)g.order * N;
+                ProfScope ps(p, MRDFT_KERNEL_PASS_FWD, s);
+                HIP_TRY(launch_upper_fwd(in_kind == IN_R32, x, Y + (int64_t)(i - 1) * N, geo, tw, s));
+                continue;
+            }
             const std::vector<int> bits = pass_bits(i);
             int ns = 0;
             for (size_t q = 0; q < bits.size(); ++q) {

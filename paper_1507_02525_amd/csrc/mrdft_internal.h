@@ -33,6 +33,7 @@ enum OutKind { OUT_STORE = 0, OUT_ADD_C64 = 1, OUT_ADD_R32 = 2 };
 
 struct Twiddles {
     const float2* tile;   // w_{4096}^e, e < 4096 (FP32, rounded once from FP64)
+    const float2* rowtw;  // row twiddles w_{2^l}^{n1*k2} of the single-pass levels (FP32, rounded once)
     const double2* hi;    // w_{2^28}^{a*2^14}, a < 2^14 (FP64)
     const double2* lo;    // w_{2^28}^{b}, b < 2^14 (FP64)
 };
@@ -41,6 +42,12 @@ hipError_t launch_tile_fwd(bool real_in, const void* x, float2* Y, const TileJob
                            const Twiddles& tw, hipStream_t s);
 hipError_t launch_tile_adj(bool real_out, const float2* gY, void* gx, const TileJob* jobs, int64_t njobs,
                            const Twiddles& tw, hipStream_t s);
+// Single-pass levels with window 2^(10 + rl), 1 <= rl <= 6 (see mrdft_upper.hip).
+constexpr int kUpperMaxLevel = 16;
+int64_t row_twiddle_offset(int lg);
+int64_t row_twiddle_entries();
+hipError_t launch_upper_fwd(bool real_in, const void* x, float2* Y, const PassGeom& g, const Twiddles& tw,
+                            hipStream_t s);
 hipError_t launch_pass(bool inv, int in_kind, int out_kind, const void* in, void* out, const PassGeom& g,
                        const Twiddles& tw, hipStream_t s);
 

@@ -26,11 +26,11 @@ __device__ __forceinline__ void column_fft(float2* B, int rl, const float2* __re
     const int fst = kColStride(1 << rl);
     int lgNs = 0;
     const int rem = rl & 3;
-    if (rem == 1) { lds_step<2, 1, INV>(B, rl, 0, fst, 1, kPassCols, tab, tid, kPassThreads); lgNs = 1; }
-    else if (rem == 2) { lds_step<4, 1, INV>(B, rl, 0, fst, 1, kPassCols, tab, tid, kPassThreads); lgNs = 2; }
-    else if (rem == 3) { lds_step<8, 1, INV>(B, rl, 0, fst, 1, kPassCols, tab, tid, kPassThreads); lgNs = 3; }
+    if (rem == 1) { lds_step<2, 1, INV>(B, rl, 0, fst, 1, kPassCols, TwGlobal{tab}, tid, kPassThreads); lgNs = 1; }
+    else if (rem == 2) { lds_step<4, 1, INV>(B, rl, 0, fst, 1, kPassCols, TwGlobal{tab}, tid, kPassThreads); lgNs = 2; }
+    else if (rem == 3) { lds_step<8, 1, INV>(B, rl, 0, fst, 1, kPassCols, TwGlobal{tab}, tid, kPassThreads); lgNs = 3; }
     while (lgNs < rl) {
-        lds_step<16, 1, INV>(B, rl, lgNs, fst, 1, kPassCols, tab, tid, kPassThreads);
+        lds_step<16, 1, INV>(B, rl, lgNs, fst, 1, kPassCols, TwGlobal{tab}, tid, kPassThreads);
         lgNs += 4;
     }
 }

@@ -69,7 +69,7 @@ struct LocalFwd {
 
 template <int LC, bool REAL>
 __device__ __forceinline__ void fwd_local(const typename XType<REAL>::T* __restrict__ xin, float2* y, int64_t ls,
-                                          typename XType<REAL>::T* Xs, float2* Ps, bool keep) {
+                                          typename XType<REAL>::T* Xs, float2* Ps, int c0, bool keep) {
     constexpr int C = 1 << LC;
     float2 xv[C], pv[C];
     if constexpr (REAL) {
@@ -102,8 +102,8 @@ __device__ __forceinline__ void fwd_local(const typename XType<REAL>::T* __restr
     if (keep) {
 #pragma unroll
         for (int e = 0; e < C; ++e) {
-            if constexpr (REAL) Xs[e] = xv[e].x; else Xs[e] = xv[e];
-            Ps[e] = pv[e];
+            if constexpr (REAL) Xs[pad(c0 + e)] = xv[e].x; else Xs[pad(c0 + e)] = xv[e];
+            Ps[pad(c0 + e)] = pv[e];
         }
     }
 }
@@ -111,8 +111,8 @@ __device__ __forceinline__ void fwd_local(const typename XType<REAL>::T* __restr
 // First Stockham step of the odd-bin FFT at level i: its inputs are the
 // twiddled window differences (x[wL+q] - x[wL+q+M]) * w_L^q read from LDS.
 template <int R, int JPT, typename XT>
-__device__ __forceinline__ void first_load_fwd(const XT* Xs, int i, int nw, const float2* __restrict__ tab,
-                                               float2* v, int tid) {
+__device__ __forceinline__ void first_load_fwd(const XT* Xs, int i, int nw, const TwQuarter& tw, float2* v,
+                                               int tid) {
     constexpr int lgR = Log2<R>::v;
     const int lgM = i - 1, M = 1 << lgM, L = 2 * M;
     const int lgper = lgM - lgR, per = 1 << lgper;
@@ -125,8 +125,8 @@ __device__ __forceinline__ void first_load_fwd(const XT* Xs, int i, int nw, cons
 #pragma unroll
             for (int s = 0; s < R; ++s) {
                 const int q = j + s * per;
-                float2 d = csub(to_c(Xs[w * L + q]), to_c(Xs[w * L + q + M]));
-                v[c * R + s] = cmul(d, tw_tile(tab, i, q));
+                float2 d = csub(to_c(Xs[pad(w * L + q)]), to_c(Xs[pad(w * L + q + M)]));
+                v[c * R + s] = cmul(d, tw(i, q));
             }
             dft_reg<R, false>(&v[c * R]);
         }
@@ -138,10 +138,10 @@ __global__ __launch_bounds__(kTileThreads) void tile_fwd_kernel(const void* __re
                                                                 const TileJob* __restrict__ jobs,
                                                                 const float2* __restrict__ tab) {
     using XT = typename XType<REAL>::T;
-    __shared__ XT Xs[kTileMax];
-    __shared__ float4 Ps4[kTileMax / 2];
-    __shared__ float2 Fs[kTileMax / 2];
-    float2* Ps = (float2*)Ps4;
+    __shared__ XT Xs[padded_size(kTileMax)];          // x tile
+    __shared__ float2 Ps[padded_size(kTileMax)];      // previous level, natural bin order
+    __shared__ float2 Fs[padded_size(kTileMax / 2)];  // odd-bin FFT work space
+    __shared__ float2 Qs[kQuarter];                   // twiddle quarter table
 
     const TileJob jb = jobs[blockIdx.x];
     const int t = jb.t;
@@ -153,16 +153,18 @@ __global__ __launch_bounds__(kTileThreads) void tile_fwd_kernel(const void* __re
 
     const int lc = t < 4 ? t : 4;
     const bool keep = t > 4;
+    if (keep) load_quarter(Qs, tab, tid, kTileThreads);
     if (tid < (T >> lc)) {
         const int c0 = tid << lc;
         switch (lc) {
-            case 1: fwd_local<1, REAL>(xin + c0, y + c0, ls, Xs + c0, Ps + c0, keep); break;
-            case 2: fwd_local<2, REAL>(xin + c0, y + c0, ls, Xs + c0, Ps + c0, keep); break;
-            case 3: fwd_local<3, REAL>(xin + c0, y + c0, ls, Xs + c0, Ps + c0, keep); break;
-            default: fwd_local<4, REAL>(xin + c0, y + c0, ls, Xs + c0, Ps + c0, keep); break;
+            case 1: fwd_local<1, REAL>(xin + c0, y + c0, ls, Xs, Ps, c0, keep); break;
+            case 2: fwd_local<2, REAL>(xin + c0, y + c0, ls, Xs, Ps, c0, keep); break;
+            case 3: fwd_local<3, REAL>(xin + c0, y + c0, ls, Xs, Ps, c0, keep); break;
+            default: fwd_local<4, REAL>(xin + c0, y + c0, ls, Xs, Ps, c0, keep); break;
         }
     }
     if (!keep) return;
+    const TwQuarter tw{Qs};
     __syncthreads();
 
     for (int i = 5; i <= t; ++i) {
@@ -173,29 +175,29 @@ __global__ __launch_bounds__(kTileThreads) void tile_fwd_kernel(const void* __re
         // First step: V^(i) and D^(i) folded into the loads.
         if (rem == 1) {
             float2 v[8];
-            first_load_fwd<2, 4>(Xs, i, nw, tab, v, tid);
-            step_store<2, 4>(Fs, lgM, 0, M, 1, nw, v, tid, kTileThreads);
+            first_load_fwd<2, 4>(Xs, i, nw, tw, v, tid);
+            step_store<2, 4, true>(Fs, lgM, 0, M, 1, nw, v, tid, kTileThreads);
             lgNs = 1;
         } else if (rem == 2) {
             float2 v[8];
-            first_load_fwd<4, 2>(Xs, i, nw, tab, v, tid);
-            step_store<4, 2>(Fs, lgM, 0, M, 1, nw, v, tid, kTileThreads);
+            first_load_fwd<4, 2>(Xs, i, nw, tw, v, tid);
+            step_store<4, 2, true>(Fs, lgM, 0, M, 1, nw, v, tid, kTileThreads);
             lgNs = 2;
         } else {
             float2 v[8];
-            first_load_fwd<8, 1>(Xs, i, nw, tab, v, tid);
-            step_store<8, 1>(Fs, lgM, 0, M, 1, nw, v, tid, kTileThreads);
+            first_load_fwd<8, 1>(Xs, i, nw, tw, v, tid);
+            step_store<8, 1, true>(Fs, lgM, 0, M, 1, nw, v, tid, kTileThreads);
             lgNs = 3;
         }
         __syncthreads();
         // Middle radix-8 steps of R^(i).
         while (lgNs + 3 < lgM) {
-            lds_step<8, 1, false>(Fs, lgM, lgNs, M, 1, nw, tab, tid, kTileThreads);
+            lds_step<8, 1, false, true>(Fs, lgM, lgNs, M, 1, nw, tw, tid, kTileThreads);
             lgNs += 3;
         }
         // Last radix-8 step: outputs stay in registers, k = j + s*Ns.
         float2 o[8];
-        step_load<8, 1, false>(Fs, lgM, lgNs, M, 1, nw, tab, o, tid, kTileThreads);
+        step_load<8, 1, false, true>(Fs, lgM, lgNs, M, 1, nw, tw, o, tid, kTileThreads);
         const int lgper = lgM - 3;
         const int jobs_last = nw << lgper;
         float2 sv[8];
@@ -206,7 +208,7 @@ __global__ __launch_bounds__(kTileThreads) void tile_fwd_kernel(const void* __re
 #pragma unroll
             for (int s = 0; s < 8; ++s) {
                 const int k = j + (s << lgper);
-                sv[s] = cadd(Ps[w * L + k], Ps[w * L + M + k]);     // U^(i): even bins
+                sv[s] = cadd(Ps[pad(w * L + k)], Ps[pad(w * L + M + k)]);     // U^(i): even bins
             }
         }
         __syncthreads();
@@ -214,12 +216,16 @@ __global__ __launch_bounds__(kTileThreads) void tile_fwd_kernel(const void* __re
 #pragma unroll
             for (int s = 0; s < 8; ++s) {
                 const int k = j + (s << lgper);
-                Ps4[(w * L + 2 * k) >> 1] = make_float4(sv[s].x, sv[s].y, o[s].x, o[s].y);
+                Ps[pad(w * L + 2 * k)] = sv[s];
+                Ps[pad(w * L + 2 * k + 1)] = o[s];
             }
         }
         __syncthreads();
         float4* yo = (float4*)(y + (int64_t)(i - 1) * ls);
-        for (int e = tid; e < T / 2; e += kTileThreads) yo[e] = Ps4[e];
+        for (int e = tid; e < T / 2; e += kTileThreads) {
+            const float2 a = Ps[pad(2 * e)], b = Ps[pad(2 * e + 1)];
+            yo[e] = make_float4(a.x, a.y, b.x, b.y);
+        }
     }
 }
 
@@ -278,12 +284,12 @@ struct LocalAdj {
 template <int LC, bool REAL>
 __device__ __forceinline__ void adj_local(const float2* __restrict__ gy, int64_t ls, typename XType<REAL>::T* gout,
                                           const float2* Gs /* LDS level-LC gradient or null */,
-                                          const typename XType<REAL>::T* Xs /* LDS partial gx or null */) {
+                                          const typename XType<REAL>::T* Xs /* LDS partial gx or null */, int c0) {
     constexpr int C = 1 << LC;
     float2 G[C], gx[C];
     if (Gs) {
 #pragma unroll
-        for (int e = 0; e < C; ++e) G[e] = Gs[e];
+        for (int e = 0; e < C; ++e) G[e] = Gs[pad(c0 + e)];
     } else {
         const float4* gl = (const float4*)(gy + (int64_t)(LC - 1) * ls);
 #pragma unroll
@@ -295,7 +301,7 @@ __device__ __forceinline__ void adj_local(const float2* __restrict__ gy, int64_t
     }
 #pragma unroll
     for (int e = 0; e < C; ++e) {
-        if (Xs) gx[e] = to_c(Xs[e]);
+        if (Xs) gx[e] = to_c(Xs[pad(c0 + e)]);
         else gx[e] = make_float2(0.0f, 0.0f);
     }
     LocalAdj<LC>::template run<C>(G, gx, gy, ls);
@@ -322,7 +328,7 @@ __device__ __forceinline__ void first_load_adj(const float2* Ps, int i, int nw, 
         if (J < jobs) {
             const int w = J >> lgper, j = J & (per - 1);
 #pragma unroll
-            for (int s = 0; s < R; ++s) v[c * R + s] = Ps[w * L + 2 * (j + s * per) + 1];
+            for (int s = 0; s < R; ++s) v[c * R + s] = Ps[pad(w * L + 2 * (j + s * per) + 1)];
             dft_reg<R, true>(&v[c * R]);
         }
     }
@@ -333,10 +339,10 @@ __global__ __launch_bounds__(kTileThreads) void tile_adj_kernel(const float2* __
                                                                 const TileJob* __restrict__ jobs,
                                                                 const float2* __restrict__ tab) {
     using XT = typename XType<REAL>::T;
-    __shared__ XT Xs[kTileMax];            // gx accumulator (real part only for real x)
-    __shared__ float4 Ps4[kTileMax / 2];   // current level gradient G
-    __shared__ float2 Fs[kTileMax / 2];
-    float2* Ps = (float2*)Ps4;
+    __shared__ XT Xs[padded_size(kTileMax)];          // gx accumulator (real part only for real x)
+    __shared__ float2 Ps[padded_size(kTileMax)];      // current level gradient G
+    __shared__ float2 Fs[padded_size(kTileMax / 2)];
+    __shared__ float2 Qs[kQuarter];
 
     const TileJob jb = jobs[blockIdx.x];
     const int t = jb.t;
@@ -347,10 +353,16 @@ __global__ __launch_bounds__(kTileThreads) void tile_adj_kernel(const float2* __
     const int64_t ls = jb.level_stride;
 
     if (t > 4) {
+        const TwQuarter tw{Qs};
+        load_quarter(Qs, tab, tid, kTileThreads);
         const float4* g4 = (const float4*)(gy + (int64_t)(t - 1) * ls);
-        for (int e = tid; e < T / 2; e += kTileThreads) Ps4[e] = g4[e];
+        for (int e = tid; e < T / 2; e += kTileThreads) {
+            const float4 a = g4[e];
+            Ps[pad(2 * e)] = make_float2(a.x, a.y);
+            Ps[pad(2 * e + 1)] = make_float2(a.z, a.w);
+        }
         for (int e = tid; e < T; e += kTileThreads) {
-            if constexpr (REAL) Xs[e] = 0.0f; else Xs[e] = make_float2(0.0f, 0.0f);
+            if constexpr (REAL) Xs[pad(e)] = 0.0f; else Xs[pad(e)] = make_float2(0.0f, 0.0f);
         }
         __syncthreads();
         for (int i = t; i >= 5; --i) {
@@ -365,45 +377,46 @@ __global__ __launch_bounds__(kTileThreads) void tile_adj_kernel(const float2* __
                 const int e = tid + c * kTileThreads;          // e = w*M + k
                 if (e < T / 2) {
                     const int w = e >> lgM, k = e & (M - 1);
-                    ge[c] = Ps[w * L + 2 * k];
+                    ge[c] = Ps[pad(w * L + 2 * k)];
                 }
             }
             if (rem == 1) {
                 float2 v[8];
                 first_load_adj<2, 4>(Ps, i, nw, v, tid);
-                step_store<2, 4>(Fs, lgM, 0, M, 1, nw, v, tid, kTileThreads);
+                step_store<2, 4, true>(Fs, lgM, 0, M, 1, nw, v, tid, kTileThreads);
                 lgNs = 1;
             } else if (rem == 2) {
                 float2 v[8];
                 first_load_adj<4, 2>(Ps, i, nw, v, tid);
-                step_store<4, 2>(Fs, lgM, 0, M, 1, nw, v, tid, kTileThreads);
+                step_store<4, 2, true>(Fs, lgM, 0, M, 1, nw, v, tid, kTileThreads);
                 lgNs = 2;
             } else {
                 float2 v[8];
                 first_load_adj<8, 1>(Ps, i, nw, v, tid);
-                step_store<8, 1>(Fs, lgM, 0, M, 1, nw, v, tid, kTileThreads);
+                step_store<8, 1, true>(Fs, lgM, 0, M, 1, nw, v, tid, kTileThreads);
                 lgNs = 3;
             }
             __syncthreads();
             while (lgNs + 3 < lgM) {
-                lds_step<8, 1, true>(Fs, lgM, lgNs, M, 1, nw, tab, tid, kTileThreads);
+                lds_step<8, 1, true, true>(Fs, lgM, lgNs, M, 1, nw, tw, tid, kTileThreads);
                 lgNs += 3;
             }
             float2 z[8];
-            step_load<8, 1, true>(Fs, lgM, lgNs, M, 1, nw, tab, z, tid, kTileThreads);
+            step_load<8, 1, true, true>(Fs, lgM, lgNs, M, 1, nw, tw, z, tid, kTileThreads);
             const int lgper = lgM - 3;
             if (tid < (nw << lgper)) {
                 const int w = tid >> lgper, j = tid & ((1 << lgper) - 1);
 #pragma unroll
                 for (int s = 0; s < 8; ++s) {
                     const int q = j + (s << lgper);
-                    const float2 zz = cmulc(z[s], tw_tile(tab, i, q));   // conj(D^(i))
+                    const float2 zz = cmulc(z[s], tw(i, q));   // conj(D^(i))
+                    const int p0 = pad(w * L + q), p1 = pad(w * L + q + M);
                     if constexpr (REAL) {
-                        Xs[w * L + q] += zz.x;
-                        Xs[w * L + q + M] -= zz.x;
+                        Xs[p0] += zz.x;
+                        Xs[p1] -= zz.x;
                     } else {
-                        Xs[w * L + q] = cadd(Xs[w * L + q], zz);
-                        Xs[w * L + q + M] = csub(Xs[w * L + q + M], zz);
+                        Xs[p0] = cadd(Xs[p0], zz);
+                        Xs[p1] = csub(Xs[p1], zz);
                     }
                 }
             }
@@ -417,8 +430,8 @@ __global__ __launch_bounds__(kTileThreads) void tile_adj_kernel(const float2* __
                 if (e < T / 2) {
                     const int w = e >> lgM, k = e & (M - 1);
                     const int p0 = w * L + k, p1 = p0 + M;
-                    Ps[p0] = cadd(ge[c], gl[p0]);
-                    Ps[p1] = cadd(ge[c], gl[p1]);
+                    Ps[pad(p0)] = cadd(ge[c], gl[p0]);
+                    Ps[pad(p1)] = cadd(ge[c], gl[p1]);
                 }
             }
             __syncthreads();
@@ -427,13 +440,13 @@ __global__ __launch_bounds__(kTileThreads) void tile_adj_kernel(const float2* __
     const int lc = t < 4 ? t : 4;
     if (tid < (T >> lc)) {
         const int c0 = tid << lc;
-        const float2* Gs = (t > 4) ? Ps + c0 : nullptr;
-        const XT* Xp = (t > 4) ? Xs + c0 : nullptr;
+        const float2* Gs = (t > 4) ? Ps : nullptr;
+        const XT* Xp = (t > 4) ? Xs : nullptr;
         switch (lc) {
-            case 1: adj_local<1, REAL>(gy + c0, ls, gout + c0, Gs, Xp); break;
-            case 2: adj_local<2, REAL>(gy + c0, ls, gout + c0, Gs, Xp); break;
-            case 3: adj_local<3, REAL>(gy + c0, ls, gout + c0, Gs, Xp); break;
-            default: adj_local<4, REAL>(gy + c0, ls, gout + c0, Gs, Xp); break;
+            case 1: adj_local<1, REAL>(gy + c0, ls, gout + c0, Gs, Xp, c0); break;
+            case 2: adj_local<2, REAL>(gy + c0, ls, gout + c0, Gs, Xp, c0); break;
+            case 3: adj_local<3, REAL>(gy + c0, ls, gout + c0, Gs, Xp, c0); break;
+            default: adj_local<4, REAL>(gy + c0, ls, gout + c0, Gs, Xp, c0); break;
         }
     }
 }
