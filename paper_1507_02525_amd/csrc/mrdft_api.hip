@@ -1,8 +1,10 @@
 // Host side of the C ABI declared in include/mrdft.h: plan creation and
 // validation, FP64 twiddle generation, tile tables, launch sequencing.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -79,6 +81,7 @@ struct mrdft_plan {
     int max_order = 0;
     TileJob* d_jobs = nullptr;
     int64_t njobs = 0;
+    int64_t njobs_full = 0;                 // leading jobs with t = 12 (full 4096-sample tiles)
     std::vector<Group> groups;
     float2* d_tw_tile = nullptr;
     double2* d_tw_hi = nullptr;
@@ -90,6 +93,13 @@ struct mrdft_plan {
     float2* d_Yv = nullptr;
     float2* d_Yz = nullptr;
     double* d_part = nullptr;
+    // side stream for the levels above the tile (they write other parts of Y,
+    // so they run concurrently with the tile kernel); fork/join via events
+    static constexpr int kSides = 4;
+    hipStream_t side[kSides] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t fork_ev = nullptr;
+    hipEvent_t join_ev[kSides] = {nullptr, nullptr, nullptr, nullptr};
+    int nsides = 0;
     // opt-in kernel timing: events recorded around every launch on its stream
     bool profiling = false;
     struct Rec {
@@ -115,6 +125,11 @@ void free_plan(mrdft_plan* p) {
         (void)hipEventDestroy(r.b);
     }
     for (auto e : p->event_pool) (void)hipEventDestroy(e);
+    if (p->fork_ev) (void)hipEventDestroy(p->fork_ev);
+    for (int k = 0; k < p->nsides; ++k) {
+        if (p->join_ev[k]) (void)hipEventDestroy(p->join_ev[k]);
+        if (p->side[k]) (void)hipStreamDestroy(p->side[k]);
+    }
     dfree(p->d_jobs);
     for (auto& g : p->groups) {
         dfree(g.d_in_sig);
@@ -196,7 +211,11 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
             gout[mj].push_back(p->out_off[j]);
         }
     }
+    // full tiles first: the real-input kernel handles exactly those
+    std::stable_partition(jobs.begin(), jobs.end(), [](const TileJob& a) { return a.t == kRealTileLog; });
     p->njobs = (int64_t)jobs.size();
+    p->njobs_full = 0;
+    while (p->njobs_full < p->njobs && jobs[p->njobs_full].t == kRealTileLog) ++p->njobs_full;
     if (hipMalloc(&p->d_jobs, sizeof(TileJob) * jobs.size()) != hipSuccess)
         return fail(MRDFT_E_ALLOC, "tile table allocation failed (%zu bytes)", sizeof(TileJob) * jobs.size());
     HIP_TRY(hipMemcpyAsync(p->d_jobs, jobs.data(), sizeof(TileJob) * jobs.size(), hipMemcpyHostToDevice, s));
@@ -220,6 +239,18 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
         }
         const int64_t need = g.count << o;
         if (need > scratch) scratch = need;
+    }
+    const char* serial = std::getenv("MRDFT_SERIAL");        // 1: keep all levels on the caller's stream
+    if (!p->groups.empty() && !(serial && serial[0] == '1')) {
+        // one side stream per level above the tile (up to kSides), default priority
+        int levels = 0;
+        for (const Group& g : p->groups) levels = std::max(levels, g.order - kTileMaxLog);
+        HIP_TRY(hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming));
+        for (int k = 0; k < std::min(levels, (int)mrdft_plan::kSides); ++k) {
+            HIP_TRY(hipStreamCreateWithFlags(&p->side[k], hipStreamNonBlocking));
+            HIP_TRY(hipEventCreateWithFlags(&p->join_ev[k], hipEventDisableTiming));
+            p->nsides = k + 1;
+        }
     }
     if (scratch > 0) {
         if (hipMalloc(&p->d_s[0], sizeof(float2) * scratch) != hipSuccess ||
@@ -268,15 +299,21 @@ struct ProfScope {
 
 // Forward transform of all levels of every signal (x of the plan dtype, or an
 // explicit override of kind `in_kind`).
-mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, hipStream_t s) {
+mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, hipStream_t s0) {
     const Twiddles tw = p->tw();
-    {
-        ProfScope ps(p, MRDFT_KERNEL_TILE_FWD, s);
-        HIP_TRY(launch_tile_fwd(in_kind == IN_R32, x, Y, p->d_jobs, p->njobs, tw, s));
+    // Levels above the tile go to the side stream, which first waits for
+    // everything already queued on the caller's stream.
+    if (p->nsides) {
+        HIP_TRY(hipEventRecord(p->fork_ev, s0));
+        for (int k = 0; k < p->nsides; ++k) HIP_TRY(hipStreamWaitEvent(p->side[k], p->fork_ev, 0));
     }
     for (const Group& g : p->groups) {
         const int64_t N = int64_t(1) << g.order;
         for (int i = kTileMaxLog + 1; i <= g.order; ++i) {
+            // single-pass levels spread over the side streams; the multi-pass
+            // levels share one scratch buffer and therefore one stream
+            const int si = (i <= kUpperMaxLevel) ? (i - kTileMaxLog - 1) : 0;
+            const hipStream_t s = p->nsides ? p->side[si % p->nsides] : s0;
             if (i <= kUpperMaxLevel) {
                 PassGeom geo;
                 geo.lg = i;
@@ -289,7 +326,10 @@ mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, h
                 geo.out_sig = g.d_out_sig;
                 geo.out_stride = (int64_t)g.order * N;
                 ProfScope ps(p, MRDFT_KERNEL_PASS_FWD, s);
-                HIP_TRY(launch_upper_fwd(in_kind == IN_R32, x, Y + (int64_t)(i - 1) * N, geo, tw, s));
+                if (in_kind == IN_R32 && upper_real_supported(i))
+                    HIP_TRY(launch_upper_real((const float*)x, Y + (int64_t)(i - 1) * N, geo, tw, s));
+                else
+                    HIP_TRY(launch_upper_fwd(in_kind == IN_R32, x, Y + (int64_t)(i - 1) * N, geo, tw, s));
                 continue;
             }
             const std::vector<int> bits = pass_bits(i);
@@ -313,6 +353,19 @@ mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, h
                 ns += bits[q];
             }
         }
+    }
+    {
+        ProfScope ps(p, MRDFT_KERNEL_TILE_FWD, s0);
+        if (in_kind == IN_R32) {
+            HIP_TRY(launch_tile_fwd_real((const float*)x, Y, p->d_jobs, p->njobs_full, tw, s0));
+            HIP_TRY(launch_tile_fwd(true, x, Y, p->d_jobs + p->njobs_full, p->njobs - p->njobs_full, tw, s0));
+        } else {
+            HIP_TRY(launch_tile_fwd(false, x, Y, p->d_jobs, p->njobs, tw, s0));
+        }
+    }
+    for (int k = 0; k < p->nsides; ++k) {
+        HIP_TRY(hipEventRecord(p->join_ev[k], p->side[k]));
+        HIP_TRY(hipStreamWaitEvent(s0, p->join_ev[k], 0));
     }
     return MRDFT_OK;
 }

@@ -40,6 +40,10 @@ struct Twiddles {
 
 hipError_t launch_tile_fwd(bool real_in, const void* x, float2* Y, const TileJob* jobs, int64_t njobs,
                            const Twiddles& tw, hipStream_t s);
+// Real input, 4096-sample tiles (levels 1..12): see mrdft_tile_real.hip.
+constexpr int kRealTileLog = 12;
+hipError_t launch_tile_fwd_real(const float* x, float2* Y, const TileJob* jobs, int64_t njobs, const Twiddles& tw,
+                                hipStream_t s);
 hipError_t launch_tile_adj(bool real_out, const float2* gY, void* gx, const TileJob* jobs, int64_t njobs,
                            const Twiddles& tw, hipStream_t s);
 // Single-pass levels with window 2^(10 + rl), 1 <= rl <= 6 (see mrdft_upper.hip).
@@ -48,6 +52,9 @@ int64_t row_twiddle_offset(int lg);
 int64_t row_twiddle_entries();
 hipError_t launch_upper_fwd(bool real_in, const void* x, float2* Y, const PassGeom& g, const Twiddles& tw,
                             hipStream_t s);
+// Real-input variant (Hermitian rows), windows 2^13 .. 2^16: mrdft_upper_real.hip.
+bool upper_real_supported(int lg);
+hipError_t launch_upper_real(const float* x, float2* Y, const PassGeom& g, const Twiddles& tw, hipStream_t s);
 hipError_t launch_pass(bool inv, int in_kind, int out_kind, const void* in, void* out, const PassGeom& g,
                        const Twiddles& tw, hipStream_t s);
 

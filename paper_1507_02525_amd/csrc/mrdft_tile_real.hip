@@ -1,0 +1,351 @@
+// Forward tile kernel for real input: levels 1..12 of a 4096-sample tile.
+//
+// Same recurrence as the complex tile kernel (Section 3, eq. (4): even bins
+// of level i are sums of the two child windows of level i-1, U^(i), eq. (2);
+// odd bins are a transform of the twiddled window difference, V^(i), eq. (3),
+// D^(i), F^(i)), specialised to real x, whose window spectra are Hermitian:
+// Y[L-k] = conj(Y[k]).
+//
+// * State: each window of length L keeps L/2 complex slots, slot k = Y[k] for
+//   0 < k < L/2 and slot 0 = (Y[0], Y[L/2]) (DC and Nyquist are real).  With
+//   this packing the U step keeps its form: new slot 2k = child0[k] + child1[k]
+//   for every k < L/4, including the packed slot 0.
+// * Odd bins O[k] = sum_q d[q] w_L^{q(2k+1)} (d = x_lo - x_hi, real, M = L/2
+//   points) are needed for k < M/2 only; they come from one complex FFT of
+//   M/2 points: z[p] = (d[2p] + j d[2p+1]) w_M^p, Z = DFT(z), and with
+//   A = (Z[k] + conj(Z[M/2-1-k]))/2, B = -j (Z[k] - conj(Z[M/2-1-k]))/2,
+//   T = w_L^{2k+1} B:  O[k] = A + T,  O[M/2-1-k] = conj(A - T).
+// * Every level is written out as the full spectrum (the upper half as
+//   conjugates), straight from registers.
+//
+// Everything level-dependent is a compile-time constant (one instantiation per
+// level), so LDS addressing folds into immediate offsets.
+#include "mrdft_internal.h"
+#include "mrdft_lds_fft.h"
+
+#include <stddef.h>
+
+namespace mrdft {
+
+constexpr int kRTLog = 12;
+constexpr int kRT = 1 << kRTLog;         // tile length
+constexpr int kRThreads = 256;
+
+struct RealTileLds {
+    float X[kRT];                        // input tile
+    float2 P[kRT / 2];                   // half spectra; also the FFT work space
+    float2 Q[kRT / 4];                   // twiddle quarter table w_4096^e, e < 1024
+};                                       // 40 KB: four workgroups per CU
+// The register phase stages 4 waves x 512 float4 in X and P.
+static_assert(offsetof(RealTileLds, P) == sizeof(float) * kRT, "X and P adjacent");
+static_assert(sizeof(float) * kRT + sizeof(float2) * kRT / 2 == (kRThreads / 64) * 512 * sizeof(float4), "staging size");
+
+// No global load may follow a global store inside this kernel: the vector
+// memory counter retires loads and stores in issue order, so such a load would
+// wait for every earlier store.  All twiddles therefore come from LDS.
+
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+
+// w_{2^LG}^e (LG <= 12, 0 <= e < 2^LG) from the LDS quarter table.
+template <int LG>
+__device__ __forceinline__ float2 wl(const float2* Q, int e) {
+    return TwQuarter{Q}(LG, e);
+}
+// Same for exponents known to lie in the first quadrant (e < 2^LG / 4).
+template <int LG>
+__device__ __forceinline__ float2 wq1(const float2* Q, int e) {
+    return Q[e << (kRTLog - LG)];
+}
+// First two quadrants (e < 2^LG / 2): w^{e} = -j w^{e - 2^LG/4} beyond the first.
+template <int LG>
+__device__ __forceinline__ float2 wq2(const float2* Q, int e) {
+    const int E = e << (kRTLog - LG);
+    const float2 a = Q[E & (kRT / 4 - 1)];
+    return (E >= kRT / 4) ? make_float2(a.y, -a.x) : a;
+}
+
+// One in-place radix-R Stockham step over NW FFTs of H points in F (contiguous
+// per window), span 2^LNS before the step.  256 threads, R in {2, 4}.
+template <int R, int H, int NW, int LNS>
+__device__ __forceinline__ void rstep(float2* F, const float2* W, int tid) {
+    constexpr int LR = (R == 2) ? 1 : 2;
+    constexpr int PER = H / R;
+    constexpr int JOBS = NW * PER;
+    constexpr int JPT = JOBS / kRThreads;
+    static_assert(JOBS % kRThreads == 0, "job count");
+    constexpr int NS = 1 << LNS;
+    float2 v[JPT][R];
+#pragma unroll
+    for (int c = 0; c < JPT; ++c) {
+        const int J = tid + c * kRThreads;
+        const int w = J / PER, j = J % PER;
+        const float2* src = F + w * H + j;
+#pragma unroll
+        for (int s = 0; s < R; ++s) v[c][s] = src[s * PER];
+        if constexpr (LNS > 0) {
+            const int jm = j & (NS - 1);
+#pragma unroll
+            for (int s = 1; s < R; ++s) v[c][s] = cmul(v[c][s], wl<LNS + LR>(W, jm * s));
+        }
+        dft_reg<R, false>(v[c]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < JPT; ++c) {
+        const int J = tid + c * kRThreads;
+        const int w = J / PER, j = J % PER;
+        const int base = ((j >> LNS) << (LNS + LR)) + (j & (NS - 1));
+        float2* dst = F + w * H + base;
+#pragma unroll
+        for (int s = 0; s < R; ++s) dst[s * NS] = v[c][s];
+    }
+    __syncthreads();
+}
+
+// Remaining radix-4 steps after span 2^LNS, until the FFT of 2^LH points is done.
+template <int H, int NW, int LNS, int LH>
+struct RSteps {
+    static __device__ __forceinline__ void run(float2* F, const float2* W, int tid) {
+        if constexpr (LNS < LH) {
+            rstep<4, H, NW, LNS>(F, W, tid);
+            RSteps<H, NW, LNS + 2, LH>::run(F, W, tid);
+        }
+    }
+};
+
+// Level I >= 5 of the tile.
+template <int I>
+__device__ __forceinline__ void real_level(RealTileLds& S, float2* __restrict__ y, int tid) {
+    constexpr int L = 1 << I, M = L / 2, H = M / 2, LH = I - 2;
+    constexpr int NW = kRT / L;
+    constexpr int R1 = (LH & 1) ? 2 : 4;        // first step radix
+    constexpr int LR1 = (R1 == 2) ? 1 : 2;
+    constexpr int PJ = NW * (H / 2);            // post jobs: (w, k), k < H/2
+    constexpr int PPT = PJ / kRThreads;
+    static_assert(PJ % kRThreads == 0, "post job count");
+    float2* F = S.P;                            // FFT work space aliases the half spectra
+    // ---- U^(i) first: even bins from the two child windows, kept in registers ----
+    // Job (w, k) also takes u[k+1] and u[H-k], the even bins its mirrored
+    // (upper-half) output pairs need; u[H] stands for the Nyquist bin.
+    float2 uk[PPT], uj[PPT], uk1[PPT], uj1[PPT];
+#pragma unroll
+    for (int c = 0; c < PPT; ++c) {
+        const int J = tid + c * kRThreads;
+        const int w = J / (H / 2), k = J % (H / 2);
+        const int j = H - 1 - k;
+        const float2* c0 = S.P + (2 * w) * H;
+        uk[c] = cadd(c0[k], c0[H + k]);
+        uj[c] = cadd(c0[j], c0[H + j]);
+        uk1[c] = cadd(c0[k + 1], c0[H + k + 1]);
+        const int jn = (k == 0) ? 0 : j + 1;
+        uj1[c] = cadd(c0[jn], c0[H + jn]);
+    }
+    __syncthreads();
+    // ---- first step: pack the real window differences, pre-twiddle w_M^p, DFT ----
+    {
+        constexpr int PER = H / R1;
+        constexpr int JOBS = NW * PER;
+        constexpr int JPT = JOBS / kRThreads;
+        float2 v[JPT][R1];
+#pragma unroll
+        for (int c = 0; c < JPT; ++c) {
+            const int J = tid + c * kRThreads;
+            const int w = J / PER, j = J % PER;
+            const float* xw = S.X + w * L;
+#pragma unroll
+            for (int s = 0; s < R1; ++s) {
+                const int p = j + s * PER;
+                const float2 lo = *(const float2*)(xw + 2 * p);
+                const float2 hi = *(const float2*)(xw + M + 2 * p);
+                const float2 z = make_float2(lo.x - hi.x, lo.y - hi.y);
+                v[c][s] = cmul(z, wq2<I - 1>(S.Q, p));                   // w_M^p, p < M/2
+            }
+            dft_reg<R1, false>(v[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < JPT; ++c) {
+            const int J = tid + c * kRThreads;
+            const int w = J / PER, j = J % PER;
+            float2* dst = F + w * H + j * R1;
+#pragma unroll
+            for (int s = 0; s < R1; ++s) dst[s] = v[c][s];
+        }
+        __syncthreads();
+    }
+    RSteps<H, NW, LR1, LH>::run(F, S.Q, tid);
+    // ---- post-processing, new half spectra and the level's output ----
+    float2 ok[PPT], oj[PPT];
+#pragma unroll
+    for (int c = 0; c < PPT; ++c) {
+        const int J = tid + c * kRThreads;
+        const int w = J / (H / 2), k = J % (H / 2);
+        const int j = H - 1 - k;
+        const float2 zk = F[w * H + k], zj = F[w * H + j];
+        const float2 zjc = cconj(zj);
+        const float2 A = cscale(cadd(zk, zjc), 0.5f);
+        const float2 B = mul_mj(cscale(csub(zk, zjc), 0.5f));
+        const float2 T = cmul(wq1<I>(S.Q, 2 * k + 1), B);              // w_L^{2k+1}, 2k+1 < L/4
+        ok[c] = cadd(A, T);
+        oj[c] = cconj(csub(A, T));
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < PPT; ++c) {
+        const int J = tid + c * kRThreads;
+        const int w = J / (H / 2), k = J % (H / 2);
+        const int j = H - 1 - k;
+        float2* pw = S.P + w * M;
+        pw[2 * k] = uk[c];
+        pw[2 * k + 1] = ok[c];
+        pw[2 * j] = uj[c];
+        pw[2 * j + 1] = oj[c];
+        // Full spectrum: bins 2k, 2k+1 (lower half) and the aligned upper pairs
+        // (L/2 + 2t, L/2 + 2t + 1) = (conj u[H-t], conj o[H-1-t]), t = j and t = k;
+        // bin 0 is real, bin L/2 (Nyquist) is the second half of slot 0.
+        float2* yw = y + (int64_t)w * L;
+        const float2 u0 = (k == 0) ? make_float2(uk[c].x, 0.0f) : uk[c];
+        const float2 ua = cconj(uk1[c]);
+        const float2 ub = (k == 0) ? make_float2(uj1[c].y, 0.0f) : cconj(uj1[c]);
+        const float2 oka = cconj(ok[c]), oja = cconj(oj[c]);
+        *(float4*)(yw + 2 * k) = make_float4(u0.x, u0.y, ok[c].x, ok[c].y);
+        *(float4*)(yw + 2 * j) = make_float4(uj[c].x, uj[c].y, oj[c].x, oj[c].y);
+        *(float4*)(yw + M + 2 * j) = make_float4(ua.x, ua.y, oka.x, oka.y);
+        *(float4*)(yw + M + 2 * k) = make_float4(ub.x, ub.y, oja.x, oja.y);
+    }
+    __syncthreads();
+}
+
+template <int I>
+struct RealLevels {
+    static __device__ __forceinline__ void run(RealTileLds& S, float2* __restrict__ y, int64_t ls, int tid) {
+        if constexpr (I <= kRTLog) {
+            real_level<I>(S, y + (int64_t)(I - 1) * ls, tid);
+            RealLevels<I + 1>::run(S, y, ls, tid);
+        }
+    }
+};
+
+// Orders LDS accesses of lanes of one wave (LDS executes a wave's
+// instructions in issue order; this only stops the compiler from moving them).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Writes one register-phase level (16 complex values per thread, one window
+// each) through the wave's private LDS region, so that every global store
+// instruction covers 1 KB of consecutive output.  Pair e of lane l sits at
+// 8l + (e ^ (l & 7)) (XOR swizzle: conflict-free writes and reads).
+__device__ __forceinline__ void stage_level(const float2* pv, float4* st, float2* __restrict__ yl, int lane) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+        st[8 * lane + (e ^ (lane & 7))] = make_float4(pv[2 * e].x, pv[2 * e].y, pv[2 * e + 1].x, pv[2 * e + 1].y);
+    wave_sync();
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const int p = 64 * r + lane, wl = p >> 3, e = p & 7;
+        *(float4*)(yl + 2 * p) = st[8 * wl + (e ^ (wl & 7))];
+    }
+    wave_sync();
+}
+
+// Register recurrence for levels I..4 of 16 samples (full spectra, natural order).
+template <int I>
+struct LocalFwdReal {
+    static __device__ __forceinline__ void run(const float2* xv, float2* pv, float4* st, float2* y, int64_t ls,
+                                               int lane) {
+        if constexpr (I <= 4) {
+            constexpr int C = 16, L = 1 << I, M = L / 2;
+            float2 nv[C];
+#pragma unroll
+            for (int w = 0; w < C / L; ++w) {
+                float2 d[M];
+#pragma unroll
+                for (int q = 0; q < M; ++q)
+                    d[q] = twiddle_small<false>(csub(xv[w * L + q], xv[w * L + q + M]), q, L);
+                dft_reg<M, false>(d);
+#pragma unroll
+                for (int k = 0; k < M; ++k) {
+                    nv[w * L + 2 * k] = cadd(pv[w * L + k], pv[w * L + M + k]);
+                    nv[w * L + 2 * k + 1] = d[k];
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < C; ++e) pv[e] = nv[e];
+            stage_level(pv, st, y + (int64_t)(I - 1) * ls, lane);
+            LocalFwdReal<I + 1>::run(xv, pv, st, y, ls, lane);
+        }
+    }
+};
+
+// Register phase: each thread takes one 16-sample window through levels 1..4;
+// wave v owns samples [1024 v, 1024 v + 1024).  X and P (32 KB, contiguous)
+// serve as staging space first; at the end they receive the samples and the
+// level-4 half spectra (8 slots per window, slot 0 = (Y[0], Y[8])).
+__device__ __forceinline__ void real_local(const float* __restrict__ xin, float2* __restrict__ y, int64_t ls,
+                                           RealTileLds& S, int tid) {
+    constexpr int C = 16;
+    const int v = tid >> 6, lane = tid & 63;
+    float* xs = S.X + 1024 * v;
+    // coalesced load of the wave's samples (8-byte aligned: signal offsets are even)
+    {
+        const float2* xg = (const float2*)(xin + 1024 * v);
+        float2 a[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) a[r] = xg[64 * r + lane];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) *(float2*)(xs + 2 * (64 * r + lane)) = a[r];
+    }
+    wave_sync();
+    float2 xv[C], pv[C];
+#pragma unroll
+    for (int e = 0; e < C / 4; ++e) {
+        const float4 a = *(const float4*)(xs + C * lane + 4 * e);
+        xv[4 * e] = make_float2(a.x, 0.0f);
+        xv[4 * e + 1] = make_float2(a.y, 0.0f);
+        xv[4 * e + 2] = make_float2(a.z, 0.0f);
+        xv[4 * e + 3] = make_float2(a.w, 0.0f);
+    }
+    __syncthreads();                             // the staging space overlaps other waves' samples
+    float4* st = (float4*)S.X + 512 * v;
+#pragma unroll
+    for (int b = 0; b < C / 2; ++b) {
+        pv[2 * b] = cadd(xv[2 * b], xv[2 * b + 1]);
+        pv[2 * b + 1] = csub(xv[2 * b], xv[2 * b + 1]);
+    }
+    float2* yv = y + 1024 * v;
+    stage_level(pv, st, yv, lane);
+    LocalFwdReal<2>::run(xv, pv, st, yv, ls, lane);
+    __syncthreads();                             // staging done in every wave
+#pragma unroll
+    for (int e = 0; e < C / 4; ++e)
+        *(float4*)(S.X + C * tid + 4 * e) = make_float4(xv[4 * e].x, xv[4 * e + 1].x, xv[4 * e + 2].x, xv[4 * e + 3].x);
+    float2* pd = S.P + tid * 8;
+    pd[0] = make_float2(pv[0].x, pv[8].x);
+#pragma unroll
+    for (int s = 1; s < 8; ++s) pd[s] = pv[s];
+}
+
+__global__ __launch_bounds__(kRThreads) void tile_fwd_real_kernel(const float* __restrict__ x, float2* __restrict__ Y,
+                                                                  const TileJob* __restrict__ jobs,
+                                                                  const float2* __restrict__ t4096) {
+    __shared__ RealTileLds S;
+    const TileJob jb = jobs[blockIdx.x];
+    const int tid = threadIdx.x;
+    float2* y = Y + jb.out_off;
+    const int64_t ls = jb.level_stride;
+    for (int e = tid; e < kRT / 4; e += kRThreads) S.Q[e] = t4096[e];       // before any store
+    real_local(x + jb.in_off, y, ls, S, tid);
+    __syncthreads();
+    RealLevels<5>::run(S, y, ls, tid);
+}
+
+hipError_t launch_tile_fwd_real(const float* x, float2* Y, const TileJob* jobs, int64_t njobs, const Twiddles& tw,
+                                hipStream_t s) {
+    if (njobs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(tile_fwd_real_kernel, dim3((unsigned)njobs), dim3(kRThreads), 0, s, x, Y, jobs, tw.tile);
+    return hipGetLastError();
+}
+
+}  // namespace mrdft
