@@ -121,9 +121,10 @@ def main():
     ms_prof = timed(fwd, args.steps, sync)
     prof = plan.read_profile()
     plan.set_profiling(False)
-    t_tile = min(m, 12)
-    per_kind_bytes = {"tile_fwd": samples * 4 + t_tile * samples * 8,
-                      "pass_fwd": (m - t_tile) * samples * 8}
+    # algorithmic bytes of each kernel kind per step: x read once, its levels written once
+    fused_levels = min(m, 16)                     # real input: tiles and levels 13..16 in one launch
+    per_kind_bytes = {"fused_fwd": samples * 4 + fused_levels * samples * 8,
+                      "pass_fwd": (m - fused_levels) * samples * 8}
     kinds = {k: v for k, v in prof.items() if v[1] > 0}
     dom = max(kinds, key=lambda k: kinds[k][0])
     tot_ms, launches = kinds[dom]

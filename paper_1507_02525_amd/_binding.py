@@ -20,7 +20,7 @@ MRDFT_E_HIP = 4
 MRDFT_C64 = 0
 MRDFT_R32 = 1
 MRDFT_MAX_ORDER = 28
-KERNEL_KINDS = ("tile_fwd", "pass_fwd", "tile_adj", "pass_adj")
+KERNEL_KINDS = ("tile_fwd", "pass_fwd", "tile_adj", "pass_adj", "fused_fwd")
 
 # Every symbol the header declares, with (restype, argtypes).
 _vp = ctypes.c_void_p

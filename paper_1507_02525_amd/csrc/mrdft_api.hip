@@ -16,6 +16,7 @@
 #include "mrdft_device.h"
 #include "mrdft_internal.h"
 #include "mrdft_loss.h"
+#include "mrdft_rows_real.h"
 
 using namespace mrdft;
 
@@ -87,6 +88,11 @@ struct mrdft_plan {
     double2* d_tw_hi = nullptr;
     double2* d_tw_lo = nullptr;
     float2* d_tw16 = nullptr;
+    float2* d_tw_rows = nullptr;
+    float4* d_tw_comb = nullptr;
+    // real input: tiles of 4096 samples and rows pieces of levels 13..16, one launch
+    RealJob* d_rjobs = nullptr;
+    int64_t nrjobs = 0;
     float2* d_s[2] = {nullptr, nullptr};    // pass ping-pong scratch
     // spectral loss workspace
     float* d_v = nullptr;
@@ -109,7 +115,7 @@ struct mrdft_plan {
     std::vector<Rec> recs;
     std::vector<hipEvent_t> event_pool;
 
-    Twiddles tw() const { return Twiddles{d_tw_tile, d_tw16, d_tw_hi, d_tw_lo}; }
+    Twiddles tw() const { return Twiddles{d_tw_tile, d_tw16, d_tw_rows, d_tw_comb, d_tw_hi, d_tw_lo}; }
 };
 
 namespace {
@@ -139,6 +145,9 @@ void free_plan(mrdft_plan* p) {
     dfree(p->d_tw_hi);
     dfree(p->d_tw_lo);
     dfree(p->d_tw16);
+    dfree(p->d_tw_rows);
+    dfree(p->d_tw_comb);
+    dfree(p->d_rjobs);
     dfree(p->d_s[0]);
     dfree(p->d_s[1]);
     dfree(p->d_v);
@@ -178,6 +187,43 @@ mrdft_status upload_twiddles(mrdft_plan* p, hipStream_t s) {
     if (hipMalloc(&p->d_tw16, sizeof(float2) * nrow) != hipSuccess)
         return fail(MRDFT_E_ALLOC, "twiddle table allocation failed");
     HIP_TRY(hipMemcpyAsync(p->d_tw16, rt.data(), sizeof(float2) * nrow, hipMemcpyHostToDevice, s));
+    // Row twiddles w_L^{n1*k2} (n1 < 256, k2 < L/256) of the real levels 13..16, [k2][n1].
+    const int64_t nrows = rows_twiddle_entries();
+    std::vector<float2> rr(nrows);
+    for (int l = kRowsMinLevel; l <= kRowsMaxLevel; ++l) {
+        const int64_t off = rows_twiddle_offset(l);
+        const int64_t Ll = int64_t(1) << l;
+        for (int64_t k2 = 0; k2 < (Ll >> kRowsLog); ++k2)
+            for (int64_t n1 = 0; n1 < kRowsN; ++n1) {
+                const double a = 2.0 * M_PI * (double)((n1 * k2) % Ll) / (double)Ll;
+                rr[off + k2 * kRowsN + n1] = make_float2((float)std::cos(a), (float)(-std::sin(a)));
+            }
+    }
+    if (hipMalloc(&p->d_tw_rows, sizeof(float2) * nrows) != hipSuccess)
+        return fail(MRDFT_E_ALLOC, "twiddle table allocation failed");
+    HIP_TRY(hipMemcpyAsync(p->d_tw_rows, rr.data(), sizeof(float2) * nrows, hipMemcpyHostToDevice, s));
+    // Column-combine factors of those levels: for piece g, pair s, row q (k = 16 g + q),
+    // wa = w_R^{2s k}, wb = w_R^{(2s+1) k}, u = (wa - j wb)/2, v = (wa + j wb)/2.
+    const int64_t ncomb = rows_combine_entries();
+    std::vector<float4> cv(ncomb);
+    for (int l = kRowsMinLevel; l <= kRowsMaxLevel; ++l) {
+        const int64_t R = int64_t(1) << (l - kRowsLog);
+        const int64_t half = R / 32;                      // pieces per window = pairs per column
+        for (int64_t g = 0; g < half; ++g)
+            for (int64_t sp = 0; sp < half; ++sp)
+                for (int q = 0; q < kRowsMax; ++q) {
+                    const int64_t k = 16 * g + q;
+                    const double aa = 2.0 * M_PI * (double)((2 * sp * k) % R) / (double)R;
+                    const double ab = 2.0 * M_PI * (double)(((2 * sp + 1) * k) % R) / (double)R;
+                    const double wax = std::cos(aa), way = -std::sin(aa), wbx = std::cos(ab), wby = -std::sin(ab);
+                    cv[rows_combine_offset(l) + (g * half + sp) * kRowsMax + q] =
+                        make_float4((float)(0.5 * (wax + wby)), (float)(0.5 * (way - wbx)),
+                                    (float)(0.5 * (wax - wby)), (float)(0.5 * (way + wbx)));
+                }
+    }
+    if (hipMalloc(&p->d_tw_comb, sizeof(float4) * ncomb) != hipSuccess)
+        return fail(MRDFT_E_ALLOC, "twiddle table allocation failed");
+    HIP_TRY(hipMemcpyAsync(p->d_tw_comb, cv.data(), sizeof(float4) * ncomb, hipMemcpyHostToDevice, s));
     if (hipMalloc(&p->d_tw_tile, sizeof(float2) * kTileMax) != hipSuccess ||
         hipMalloc(&p->d_tw_hi, sizeof(double2) * nf) != hipSuccess ||
         hipMalloc(&p->d_tw_lo, sizeof(double2) * nf) != hipSuccess)
@@ -188,6 +234,8 @@ mrdft_status upload_twiddles(mrdft_plan* p, hipStream_t s) {
     HIP_TRY(hipStreamSynchronize(s));
     return MRDFT_OK;
 }
+
+std::vector<RealJob> real_jobs(const mrdft_plan* p);
 
 mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
     std::vector<TileJob> jobs;
@@ -219,6 +267,15 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
     if (hipMalloc(&p->d_jobs, sizeof(TileJob) * jobs.size()) != hipSuccess)
         return fail(MRDFT_E_ALLOC, "tile table allocation failed (%zu bytes)", sizeof(TileJob) * jobs.size());
     HIP_TRY(hipMemcpyAsync(p->d_jobs, jobs.data(), sizeof(TileJob) * jobs.size(), hipMemcpyHostToDevice, s));
+    if (p->dtype == MRDFT_R32) {
+        const std::vector<RealJob> rj = real_jobs(p);
+        p->nrjobs = (int64_t)rj.size();
+        if (!rj.empty()) {
+            if (hipMalloc(&p->d_rjobs, sizeof(RealJob) * rj.size()) != hipSuccess)
+                return fail(MRDFT_E_ALLOC, "job table allocation failed (%zu bytes)", sizeof(RealJob) * rj.size());
+            HIP_TRY(hipMemcpyAsync(p->d_rjobs, rj.data(), sizeof(RealJob) * rj.size(), hipMemcpyHostToDevice, s));
+        }
+    }
     int64_t scratch = 0;
     for (int o = kTileMaxLog + 1; o <= kMaxOrder; ++o) {
         if (gin[o].empty()) continue;
@@ -241,10 +298,13 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
         if (need > scratch) scratch = need;
     }
     const char* serial = std::getenv("MRDFT_SERIAL");        // 1: keep all levels on the caller's stream
-    if (!p->groups.empty() && !(serial && serial[0] == '1')) {
+    bool need_side = false;
+    for (const Group& g : p->groups) need_side |= p->dtype != MRDFT_R32 || g.order > kRowsMaxLevel;
+    if (need_side && !(serial && serial[0] == '1')) {
         // one side stream per level above the tile (up to kSides), default priority
         int levels = 0;
         for (const Group& g : p->groups) levels = std::max(levels, g.order - kTileMaxLog);
+        if (p->dtype == MRDFT_R32) levels = std::min(levels, 1);     // the real launch covers levels <= 16
         HIP_TRY(hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming));
         for (int k = 0; k < std::min(levels, (int)mrdft_plan::kSides); ++k) {
             HIP_TRY(hipStreamCreateWithFlags(&p->side[k], hipStreamNonBlocking));
@@ -259,6 +319,69 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
     }
     HIP_TRY(hipStreamSynchronize(s));
     return MRDFT_OK;
+}
+
+// Job table of the real forward launch.  Workgroups are dealt to the 8 XCDs
+// in block order (block b runs on XCD b mod 8), so all pieces of one window
+// go to one bucket = one XCD: their shared x columns then come from that
+// XCD's L2.  Inside a bucket the tiles come first (store-bound, they keep
+// HBM busy from the start), then the rows pieces from the highest level down
+// (longest first, so that the short ones fill the tail).
+std::vector<RealJob> real_jobs(const mrdft_plan* p) {
+    constexpr int kX = 8;
+    std::vector<std::vector<RealJob>> tiles(kX), rows(kX);
+    std::vector<int64_t> load(kX, 0);
+    auto lightest = [&]() { return (int)(std::min_element(load.begin(), load.end()) - load.begin()); };
+    for (int64_t j = 0; j < p->batch; ++j) {
+        const int mj = p->orders[j];
+        if (mj < kRealTileLog) continue;
+        const int64_t N = int64_t(1) << mj;
+        for (int64_t tau = 0; tau < (N >> kRealTileLog); ++tau) {
+            RealJob jb;
+            jb.in_off = p->in_off[j] + (tau << kRealTileLog);
+            jb.out_off = p->out_off[j] + (tau << kRealTileLog);
+            jb.level_stride = N;
+            jb.lg = 0;
+            jb.g = 0;
+            const int b = lightest();
+            tiles[b].push_back(jb);
+            load[b] += 6;                 // a tile writes 12 x 32 KB, a rows piece 64 KB
+        }
+        for (int lg = kRowsMinLevel; lg <= std::min(mj, kRowsMaxLevel); ++lg) {
+            const int64_t L = int64_t(1) << lg;
+            const int pieces = 1 << (lg - kRowsMinLevel);
+            for (int64_t w = 0; w < N / L; ++w) {
+                const int b = lightest();
+                for (int g = 0; g < pieces; ++g) {
+                    RealJob jb;
+                    jb.in_off = p->in_off[j] + w * L;
+                    jb.out_off = p->out_off[j] + (int64_t)(lg - 1) * N + w * L;
+                    jb.level_stride = 0;
+                    jb.lg = lg;
+                    jb.g = g;
+                    rows[b].push_back(jb);
+                }
+                load[b] += pieces;
+            }
+        }
+    }
+    std::vector<std::vector<RealJob>> bucket(kX);
+    for (int b = 0; b < kX; ++b) {
+        bucket[b] = tiles[b];
+        std::stable_sort(rows[b].begin(), rows[b].end(), [](const RealJob& a, const RealJob& c) { return a.lg > c.lg; });
+        bucket[b].insert(bucket[b].end(), rows[b].begin(), rows[b].end());
+    }
+    std::vector<RealJob> out;
+    for (size_t i = 0;; ++i) {
+        bool any = false;
+        for (int b = 0; b < kX; ++b)
+            if (i < bucket[b].size()) {
+                out.push_back(bucket[b][i]);
+                any = true;
+            }
+        if (!any) break;
+    }
+    return out;
 }
 
 hipEvent_t take_event(mrdft_plan* p) {
@@ -307,9 +430,11 @@ mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, h
         HIP_TRY(hipEventRecord(p->fork_ev, s0));
         for (int k = 0; k < p->nsides; ++k) HIP_TRY(hipStreamWaitEvent(p->side[k], p->fork_ev, 0));
     }
+    const bool real_jobs_cover = in_kind == IN_R32 && p->d_rjobs;
     for (const Group& g : p->groups) {
         const int64_t N = int64_t(1) << g.order;
         for (int i = kTileMaxLog + 1; i <= g.order; ++i) {
+            if (real_jobs_cover && i <= kRowsMaxLevel) continue;     // in the real launch
             // single-pass levels spread over the side streams; the multi-pass
             // levels share one scratch buffer and therefore one stream
             const int si = (i <= kUpperMaxLevel) ? (i - kTileMaxLog - 1) : 0;
@@ -326,10 +451,7 @@ mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, h
                 geo.out_sig = g.d_out_sig;
                 geo.out_stride = (int64_t)g.order * N;
                 ProfScope ps(p, MRDFT_KERNEL_PASS_FWD, s);
-                if (in_kind == IN_R32 && upper_real_supported(i))
-                    HIP_TRY(launch_upper_real((const float*)x, Y + (int64_t)(i - 1) * N, geo, tw, s));
-                else
-                    HIP_TRY(launch_upper_fwd(in_kind == IN_R32, x, Y + (int64_t)(i - 1) * N, geo, tw, s));
+                HIP_TRY(launch_upper_fwd(in_kind == IN_R32, x, Y + (int64_t)(i - 1) * N, geo, tw, s));
                 continue;
             }
             const std::vector<int> bits = pass_bits(i);
@@ -355,11 +477,20 @@ mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, h
         }
     }
     {
-        ProfScope ps(p, MRDFT_KERNEL_TILE_FWD, s0);
-        if (in_kind == IN_R32) {
-            HIP_TRY(launch_tile_fwd_real((const float*)x, Y, p->d_jobs, p->njobs_full, tw, s0));
-            HIP_TRY(launch_tile_fwd(true, x, Y, p->d_jobs + p->njobs_full, p->njobs - p->njobs_full, tw, s0));
+        if (real_jobs_cover) {
+            {
+                ProfScope ps(p, MRDFT_KERNEL_FUSED_FWD, s0);
+                HIP_TRY(launch_fwd_real((const float*)x, Y, p->d_rjobs, p->nrjobs, tw, s0));
+            }
+            if (p->njobs > p->njobs_full) {
+                ProfScope ps(p, MRDFT_KERNEL_TILE_FWD, s0);
+                HIP_TRY(launch_tile_fwd(true, x, Y, p->d_jobs + p->njobs_full, p->njobs - p->njobs_full, tw, s0));
+            }
+        } else if (in_kind == IN_R32) {
+            ProfScope ps(p, MRDFT_KERNEL_TILE_FWD, s0);
+            HIP_TRY(launch_tile_fwd(true, x, Y, p->d_jobs, p->njobs, tw, s0));
         } else {
+            ProfScope ps(p, MRDFT_KERNEL_TILE_FWD, s0);
             HIP_TRY(launch_tile_fwd(false, x, Y, p->d_jobs, p->njobs, tw, s0));
         }
     }

@@ -34,16 +34,31 @@ enum OutKind { OUT_STORE = 0, OUT_ADD_C64 = 1, OUT_ADD_R32 = 2 };
 struct Twiddles {
     const float2* tile;   // w_{4096}^e, e < 4096 (FP32, rounded once from FP64)
     const float2* rowtw;  // row twiddles w_{2^l}^{n1*k2} of the single-pass levels (FP32, rounded once)
+    const float2* rows;   // row twiddles of the real 256-point-row levels 13..16 (FP32, rounded once)
+    const float4* rows_comb;  // column-combine factors of those levels (FP32, rounded once)
     const double2* hi;    // w_{2^28}^{a*2^14}, a < 2^14 (FP64)
     const double2* lo;    // w_{2^28}^{b}, b < 2^14 (FP64)
 };
 
+// One job of the real forward launch (mrdft_fwd_real.hip).
+struct RealJob {
+    int64_t in_off;        // x offset of the tile, or of the window
+    int64_t out_off;       // Y offset of the tile's level-1 output, or of the window's output at its level
+    int64_t level_stride;  // tile: distance in Y between two levels (= N); rows piece: unused
+    int32_t lg;            // 0: tile of 4096 samples (levels 1..12); 13..16: rows piece of level lg
+    int32_t g;             // rows piece index, 0 <= g < 2^(lg-13)
+};
+// Row twiddles w_L^{n1 k2} (n1 < 256, k2 < L/256) of levels 13..16, [k2][n1] per level.
+__host__ __device__ constexpr int64_t rows_twiddle_offset(int lg) {
+    return lg <= 13 ? 0 : rows_twiddle_offset(lg - 1) + ((int64_t)1 << (lg - 1));
+}
+constexpr int64_t rows_twiddle_entries() { return rows_twiddle_offset(17); }
+hipError_t launch_fwd_real(const float* x, float2* Y, const RealJob* jobs, int64_t njobs, const Twiddles& tw,
+                           hipStream_t s);
 hipError_t launch_tile_fwd(bool real_in, const void* x, float2* Y, const TileJob* jobs, int64_t njobs,
                            const Twiddles& tw, hipStream_t s);
-// Real input, 4096-sample tiles (levels 1..12): see mrdft_tile_real.hip.
+// Real input, 4096-sample tiles (levels 1..12): see mrdft_tile_real.h.
 constexpr int kRealTileLog = 12;
-hipError_t launch_tile_fwd_real(const float* x, float2* Y, const TileJob* jobs, int64_t njobs, const Twiddles& tw,
-                                hipStream_t s);
 hipError_t launch_tile_adj(bool real_out, const float2* gY, void* gx, const TileJob* jobs, int64_t njobs,
                            const Twiddles& tw, hipStream_t s);
 // Single-pass levels with window 2^(10 + rl), 1 <= rl <= 6 (see mrdft_upper.hip).
@@ -52,9 +67,6 @@ int64_t row_twiddle_offset(int lg);
 int64_t row_twiddle_entries();
 hipError_t launch_upper_fwd(bool real_in, const void* x, float2* Y, const PassGeom& g, const Twiddles& tw,
                             hipStream_t s);
-// Real-input variant (Hermitian rows), windows 2^13 .. 2^16: mrdft_upper_real.hip.
-bool upper_real_supported(int lg);
-hipError_t launch_upper_real(const float* x, float2* Y, const PassGeom& g, const Twiddles& tw, hipStream_t s);
 hipError_t launch_pass(bool inv, int in_kind, int out_kind, const void* in, void* out, const PassGeom& g,
                        const Twiddles& tw, hipStream_t s);
 

@@ -1,4 +1,4 @@
-// Forward tile kernel for real input: levels 1..12 of a 4096-sample tile.
+// Forward tile for real input: levels 1..12 of a 4096-sample tile.
 //
 // Same recurrence as the complex tile kernel (Section 3, eq. (4): even bins
 // of level i are sums of the two child windows of level i-1, U^(i), eq. (2);
@@ -20,10 +20,11 @@
 //
 // Everything level-dependent is a compile-time constant (one instantiation per
 // level), so LDS addressing folds into immediate offsets.
+#pragma once
+#include <stddef.h>
+
 #include "mrdft_internal.h"
 #include "mrdft_lds_fft.h"
-
-#include <stddef.h>
 
 namespace mrdft {
 
@@ -327,25 +328,14 @@ __device__ __forceinline__ void real_local(const float* __restrict__ xin, float2
     for (int s = 1; s < 8; ++s) pd[s] = pv[s];
 }
 
-__global__ __launch_bounds__(kRThreads) void tile_fwd_real_kernel(const float* __restrict__ x, float2* __restrict__ Y,
-                                                                  const TileJob* __restrict__ jobs,
-                                                                  const float2* __restrict__ t4096) {
-    __shared__ RealTileLds S;
-    const TileJob jb = jobs[blockIdx.x];
-    const int tid = threadIdx.x;
-    float2* y = Y + jb.out_off;
-    const int64_t ls = jb.level_stride;
+// One full tile: x points at the tile's first sample, y at its level-1 output
+// (level i at y + (i-1)*ls).
+__device__ __forceinline__ void real_tile_body(RealTileLds& S, const float* __restrict__ x, float2* __restrict__ y,
+                                               int64_t ls, const float2* __restrict__ t4096, int tid) {
     for (int e = tid; e < kRT / 4; e += kRThreads) S.Q[e] = t4096[e];       // before any store
-    real_local(x + jb.in_off, y, ls, S, tid);
+    real_local(x, y, ls, S, tid);
     __syncthreads();
     RealLevels<5>::run(S, y, ls, tid);
-}
-
-hipError_t launch_tile_fwd_real(const float* x, float2* Y, const TileJob* jobs, int64_t njobs, const Twiddles& tw,
-                                hipStream_t s) {
-    if (njobs <= 0) return hipSuccess;
-    hipLaunchKernelGGL(tile_fwd_real_kernel, dim3((unsigned)njobs), dim3(kRThreads), 0, s, x, Y, jobs, tw.tile);
-    return hipGetLastError();
 }
 
 }  // namespace mrdft
