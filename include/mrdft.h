@@ -64,6 +64,14 @@ typedef enum {
 
 /* Plan flags */
 #define MRDFT_FLAG_NONE 0u
+/* Time the candidate schedules (tile depth, job order, persistent grid) on
+ * scratch buffers at plan creation and keep the fastest; without it the
+ * defaults are used.  Costs a few forward calls at creation. */
+#define MRDFT_FLAG_TUNE 1u
+/* Capture mrdft_forward into a HIP graph on first use for a given (x, Y) pair
+ * and replay it afterwards (one graph launch per call); a call with other
+ * pointers captures again.  Not combinable with kernel timing. */
+#define MRDFT_FLAG_GRAPH 2u
 
 /*
  * Create a plan.  Section 2 (problem statement of eq. (1)).
@@ -75,7 +83,7 @@ typedef enum {
  *             offsets, offsets[0] = 0, each length offsets[j+1]-offsets[j] a
  *             power of two 2^m_j with 1 <= m_j <= MRDFT_MAX_ORDER.
  *   dtype   : element type of x (MRDFT_C64 or MRDFT_R32).
- *   flags   : MRDFT_FLAG_NONE.
+ *   flags   : MRDFT_FLAG_NONE or an OR of MRDFT_FLAG_TUNE, MRDFT_FLAG_GRAPH.
  *   stream  : stream used for the plan's one-time uploads (synchronised
  *             before return).
  * Errors: MRDFT_E_INVALID_ARG for any violated rule, MRDFT_E_ALLOC, MRDFT_E_HIP.
@@ -91,6 +99,31 @@ mrdft_status mrdft_plan_output_offsets(mrdft_plan_t plan, int64_t* out);
 
 /* Total number of input samples and of complex outputs of the plan. */
 mrdft_status mrdft_plan_sizes(mrdft_plan_t plan, int64_t* n_in, int64_t* n_out);
+
+/*
+ * Schedule of the forward transform chosen at creation (by the tuner when
+ * MRDFT_FLAG_TUNE was given, else the defaults):
+ *   tile_log : levels computed per on-chip tile (11 or 12 for complex plans,
+ *              12 for real plans); the levels above come from the upper-level
+ *              jobs and passes.
+ *   grid     : workgroups of the persistent complex launch (0: not used).
+ *   order    : job order, MRDFT_ORDER_*.
+ * Any output pointer may be NULL.
+ */
+#define MRDFT_ORDER_TILES_FIRST 0 /* tiles, then upper-level pieces from the highest level down */
+#define MRDFT_ORDER_ROWS_FIRST 1  /* upper-level pieces (highest level first), then tiles */
+#define MRDFT_ORDER_INTERLEAVED 2 /* tiles and pieces alternate in proportion */
+mrdft_status mrdft_plan_schedule(mrdft_plan_t plan, int* tile_log, int* grid, int* order);
+
+/*
+ * Pin the forward schedule (e.g. one saved from an earlier tuning run) instead
+ * of tuning again.  tile_log: 11 or 12 for complex plans, 12 for real plans;
+ * grid: workgroups of the persistent complex launch (>= 1, ignored otherwise);
+ * order: MRDFT_ORDER_*.  Drops a captured forward graph.  Synchronises
+ * `stream` (the job table is re-uploaded).
+ * Errors: MRDFT_E_INVALID_ARG for values outside these sets.
+ */
+mrdft_status mrdft_plan_set_schedule(mrdft_plan_t plan, int tile_log, int grid, int order, hipStream_t stream);
 
 /*
  * Forward MrDFT, eq. (1) computed by eq. (4).

@@ -20,6 +20,10 @@ MRDFT_E_HIP = 4
 MRDFT_C64 = 0
 MRDFT_R32 = 1
 MRDFT_MAX_ORDER = 28
+MRDFT_FLAG_NONE = 0
+MRDFT_FLAG_TUNE = 1
+MRDFT_FLAG_GRAPH = 2
+ORDERS = ("tiles_first", "rows_first", "interleaved")
 KERNEL_KINDS = ("tile_fwd", "pass_fwd", "tile_adj", "pass_adj", "fused_fwd")
 
 # Every symbol the header declares, with (restype, argtypes).
@@ -31,6 +35,9 @@ SIGNATURES = {
                                          ctypes.c_uint, _vp]),
     "mrdft_plan_output_offsets": (ctypes.c_int, [_vp, _i64p]),
     "mrdft_plan_sizes": (ctypes.c_int, [_vp, _i64p, _i64p]),
+    "mrdft_plan_schedule": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                           ctypes.POINTER(ctypes.c_int)]),
+    "mrdft_plan_set_schedule": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp]),
     "mrdft_forward": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "mrdft_adjoint": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "mrdft_spectral_loss_fwd": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),

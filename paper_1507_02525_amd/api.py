@@ -35,9 +35,12 @@ class Plan:
 
     Uniform batch: ``Plan(m=m, batch=B, dtype="c64"|"r32")``.
     Ragged batch:  ``Plan(offsets=int64 array [batch+1], dtype=...)``.
+    ``tune=True`` times the candidate schedules at creation; ``graph=True``
+    replays mrdft_forward from a captured HIP graph.
     """
 
-    def __init__(self, m: int = 0, batch: int = 1, offsets=None, dtype: str = "c64", device=None):
+    def __init__(self, m: int = 0, batch: int = 1, offsets=None, dtype: str = "c64", device=None,
+                 tune: bool = False, graph: bool = False):
         lib = B.lib()
         self.dtype = dtype
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
@@ -54,7 +57,8 @@ class Plan:
             offp = None
         with torch.cuda.device(self.device):
             stream = ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
-            B.check(lib.mrdft_plan_create(ctypes.byref(h), int(m), int(batch), offp, code, 0, stream))
+            flags = (B.MRDFT_FLAG_TUNE if tune else 0) | (B.MRDFT_FLAG_GRAPH if graph else 0)
+            B.check(lib.mrdft_plan_create(ctypes.byref(h), int(m), int(batch), offp, code, flags, stream))
         self.handle = h
         self.m = int(m)
         self.batch = int(batch)
@@ -66,6 +70,19 @@ class Plan:
         self.n_out = n_out.value
 
     # -- C ABI mirrors -------------------------------------------------------
+    def schedule(self) -> dict:
+        """Forward schedule chosen at creation: tile_log, grid, order."""
+        t, g, o = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        B.check(B.lib().mrdft_plan_schedule(self.handle, ctypes.byref(t), ctypes.byref(g), ctypes.byref(o)))
+        return {"tile_log": t.value, "grid": g.value, "order": B.ORDERS[o.value]}
+
+    def set_schedule(self, tile_log: int, grid: int, order: str):
+        """Pin the forward schedule (values as returned by schedule())."""
+        with torch.cuda.device(self.device):
+            stream = ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+            B.check(B.lib().mrdft_plan_set_schedule(self.handle, int(tile_log), int(grid), B.ORDERS.index(order),
+                                                    stream))
+
     def output_offsets(self) -> np.ndarray:
         out = np.empty(self.batch + 1, dtype=np.int64)
         B.check(B.lib().mrdft_plan_output_offsets(self.handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))

@@ -16,6 +16,7 @@
 #include "mrdft_device.h"
 #include "mrdft_internal.h"
 #include "mrdft_loss.h"
+#include "mrdft_rows_c64.h"
 #include "mrdft_rows_real.h"
 
 using namespace mrdft;
@@ -90,9 +91,30 @@ struct mrdft_plan {
     float2* d_tw16 = nullptr;
     float2* d_tw_rows = nullptr;
     float4* d_tw_comb = nullptr;
+    float2* d_tw_ccomb = nullptr;
     // real input: tiles of 4096 samples and rows pieces of levels 13..16, one launch
     RealJob* d_rjobs = nullptr;
     int64_t nrjobs = 0;
+    // complex input: tiles of 2048 samples and rows pieces of levels 12..16 in
+    // one persistent launch (tile_log 11), or the tile kernel with 4096-sample
+    // tiles and one launch per upper level (tile_log 12)
+    RealJob* d_cjobs = nullptr;
+    int64_t ncjobs = 0;
+    TileJob* d_small = nullptr;             // tiles of complex signals of order < 11
+    int64_t nsmall = 0;
+    unsigned* d_queue = nullptr;            // persistent launch: next job, workgroups done
+    // schedule (tuned or default)
+    unsigned flags = 0;
+    int tile_log = kTileMaxLog;
+    int grid = 0;
+    int order = MRDFT_ORDER_TILES_FIRST;
+    int num_cu = 0;
+    // graph replay of the forward
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    const void* gkey_x = nullptr;
+    void* gkey_y = nullptr;
     float2* d_s[2] = {nullptr, nullptr};    // pass ping-pong scratch
     // spectral loss workspace
     float* d_v = nullptr;
@@ -115,7 +137,7 @@ struct mrdft_plan {
     std::vector<Rec> recs;
     std::vector<hipEvent_t> event_pool;
 
-    Twiddles tw() const { return Twiddles{d_tw_tile, d_tw16, d_tw_rows, d_tw_comb, d_tw_hi, d_tw_lo}; }
+    Twiddles tw() const { return Twiddles{d_tw_tile, d_tw16, d_tw_rows, d_tw_comb, d_tw_ccomb, d_tw_hi, d_tw_lo}; }
 };
 
 namespace {
@@ -147,7 +169,14 @@ void free_plan(mrdft_plan* p) {
     dfree(p->d_tw16);
     dfree(p->d_tw_rows);
     dfree(p->d_tw_comb);
+    dfree(p->d_tw_ccomb);
     dfree(p->d_rjobs);
+    dfree(p->d_cjobs);
+    dfree(p->d_small);
+    dfree(p->d_queue);
+    if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
     dfree(p->d_s[0]);
     dfree(p->d_s[1]);
     dfree(p->d_v);
@@ -190,7 +219,7 @@ mrdft_status upload_twiddles(mrdft_plan* p, hipStream_t s) {
     // Row twiddles w_L^{n1*k2} (n1 < 256, k2 < L/256) of the real levels 13..16, [k2][n1].
     const int64_t nrows = rows_twiddle_entries();
     std::vector<float2> rr(nrows);
-    for (int l = kRowsMinLevel; l <= kRowsMaxLevel; ++l) {
+    for (int l = kCRowsMinLevel; l <= kRowsMaxLevel; ++l) {
         const int64_t off = rows_twiddle_offset(l);
         const int64_t Ll = int64_t(1) << l;
         for (int64_t k2 = 0; k2 < (Ll >> kRowsLog); ++k2)
@@ -224,6 +253,22 @@ mrdft_status upload_twiddles(mrdft_plan* p, hipStream_t s) {
     if (hipMalloc(&p->d_tw_comb, sizeof(float4) * ncomb) != hipSuccess)
         return fail(MRDFT_E_ALLOC, "twiddle table allocation failed");
     HIP_TRY(hipMemcpyAsync(p->d_tw_comb, cv.data(), sizeof(float4) * ncomb, hipMemcpyHostToDevice, s));
+    // Combine factors of the complex levels 12..16: w_R^{r (16 g + q)}, index ((g * P + r) * 16 + q).
+    const int64_t nccomb = crows_combine_entries();
+    std::vector<float2> cc(nccomb);
+    for (int l = kCRowsMinLevel; l <= kRowsMaxLevel; ++l) {
+        const int64_t R = int64_t(1) << (l - kRowsLog), P = R / 16;
+        for (int64_t g = 0; g < R / 16; ++g)
+            for (int64_t r = 0; r < P; ++r)
+                for (int q = 0; q < 16; ++q) {
+                    const double a = 2.0 * M_PI * (double)((r * (16 * g + q)) % R) / (double)R;
+                    cc[crows_combine_offset(l) + (g * P + r) * 16 + q] =
+                        make_float2((float)std::cos(a), (float)(-std::sin(a)));
+                }
+    }
+    if (hipMalloc(&p->d_tw_ccomb, sizeof(float2) * nccomb) != hipSuccess)
+        return fail(MRDFT_E_ALLOC, "twiddle table allocation failed");
+    HIP_TRY(hipMemcpyAsync(p->d_tw_ccomb, cc.data(), sizeof(float2) * nccomb, hipMemcpyHostToDevice, s));
     if (hipMalloc(&p->d_tw_tile, sizeof(float2) * kTileMax) != hipSuccess ||
         hipMalloc(&p->d_tw_hi, sizeof(double2) * nf) != hipSuccess ||
         hipMalloc(&p->d_tw_lo, sizeof(double2) * nf) != hipSuccess)
@@ -235,7 +280,9 @@ mrdft_status upload_twiddles(mrdft_plan* p, hipStream_t s) {
     return MRDFT_OK;
 }
 
-std::vector<RealJob> real_jobs(const mrdft_plan* p);
+std::vector<RealJob> real_jobs(const mrdft_plan* p, int order);
+std::vector<RealJob> complex_jobs(const mrdft_plan* p, int order);
+mrdft_status upload_jobs(const std::vector<RealJob>& v, RealJob** dst, int64_t* n, hipStream_t s);
 
 mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
     std::vector<TileJob> jobs;
@@ -268,12 +315,29 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
         return fail(MRDFT_E_ALLOC, "tile table allocation failed (%zu bytes)", sizeof(TileJob) * jobs.size());
     HIP_TRY(hipMemcpyAsync(p->d_jobs, jobs.data(), sizeof(TileJob) * jobs.size(), hipMemcpyHostToDevice, s));
     if (p->dtype == MRDFT_R32) {
-        const std::vector<RealJob> rj = real_jobs(p);
-        p->nrjobs = (int64_t)rj.size();
-        if (!rj.empty()) {
-            if (hipMalloc(&p->d_rjobs, sizeof(RealJob) * rj.size()) != hipSuccess)
-                return fail(MRDFT_E_ALLOC, "job table allocation failed (%zu bytes)", sizeof(RealJob) * rj.size());
-            HIP_TRY(hipMemcpyAsync(p->d_rjobs, rj.data(), sizeof(RealJob) * rj.size(), hipMemcpyHostToDevice, s));
+        mrdft_status st = upload_jobs(real_jobs(p, p->order), &p->d_rjobs, &p->nrjobs, s);
+        if (st) return st;
+    } else {
+        mrdft_status st = upload_jobs(complex_jobs(p, p->order), &p->d_cjobs, &p->ncjobs, s);
+        if (st) return st;
+        std::vector<TileJob> small;
+        for (int64_t j = 0; j < p->batch; ++j) {
+            const int mj = p->orders[j];
+            if (mj >= kC64TileLog) continue;
+            small.push_back(TileJob{p->in_off[j], p->out_off[j], int64_t(1) << mj, mj, 0});
+        }
+        p->nsmall = (int64_t)small.size();
+        if (!small.empty()) {
+            if (hipMalloc(&p->d_small, sizeof(TileJob) * small.size()) != hipSuccess)
+                return fail(MRDFT_E_ALLOC, "tile table allocation failed");
+            HIP_TRY(hipMemcpyAsync(p->d_small, small.data(), sizeof(TileJob) * small.size(), hipMemcpyHostToDevice, s));
+        }
+        if (p->ncjobs > 0) {
+            if (hipMalloc(&p->d_queue, 2 * sizeof(unsigned)) != hipSuccess)
+                return fail(MRDFT_E_ALLOC, "queue allocation failed");
+            HIP_TRY(hipMemsetAsync(p->d_queue, 0, 2 * sizeof(unsigned), s));   // once; kernels restore it
+            p->tile_log = kC64TileLog;
+            p->grid = (int)std::min<int64_t>(p->ncjobs, 4 * (int64_t)p->num_cu);
         }
     }
     int64_t scratch = 0;
@@ -321,67 +385,123 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
     return MRDFT_OK;
 }
 
-// Job table of the real forward launch.  Workgroups are dealt to the 8 XCDs
-// in block order (block b runs on XCD b mod 8), so all pieces of one window
-// go to one bucket = one XCD: their shared x columns then come from that
-// XCD's L2.  Inside a bucket the tiles come first (store-bound, they keep
-// HBM busy from the start), then the rows pieces from the highest level down
-// (longest first, so that the short ones fill the tail).
-std::vector<RealJob> real_jobs(const mrdft_plan* p) {
-    constexpr int kX = 8;
-    std::vector<std::vector<RealJob>> tiles(kX), rows(kX);
-    std::vector<int64_t> load(kX, 0);
-    auto lightest = [&]() { return (int)(std::min_element(load.begin(), load.end()) - load.begin()); };
+// Job tables of the one-launch forwards.  Workgroups of a launch are dealt
+// to the 8 XCDs in block order (block b runs on XCD b mod 8), so all pieces of
+// one window go to one bucket: launched one workgroup per job, they share the
+// window's x columns through that XCD's L2.  Inside a bucket the order is
+//   tiles first : tiles (store-bound, they keep HBM busy from the start), then
+//                 the pieces from the highest level down (longest first, the
+//                 short ones fill the tail);
+//   rows first  : the pieces (highest level first), then the tiles;
+//   interleaved : tiles and pieces alternate in proportion.
+struct JobBuckets {
+    static constexpr int kX = 8;
+    std::vector<std::vector<RealJob>> tiles = std::vector<std::vector<RealJob>>(kX);
+    std::vector<std::vector<RealJob>> rows = std::vector<std::vector<RealJob>>(kX);
+    std::vector<int64_t> load = std::vector<int64_t>(kX, 0);
+    int lightest() const { return (int)(std::min_element(load.begin(), load.end()) - load.begin()); }
+    void add_tile(const RealJob& jb, int64_t cost) {
+        const int b = lightest();
+        tiles[b].push_back(jb);
+        load[b] += cost;
+    }
+    // all pieces of one window, into one bucket
+    void add_window(const RealJob& first, int pieces) {
+        const int b = lightest();
+        for (int g = 0; g < pieces; ++g) {
+            RealJob jb = first;
+            jb.g = g;
+            rows[b].push_back(jb);
+        }
+        load[b] += pieces;
+    }
+    std::vector<RealJob> deal(int order) {
+        std::vector<std::vector<RealJob>> bucket(kX);
+        for (int b = 0; b < kX; ++b) {
+            std::stable_sort(rows[b].begin(), rows[b].end(),
+                             [](const RealJob& a, const RealJob& c) { return a.lg > c.lg; });
+            if (order == MRDFT_ORDER_ROWS_FIRST) {
+                bucket[b] = rows[b];
+                bucket[b].insert(bucket[b].end(), tiles[b].begin(), tiles[b].end());
+            } else if (order == MRDFT_ORDER_INTERLEAVED) {
+                const size_t nt = tiles[b].size(), nr = rows[b].size();
+                size_t it = 0, ir = 0;
+                while (it < nt || ir < nr) {
+                    if (ir < nr && (it >= nt || ir * nt <= it * nr)) bucket[b].push_back(rows[b][ir++]);
+                    else bucket[b].push_back(tiles[b][it++]);
+                }
+            } else {
+                bucket[b] = tiles[b];
+                bucket[b].insert(bucket[b].end(), rows[b].begin(), rows[b].end());
+            }
+        }
+        std::vector<RealJob> out;
+        for (size_t i = 0;; ++i) {
+            bool any = false;
+            for (int b = 0; b < kX; ++b)
+                if (i < bucket[b].size()) {
+                    out.push_back(bucket[b][i]);
+                    any = true;
+                }
+            if (!any) break;
+        }
+        return out;
+    }
+};
+
+// Real signals of order >= 12: 4096-sample tiles and pieces of levels 13..16
+// (2^(lg-13) pieces per window).
+std::vector<RealJob> real_jobs(const mrdft_plan* p, int order) {
+    JobBuckets jb;
     for (int64_t j = 0; j < p->batch; ++j) {
         const int mj = p->orders[j];
         if (mj < kRealTileLog) continue;
         const int64_t N = int64_t(1) << mj;
-        for (int64_t tau = 0; tau < (N >> kRealTileLog); ++tau) {
-            RealJob jb;
-            jb.in_off = p->in_off[j] + (tau << kRealTileLog);
-            jb.out_off = p->out_off[j] + (tau << kRealTileLog);
-            jb.level_stride = N;
-            jb.lg = 0;
-            jb.g = 0;
-            const int b = lightest();
-            tiles[b].push_back(jb);
-            load[b] += 6;                 // a tile writes 12 x 32 KB, a rows piece 64 KB
-        }
+        for (int64_t tau = 0; tau < (N >> kRealTileLog); ++tau)
+            jb.add_tile(RealJob{p->in_off[j] + (tau << kRealTileLog), p->out_off[j] + (tau << kRealTileLog), N, 0, 0},
+                        6);                                    // 12 x 32 KB against 64 KB per piece
         for (int lg = kRowsMinLevel; lg <= std::min(mj, kRowsMaxLevel); ++lg) {
             const int64_t L = int64_t(1) << lg;
-            const int pieces = 1 << (lg - kRowsMinLevel);
-            for (int64_t w = 0; w < N / L; ++w) {
-                const int b = lightest();
-                for (int g = 0; g < pieces; ++g) {
-                    RealJob jb;
-                    jb.in_off = p->in_off[j] + w * L;
-                    jb.out_off = p->out_off[j] + (int64_t)(lg - 1) * N + w * L;
-                    jb.level_stride = 0;
-                    jb.lg = lg;
-                    jb.g = g;
-                    rows[b].push_back(jb);
-                }
-                load[b] += pieces;
-            }
+            for (int64_t w = 0; w < N / L; ++w)
+                jb.add_window(RealJob{p->in_off[j] + w * L, p->out_off[j] + (int64_t)(lg - 1) * N + w * L, 0, lg, 0},
+                              1 << (lg - kRowsMinLevel));
         }
     }
-    std::vector<std::vector<RealJob>> bucket(kX);
-    for (int b = 0; b < kX; ++b) {
-        bucket[b] = tiles[b];
-        std::stable_sort(rows[b].begin(), rows[b].end(), [](const RealJob& a, const RealJob& c) { return a.lg > c.lg; });
-        bucket[b].insert(bucket[b].end(), rows[b].begin(), rows[b].end());
+    return jb.deal(order);
+}
+
+// Complex signals of order >= 11: 2048-sample tiles and pieces of levels
+// 12..16 (2^(lg-12) pieces of 16 rows per window).
+std::vector<RealJob> complex_jobs(const mrdft_plan* p, int order) {
+    JobBuckets jb;
+    for (int64_t j = 0; j < p->batch; ++j) {
+        const int mj = p->orders[j];
+        if (mj < kC64TileLog) continue;
+        const int64_t N = int64_t(1) << mj;
+        for (int64_t tau = 0; tau < (N >> kC64TileLog); ++tau)
+            jb.add_tile(RealJob{p->in_off[j] + (tau << kC64TileLog), p->out_off[j] + (tau << kC64TileLog), N, 0, 0},
+                        5);                                    // 11 x 16 KB against 32 KB per piece
+        for (int lg = kCRowsMinLevel; lg <= std::min(mj, kRowsMaxLevel); ++lg) {
+            const int64_t L = int64_t(1) << lg;
+            for (int64_t w = 0; w < N / L; ++w)
+                jb.add_window(RealJob{p->in_off[j] + w * L, p->out_off[j] + (int64_t)(lg - 1) * N + w * L, 0, lg, 0},
+                              1 << (lg - kCRowsMinLevel));
+        }
     }
-    std::vector<RealJob> out;
-    for (size_t i = 0;; ++i) {
-        bool any = false;
-        for (int b = 0; b < kX; ++b)
-            if (i < bucket[b].size()) {
-                out.push_back(bucket[b][i]);
-                any = true;
-            }
-        if (!any) break;
-    }
-    return out;
+    return jb.deal(order);
+}
+
+// Upload a job table (replacing a previous one of the same slot).
+mrdft_status upload_jobs(const std::vector<RealJob>& v, RealJob** dst, int64_t* n, hipStream_t s) {
+    dfree(*dst);
+    *dst = nullptr;
+    *n = (int64_t)v.size();
+    if (v.empty()) return MRDFT_OK;
+    if (hipMalloc(dst, sizeof(RealJob) * v.size()) != hipSuccess)
+        return fail(MRDFT_E_ALLOC, "job table allocation failed (%zu bytes)", sizeof(RealJob) * v.size());
+    HIP_TRY(hipMemcpyAsync(*dst, v.data(), sizeof(RealJob) * v.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return MRDFT_OK;
 }
 
 hipEvent_t take_event(mrdft_plan* p) {
@@ -431,10 +551,11 @@ mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, h
         for (int k = 0; k < p->nsides; ++k) HIP_TRY(hipStreamWaitEvent(p->side[k], p->fork_ev, 0));
     }
     const bool real_jobs_cover = in_kind == IN_R32 && p->d_rjobs;
+    const bool cjobs_cover = in_kind == IN_C64 && p->d_cjobs && p->tile_log == kC64TileLog;
     for (const Group& g : p->groups) {
         const int64_t N = int64_t(1) << g.order;
         for (int i = kTileMaxLog + 1; i <= g.order; ++i) {
-            if (real_jobs_cover && i <= kRowsMaxLevel) continue;     // in the real launch
+            if ((real_jobs_cover || cjobs_cover) && i <= kRowsMaxLevel) continue;     // in the one launch
             // single-pass levels spread over the side streams; the multi-pass
             // levels share one scratch buffer and therefore one stream
             const int si = (i <= kUpperMaxLevel) ? (i - kTileMaxLog - 1) : 0;
@@ -489,6 +610,15 @@ mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, h
         } else if (in_kind == IN_R32) {
             ProfScope ps(p, MRDFT_KERNEL_TILE_FWD, s0);
             HIP_TRY(launch_tile_fwd(true, x, Y, p->d_jobs, p->njobs, tw, s0));
+        } else if (cjobs_cover) {
+            {
+                ProfScope ps(p, MRDFT_KERNEL_FUSED_FWD, s0);
+                HIP_TRY(launch_fwd_c64((const float2*)x, Y, p->d_cjobs, p->ncjobs, p->d_queue, p->grid, tw, s0));
+            }
+            if (p->nsmall) {
+                ProfScope ps(p, MRDFT_KERNEL_TILE_FWD, s0);
+                HIP_TRY(launch_tile_fwd(false, x, Y, p->d_small, p->nsmall, tw, s0));
+            }
         } else {
             ProfScope ps(p, MRDFT_KERNEL_TILE_FWD, s0);
             HIP_TRY(launch_tile_fwd(false, x, Y, p->d_jobs, p->njobs, tw, s0));
@@ -536,6 +666,120 @@ mrdft_status run_adjoint(mrdft_plan* p, const float2* gY, void* gx, bool real_ou
     return MRDFT_OK;
 }
 
+// Time one candidate schedule: forward on scratch buffers, median of 3.
+mrdft_status time_forward(mrdft_plan* p, const void* x, float2* Y, hipStream_t s, float* ms_out) {
+    const int in_kind = p->dtype == MRDFT_R32 ? IN_R32 : IN_C64;
+    hipEvent_t a = nullptr, b = nullptr;
+    HIP_TRY(hipEventCreate(&a));
+    HIP_TRY(hipEventCreate(&b));
+    float best[3];
+    mrdft_status st = run_forward(p, x, in_kind, Y, s);          // warm-up
+    for (int r = 0; r < 3 && st == MRDFT_OK; ++r) {
+        HIP_TRY(hipEventRecord(a, s));
+        st = run_forward(p, x, in_kind, Y, s);
+        HIP_TRY(hipEventRecord(b, s));
+        HIP_TRY(hipEventSynchronize(b));
+        HIP_TRY(hipEventElapsedTime(&best[r], a, b));
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (st) return st;
+    std::sort(best, best + 3);
+    *ms_out = best[1];
+    return MRDFT_OK;
+}
+
+// Autotuner: time the candidate schedules on zero-filled scratch buffers and
+// keep the fastest.  Complex plans: tile depth 12 (tile kernel, one launch per
+// upper level) or 11 (one persistent launch) with each job order and grid of
+// 1, 2 or 4 workgroups per CU; real plans: the job order.
+mrdft_status tune(mrdft_plan* p, hipStream_t s) {
+    const bool real = p->dtype == MRDFT_R32;
+    if (real ? p->nrjobs == 0 : p->ncjobs == 0) return MRDFT_OK;
+    void* x = nullptr;
+    float2* Y = nullptr;
+    const size_t xbytes = (size_t)p->n_in * (real ? sizeof(float) : sizeof(float2));
+    if (hipMalloc(&x, xbytes) != hipSuccess || hipMalloc(&Y, sizeof(float2) * (size_t)p->n_out) != hipSuccess) {
+        dfree(x);
+        return fail(MRDFT_E_ALLOC, "tuning buffers allocation failed");
+    }
+    mrdft_status st = MRDFT_OK;
+    if (hipMemsetAsync(x, 0, xbytes, s) != hipSuccess) st = fail(MRDFT_E_HIP, "tuning buffer clear failed");
+    struct Cand {
+        int tile_log, order, grid;
+    };
+    std::vector<Cand> cands;
+    for (int order = 0; order < 3; ++order) {
+        if (real) {
+            cands.push_back({kRealTileLog, order, 0});
+        } else {
+            for (int per = 1; per <= 4; per *= 2)
+                cands.push_back({kC64TileLog, order, (int)std::min<int64_t>(p->ncjobs, (int64_t)per * p->num_cu)});
+        }
+    }
+    if (!real) cands.push_back({kTileMaxLog, MRDFT_ORDER_TILES_FIRST, 0});
+    float best_ms = 1e30f;
+    Cand best = {p->tile_log, p->order, p->grid};
+    int cur_order = p->order;
+    for (const Cand& c : cands) {
+        if (st) break;
+        if (c.tile_log != kTileMaxLog && c.order != cur_order) {
+            st = real ? upload_jobs(real_jobs(p, c.order), &p->d_rjobs, &p->nrjobs, s)
+                      : upload_jobs(complex_jobs(p, c.order), &p->d_cjobs, &p->ncjobs, s);
+            cur_order = c.order;
+            if (st) break;
+        }
+        p->tile_log = c.tile_log;
+        p->grid = c.grid;
+        float ms = 0.0f;
+        st = time_forward(p, x, Y, s, &ms);
+        if (!st && ms < best_ms) {
+            best_ms = ms;
+            best = c;
+        }
+    }
+    if (!st && best.tile_log != kTileMaxLog && best.order != cur_order)
+        st = real ? upload_jobs(real_jobs(p, best.order), &p->d_rjobs, &p->nrjobs, s)
+                  : upload_jobs(complex_jobs(p, best.order), &p->d_cjobs, &p->ncjobs, s);
+    p->tile_log = best.tile_log;
+    p->order = best.tile_log == kTileMaxLog && !real ? cur_order : best.order;
+    p->grid = best.grid;
+    if (hipStreamSynchronize(s) != hipSuccess && !st) st = fail(MRDFT_E_HIP, "tuning failed");
+    dfree(x);
+    dfree(Y);
+    return st;
+}
+
+// Graph replay of the forward: capture once per (x, Y) pair on the plan's own
+// stream, then launch the instantiated graph on the caller's stream.
+mrdft_status graph_forward(mrdft_plan* p, const void* x, float2* Y, hipStream_t stream) {
+    const int in_kind = p->dtype == MRDFT_R32 ? IN_R32 : IN_C64;
+    if (!p->gexec || p->gkey_x != x || p->gkey_y != (void*)Y) {
+        if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+        if (p->graph) (void)hipGraphDestroy(p->graph);
+        p->gexec = nullptr;
+        p->graph = nullptr;
+        // capturing records work without running it; the replay on the
+        // caller's stream is ordered after what the caller queued before
+        if (!p->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+        HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeRelaxed));
+        mrdft_status st = run_forward(p, x, in_kind, Y, p->cap_stream);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(p->cap_stream, &g);
+        if (st) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess) return fail(MRDFT_E_HIP, "graph capture failed: %s", hipGetErrorString(e));
+        p->graph = g;
+        HIP_TRY(hipGraphInstantiate(&p->gexec, p->graph, nullptr, nullptr, 0));
+        p->gkey_x = x;
+        p->gkey_y = Y;
+    }
+    HIP_TRY(hipGraphLaunch(p->gexec, stream));
+    return MRDFT_OK;
+}
+
 bool misaligned(const void* ptr, size_t a) { return (reinterpret_cast<uintptr_t>(ptr) & (a - 1)) != 0; }
 
 mrdft_status check_plan(mrdft_plan_t plan) {
@@ -578,11 +822,12 @@ mrdft_status mrdft_plan_create(mrdft_plan_t* plan, int m, int64_t batch, const i
     *plan = nullptr;
     if (batch < 1) return fail(MRDFT_E_INVALID_ARG, "batch must be >= 1 (got %lld)", (long long)batch);
     if (dtype != MRDFT_C64 && dtype != MRDFT_R32) return fail(MRDFT_E_INVALID_ARG, "unknown dtype %d", (int)dtype);
-    if (flags != MRDFT_FLAG_NONE) return fail(MRDFT_E_INVALID_ARG, "unknown flags 0x%x", flags);
+    if (flags & ~(MRDFT_FLAG_TUNE | MRDFT_FLAG_GRAPH)) return fail(MRDFT_E_INVALID_ARG, "unknown flags 0x%x", flags);
     mrdft_plan* p = new (std::nothrow) mrdft_plan();
     if (!p) return fail(MRDFT_E_ALLOC, "host allocation failed");
     p->batch = batch;
     p->dtype = dtype;
+    p->flags = flags;
     p->in_off.resize(batch + 1);
     p->out_off.resize(batch + 1);
     p->orders.resize(batch);
@@ -624,8 +869,18 @@ mrdft_status mrdft_plan_create(mrdft_plan_t* plan, int m, int64_t batch, const i
     p->m = offsets ? 0 : m;
     p->n_in = p->in_off[batch];
     p->n_out = p->out_off[batch];
+    {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&p->num_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            p->num_cu < 1) {
+            delete p;
+            return fail(MRDFT_E_HIP, "no usable HIP device");
+        }
+    }
     mrdft_status st = upload_twiddles(p, stream);
     if (st == MRDFT_OK) st = build_tables(p, stream);
+    if (st == MRDFT_OK && (flags & MRDFT_FLAG_TUNE)) st = tune(p, stream);
     if (st != MRDFT_OK) {
         free_plan(p);
         return st;
@@ -661,7 +916,43 @@ mrdft_status mrdft_forward(mrdft_plan_t plan, const void* x, void* Y, hipStream_
     if (!x || !Y) return fail(MRDFT_E_INVALID_ARG, "x and Y must be non-NULL");
     if (misaligned(Y, 16) || misaligned(x, plan->dtype == MRDFT_C64 ? 16 : 8))
         return fail(MRDFT_E_INVALID_ARG, "x or Y is not sufficiently aligned");
+    if ((plan->flags & MRDFT_FLAG_GRAPH) && !plan->profiling) return graph_forward(plan, x, (float2*)Y, stream);
     return run_forward(plan, x, plan->dtype == MRDFT_R32 ? IN_R32 : IN_C64, (float2*)Y, stream);
+}
+
+mrdft_status mrdft_plan_set_schedule(mrdft_plan_t plan, int tile_log, int grid, int order, hipStream_t stream) {
+    mrdft_status st = check_plan(plan);
+    if (st) return st;
+    const bool real = plan->dtype == MRDFT_R32;
+    if (order < MRDFT_ORDER_TILES_FIRST || order > MRDFT_ORDER_INTERLEAVED)
+        return fail(MRDFT_E_INVALID_ARG, "unknown job order %d", order);
+    if (real ? tile_log != kRealTileLog : (tile_log != kC64TileLog && tile_log != kTileMaxLog))
+        return fail(MRDFT_E_INVALID_ARG, "tile_log %d is not available for this plan", tile_log);
+    if (!real && tile_log == kC64TileLog && grid < 1) return fail(MRDFT_E_INVALID_ARG, "grid must be >= 1");
+    if (order != plan->order) {
+        st = real ? upload_jobs(real_jobs(plan, order), &plan->d_rjobs, &plan->nrjobs, stream)
+                  : upload_jobs(complex_jobs(plan, order), &plan->d_cjobs, &plan->ncjobs, stream);
+        if (st) return st;
+        plan->order = order;
+    }
+    if (!real) {
+        plan->tile_log = plan->ncjobs > 0 ? tile_log : kTileMaxLog;
+        plan->grid = grid;
+    }
+    if (plan->gexec) (void)hipGraphExecDestroy(plan->gexec);
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    plan->gexec = nullptr;
+    plan->graph = nullptr;
+    return MRDFT_OK;
+}
+
+mrdft_status mrdft_plan_schedule(mrdft_plan_t plan, int* tile_log, int* grid, int* order) {
+    mrdft_status st = check_plan(plan);
+    if (st) return st;
+    if (tile_log) *tile_log = plan->dtype == MRDFT_R32 ? kRealTileLog : plan->tile_log;
+    if (grid) *grid = (plan->dtype == MRDFT_C64 && plan->tile_log == kC64TileLog) ? plan->grid : 0;
+    if (order) *order = plan->order;
+    return MRDFT_OK;
 }
 
 mrdft_status mrdft_adjoint(mrdft_plan_t plan, const void* gY, void* gx, hipStream_t stream) {

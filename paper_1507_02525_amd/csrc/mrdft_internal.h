@@ -35,7 +35,8 @@ struct Twiddles {
     const float2* tile;   // w_{4096}^e, e < 4096 (FP32, rounded once from FP64)
     const float2* rowtw;  // row twiddles w_{2^l}^{n1*k2} of the single-pass levels (FP32, rounded once)
     const float2* rows;   // row twiddles of the real 256-point-row levels 13..16 (FP32, rounded once)
-    const float4* rows_comb;  // column-combine factors of those levels (FP32, rounded once)
+    const float4* rows_comb;  // column-combine factors of the real levels (FP32, rounded once)
+    const float2* crows_comb; // column-combine factors of the complex levels 12..16 (FP32, rounded once)
     const double2* hi;    // w_{2^28}^{a*2^14}, a < 2^14 (FP64)
     const double2* lo;    // w_{2^28}^{b}, b < 2^14 (FP64)
 };
@@ -48,13 +49,20 @@ struct RealJob {
     int32_t lg;            // 0: tile of 4096 samples (levels 1..12); 13..16: rows piece of level lg
     int32_t g;             // rows piece index, 0 <= g < 2^(lg-13)
 };
-// Row twiddles w_L^{n1 k2} (n1 < 256, k2 < L/256) of levels 13..16, [k2][n1] per level.
+// Row twiddles w_L^{n1 k2} (n1 < 256, k2 < L/256) of levels 12..16, [k2][n1] per level.
 __host__ __device__ constexpr int64_t rows_twiddle_offset(int lg) {
-    return lg <= 13 ? 0 : rows_twiddle_offset(lg - 1) + ((int64_t)1 << (lg - 1));
+    return lg <= 12 ? 0 : rows_twiddle_offset(lg - 1) + ((int64_t)1 << (lg - 1));
 }
 constexpr int64_t rows_twiddle_entries() { return rows_twiddle_offset(17); }
 hipError_t launch_fwd_real(const float* x, float2* Y, const RealJob* jobs, int64_t njobs, const Twiddles& tw,
                            hipStream_t s);
+// Complex input: 2048-sample tiles (lg = 0, levels 1..11) and pieces of levels
+// 12..16 (mrdft_fwd_c64.hip).  Persistent: `grid` workgroups take jobs from
+// queue[0] until the table is exhausted; the last workgroup out clears
+// queue[0..1] for the next launch (the plan zeroes them once at creation).
+constexpr int kC64TileLog = 11;
+hipError_t launch_fwd_c64(const float2* x, float2* Y, const RealJob* jobs, int64_t njobs, unsigned* queue, int grid,
+                          const Twiddles& tw, hipStream_t s);
 hipError_t launch_tile_fwd(bool real_in, const void* x, float2* Y, const TileJob* jobs, int64_t njobs,
                            const Twiddles& tw, hipStream_t s);
 // Real input, 4096-sample tiles (levels 1..12): see mrdft_tile_real.h.

@@ -1,0 +1,264 @@
+// Forward tile for complex input: levels 1..11 of a 2048-sample tile, 256
+// threads, 40 KB of LDS.
+//
+// The recurrence of Section 3 (eq. (4)), level by level, on chip:
+// * even bins: U^(i) (eq. (2)), Y^(i)[w][2k] = Y^(i-1)[2w][k] + Y^(i-1)[2w+1][k];
+// * odd bins: V^(i), D^(i), F^(i) (eq. (3)): the L/2-point DFT of the window
+//   difference d[q] = x[wL + q] - x[wL + q + L/2] twiddled by w_L^q,
+//   Y^(i)[w][2k+1] = DFT(d)[k].  The DFT runs as Stockham steps (natural
+//   order out, so the bit reversal of Section 3 is never executed).
+// Levels 1..3 run in registers (one 8-sample window per thread) and are
+// written through wave-private LDS staging, so that every store instruction
+// covers 1 KB of consecutive output; levels 4..11 run in LDS.  U^(i) is formed
+// first and kept in registers, which lets the FFT work space overlay the
+// level spectra.
+#pragma once
+#include "mrdft_device.h"
+#include "mrdft_lds_fft.h"
+
+namespace mrdft {
+
+constexpr int kCTLog = 11;
+constexpr int kCT = 1 << kCTLog;        // tile length (complex samples)
+constexpr int kCThreads = 256;
+
+struct CTileLds {
+    float2 X[kCT];                      // samples
+    float2 P[kCT];                      // level spectra; the FFT work space overlays them
+    float2 Q[kCT / 4];                  // w_2048^e, e < 512
+};                                      // 36 KB
+static_assert(sizeof(CTileLds) <= 40 * 1024 - 256, "four workgroups per CU");
+
+// w_{2^lg}^e (lg <= 11) from the quarter table q[r] = w_2048^r, r < 512:
+// w^{r + 512 c} = (-j)^c w^r.
+struct TwQ2048 {
+    const float2* q;
+    __device__ __forceinline__ float2 operator()(int lg, int e) const {
+        const int E = (e << (kCTLog - lg)) & (kCT - 1);
+        const float2 a = q[E & (kCT / 4 - 1)];
+        const int c = E >> (kCTLog - 2);
+        float re = (c & 1) ? a.y : a.x;
+        float im = (c & 1) ? -a.x : a.y;
+        if (c & 2) {
+            re = -re;
+            im = -im;
+        }
+        return make_float2(re, im);
+    }
+};
+
+// FFT work space index: one spare element after every 32 (bank spread of the
+// strided Stockham accesses); 1024 points need 1056 slots of P.
+__device__ __forceinline__ int cfpad(int i) { return i + (i >> 5); }
+
+__device__ __forceinline__ void ct_wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One radix-R Stockham step (R = 2 or 4) over NW FFTs of M points stored
+// contiguously per window in F (padded), span 2^LNS before the step; 1024
+// points, 256 threads.
+template <int R, int M, int LNS>
+__device__ __forceinline__ void ct_step(float2* F, const float2* Q, int tid) {
+    constexpr int LR = (R == 2) ? 1 : 2;
+    constexpr int PER = M / R;
+    constexpr int JPT = kCT / 2 / R / kCThreads;
+    static_assert(JPT >= 1, "jobs per thread");
+    constexpr int NS = 1 << LNS;
+    float2 v[JPT][R];
+#pragma unroll
+    for (int c = 0; c < JPT; ++c) {
+        const int J = tid + c * kCThreads;
+        const int w = J / PER, j = J % PER;
+#pragma unroll
+        for (int s = 0; s < R; ++s) v[c][s] = F[cfpad(w * M + j + s * PER)];
+        if constexpr (LNS > 0) {
+            const int jm = j & (NS - 1);
+#pragma unroll
+            for (int s = 1; s < R; ++s) v[c][s] = cmul(v[c][s], TwQ2048{Q}(LNS + LR, jm * s));
+        }
+        dft_reg<R, false>(v[c]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < JPT; ++c) {
+        const int J = tid + c * kCThreads;
+        const int w = J / PER, j = J % PER;
+        const int base = w * M + ((j >> LNS) << (LNS + LR)) + (j & (NS - 1));
+#pragma unroll
+        for (int s = 0; s < R; ++s) F[cfpad(base + s * NS)] = v[c][s];
+    }
+    __syncthreads();
+}
+
+template <int M, int LNS, int LM>
+struct CtSteps {
+    static __device__ __forceinline__ void run(float2* F, const float2* Q, int tid) {
+        if constexpr (LNS < LM) {
+            ct_step<4, M, LNS>(F, Q, tid);
+            CtSteps<M, LNS + 2, LM>::run(F, Q, tid);
+        }
+    }
+};
+
+// LDS level I (4 <= I <= 11) of the tile; y points at this level's output.
+template <int I>
+__device__ __forceinline__ void ct_level(CTileLds& S, float2* __restrict__ y, int tid) {
+    constexpr int L = 1 << I, M = L / 2, LM = I - 1;
+    constexpr int NW = kCT / L;
+    constexpr int PPT = NW * M / kCThreads;              // (w, k) jobs per thread
+    constexpr int R1 = (LM & 1) ? 2 : 4;                 // first FFT step radix
+    constexpr int LR1 = (R1 == 2) ? 1 : 2;
+    float2* F = S.P;
+    // ---- U^(i): even bins from the two child windows (length M each) ----
+    float2 u[PPT];
+#pragma unroll
+    for (int c = 0; c < PPT; ++c) {
+        const int J = tid + c * kCThreads;
+        const int w = J / M, k = J % M;
+        u[c] = cadd(S.P[2 * w * M + k], S.P[(2 * w + 1) * M + k]);
+    }
+    __syncthreads();
+    // ---- first FFT step fused with the twiddled difference d[q] w_L^q ----
+    {
+        constexpr int PER = M / R1;
+        constexpr int JPT = NW * PER / kCThreads;
+        float2 v[JPT][R1];
+#pragma unroll
+        for (int c = 0; c < JPT; ++c) {
+            const int J = tid + c * kCThreads;
+            const int w = J / PER, j = J % PER;
+            const float2* xw = S.X + w * L;
+#pragma unroll
+            for (int s = 0; s < R1; ++s) {
+                const int q = j + s * PER;
+                v[c][s] = cmul(csub(xw[q], xw[q + M]), TwQ2048{S.Q}(I, q));
+            }
+            dft_reg<R1, false>(v[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < JPT; ++c) {
+            const int J = tid + c * kCThreads;
+            const int w = J / PER, j = J % PER;
+#pragma unroll
+            for (int s = 0; s < R1; ++s) F[cfpad(w * M + j * R1 + s)] = v[c][s];
+        }
+        __syncthreads();
+    }
+    CtSteps<M, LR1, LM>::run(F, S.Q, tid);
+    // ---- odd bins, new spectra, output (u, D) pairs ----
+    float2 d[PPT];
+#pragma unroll
+    for (int c = 0; c < PPT; ++c) {
+        const int J = tid + c * kCThreads;
+        const int w = J / M, k = J % M;
+        d[c] = F[cfpad(w * M + k)];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < PPT; ++c) {
+        const int J = tid + c * kCThreads;          // = w * M + k: the pair (2k, 2k+1) of window w
+        const float4 pr = make_float4(u[c].x, u[c].y, d[c].x, d[c].y);
+        *(float4*)(S.P + 2 * J) = pr;
+        *(float4*)(y + 2 * J) = pr;
+    }
+    __syncthreads();
+}
+
+template <int I>
+struct CtLevels {
+    static __device__ __forceinline__ void run(CTileLds& S, float2* __restrict__ y, int64_t ls, int tid) {
+        if constexpr (I <= kCTLog) {
+            ct_level<I>(S, y + (int64_t)(I - 1) * ls, tid);
+            CtLevels<I + 1>::run(S, y, ls, tid);
+        }
+    }
+};
+
+// Writes one register level (8 values per thread, one window each) through
+// the wave's 4 KB of staging (pair e of lane l at 4l + (e ^ (l & 3))).
+__device__ __forceinline__ void ct_stage(const float2* pv, float4* st, float2* __restrict__ yl, int lane) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+        st[4 * lane + (e ^ (lane & 3))] = make_float4(pv[2 * e].x, pv[2 * e].y, pv[2 * e + 1].x, pv[2 * e + 1].y);
+    ct_wave_sync();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int p = 64 * r + lane, wl = p >> 2, e = p & 3;
+        *(float4*)(yl + 2 * p) = st[4 * wl + (e ^ (wl & 3))];
+    }
+    ct_wave_sync();
+}
+
+// Register levels I..3 of an 8-sample window (full spectra, natural order).
+template <int I>
+struct CtLocal {
+    static __device__ __forceinline__ void run(const float2* xv, float2* pv, float4* st, float2* y, int64_t ls,
+                                               int lane) {
+        if constexpr (I <= 3) {
+            constexpr int C = 8, L = 1 << I, M = L / 2;
+            float2 nv[C];
+#pragma unroll
+            for (int w = 0; w < C / L; ++w) {
+                float2 d[M];
+#pragma unroll
+                for (int q = 0; q < M; ++q) d[q] = twiddle_small<false>(csub(xv[w * L + q], xv[w * L + q + M]), q, L);
+                dft_reg<M, false>(d);
+#pragma unroll
+                for (int k = 0; k < M; ++k) {
+                    nv[w * L + 2 * k] = cadd(pv[w * L + k], pv[w * L + M + k]);
+                    nv[w * L + 2 * k + 1] = d[k];
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < C; ++e) pv[e] = nv[e];
+            ct_stage(pv, st, y + (int64_t)(I - 1) * ls, lane);
+            CtLocal<I + 1>::run(xv, pv, st, y, ls, lane);
+        }
+    }
+};
+
+// One tile: x at its first sample, y at its level-1 output (level i at
+// y + (i-1) ls).  Wave v owns samples [512 v, 512 v + 512).
+__device__ __forceinline__ void c64_tile_body(CTileLds& S, const float2* __restrict__ x, float2* __restrict__ y,
+                                              int64_t ls, const float2* __restrict__ t4096, int tid) {
+    constexpr int C = 8;
+    const int v = tid >> 6, lane = tid & 63;
+    for (int e = tid; e < kCT / 4; e += kCThreads) S.Q[e] = t4096[2 * e];    // before any store
+    // coalesced load of the wave's samples into X (their final place)
+    {
+        const float4* xg = (const float4*)(x + 512 * v);
+        float4 a[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) a[r] = xg[64 * r + lane];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) *(float4*)(S.X + 512 * v + 2 * (64 * r + lane)) = a[r];
+    }
+    ct_wave_sync();
+    float2 xv[C], pv[C];
+#pragma unroll
+    for (int e = 0; e < C / 2; ++e) {
+        const float4 a = *(const float4*)(S.X + C * tid + 2 * e);
+        xv[2 * e] = make_float2(a.x, a.y);
+        xv[2 * e + 1] = make_float2(a.z, a.w);
+    }
+#pragma unroll
+    for (int b = 0; b < C / 2; ++b) {
+        pv[2 * b] = cadd(xv[2 * b], xv[2 * b + 1]);
+        pv[2 * b + 1] = csub(xv[2 * b], xv[2 * b + 1]);
+    }
+    float4* st = (float4*)S.P + 256 * v;            // the wave's 4 KB of P
+    float2* yv = y + 512 * v;
+    ct_stage(pv, st, yv, lane);
+    CtLocal<2>::run(xv, pv, st, yv, ls, lane);
+    // level-3 spectra into P (this wave's own region, after its staging reads)
+#pragma unroll
+    for (int e = 0; e < C / 2; ++e)
+        *(float4*)(S.P + C * tid + 2 * e) = make_float4(pv[2 * e].x, pv[2 * e].y, pv[2 * e + 1].x, pv[2 * e + 1].y);
+    __syncthreads();
+    CtLevels<4>::run(S, y, ls, tid);
+}
+
+}  // namespace mrdft

@@ -87,6 +87,10 @@ def test_null_and_unknown_handles():
     assert lib.mrdft_plan_destroy(None) == b.MRDFT_OK
     n = (ctypes.c_int64 * 2)()
     assert lib.mrdft_plan_output_offsets(bogus, n) == b.MRDFT_E_INVALID_ARG
+    t, g, o = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    assert lib.mrdft_plan_schedule(bogus, ctypes.byref(t), ctypes.byref(g), ctypes.byref(o)) == b.MRDFT_E_INVALID_ARG
+    assert lib.mrdft_plan_schedule(None, None, None, None) == b.MRDFT_E_INVALID_ARG
+    assert lib.mrdft_plan_set_schedule(bogus, 11, 1, 0, None) == b.MRDFT_E_INVALID_ARG
 
 
 def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):

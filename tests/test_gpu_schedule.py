@@ -1,0 +1,145 @@
+"""Schedules of the forward launch against the FP64 oracle (GPU).
+
+Covers the persistent complex launch (any grid, including a single workgroup
+that takes every job), each job order, the tile kernel with one launch per
+upper level, the tuner's choice, the queue that the persistent launch leaves
+cleared for the next call, and graph replay against eager calls.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1507_02525_amd import api, workloads
+from tests.gpu_util import FWD_TOL, log, need_gpu, to_dev, worst_level_err
+
+pytestmark = pytest.mark.gpu
+
+ORDERS = ("tiles_first", "rows_first", "interleaved")
+
+
+def _ragged(orders, seed, dtype="c64"):
+    rng = np.random.default_rng(seed)
+    n = [1 << o for o in orders]
+    offs = np.concatenate([[0], np.cumsum(n)]).astype(np.int64)
+    if dtype == "c64":
+        x = workloads.gaussian_complex(rng, (int(offs[-1]),))
+    else:
+        x = workloads.gaussian_real(rng, (int(offs[-1]),))
+    return x, offs
+
+
+def _check_ragged(Y, x, offs, orders, plan):
+    oo = plan.output_offsets()
+    Yh = Y.cpu().numpy()
+    worst = 0.0
+    for j, m in enumerate(orders):
+        N = 1 << m
+        ref = oracle.forward(x[offs[j]:offs[j + 1]].astype(np.complex128))
+        got = Yh[oo[j]:oo[j + 1]].reshape(m, N)
+        worst = max(worst, worst_level_err(got, ref))
+    return worst
+
+
+# orders around every boundary: tile sizes 2^11 / 2^12, upper pieces up to 2^16, passes above
+C_ORDERS = [11, 12, 9, 13, 14, 16, 17, 15, 5, 12]
+
+
+@pytest.mark.parametrize("tile_log,grid,order", [(11, 1, "tiles_first"), (11, 7, "rows_first"),
+                                                 (11, 1024, "interleaved"), (11, 256, "tiles_first"),
+                                                 (12, 0, "tiles_first")])
+def test_complex_schedules_match_oracle(tile_log, grid, order):
+    need_gpu()
+    log("complex schedule tile_log=%d grid=%d order=%s" % (tile_log, grid, order))
+    x, offs = _ragged(C_ORDERS, 41)
+    plan = api.Plan(offsets=offs, dtype="c64")
+    plan.set_schedule(tile_log, grid, order)
+    assert plan.schedule() == {"tile_log": tile_log, "grid": grid if tile_log == 11 else 0, "order": order}
+    Y = torch.empty(plan.n_out, dtype=torch.complex64, device="cuda")
+    plan.mrdft_forward(to_dev(x), Y)
+    err = _check_ragged(Y, x, offs, C_ORDERS, plan)
+    log("  worst rel err %.3e" % err)
+    assert err <= FWD_TOL
+
+
+@pytest.mark.parametrize("order", ORDERS)
+def test_real_orders_match_oracle(order):
+    need_gpu()
+    orders = [12, 16, 13, 8, 14, 15]
+    log("real order %s" % order)
+    x, offs = _ragged(orders, 43, dtype="r32")
+    plan = api.Plan(offsets=offs, dtype="r32")
+    plan.set_schedule(12, 0, order)
+    Y = torch.empty(plan.n_out, dtype=torch.complex64, device="cuda")
+    plan.mrdft_forward(to_dev(x), Y)
+    err = _check_ragged(Y, x, offs, orders, plan)
+    log("  worst rel err %.3e" % err)
+    assert err <= FWD_TOL
+
+
+def test_persistent_queue_is_reusable():
+    """Each call of the persistent launch must find the job queue cleared by
+    the previous one: repeated calls into a zeroed Y give identical results."""
+    need_gpu()
+    x, offs = _ragged([13, 11, 14, 12], 45)
+    plan = api.Plan(offsets=offs, dtype="c64")
+    plan.set_schedule(11, 3, "tiles_first")
+    xd = to_dev(x)
+    Y = torch.empty(plan.n_out, dtype=torch.complex64, device="cuda")
+    first = None
+    for it in range(5):
+        Y.zero_()
+        plan.mrdft_forward(xd, Y)
+        cur = Y.cpu()
+        if first is None:
+            first = cur
+            assert _check_ragged(Y, x, offs, [13, 11, 14, 12], plan) <= FWD_TOL
+        else:
+            assert torch.equal(cur, first), "call %d differs" % it
+
+
+@pytest.mark.parametrize("dtype", ["c64", "r32"])
+def test_graph_replay_matches_eager(dtype):
+    need_gpu()
+    orders = [14, 12, 16, 10] if dtype == "c64" else [12, 16, 14]
+    log("graph replay %s" % dtype)
+    xs = [_ragged(orders, 50 + k, dtype=dtype)[0] for k in range(3)]
+    offs = _ragged(orders, 50, dtype=dtype)[1]
+    eager = api.Plan(offsets=offs, dtype=dtype)
+    graphed = api.Plan(offsets=offs, dtype=dtype, graph=True)
+    xd = to_dev(xs[0])
+    Yg = torch.empty(eager.n_out, dtype=torch.complex64, device="cuda")
+    Ye = torch.empty_like(Yg)
+    for k in range(3):
+        xd.copy_(to_dev(xs[k]))              # same pointers, new contents
+        Yg.zero_()
+        graphed.mrdft_forward(xd, Yg)        # first call captures, later calls replay
+        junk = torch.randn(1 << 20, device="cuda") * 2.0     # eager work between replays
+        eager.mrdft_forward(xd, Ye)
+        torch.cuda.synchronize()
+        assert torch.equal(Yg, Ye), "replay %d differs from the eager call" % k
+        del junk
+    assert _check_ragged(Yg, xs[2], offs, orders, graphed) <= FWD_TOL
+
+
+def test_tuned_plan_matches_oracle():
+    need_gpu()
+    d = workloads.make(4, count=60, m_hi=17)
+    x, offs = d["x"], d["offsets"]
+    orders = [int(np.log2(offs[j + 1] - offs[j])) for j in range(len(offs) - 1)]
+    plan = api.Plan(offsets=offs, dtype="c64", tune=True)
+    sch = plan.schedule()
+    log("tuned schedule %s" % sch)
+    assert sch["tile_log"] in (11, 12) and sch["order"] in ORDERS
+    Y = torch.empty(plan.n_out, dtype=torch.complex64, device="cuda")
+    plan.mrdft_forward(to_dev(x), Y)
+    # sampled: the 6 largest and 6 random signals
+    oo = plan.output_offsets()
+    Yh = Y.cpu().numpy()
+    rng = np.random.default_rng(7)
+    pick = list(np.argsort(orders)[-6:]) + list(rng.choice(len(orders), 6, replace=False))
+    for j in pick:
+        m = orders[j]
+        ref = oracle.forward(x[offs[j]:offs[j + 1]].astype(np.complex128))
+        err = worst_level_err(Yh[oo[j]:oo[j + 1]].reshape(m, 1 << m), ref)
+        assert err <= FWD_TOL, (j, m, err)
