@@ -30,12 +30,14 @@ struct CTileLds {
 static_assert(sizeof(CTileLds) <= 40 * 1024 - 256, "four workgroups per CU");
 
 // w_{2^lg}^e (lg <= 11) from the quarter table q[r] = w_2048^r, r < 512:
-// w^{r + 512 c} = (-j)^c w^r.
+// w^{r + 512 c} = (-j)^c w^r.  Entry r sits at r ^ ((r >> 5) & 15): the
+// twiddles of one Stockham step (a power-of-two stride) spread over the banks.
+__device__ __forceinline__ int cqswz(int r) { return r ^ ((r >> 5) & 15); }
 struct TwQ2048 {
     const float2* q;
     __device__ __forceinline__ float2 operator()(int lg, int e) const {
         const int E = (e << (kCTLog - lg)) & (kCT - 1);
-        const float2 a = q[E & (kCT / 4 - 1)];
+        const float2 a = q[cqswz(E & (kCT / 4 - 1))];
         const int c = E >> (kCTLog - 2);
         float re = (c & 1) ? a.y : a.x;
         float im = (c & 1) ? -a.x : a.y;
@@ -226,7 +228,7 @@ __device__ __forceinline__ void c64_tile_body(CTileLds& S, const float2* __restr
                                               int64_t ls, const float2* __restrict__ t4096, int tid) {
     constexpr int C = 8;
     const int v = tid >> 6, lane = tid & 63;
-    for (int e = tid; e < kCT / 4; e += kCThreads) S.Q[e] = t4096[2 * e];    // before any store
+    for (int e = tid; e < kCT / 4; e += kCThreads) S.Q[cqswz(e)] = t4096[2 * e];   // before any store
     // coalesced load of the wave's samples into X (their final place)
     {
         const float4* xg = (const float4*)(x + 512 * v);

@@ -47,23 +47,43 @@ static_assert(sizeof(float) * kRT + sizeof(float2) * kRT / 2 == (kRThreads / 64)
 
 __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
 
-// w_{2^LG}^e (LG <= 12, 0 <= e < 2^LG) from the LDS quarter table.
+// The quarter table w_4096^e (e < 1024) sits at a swizzled index: the low 5
+// bits are XORed with bits 5..9, so that entries at a power-of-two stride of
+// 32 or more (the twiddles of one Stockham step) fall on different banks.
+__device__ __forceinline__ int qswz(int E) { return E ^ ((E >> 5) & 31); }
+
+// w_{2^LG}^e (LG <= 12, 0 <= e < 2^LG) from the LDS quarter table:
+// w^{r + 1024 c} = (-j)^c w^r.
 template <int LG>
 __device__ __forceinline__ float2 wl(const float2* Q, int e) {
-    return TwQuarter{Q}(LG, e);
+    const int E = (e << (kRTLog - LG)) & (kRT - 1);
+    const float2 a = Q[qswz(E & (kRT / 4 - 1))];
+    const int c = E >> (kRTLog - 2);
+    float re = (c & 1) ? a.y : a.x;
+    float im = (c & 1) ? -a.x : a.y;
+    if (c & 2) {
+        re = -re;
+        im = -im;
+    }
+    return make_float2(re, im);
 }
 // Same for exponents known to lie in the first quadrant (e < 2^LG / 4).
 template <int LG>
 __device__ __forceinline__ float2 wq1(const float2* Q, int e) {
-    return Q[e << (kRTLog - LG)];
+    return Q[qswz(e << (kRTLog - LG))];
 }
 // First two quadrants (e < 2^LG / 2): w^{e} = -j w^{e - 2^LG/4} beyond the first.
 template <int LG>
 __device__ __forceinline__ float2 wq2(const float2* Q, int e) {
     const int E = e << (kRTLog - LG);
-    const float2 a = Q[E & (kRT / 4 - 1)];
+    const float2 a = Q[qswz(E & (kRT / 4 - 1))];
     return (E >= kRT / 4) ? make_float2(a.y, -a.x) : a;
 }
+
+// FFT work space index: one spare element after every 32, so that the
+// strided Stockham accesses spread over the banks (1024 points use 1056
+// slots of P).
+__device__ __forceinline__ int fpad(int i) { return i + (i >> 5); }
 
 // One in-place radix-R Stockham step over NW FFTs of H points in F (contiguous
 // per window), span 2^LNS before the step.  256 threads, R in {2, 4}.
@@ -80,9 +100,8 @@ __device__ __forceinline__ void rstep(float2* F, const float2* W, int tid) {
     for (int c = 0; c < JPT; ++c) {
         const int J = tid + c * kRThreads;
         const int w = J / PER, j = J % PER;
-        const float2* src = F + w * H + j;
 #pragma unroll
-        for (int s = 0; s < R; ++s) v[c][s] = src[s * PER];
+        for (int s = 0; s < R; ++s) v[c][s] = F[fpad(w * H + j + s * PER)];
         if constexpr (LNS > 0) {
             const int jm = j & (NS - 1);
 #pragma unroll
@@ -95,10 +114,9 @@ __device__ __forceinline__ void rstep(float2* F, const float2* W, int tid) {
     for (int c = 0; c < JPT; ++c) {
         const int J = tid + c * kRThreads;
         const int w = J / PER, j = J % PER;
-        const int base = ((j >> LNS) << (LNS + LR)) + (j & (NS - 1));
-        float2* dst = F + w * H + base;
+        const int base = w * H + ((j >> LNS) << (LNS + LR)) + (j & (NS - 1));
 #pragma unroll
-        for (int s = 0; s < R; ++s) dst[s * NS] = v[c][s];
+        for (int s = 0; s < R; ++s) F[fpad(base + s * NS)] = v[c][s];
     }
     __syncthreads();
 }
@@ -167,9 +185,8 @@ __device__ __forceinline__ void real_level(RealTileLds& S, float2* __restrict__ 
         for (int c = 0; c < JPT; ++c) {
             const int J = tid + c * kRThreads;
             const int w = J / PER, j = J % PER;
-            float2* dst = F + w * H + j * R1;
 #pragma unroll
-            for (int s = 0; s < R1; ++s) dst[s] = v[c][s];
+            for (int s = 0; s < R1; ++s) F[fpad(w * H + j * R1 + s)] = v[c][s];
         }
         __syncthreads();
     }
@@ -181,7 +198,7 @@ __device__ __forceinline__ void real_level(RealTileLds& S, float2* __restrict__ 
         const int J = tid + c * kRThreads;
         const int w = J / (H / 2), k = J % (H / 2);
         const int j = H - 1 - k;
-        const float2 zk = F[w * H + k], zj = F[w * H + j];
+        const float2 zk = F[fpad(w * H + k)], zj = F[fpad(w * H + j)];
         const float2 zjc = cconj(zj);
         const float2 A = cscale(cadd(zk, zjc), 0.5f);
         const float2 B = mul_mj(cscale(csub(zk, zjc), 0.5f));
@@ -332,7 +349,7 @@ __device__ __forceinline__ void real_local(const float* __restrict__ xin, float2
 // (level i at y + (i-1)*ls).
 __device__ __forceinline__ void real_tile_body(RealTileLds& S, const float* __restrict__ x, float2* __restrict__ y,
                                                int64_t ls, const float2* __restrict__ t4096, int tid) {
-    for (int e = tid; e < kRT / 4; e += kRThreads) S.Q[e] = t4096[e];       // before any store
+    for (int e = tid; e < kRT / 4; e += kRThreads) S.Q[qswz(e)] = t4096[e];   // before any store
     real_local(x, y, ls, S, tid);
     __syncthreads();
     RealLevels<5>::run(S, y, ls, tid);
