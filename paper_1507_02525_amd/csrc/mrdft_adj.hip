@@ -1,0 +1,117 @@
+// Adjoint MrDFT (gx = sum_i A_i^H gY^(i)) in two launches.
+//   (a) one workgroup per job: 2048-sample tiles (levels 11..1 by the
+//       transposed recurrence, mrdft_adj_tile.h; gx of the tile is written)
+//       and rows pieces of the levels 12..16 (scratch B, mrdft_adj_rows.h);
+//   (b) one workgroup per (region, 16 columns): the column DFTs of the levels
+//       12..16, summed and added to gx.
+// Real plans accumulate Re(gx) only.
+#include "mrdft_adj_rows.h"
+#include "mrdft_adj_tile.h"
+#include "mrdft_internal.h"
+
+namespace mrdft {
+
+namespace {
+
+template <bool REAL>
+union AdjALds {
+    AdjTileLds<REAL> tile;
+    CRowsLds rows;
+};
+
+template <bool REAL>
+__global__ __launch_bounds__(kCThreads, 4) void adj_a_kernel(const float2* __restrict__ gY, void* __restrict__ gx,
+                                                             float2* __restrict__ scratch,
+                                                             const RealJob* __restrict__ jobs,
+                                                             const float2* __restrict__ t4096,
+                                                             const float2* __restrict__ rowtw) {
+    __shared__ AdjALds<REAL> S;
+    const RealJob jb = jobs[blockIdx.x];
+    const int tid = threadIdx.x;
+    const float2* gyj = gY + jb.in_off;
+    switch (jb.lg) {
+        case 0: {
+            void* gxj = REAL ? (void*)((float*)gx + jb.out_off) : (void*)((float2*)gx + jb.out_off);
+            adj_tile_body<REAL>(S.tile, gyj, gxj, jb.level_stride, t4096, tid);
+            break;
+        }
+        case 12: adj_rows_body<4>(S.rows, gyj, scratch + jb.out_off, jb.g, t4096, rowtw + rows_twiddle_offset(12), tid); break;
+        case 13: adj_rows_body<5>(S.rows, gyj, scratch + jb.out_off, jb.g, t4096, rowtw + rows_twiddle_offset(13), tid); break;
+        case 14: adj_rows_body<6>(S.rows, gyj, scratch + jb.out_off, jb.g, t4096, rowtw + rows_twiddle_offset(14), tid); break;
+        case 15: adj_rows_body<7>(S.rows, gyj, scratch + jb.out_off, jb.g, t4096, rowtw + rows_twiddle_offset(15), tid); break;
+        case 16: adj_rows_body<8>(S.rows, gyj, scratch + jb.out_off, jb.g, t4096, rowtw + rows_twiddle_offset(16), tid); break;
+        default: break;
+    }
+}
+
+template <bool REAL>
+__global__ __launch_bounds__(kRowsThreads, 4) void adj_b_kernel(void* __restrict__ gx, const float2* __restrict__ scratch,
+                                                               const AdjColJob* __restrict__ jobs,
+                                                               const float2* __restrict__ t4096) {
+    __shared__ AdjColsLds S;
+    const AdjColJob jb = jobs[blockIdx.x];
+    const int tid = threadIdx.x;
+    S.T[tid] = t4096[tid << (kTileMaxLog - kRowsLog)];
+    typedef typename std::conditional<REAL, float, float2>::type Acc;
+    Acc acc[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        if constexpr (REAL) acc[s] = 0.0f;
+        else acc[s] = make_float2(0.0f, 0.0f);
+    }
+    const int c0 = 16 * jb.c;
+    const int top = jb.region_log < kRowsMaxLevel ? jb.region_log : kRowsMaxLevel;
+    for (int lg = kCRowsMinLevel; lg <= top; ++lg) {
+        const float2* scr = scratch + jb.scr_off + (int64_t)(lg - kCRowsMinLevel) * jb.level_stride;
+        // a fresh copy of the thread index per level: nothing derived from it is
+        // hoisted out of this loop (five inlined bodies would spill)
+        int t;
+        asm volatile("v_mov_b32 %0, %1" : "=v"(t) : "v"(tid));
+        switch (lg) {
+            case 12: adj_cols_level<4, REAL>(S, scr, jb.region_log, c0, acc, t); break;
+            case 13: adj_cols_level<5, REAL>(S, scr, jb.region_log, c0, acc, t); break;
+            case 14: adj_cols_level<6, REAL>(S, scr, jb.region_log, c0, acc, t); break;
+            case 15: adj_cols_level<7, REAL>(S, scr, jb.region_log, c0, acc, t); break;
+            default: adj_cols_level<8, REAL>(S, scr, jb.region_log, c0, acc, t); break;
+        }
+    }
+    // gx[region + c0 + col + 256 rho] += acc
+    const int col = tid & 15;
+    const int rows = 1 << (jb.region_log - kRowsLog);
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        const int rho = (tid >> 4) + 16 * s;
+        if (rho < rows) {
+            const int64_t i = jb.gx_off + c0 + col + (int64_t)kRowsN * rho;
+            if constexpr (REAL) ((float*)gx)[i] += acc[s];
+            else ((float2*)gx)[i] = cadd(((float2*)gx)[i], acc[s]);
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_adj_a(bool real_out, const float2* gY, void* gx, float2* scratch, const RealJob* jobs, int64_t njobs,
+                        const Twiddles& tw, hipStream_t s) {
+    if (njobs <= 0) return hipSuccess;
+    if (real_out)
+        hipLaunchKernelGGL(adj_a_kernel<true>, dim3((unsigned)njobs), dim3(kCThreads), 0, s, gY, gx, scratch, jobs,
+                           tw.tile, tw.rows);
+    else
+        hipLaunchKernelGGL(adj_a_kernel<false>, dim3((unsigned)njobs), dim3(kCThreads), 0, s, gY, gx, scratch, jobs,
+                           tw.tile, tw.rows);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_b(bool real_out, void* gx, const float2* scratch, const AdjColJob* jobs, int64_t njobs,
+                        const Twiddles& tw, hipStream_t s) {
+    if (njobs <= 0) return hipSuccess;
+    if (real_out)
+        hipLaunchKernelGGL(adj_b_kernel<true>, dim3((unsigned)njobs), dim3(kRowsThreads), 0, s, gx, scratch, jobs, tw.tile);
+    else
+        hipLaunchKernelGGL(adj_b_kernel<false>, dim3((unsigned)njobs), dim3(kRowsThreads), 0, s, gx, scratch, jobs,
+                           tw.tile);
+    return hipGetLastError();
+}
+
+}  // namespace mrdft

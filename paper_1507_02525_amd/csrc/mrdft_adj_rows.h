@@ -1,0 +1,171 @@
+// Adjoint of the levels above the tile (12..16), in two phases.
+//
+// For a window of L = R * 256 points, the level's adjoint (conjugate
+// transpose of the window DFT of eq. (1)) factors as
+//
+//     g[n1 + 256 n2] = sum_{k2} w_R^{-n2 k2} B[k2][n1],
+//     B[k2][n1]      = w_L^{-n1 k2} sum_{k1} gY[k2 + R k1] w_256^{-n1 k1}.
+//
+// * Rows phase: piece g takes the rows k2 = 16g .. 16g+15 (16 consecutive
+//   gradient values, 128 bytes, per k1), runs their conjugate 256-point DFTs
+//   in LDS and writes B rows to a scratch block laid out like the level.
+// * Columns phase: for 16 consecutive columns n1 of a region of up to 2^16
+//   samples, the conjugate R-point DFTs over k2 of every level 12..16 that
+//   covers the region run in LDS, their sum stays in registers, and gx is
+//   updated once (the tiles wrote the levels below before).
+#pragma once
+#include <type_traits>
+
+#include "mrdft_device.h"
+#include "mrdft_rows_c64.h"
+
+namespace mrdft {
+
+constexpr int kAdjRegionLog = 16;                    // columns phase region: up to 2^16 samples
+constexpr int kAdjColsPoints = 4096;                 // 16 columns x 2^16 / 256 rows
+
+// One radix-16 conjugate Stockham step over the 16 rows of a rows piece.
+template <int LNS>
+__device__ __forceinline__ void adj_rows_step(CRowsLds& S, int tid) {
+    constexpr int NS = 1 << LNS;
+    const int r = tid >> 4, j = tid & 15;
+    float2 v[16];
+    const float2* src = S.C + r * kRowsStride;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) v[s] = src[rpad(j + 16 * s)];
+    if constexpr (LNS > 0) {
+        const int jm = j & (NS - 1);
+#pragma unroll
+        for (int s = 1; s < 16; ++s) v[s] = cmulc(v[s], S.T[(jm * s) << (kRowsLog - LNS - 4)]);
+    }
+    dft_reg<16, true>(v);
+    __syncthreads();
+    float2* dst = S.C + r * kRowsStride;
+    const int base = ((j >> LNS) << (LNS + 4)) + (j & (NS - 1));
+#pragma unroll
+    for (int s = 0; s < 16; ++s) dst[rpad(base + s * NS)] = v[s];
+    __syncthreads();
+}
+
+// Rows piece g of one window of level lg = RL + 8.
+//   gyw   : the window's gradient at its level       scw: the window's scratch block (L values)
+//   rowtw : this level's row twiddles rowtw[k2 * 256 + n1] = w_L^{n1 k2}
+template <int RL>
+__device__ __forceinline__ void adj_rows_body(CRowsLds& S, const float2* __restrict__ gyw, float2* __restrict__ scw,
+                                              int g, const float2* __restrict__ t4096,
+                                              const float2* __restrict__ rowtw, int tid) {
+    constexpr int R = 1 << RL;
+    const int k0 = 16 * g;
+    S.T[tid] = t4096[tid << (kTileMaxLog - kRowsLog)];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int e = tid + u * kRowsThreads;
+        const int k1 = e >> 3, kp = (e & 7) * 2;
+        const float4 v = *(const float4*)(gyw + k0 + kp + (int64_t)R * k1);
+        S.C[kp * kRowsStride + rpad(k1)] = make_float2(v.x, v.y);
+        S.C[(kp + 1) * kRowsStride + rpad(k1)] = make_float2(v.z, v.w);
+    }
+    __syncthreads();
+    adj_rows_step<0>(S, tid);
+    adj_rows_step<4>(S, tid);
+    const int n1 = tid;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int k2 = k0 + q;
+        scw[k2 * kRowsN + n1] = cmulc(S.C[q * kRowsStride + rpad(n1)], rowtw[k2 * kRowsN + n1]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Columns phase.
+
+struct AdjColsLds {
+    float2 V[kAdjColsPoints + kAdjColsPoints / 16];   // FFTs of one level, padded
+    float2 T[kRowsN];                                 // w_256^e
+};
+
+__device__ __forceinline__ int cpad(int i) { return i + (i >> 4); }
+
+// One conjugate Stockham step of radix RR over the 4096 points of V (NF FFTs
+// of R points, FFT f at f * R), span 2^LNS; 4096 / RR jobs over 256 threads.
+template <int RR, int R, int LNS>
+__device__ __forceinline__ void adj_cols_step(AdjColsLds& S, int tid) {
+    constexpr int LR = (RR == 2) ? 1 : (RR == 4) ? 2 : (RR == 8) ? 3 : 4;
+    constexpr int PER = R / RR;
+    constexpr int JPT = kAdjColsPoints / RR / kRowsThreads;
+    constexpr int NS = 1 << LNS;
+    float2 v[JPT][RR];
+#pragma unroll
+    for (int c = 0; c < JPT; ++c) {
+        const int J = tid + c * kRowsThreads;
+        const int f = J / PER, j = J % PER;
+#pragma unroll
+        for (int s = 0; s < RR; ++s) v[c][s] = S.V[cpad(f * R + j + s * PER)];
+        if constexpr (LNS > 0) {
+            const int jm = j & (NS - 1);
+#pragma unroll
+            for (int s = 1; s < RR; ++s) v[c][s] = cmulc(v[c][s], S.T[(jm * s) << (kRowsLog - LNS - LR)]);
+        }
+        dft_reg<RR, true>(v[c]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < JPT; ++c) {
+        const int J = tid + c * kRowsThreads;
+        const int f = J / PER, j = J % PER;
+        const int base = f * R + ((j >> LNS) << (LNS + LR)) + (j & (NS - 1));
+#pragma unroll
+        for (int s = 0; s < RR; ++s) S.V[cpad(base + s * NS)] = v[c][s];
+    }
+    __syncthreads();
+}
+
+// R-point conjugate DFTs (R = 16 .. 256): a first step of radix R/16 (if R > 16),
+// then radix 16.
+template <int R>
+__device__ __forceinline__ void adj_cols_fft(AdjColsLds& S, int tid) {
+    if constexpr (R == 16) {
+        adj_cols_step<16, R, 0>(S, tid);
+    } else {
+        constexpr int R0 = R / 16;
+        constexpr int L0 = (R0 == 2) ? 1 : (R0 == 4) ? 2 : (R0 == 8) ? 3 : 4;
+        adj_cols_step<R0, R, 0>(S, tid);
+        adj_cols_step<16, R, L0>(S, tid);
+    }
+}
+
+// One level lg = RL + 8 of a columns job: region of `region` samples (a
+// multiple of L), columns c0 .. c0+15; acc[s] is the contribution to the
+// thread's gx values at region row rho = (tid >> 4) + 16 s, column tid & 15.
+//   scr : the scratch block of this level at the region's first sample
+template <int RL, bool REAL, class ACC>
+__device__ __forceinline__ void adj_cols_level(AdjColsLds& S, const float2* __restrict__ scr, int region_log, int c0,
+                                               ACC* acc, int tid) {
+    constexpr int R = 1 << RL, L = R * kRowsN;
+    const int nwin = 1 << (region_log - RL - kRowsLog);          // windows of this level in the region
+    const int rows = nwin * R;                                    // = region / 256
+    // load B[w][k2][c0 + col] (128-byte chunks) into FFT f = w * 16 + col, point k2
+    for (int e = tid; e < rows * 16; e += kRowsThreads) {
+        const int col = e & 15, rr = e >> 4;                      // rr = w * R + k2
+        const int w = rr / R, k2 = rr % R;
+        S.V[cpad((w * 16 + col) * R + k2)] = scr[(int64_t)w * L + k2 * kRowsN + c0 + col];
+    }
+    __syncthreads();
+    // all 4096 points go through the steps; with a region below 2^16 the FFTs
+    // past rows * 16 points hold stale values and are never read
+    adj_cols_fft<R>(S, tid);
+    const int col = tid & 15;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        const int rho = (tid >> 4) + 16 * s;
+        if (rho < rows) {
+            const int w = rho / R, n2 = rho % R;
+            const float2 v = S.V[cpad((w * 16 + col) * R + n2)];
+            if constexpr (REAL) acc[s] += v.x;
+            else acc[s] = cadd(acc[s], v);
+        }
+    }
+    __syncthreads();
+}
+
+}  // namespace mrdft

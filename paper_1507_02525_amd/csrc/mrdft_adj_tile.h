@@ -1,0 +1,185 @@
+// Adjoint tile: levels 11..1 of a 2048-sample tile, real or complex gx.
+//
+// The adjoint of eq. (1) is gx = sum_i A_i^H gY^(i).  It is computed with
+// the transpose of the recurrence of Section 3 (eq. (4)), top level down:
+// with G_i the gradient reaching level i (G_11 = gY^(11)),
+// * odd bins (transpose of V^(i), D^(i), F^(i), eq. (3)): the conjugate
+//   L/2-point DFT of G_i[w][2k+1] gives d[q]; d[q] w_L^{-q} is added to
+//   gx[wL + q] and subtracted from gx[wL + q + L/2];
+// * even bins (transpose of U^(i), eq. (2)): G_i[w][2k] is added to bin k of
+//   both child windows, G_{i-1} = gY^(i-1) + U^T G_i;
+// * level 1: gx[2w] += g0 + g1, gx[2w+1] += g0 - g1.
+// The conjugate DFTs run as Stockham steps on the natural-order bins.  Only
+// Re(gx) is accumulated for a real signal (the real part is linear).  256
+// threads; 28 KB of LDS (real gx) or 36 KB (complex gx).
+#pragma once
+#include "mrdft_device.h"
+#include "mrdft_tile_c64.h"
+
+namespace mrdft {
+
+template <bool REAL>
+struct AdjTileLds {
+    float2 P[kCT];                                   // G_i; the FFT work space overlays it
+    typename std::conditional<REAL, float, float2>::type A[kCT];   // gx accumulator
+    float2 Q[kCT / 4];                               // w_2048^e, e < 512 (swizzled)
+};
+
+// conj(w_{2^lg}^e)
+__device__ __forceinline__ float2 adj_tw(const float2* Q, int lg, int e) { return cconj(TwQ2048{Q}(lg, e)); }
+
+// One radix-R conjugate Stockham step over the 1024 points of F.
+template <int R, int M, int LNS>
+__device__ __forceinline__ void adj_step(float2* F, const float2* Q, int tid) {
+    constexpr int LR = (R == 2) ? 1 : 2;
+    constexpr int PER = M / R;
+    constexpr int JPT = kCT / 2 / R / kCThreads;
+    constexpr int NS = 1 << LNS;
+    float2 v[JPT][R];
+#pragma unroll
+    for (int c = 0; c < JPT; ++c) {
+        const int J = tid + c * kCThreads;
+        const int w = J / PER, j = J % PER;
+#pragma unroll
+        for (int s = 0; s < R; ++s) v[c][s] = F[cfpad(w * M + j + s * PER)];
+        if constexpr (LNS > 0) {
+            const int jm = j & (NS - 1);
+#pragma unroll
+            for (int s = 1; s < R; ++s) v[c][s] = cmul(v[c][s], adj_tw(Q, LNS + LR, jm * s));
+        }
+        dft_reg<R, true>(v[c]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < JPT; ++c) {
+        const int J = tid + c * kCThreads;
+        const int w = J / PER, j = J % PER;
+        const int base = w * M + ((j >> LNS) << (LNS + LR)) + (j & (NS - 1));
+#pragma unroll
+        for (int s = 0; s < R; ++s) F[cfpad(base + s * NS)] = v[c][s];
+    }
+    __syncthreads();
+}
+
+template <int M, int LNS, int LM>
+struct AdjSteps {
+    static __device__ __forceinline__ void run(float2* F, const float2* Q, int tid) {
+        if constexpr (LNS < LM) {
+            adj_step<((LM - LNS) & 1) ? 2 : 4, M, LNS>(F, Q, tid);
+            AdjSteps<M, LNS + (((LM - LNS) & 1) ? 1 : 2), LM>::run(F, Q, tid);
+        }
+    }
+};
+
+template <bool REAL>
+__device__ __forceinline__ void adj_acc(AdjTileLds<REAL>& S, int i, float2 v, bool add) {
+    if constexpr (REAL) {
+        if (add) S.A[i] += v.x;
+        else S.A[i] = v.x;
+    } else {
+        S.A[i] = add ? cadd(S.A[i], v) : v;
+    }
+}
+
+// Level I (2 <= I <= 11): P holds G_I on entry and G_{I-1} on exit.
+//   gyl : gY of level I-1 at this tile (level-major, complex64)
+template <int I, bool REAL>
+__device__ __forceinline__ void adj_level(AdjTileLds<REAL>& S, const float2* __restrict__ gyl, int tid) {
+    constexpr int L = 1 << I, M = L / 2, LM = I - 1;
+    constexpr int PPT = kCT / 2 / kCThreads;            // (w, k) jobs per thread
+    constexpr bool FIRST = (I == kCTLog);               // A not yet written
+    float2* F = S.P;
+    float2 e[PPT], nxt0[PPT], nxt1[PPT];
+#pragma unroll
+    for (int c = 0; c < PPT; ++c) {
+        const int J = tid + c * kCThreads;               // = w * M + k
+        const int w = J / M, k = J % M;
+        // level I-1 gradient inputs of the two children (loaded early)
+        nxt0[c] = gyl[2 * w * M + k];
+        nxt1[c] = gyl[(2 * w + 1) * M + k];
+        e[c] = S.P[2 * J];
+    }
+    float2 d[PPT];
+#pragma unroll
+    for (int c = 0; c < PPT; ++c) d[c] = S.P[2 * (tid + c * kCThreads) + 1];
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < PPT; ++c) F[cfpad(tid + c * kCThreads)] = d[c];
+    __syncthreads();
+    AdjSteps<M, 0, LM>::run(F, S.Q, tid);
+    // untwiddle and scatter: +d w_L^{-q} at wL + q, - at wL + q + M
+#pragma unroll
+    for (int c = 0; c < PPT; ++c) {
+        const int J = tid + c * kCThreads;
+        const int w = J / M, q = J % M;
+        const float2 t = cmul(F[cfpad(J)], adj_tw(S.Q, I, q));
+        adj_acc<REAL>(S, w * L + q, t, !FIRST);
+        adj_acc<REAL>(S, w * L + q + M, make_float2(-t.x, -t.y), !FIRST);
+    }
+    __syncthreads();
+    // G_{I-1} = gY^(I-1) + even bins of G_I on both children
+#pragma unroll
+    for (int c = 0; c < PPT; ++c) {
+        const int J = tid + c * kCThreads;
+        const int w = J / M, k = J % M;
+        S.P[2 * w * M + k] = cadd(nxt0[c], e[c]);
+        S.P[(2 * w + 1) * M + k] = cadd(nxt1[c], e[c]);
+    }
+    __syncthreads();
+}
+
+template <int I, bool REAL>
+struct AdjLevels {
+    static __device__ __forceinline__ void run(AdjTileLds<REAL>& S, const float2* __restrict__ gy, int64_t ls,
+                                               int tid) {
+        if constexpr (I >= 2) {
+            adj_level<I, REAL>(S, gy + (int64_t)(I - 2) * ls, tid);
+            AdjLevels<I - 1, REAL>::run(S, gy, ls, tid);
+        }
+    }
+};
+
+// One tile: gy at the tile's level-1 gradient (level i at gy + (i-1) ls),
+// gx at the tile's first sample (float for REAL, float2 otherwise); gx is
+// overwritten.
+template <bool REAL>
+__device__ __forceinline__ void adj_tile_body(AdjTileLds<REAL>& S, const float2* __restrict__ gy, void* __restrict__ gx,
+                                              int64_t ls, const float2* __restrict__ t4096, int tid) {
+    for (int e = tid; e < kCT / 4; e += kCThreads) S.Q[cqswz(e)] = t4096[2 * e];
+    {
+        const float4* g11 = (const float4*)(gy + (int64_t)(kCTLog - 1) * ls);
+#pragma unroll
+        for (int r = 0; r < kCT / 2 / kCThreads; ++r) {
+            const int p = tid + r * kCThreads;
+            *(float4*)(S.P + 2 * p) = g11[p];
+        }
+    }
+    __syncthreads();
+    AdjLevels<kCTLog, REAL>::run(S, gy, ls, tid);
+    // level 1: windows of two
+#pragma unroll
+    for (int r = 0; r < kCT / 2 / kCThreads; ++r) {
+        const int w = tid + r * kCThreads;
+        const float2 g0 = S.P[2 * w], g1 = S.P[2 * w + 1];
+        adj_acc<REAL>(S, 2 * w, cadd(g0, g1), true);
+        adj_acc<REAL>(S, 2 * w + 1, csub(g0, g1), true);
+    }
+    __syncthreads();
+    if constexpr (REAL) {
+        float2* o = (float2*)gx;                      // real signals start at even samples (8-byte aligned)
+#pragma unroll
+        for (int r = 0; r < kCT / 2 / kCThreads; ++r) {
+            const int p = tid + r * kCThreads;
+            o[p] = make_float2(S.A[2 * p], S.A[2 * p + 1]);
+        }
+    } else {
+        float4* o = (float4*)gx;
+#pragma unroll
+        for (int r = 0; r < kCT / 2 / kCThreads; ++r) {
+            const int p = tid + r * kCThreads;
+            o[p] = make_float4(S.A[2 * p].x, S.A[2 * p].y, S.A[2 * p + 1].x, S.A[2 * p + 1].y);
+        }
+    }
+}
+
+}  // namespace mrdft

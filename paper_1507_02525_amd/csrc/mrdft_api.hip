@@ -103,6 +103,14 @@ struct mrdft_plan {
     TileJob* d_small = nullptr;             // tiles of complex signals of order < 11
     int64_t nsmall = 0;
     unsigned* d_queue = nullptr;            // persistent launch: next job, workgroups done
+    // adjoint: launch (a) tiles + rows pieces, launch (b) columns jobs, scratch B
+    RealJob* d_ajobs = nullptr;
+    int64_t najobs = 0;
+    AdjColJob* d_acols = nullptr;
+    int64_t nacols = 0;
+    TileJob* d_asmall = nullptr;            // signals of order < 11: tile adjoint kernel
+    int64_t nasmall = 0;
+    float2* d_ascratch = nullptr;
     // schedule (tuned or default)
     unsigned flags = 0;
     int tile_log = kTileMaxLog;
@@ -174,6 +182,10 @@ void free_plan(mrdft_plan* p) {
     dfree(p->d_cjobs);
     dfree(p->d_small);
     dfree(p->d_queue);
+    dfree(p->d_ajobs);
+    dfree(p->d_acols);
+    dfree(p->d_asmall);
+    dfree(p->d_ascratch);
     if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
@@ -339,6 +351,53 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
             p->tile_log = kC64TileLog;
             p->grid = (int)std::min<int64_t>(p->ncjobs, 4 * (int64_t)p->num_cu);
         }
+    }
+    {
+        // adjoint tables: 2048-sample tiles and rows pieces of levels 12..16 (launch a),
+        // columns jobs per region of up to 2^16 samples (launch b), scratch B per signal
+        std::vector<RealJob> aj;
+        std::vector<AdjColJob> cj;
+        std::vector<TileJob> sm;
+        int64_t scr = 0;
+        static const int kColOrder[16] = {0, 2, 4, 6, 8, 10, 12, 14, 1, 3, 5, 7, 9, 11, 13, 15};
+        for (int64_t j = 0; j < p->batch; ++j) {
+            const int mj = p->orders[j];
+            const int64_t N = int64_t(1) << mj;
+            if (mj < kC64TileLog) {
+                sm.push_back(TileJob{p->in_off[j], p->out_off[j], N, mj, 0});
+                continue;
+            }
+            for (int64_t tau = 0; tau < (N >> kC64TileLog); ++tau)
+                aj.push_back(RealJob{p->out_off[j] + (tau << kC64TileLog), p->in_off[j] + (tau << kC64TileLog), N, 0, 0});
+            const int top = std::min(mj, kRowsMaxLevel);
+            for (int lg = kCRowsMinLevel; lg <= top; ++lg) {
+                const int64_t L = int64_t(1) << lg;
+                for (int64_t w = 0; w < N / L; ++w)
+                    for (int g = 0; g < (1 << (lg - kCRowsMinLevel)); ++g)
+                        aj.push_back(RealJob{p->out_off[j] + (int64_t)(lg - 1) * N + w * L,
+                                             scr + (int64_t)(lg - kCRowsMinLevel) * N + w * L, 0, lg, g});
+            }
+            if (top >= kCRowsMinLevel) {
+                const int64_t region = int64_t(1) << top;
+                for (int64_t r = 0; r < N / region; ++r)
+                    for (int c = 0; c < 16; ++c)
+                        cj.push_back(AdjColJob{p->in_off[j] + r * region, scr + r * region, N, top, kColOrder[c]});
+                scr += (int64_t)(top - kCRowsMinLevel + 1) * N;
+            }
+        }
+        p->najobs = (int64_t)aj.size();
+        p->nacols = (int64_t)cj.size();
+        p->nasmall = (int64_t)sm.size();
+        if ((!aj.empty() && hipMalloc(&p->d_ajobs, sizeof(RealJob) * aj.size()) != hipSuccess) ||
+            (!cj.empty() && hipMalloc(&p->d_acols, sizeof(AdjColJob) * cj.size()) != hipSuccess) ||
+            (!sm.empty() && hipMalloc(&p->d_asmall, sizeof(TileJob) * sm.size()) != hipSuccess) ||
+            (scr > 0 && hipMalloc(&p->d_ascratch, sizeof(float2) * scr) != hipSuccess))
+            return fail(MRDFT_E_ALLOC, "adjoint tables or scratch allocation failed (%lld complex)", (long long)scr);
+        if (!aj.empty()) HIP_TRY(hipMemcpyAsync(p->d_ajobs, aj.data(), sizeof(RealJob) * aj.size(), hipMemcpyHostToDevice, s));
+        if (!cj.empty())
+            HIP_TRY(hipMemcpyAsync(p->d_acols, cj.data(), sizeof(AdjColJob) * cj.size(), hipMemcpyHostToDevice, s));
+        if (!sm.empty()) HIP_TRY(hipMemcpyAsync(p->d_asmall, sm.data(), sizeof(TileJob) * sm.size(), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));
     }
     int64_t scratch = 0;
     for (int o = kTileMaxLog + 1; o <= kMaxOrder; ++o) {
@@ -633,13 +692,22 @@ mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, h
 
 mrdft_status run_adjoint(mrdft_plan* p, const float2* gY, void* gx, bool real_out, hipStream_t s) {
     const Twiddles tw = p->tw();
-    {
+    if (p->najobs) {
         ProfScope ps(p, MRDFT_KERNEL_TILE_ADJ, s);
-        HIP_TRY(launch_tile_adj(real_out, gY, gx, p->d_jobs, p->njobs, tw, s));
+        HIP_TRY(launch_adj_a(real_out, gY, gx, p->d_ascratch, p->d_ajobs, p->najobs, tw, s));
     }
+    if (p->nasmall) {
+        ProfScope ps(p, MRDFT_KERNEL_TILE_ADJ, s);
+        HIP_TRY(launch_tile_adj(real_out, gY, gx, p->d_asmall, p->nasmall, tw, s));
+    }
+    if (p->nacols) {
+        ProfScope ps(p, MRDFT_KERNEL_PASS_ADJ, s);
+        HIP_TRY(launch_adj_b(real_out, gx, p->d_ascratch, p->d_acols, p->nacols, tw, s));
+    }
+    // levels above 16: global passes accumulating into gx
     for (const Group& g : p->groups) {
         const int64_t N = int64_t(1) << g.order;
-        for (int i = kTileMaxLog + 1; i <= g.order; ++i) {
+        for (int i = kRowsMaxLevel + 1; i <= g.order; ++i) {
             const std::vector<int> bits = pass_bits(i);
             int ns = 0;
             for (size_t q = 0; q < bits.size(); ++q) {

@@ -61,6 +61,21 @@ hipError_t launch_fwd_real(const float* x, float2* Y, const RealJob* jobs, int64
 // queue[0] until the table is exhausted; the last workgroup out clears
 // queue[0..1] for the next launch (the plan zeroes them once at creation).
 constexpr int kC64TileLog = 11;
+// Adjoint (mrdft_adj.hip).  Launch (a): RealJob with in_off = gY offset (the
+// tile's level-1 gradient, or the window's gradient at its level), out_off =
+// gx offset of the tile or scratch offset of the window's block, lg = 0 for a
+// 2048-sample tile, 12..16 for a rows piece g.  Launch (b): one columns job.
+struct AdjColJob {
+    int64_t gx_off;        // gx offset of the region's first sample
+    int64_t scr_off;       // scratch offset of the region in the level-12 block
+    int64_t level_stride;  // distance between two levels' scratch blocks (= N)
+    int32_t region_log;    // region of 2^region_log samples (12 .. 16)
+    int32_t c;             // columns 16c .. 16c+15
+};
+hipError_t launch_adj_a(bool real_out, const float2* gY, void* gx, float2* scratch, const RealJob* jobs, int64_t njobs,
+                        const Twiddles& tw, hipStream_t s);
+hipError_t launch_adj_b(bool real_out, void* gx, const float2* scratch, const AdjColJob* jobs, int64_t njobs,
+                        const Twiddles& tw, hipStream_t s);
 hipError_t launch_fwd_c64(const float2* x, float2* Y, const RealJob* jobs, int64_t njobs, unsigned* queue, int grid,
                           const Twiddles& tw, hipStream_t s);
 hipError_t launch_tile_fwd(bool real_in, const void* x, float2* Y, const TileJob* jobs, int64_t njobs,
