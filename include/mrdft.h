@@ -178,7 +178,8 @@ mrdft_status mrdft_spectral_loss_bwd(mrdft_plan_t plan, const float* x, const fl
 #define MRDFT_KERNEL_TILE_ADJ 2 /* on-chip tile levels, adjoint */
 #define MRDFT_KERNEL_PASS_ADJ 3 /* global pass, adjoint */
 #define MRDFT_KERNEL_FUSED_FWD 4 /* real input: tiles and levels 13..16 in one launch, forward */
-#define MRDFT_KERNEL_KINDS 5
+#define MRDFT_KERNEL_LOSS 5      /* spectral loss: level norms of the one-launch forward, Y not written */
+#define MRDFT_KERNEL_KINDS 6
 mrdft_status mrdft_plan_set_profiling(mrdft_plan_t plan, int enable);
 mrdft_status mrdft_plan_read_profile(mrdft_plan_t plan, int nkinds, double* total_ms, int64_t* launches);
 

@@ -129,6 +129,8 @@ struct mrdft_plan {
     float2* d_Yv = nullptr;
     float2* d_Yz = nullptr;
     double* d_part = nullptr;
+    double* d_sums = nullptr;               // fused loss: [2][batch * m] (num, den) sums
+    float* d_alpha = nullptr;               // loss gradient: per-level factors [batch * m]
     // side stream for the levels above the tile (they write other parts of Y,
     // so they run concurrently with the tile kernel); fork/join via events
     static constexpr int kSides = 4;
@@ -195,6 +197,8 @@ void free_plan(mrdft_plan* p) {
     dfree(p->d_Yv);
     dfree(p->d_Yz);
     dfree(p->d_part);
+    dfree(p->d_sums);
+    dfree(p->d_alpha);
     delete p;
 }
 
@@ -522,7 +526,7 @@ std::vector<RealJob> real_jobs(const mrdft_plan* p, int order) {
         for (int lg = kRowsMinLevel; lg <= std::min(mj, kRowsMaxLevel); ++lg) {
             const int64_t L = int64_t(1) << lg;
             for (int64_t w = 0; w < N / L; ++w)
-                jb.add_window(RealJob{p->in_off[j] + w * L, p->out_off[j] + (int64_t)(lg - 1) * N + w * L, 0, lg, 0},
+                jb.add_window(RealJob{p->in_off[j] + w * L, p->out_off[j] + (int64_t)(lg - 1) * N + w * L, N, lg, 0},
                               1 << (lg - kRowsMinLevel));
         }
     }
@@ -734,6 +738,40 @@ mrdft_status run_adjoint(mrdft_plan* p, const float2* gY, void* gx, bool real_ou
     return MRDFT_OK;
 }
 
+// Levels above 16 of a uniform plan through the global passes, written to
+// W[b][i - 17][n] (compact) or to the plan's output layout W[b][i - 1][n].
+mrdft_status upper_passes(mrdft_plan* p, const float* x, float2* W, hipStream_t s, bool full_layout = false) {
+    const Twiddles tw = p->tw();
+    const int64_t N = int64_t(1) << p->m;
+    const int top = p->m - kRowsMaxLevel;
+    for (const Group& g : p->groups) {
+        for (int i = kRowsMaxLevel + 1; i <= g.order; ++i) {
+            const std::vector<int> bits = pass_bits(i);
+            int ns = 0;
+            for (size_t q = 0; q < bits.size(); ++q) {
+                const bool first = q == 0, last = q + 1 == bits.size();
+                PassGeom geo;
+                geo.lg = i;
+                geo.r_log = bits[q];
+                geo.ns_log = ns;
+                geo.nwin = g.count * (N >> i);
+                geo.wps = N >> i;
+                geo.in_sig = nullptr;
+                geo.in_stride = N;
+                geo.out_sig = nullptr;
+                geo.out_stride = last ? (int64_t)(full_layout ? p->m : top) * N : N;
+                const int slot = full_layout ? i - 1 : i - kRowsMaxLevel - 1;
+                const void* in = first ? (const void*)x : (const void*)p->d_s[(q - 1) & 1];
+                void* out = last ? (void*)(W + (int64_t)slot * N) : (void*)p->d_s[q & 1];
+                ProfScope ps(p, MRDFT_KERNEL_PASS_FWD, s);
+                HIP_TRY(launch_pass(false, first ? IN_R32 : IN_C64, OUT_STORE, in, out, geo, tw, s));
+                ns += bits[q];
+            }
+        }
+    }
+    return MRDFT_OK;
+}
+
 // Time one candidate schedule: forward on scratch buffers, median of 3.
 mrdft_status time_forward(mrdft_plan* p, const void* x, float2* Y, hipStream_t s, float* ms_out) {
     const int in_kind = p->dtype == MRDFT_R32 ? IN_R32 : IN_C64;
@@ -862,7 +900,9 @@ mrdft_status ensure_loss_workspace(mrdft_plan* p) {
     const int64_t rows = p->batch * p->m;
     const int64_t N = int64_t(1) << p->m;
     const int nch = loss_chunks(N);
-    if (hipMalloc(&p->d_v, sizeof(float) * p->n_in) != hipSuccess ||
+    if (hipMalloc(&p->d_sums, sizeof(double) * 2 * rows) != hipSuccess ||
+        hipMalloc(&p->d_alpha, sizeof(float) * rows) != hipSuccess ||
+        hipMalloc(&p->d_v, sizeof(float) * p->n_in) != hipSuccess ||
         hipMalloc(&p->d_Yv, sizeof(float2) * p->n_out) != hipSuccess ||
         hipMalloc(&p->d_Yz, sizeof(float2) * p->n_out) != hipSuccess ||
         hipMalloc(&p->d_part, sizeof(double) * 2 * rows * nch) != hipSuccess) {
@@ -1046,6 +1086,32 @@ mrdft_status mrdft_spectral_loss_fwd(mrdft_plan_t plan, const float* x, const fl
     const int64_t N = int64_t(1) << plan->m;
     const int64_t rows = plan->batch * plan->m;
     const int nch = loss_chunks(N);
+    if (plan->d_rjobs) {
+        // Fused: levels 1..16 of x - z and of z reduced on chip (Y never
+        // written), levels above 16 through the passes into the workspace.
+        const Twiddles tw = plan->tw();
+        double* snum = plan->d_sums;
+        double* sden = plan->d_sums + rows;
+        HIP_TRY(hipMemsetAsync(plan->d_sums, 0, sizeof(double) * 2 * rows, stream));
+        {
+            ProfScope ps(plan, MRDFT_KERNEL_LOSS, stream);
+            HIP_TRY(launch_fwd_real_norms(x, z, snum, plan->m, plan->d_rjobs, plan->nrjobs, tw, stream));
+            HIP_TRY(launch_fwd_real_norms(z, nullptr, sden, plan->m, plan->d_rjobs, plan->nrjobs, tw, stream));
+        }
+        if (plan->m > kRowsMaxLevel) {
+            HIP_TRY(launch_sub_real(x, z, plan->d_v, plan->n_in, stream));
+            const int top = plan->m - kRowsMaxLevel;                   // levels above 16 per signal
+            for (int pass = 0; pass < 2; ++pass) {
+                st = upper_passes(plan, pass == 0 ? plan->d_v : z, plan->d_Yv, stream);
+                if (st) return st;
+                HIP_TRY(launch_sumsq(plan->d_Yv, plan->d_part, plan->batch * top, N, stream));
+                HIP_TRY(launch_add_rows(plan->d_part, loss_chunks(N), pass == 0 ? snum : sden, plan->batch, plan->m,
+                                        kRowsMaxLevel, stream));
+            }
+        }
+        HIP_TRY(launch_finalize(snum, sden, num_den, L, plan->batch, plan->m, 1, stream));
+        return MRDFT_OK;
+    }
     HIP_TRY(launch_sub_real(x, z, plan->d_v, plan->n_in, stream));
     st = run_forward(plan, plan->d_v, IN_R32, plan->d_Yv, stream);
     if (st) return st;
@@ -1053,7 +1119,7 @@ mrdft_status mrdft_spectral_loss_fwd(mrdft_plan_t plan, const float* x, const fl
     if (st) return st;
     HIP_TRY(launch_sumsq(plan->d_Yv, plan->d_part, rows, N, stream));
     HIP_TRY(launch_sumsq(plan->d_Yz, plan->d_part + rows * nch, rows, N, stream));
-    HIP_TRY(launch_finalize(plan->d_part, plan->d_part + rows * nch, num_den, L, plan->batch, plan->m, N, stream));
+    HIP_TRY(launch_finalize(plan->d_part, plan->d_part + rows * nch, num_den, L, plan->batch, plan->m, nch, stream));
     return MRDFT_OK;
 }
 
@@ -1070,6 +1136,24 @@ mrdft_status mrdft_spectral_loss_bwd(mrdft_plan_t plan, const float* x, const fl
     if (st) return st;
     const int64_t N = int64_t(1) << plan->m;
     const int64_t rows = plan->batch * plan->m;
+    if (plan->d_rjobs) {
+        // Recompute the spectra of x - z with each level already scaled by its
+        // gradient factor (levels 1..16 in the one-launch forward), then the adjoint.
+        HIP_TRY(launch_loss_alpha(num_den, gL, plan->d_alpha, rows, plan->m, stream));
+        {
+            ProfScope ps(plan, MRDFT_KERNEL_LOSS, stream);
+            HIP_TRY(launch_fwd_real_scaled(x, z, plan->d_alpha, plan->m, plan->d_Yv, plan->d_rjobs, plan->nrjobs,
+                                           plan->tw(), stream));
+        }
+        if (plan->m > kRowsMaxLevel) {
+            HIP_TRY(launch_sub_real(x, z, plan->d_v, plan->n_in, stream));
+            st = upper_passes(plan, plan->d_v, plan->d_Yv, stream, true);
+            if (st) return st;
+            HIP_TRY(launch_scale_levels(plan->d_Yv, num_den, gL, plan->m, N, plan->batch * (plan->m - kRowsMaxLevel),
+                                        stream, kRowsMaxLevel));
+        }
+        return run_adjoint(plan, plan->d_Yv, gx, true, stream);
+    }
     HIP_TRY(launch_sub_real(x, z, plan->d_v, plan->n_in, stream));
     st = run_forward(plan, plan->d_v, IN_R32, plan->d_Yv, stream);
     if (st) return st;

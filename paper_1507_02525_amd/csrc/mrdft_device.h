@@ -28,6 +28,7 @@ __device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y
 __device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
     return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
 }
+__device__ __forceinline__ float norm2(float2 a) { return a.x * a.x + a.y * a.y; }
 // a * (-j) and a * (+j)
 __device__ __forceinline__ float2 mul_mj(float2 a) { return make_float2(a.y, -a.x); }
 __device__ __forceinline__ float2 mul_pj(float2 a) { return make_float2(-a.y, a.x); }

@@ -19,28 +19,79 @@ union FwdRealLds {
 static_assert(sizeof(FwdRealLds) <= 40 * 1024, "four workgroups per CU");
 static_assert(kRThreads == kRowsThreads, "one block size for both job kinds");
 
-// at least 4 waves per SIMD: 4 workgroups per CU (128 VGPRs)
+// Sum of v over the 64 lanes of a wave (all lanes receive it).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// RED = false: the level spectra are stored to Y; with `alpha` (spectral-loss
+// gradient) the input is x - xsub and level i of signal b is stored times
+// alpha[b * m + i - 1].  RED = true (spectral loss): the input is x - xsub
+// (xsub may be null) and only the squared magnitudes of every level are
+// summed, into sums[b * m + level - 1]; Y is not touched.  Both need a
+// uniform batch (signal b = in_off / N).
+// At least 4 waves per SIMD: 4 workgroups per CU (128 VGPRs).
+template <bool RED>
 __global__ __launch_bounds__(kRThreads, 4) void fwd_real_kernel(const float* __restrict__ x, float2* __restrict__ Y,
-                                                             const RealJob* __restrict__ jobs,
-                                                             const float2* __restrict__ t4096,
-                                                             const float2* __restrict__ rowtw,
-                                                             const float4* __restrict__ comb) {
+                                                                const RealJob* __restrict__ jobs,
+                                                                const float2* __restrict__ t4096,
+                                                                const float2* __restrict__ rowtw,
+                                                                const float4* __restrict__ comb,
+                                                                const float* __restrict__ xsub,
+                                                                double* __restrict__ sums,
+                                                                const float* __restrict__ alpha, int m) {
     __shared__ FwdRealLds S;
     const RealJob jb = jobs[blockIdx.x];
     const int tid = threadIdx.x;
     const float* xj = x + jb.in_off;
-    float2* yj = Y + jb.out_off;
-    switch (jb.lg) {
-        case 0: real_tile_body(S.tile, xj, yj, jb.level_stride, t4096, tid); break;
-        case 13: rows_real_body<5>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(13),
-                                         comb + rows_combine_offset(13), tid); break;
-        case 14: rows_real_body<6>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(14),
-                                         comb + rows_combine_offset(14), tid); break;
-        case 15: rows_real_body<7>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(15),
-                                         comb + rows_combine_offset(15), tid); break;
-        case 16: rows_real_body<8>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(16),
-                                         comb + rows_combine_offset(16), tid); break;
-        default: break;
+    const float* zj = (RED && xsub) ? xsub + jb.in_off : nullptr;
+    float2* yj = RED ? nullptr : Y + jb.out_off;
+    if constexpr (!RED) {
+        StoreOut out;
+        const float* za = nullptr;
+        float sc = 1.0f;
+        if (alpha) {
+            out.alpha = alpha + (jb.in_off / jb.level_stride) * m;
+            za = xsub ? xsub + jb.in_off : nullptr;
+            if (jb.lg > 0) sc = out.alpha[jb.lg - 1];
+        }
+        switch (jb.lg) {
+            case 0: real_tile_body(S.tile, xj, za, yj, jb.level_stride, t4096, tid, out); break;
+            case 13: rows_real_body<5, false>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(13),
+                                              comb + rows_combine_offset(13), tid, za, nullptr, sc); break;
+            case 14: rows_real_body<6, false>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(14),
+                                              comb + rows_combine_offset(14), tid, za, nullptr, sc); break;
+            case 15: rows_real_body<7, false>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(15),
+                                              comb + rows_combine_offset(15), tid, za, nullptr, sc); break;
+            case 16: rows_real_body<8, false>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(16),
+                                              comb + rows_combine_offset(16), tid, za, nullptr, sc); break;
+            default: break;
+        }
+    } else {
+        const int64_t b = jb.in_off / jb.level_stride;
+        double* sb = sums + b * m;
+        const int lane = tid & 63;
+        if (jb.lg == 0) {
+            NormOut out{sb};                          // flushes each level's sums as it completes
+            real_tile_body(S.tile, xj, zj, nullptr, jb.level_stride, t4096, tid, out);
+        } else {
+            double acc = 0.0;
+            switch (jb.lg) {
+                case 13: rows_real_body<5, true>(S.rows, xj, nullptr, jb.g, t4096, rowtw + rows_twiddle_offset(13),
+                                                 comb + rows_combine_offset(13), tid, zj, &acc); break;
+                case 14: rows_real_body<6, true>(S.rows, xj, nullptr, jb.g, t4096, rowtw + rows_twiddle_offset(14),
+                                                 comb + rows_combine_offset(14), tid, zj, &acc); break;
+                case 15: rows_real_body<7, true>(S.rows, xj, nullptr, jb.g, t4096, rowtw + rows_twiddle_offset(15),
+                                                 comb + rows_combine_offset(15), tid, zj, &acc); break;
+                case 16: rows_real_body<8, true>(S.rows, xj, nullptr, jb.g, t4096, rowtw + rows_twiddle_offset(16),
+                                                 comb + rows_combine_offset(16), tid, zj, &acc); break;
+                default: break;
+            }
+            const double t = wave_sum(acc);
+            if (lane == 0) atomicAdd(sb + jb.lg - 1, t);
+        }
     }
 }
 
@@ -49,8 +100,24 @@ __global__ __launch_bounds__(kRThreads, 4) void fwd_real_kernel(const float* __r
 hipError_t launch_fwd_real(const float* x, float2* Y, const RealJob* jobs, int64_t njobs, const Twiddles& tw,
                            hipStream_t s) {
     if (njobs <= 0) return hipSuccess;
-    hipLaunchKernelGGL(fwd_real_kernel, dim3((unsigned)njobs), dim3(kRThreads), 0, s, x, Y, jobs, tw.tile, tw.rows,
-                       tw.rows_comb);
+    hipLaunchKernelGGL(fwd_real_kernel<false>, dim3((unsigned)njobs), dim3(kRThreads), 0, s, x, Y, jobs, tw.tile,
+                       tw.rows, tw.rows_comb, nullptr, nullptr, nullptr, 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_fwd_real_scaled(const float* x, const float* xsub, const float* alpha, int m, float2* Y,
+                                  const RealJob* jobs, int64_t njobs, const Twiddles& tw, hipStream_t s) {
+    if (njobs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fwd_real_kernel<false>, dim3((unsigned)njobs), dim3(kRThreads), 0, s, x, Y, jobs, tw.tile,
+                       tw.rows, tw.rows_comb, xsub, nullptr, alpha, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_fwd_real_norms(const float* x, const float* xsub, double* sums, int m, const RealJob* jobs,
+                                 int64_t njobs, const Twiddles& tw, hipStream_t s) {
+    if (njobs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fwd_real_kernel<true>, dim3((unsigned)njobs), dim3(kRThreads), 0, s, x, nullptr, jobs,
+                       tw.tile, tw.rows, tw.rows_comb, xsub, sums, nullptr, m);
     return hipGetLastError();
 }
 

@@ -56,6 +56,15 @@ __host__ __device__ constexpr int64_t rows_twiddle_offset(int lg) {
 constexpr int64_t rows_twiddle_entries() { return rows_twiddle_offset(17); }
 hipError_t launch_fwd_real(const float* x, float2* Y, const RealJob* jobs, int64_t njobs, const Twiddles& tw,
                            hipStream_t s);
+// Same jobs, spectral loss: the input is x - xsub (xsub may be null) and the
+// squared magnitudes of every level are added to sums[b * m + level - 1]
+// (uniform batch; the rows jobs carry level_stride = N).  Y is not written.
+// Same jobs, spectral-loss gradient: input x - xsub, level i of signal b
+// stored times alpha[b * m + i - 1] (uniform batch).
+hipError_t launch_fwd_real_scaled(const float* x, const float* xsub, const float* alpha, int m, float2* Y,
+                                  const RealJob* jobs, int64_t njobs, const Twiddles& tw, hipStream_t s);
+hipError_t launch_fwd_real_norms(const float* x, const float* xsub, double* sums, int m, const RealJob* jobs,
+                                 int64_t njobs, const Twiddles& tw, hipStream_t s);
 // Complex input: 2048-sample tiles (lg = 0, levels 1..11) and pieces of levels
 // 12..16 (mrdft_fwd_c64.hip).  Persistent: `grid` workgroups take jobs from
 // queue[0] until the table is exhausted; the last workgroup out clears

@@ -11,7 +11,12 @@ hipError_t launch_sub_real(const float* x, const float* z, float* v, int64_t n, 
 hipError_t launch_sumsq(const float2* Y, double* part, int64_t rows, int64_t N, hipStream_t s);
 hipError_t launch_finalize(const double* pnum, const double* pden, double* num_den, float* L, int64_t batch, int m,
                            int64_t N, hipStream_t s);
+// sums[b * m + first + i] += sum of the nch partials of row b * (m - first) + i
+hipError_t launch_add_rows(const double* part, int nch, double* sums, int64_t batch, int m, int first, hipStream_t s);
+// Y[b][i][:] *= gL * 2 / (m * den_{b,i}) for levels i > first (rows = batch * (m - first)).
 hipError_t launch_scale_levels(float2* Y, const double* num_den, const float* gL, int m, int64_t N, int64_t rows,
-                               hipStream_t s);
+                               hipStream_t s, int first = 0);
+// alpha[b * m + i] = gL * 2 / (m * den_{b,i})
+hipError_t launch_loss_alpha(const double* num_den, const float* gL, float* alpha, int64_t rows, int m, hipStream_t s);
 
 }  // namespace mrdft

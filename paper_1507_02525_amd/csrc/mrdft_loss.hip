@@ -69,11 +69,14 @@ __global__ void finalize_kernel(const double* __restrict__ pnum, const double* _
 }
 
 // Y[b][i][:] *= gL * 2 / (m * den_{b,i})
+// Levels first+1 .. m of every signal (rows = batch * (m - first)).
 __global__ __launch_bounds__(256) void scale_levels_kernel(float2* __restrict__ Y, const double* __restrict__ num_den,
                                                            const float* __restrict__ gL, int m, int64_t N,
-                                                           int64_t rows) {
-    const int64_t row = blockIdx.y;
-    if (row >= rows) return;
+                                                           int64_t rows, int first) {
+    const int64_t r = blockIdx.y;
+    if (r >= rows) return;
+    const int per = m - first;
+    const int64_t row = (r / per) * m + first + (r % per);
     const double s = (double)(*gL) * 2.0 / ((double)m * num_den[2 * row + 1]);
     const float sf = (float)s;
     float2* p = Y + row * N;
@@ -81,6 +84,25 @@ __global__ __launch_bounds__(256) void scale_levels_kernel(float2* __restrict__ 
         float2 v = p[e];
         p[e] = make_float2(v.x * sf, v.y * sf);
     }
+}
+
+__global__ void add_rows_kernel(const double* __restrict__ part, int nch, double* __restrict__ sums, int64_t batch,
+                                int m, int first) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int per = m - first;
+    if (r >= batch * per) return;
+    double t = 0.0;
+    for (int c = 0; c < nch; ++c) t += part[r * nch + c];
+    const int64_t b = r / per;
+    sums[b * m + first + (r - b * per)] += t;
+}
+
+hipError_t launch_add_rows(const double* part, int nch, double* sums, int64_t batch, int m, int first, hipStream_t s) {
+    const int64_t n = batch * (m - first);
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(add_rows_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part, nch, sums, batch, m,
+                       first);
+    return hipGetLastError();
 }
 
 hipError_t launch_sub_real(const float* x, const float* z, float* v, int64_t n, hipStream_t s) {
@@ -105,11 +127,25 @@ hipError_t launch_finalize(const double* pnum, const double* pden, double* num_d
 }
 
 hipError_t launch_scale_levels(float2* Y, const double* num_den, const float* gL, int m, int64_t N, int64_t rows,
-                               hipStream_t s) {
+                               hipStream_t s, int first) {
     int64_t bx = (N + 255) / 256;
     if (bx > 256) bx = 256;
+    if (rows <= 0) return hipSuccess;
     hipLaunchKernelGGL(scale_levels_kernel, dim3((unsigned)bx, (unsigned)rows), dim3(256), 0, s, Y, num_den, gL, m,
-                       N, rows);
+                       N, rows, first);
+    return hipGetLastError();
+}
+
+// alpha[row] = gL * 2 / (m * den_row), the per-level factor of the loss gradient.
+__global__ void loss_alpha_kernel(const double* __restrict__ num_den, const float* __restrict__ gL, float* alpha,
+                                  int64_t rows, int m) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < rows) alpha[r] = (float)((double)(*gL) * 2.0 / ((double)m * num_den[2 * r + 1]));
+}
+
+hipError_t launch_loss_alpha(const double* num_den, const float* gL, float* alpha, int64_t rows, int m, hipStream_t s) {
+    hipLaunchKernelGGL(loss_alpha_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, num_den, gL, alpha,
+                       rows, m);
     return hipGetLastError();
 }
 

@@ -111,11 +111,12 @@ constexpr int64_t rows_combine_entries() { return rows_combine_offset(kRowsMaxLe
 //   t4096 : w_4096^e, e < 4096 (FP32, rounded once from FP64)
 //   rowtw : this level's row twiddles, rowtw[k2 * 256 + n1] = w_L^{n1 k2}
 //   comb  : this level's column-combine factors (see rows_combine_offset)
-template <int RL>
+template <int RL, bool RED = false>
 __device__ __forceinline__ void rows_real_body(RowsLds& S, const float* __restrict__ xw, float2* __restrict__ yw,
                                                int g, const float2* __restrict__ t4096,
                                                const float2* __restrict__ rowtw, const float4* __restrict__ comb,
-                                               int tid) {
+                                               int tid, const float* __restrict__ xsub = nullptr,
+                                               double* norm = nullptr, float scale = 1.0f) {
     constexpr int R = 1 << RL, P = R / 16, NG = R / 16;
     static_assert(P >= 2 && P <= 16, "rows of 256 cover windows of 2^13 .. 2^16");
     const int k0 = 16 * g;
@@ -132,8 +133,13 @@ __device__ __forceinline__ void rows_real_body(RowsLds& S, const float* __restri
     const __amdgpu_buffer_rsrc_t xr =
         __builtin_amdgcn_make_buffer_rsrc((void*)xw, (short)0, R * kRowsN * (int)sizeof(float), kBufferWord3);
     const int vo = n1 * (int)sizeof(float);
+    const __amdgpu_buffer_rsrc_t zr = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(xsub ? xsub : xw), (short)0, R * kRowsN * (int)sizeof(float), kBufferWord3);
     auto xload = [&](int n2) {
-        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(xr, vo, n2 * kRowsN * (int)sizeof(float), 0));
+        const int so = n2 * kRowsN * (int)sizeof(float);
+        float a = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(xr, vo, so, 0));
+        if (xsub) a -= __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(zr, vo, so, 0));   // x - xsub
+        return a;
     };
     const float4* cb = comb + (int64_t)g * (P / 2) * kRowsMax;
     float2 acc[kRowsMax];
@@ -173,13 +179,27 @@ __device__ __forceinline__ void rows_real_body(RowsLds& S, const float* __restri
     __syncthreads();                              // row 16 (wave 0) before the outputs
     // ---- outputs: group g rows 0..15 direct, group NG-1-g from rows 16..1 conjugated ----
     const int gm = NG - 1 - g;
+    if constexpr (RED) {
+        // spectral loss: only the squared magnitudes of both groups, per thread
+        float t = 0.0f;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = tid + u * kRowsThreads;
+            const int k1 = e >> 3, kp = (e & 7) * 2;
+            t += norm2(S.C[kp * kRowsStride + rpad(k1)]) + norm2(S.C[(kp + 1) * kRowsStride + rpad(k1)]) +
+                 norm2(S.C[(16 - kp) * kRowsStride + rpad(kRowsN - 1 - k1)]) +
+                 norm2(S.C[(15 - kp) * kRowsStride + rpad(kRowsN - 1 - k1)]);
+        }
+        *norm += (double)t;
+        return;
+    }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
         const int e = tid + u * kRowsThreads;
         const int k1 = e >> 3, kp = (e & 7) * 2;
         const float2 a = S.C[kp * kRowsStride + rpad(k1)];
         const float2 c = S.C[(kp + 1) * kRowsStride + rpad(k1)];
-        *(float4*)(yw + k0 + kp + (int64_t)R * k1) = make_float4(a.x, a.y, c.x, c.y);
+        *(float4*)(yw + k0 + kp + (int64_t)R * k1) = make_float4(scale * a.x, scale * a.y, scale * c.x, scale * c.y);
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
@@ -188,7 +208,8 @@ __device__ __forceinline__ void rows_real_body(RowsLds& S, const float* __restri
         // bin 16 gm + kp (+1) at k1 = conj(row 16 - kp (15 - kp) at 255 - k1)
         const float2 a = S.C[(16 - kp) * kRowsStride + rpad(kRowsN - 1 - k1)];
         const float2 c = S.C[(15 - kp) * kRowsStride + rpad(kRowsN - 1 - k1)];
-        *(float4*)(yw + 16 * gm + kp + (int64_t)R * k1) = make_float4(a.x, -a.y, c.x, -c.y);
+        *(float4*)(yw + 16 * gm + kp + (int64_t)R * k1) = make_float4(scale * a.x, -scale * a.y, scale * c.x,
+                                                                       -scale * c.y);
     }
 }
 

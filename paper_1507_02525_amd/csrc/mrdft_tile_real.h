@@ -47,6 +47,30 @@ static_assert(sizeof(float) * kRT + sizeof(float2) * kRT / 2 == (kRThreads / 64)
 
 __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
 
+// Where the level spectra go: stored to Y, or (spectral loss) only their
+// squared magnitudes summed per level in FP64, Y never written.
+struct StoreOut {
+    static constexpr bool kReduce = false;
+    const float* alpha = nullptr;                  // per-level factors (spectral-loss gradient), or none
+    __device__ __forceinline__ float2 sc(int level, float2 v) const {
+        if (!alpha) return v;
+        const float a = alpha[level - 1];
+        return make_float2(a * v.x, a * v.y);
+    }
+};
+struct NormOut {
+    static constexpr bool kReduce = true;
+    double* sums;                                   // this signal's per-level sums
+    __device__ __forceinline__ float2 sc(int, float2 v) const { return v; }
+    // Adds the wave's partial sums of one level (every lane must call it).
+    __device__ __forceinline__ void add(int level, float t) {
+        double v = (double)t;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+        if ((threadIdx.x & 63) == 0) atomicAdd(sums + level - 1, v);
+    }
+};
+
 // The quarter table w_4096^e (e < 1024) sits at a swizzled index: the low 5
 // bits are XORed with bits 5..9, so that entries at a power-of-two stride of
 // 32 or more (the twiddles of one Stockham step) fall on different banks.
@@ -133,8 +157,8 @@ struct RSteps {
 };
 
 // Level I >= 5 of the tile.
-template <int I>
-__device__ __forceinline__ void real_level(RealTileLds& S, float2* __restrict__ y, int tid) {
+template <int I, class O>
+__device__ __forceinline__ void real_level(RealTileLds& S, float2* __restrict__ y, int tid, O& out) {
     constexpr int L = 1 << I, M = L / 2, H = M / 2, LH = I - 2;
     constexpr int NW = kRT / L;
     constexpr int R1 = (LH & 1) ? 2 : 4;        // first step radix
@@ -193,6 +217,7 @@ __device__ __forceinline__ void real_level(RealTileLds& S, float2* __restrict__ 
     RSteps<H, NW, LR1, LH>::run(F, S.Q, tid);
     // ---- post-processing, new half spectra and the level's output ----
     float2 ok[PPT], oj[PPT];
+    float nrm = 0.0f;
 #pragma unroll
     for (int c = 0; c < PPT; ++c) {
         const int J = tid + c * kRThreads;
@@ -225,20 +250,28 @@ __device__ __forceinline__ void real_level(RealTileLds& S, float2* __restrict__ 
         const float2 ua = cconj(uk1[c]);
         const float2 ub = (k == 0) ? make_float2(uj1[c].y, 0.0f) : cconj(uj1[c]);
         const float2 oka = cconj(ok[c]), oja = cconj(oj[c]);
-        *(float4*)(yw + 2 * k) = make_float4(u0.x, u0.y, ok[c].x, ok[c].y);
-        *(float4*)(yw + 2 * j) = make_float4(uj[c].x, uj[c].y, oj[c].x, oj[c].y);
-        *(float4*)(yw + M + 2 * j) = make_float4(ua.x, ua.y, oka.x, oka.y);
-        *(float4*)(yw + M + 2 * k) = make_float4(ub.x, ub.y, oja.x, oja.y);
+        if constexpr (O::kReduce) {
+            nrm += norm2(u0) + norm2(ok[c]) + norm2(uj[c]) + norm2(oj[c]) + norm2(ua) + norm2(oka) + norm2(ub) +
+                   norm2(oja);
+        } else {
+            const float2 s0 = out.sc(I, u0), s1 = out.sc(I, ok[c]), s2 = out.sc(I, uj[c]), s3 = out.sc(I, oj[c]);
+            const float2 s4 = out.sc(I, ua), s5 = out.sc(I, oka), s6 = out.sc(I, ub), s7 = out.sc(I, oja);
+            *(float4*)(yw + 2 * k) = make_float4(s0.x, s0.y, s1.x, s1.y);
+            *(float4*)(yw + 2 * j) = make_float4(s2.x, s2.y, s3.x, s3.y);
+            *(float4*)(yw + M + 2 * j) = make_float4(s4.x, s4.y, s5.x, s5.y);
+            *(float4*)(yw + M + 2 * k) = make_float4(s6.x, s6.y, s7.x, s7.y);
+        }
     }
+    if constexpr (O::kReduce) out.add(I, nrm);
     __syncthreads();
 }
 
-template <int I>
+template <int I, class O>
 struct RealLevels {
-    static __device__ __forceinline__ void run(RealTileLds& S, float2* __restrict__ y, int64_t ls, int tid) {
+    static __device__ __forceinline__ void run(RealTileLds& S, float2* __restrict__ y, int64_t ls, int tid, O& out) {
         if constexpr (I <= kRTLog) {
-            real_level<I>(S, y + (int64_t)(I - 1) * ls, tid);
-            RealLevels<I + 1>::run(S, y, ls, tid);
+            real_level<I, O>(S, y + (int64_t)(I - 1) * ls, tid, out);
+            RealLevels<I + 1, O>::run(S, y, ls, tid, out);
         }
     }
 };
@@ -255,10 +288,21 @@ __device__ __forceinline__ void wave_sync() {
 // each) through the wave's private LDS region, so that every global store
 // instruction covers 1 KB of consecutive output.  Pair e of lane l sits at
 // 8l + (e ^ (l & 7)) (XOR swizzle: conflict-free writes and reads).
-__device__ __forceinline__ void stage_level(const float2* pv, float4* st, float2* __restrict__ yl, int lane) {
+template <class O>
+__device__ __forceinline__ void stage_level(const float2* pv, float4* st, float2* __restrict__ yl, int lane, O& out,
+                                            int level) {
+    if constexpr (O::kReduce) {
+        float t = 0.0f;
 #pragma unroll
-    for (int e = 0; e < 8; ++e)
-        st[8 * lane + (e ^ (lane & 7))] = make_float4(pv[2 * e].x, pv[2 * e].y, pv[2 * e + 1].x, pv[2 * e + 1].y);
+        for (int e = 0; e < 16; ++e) t += norm2(pv[e]);
+        out.add(level, t);
+        return;
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const float2 a = out.sc(level, pv[2 * e]), b = out.sc(level, pv[2 * e + 1]);
+        st[8 * lane + (e ^ (lane & 7))] = make_float4(a.x, a.y, b.x, b.y);
+    }
     wave_sync();
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
@@ -269,10 +313,10 @@ __device__ __forceinline__ void stage_level(const float2* pv, float4* st, float2
 }
 
 // Register recurrence for levels I..4 of 16 samples (full spectra, natural order).
-template <int I>
+template <int I, class O>
 struct LocalFwdReal {
     static __device__ __forceinline__ void run(const float2* xv, float2* pv, float4* st, float2* y, int64_t ls,
-                                               int lane) {
+                                               int lane, O& out) {
         if constexpr (I <= 4) {
             constexpr int C = 16, L = 1 << I, M = L / 2;
             float2 nv[C];
@@ -291,8 +335,8 @@ struct LocalFwdReal {
             }
 #pragma unroll
             for (int e = 0; e < C; ++e) pv[e] = nv[e];
-            stage_level(pv, st, y + (int64_t)(I - 1) * ls, lane);
-            LocalFwdReal<I + 1>::run(xv, pv, st, y, ls, lane);
+            stage_level<O>(pv, st, y + (int64_t)(I - 1) * ls, lane, out, I);
+            LocalFwdReal<I + 1, O>::run(xv, pv, st, y, ls, lane, out);
         }
     }
 };
@@ -301,8 +345,9 @@ struct LocalFwdReal {
 // wave v owns samples [1024 v, 1024 v + 1024).  X and P (32 KB, contiguous)
 // serve as staging space first; at the end they receive the samples and the
 // level-4 half spectra (8 slots per window, slot 0 = (Y[0], Y[8])).
-__device__ __forceinline__ void real_local(const float* __restrict__ xin, float2* __restrict__ y, int64_t ls,
-                                           RealTileLds& S, int tid) {
+template <class O>
+__device__ __forceinline__ void real_local(const float* __restrict__ xin, const float* __restrict__ xsub,
+                                           float2* __restrict__ y, int64_t ls, RealTileLds& S, int tid, O& out) {
     constexpr int C = 16;
     const int v = tid >> 6, lane = tid & 63;
     float* xs = S.X + 1024 * v;
@@ -312,6 +357,14 @@ __device__ __forceinline__ void real_local(const float* __restrict__ xin, float2
         float2 a[8];
 #pragma unroll
         for (int r = 0; r < 8; ++r) a[r] = xg[64 * r + lane];
+        if (xsub) {                                   // input x - xsub (spectral loss)
+            const float2* zg = (const float2*)(xsub + 1024 * v);
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                const float2 b = zg[64 * r + lane];
+                a[r] = make_float2(a[r].x - b.x, a[r].y - b.y);
+            }
+        }
 #pragma unroll
         for (int r = 0; r < 8; ++r) *(float2*)(xs + 2 * (64 * r + lane)) = a[r];
     }
@@ -333,8 +386,8 @@ __device__ __forceinline__ void real_local(const float* __restrict__ xin, float2
         pv[2 * b + 1] = csub(xv[2 * b], xv[2 * b + 1]);
     }
     float2* yv = y + 1024 * v;
-    stage_level(pv, st, yv, lane);
-    LocalFwdReal<2>::run(xv, pv, st, yv, ls, lane);
+    stage_level<O>(pv, st, yv, lane, out, 1);
+    LocalFwdReal<2, O>::run(xv, pv, st, yv, ls, lane, out);
     __syncthreads();                             // staging done in every wave
 #pragma unroll
     for (int e = 0; e < C / 4; ++e)
@@ -345,14 +398,16 @@ __device__ __forceinline__ void real_local(const float* __restrict__ xin, float2
     for (int s = 1; s < 8; ++s) pd[s] = pv[s];
 }
 
-// One full tile: x points at the tile's first sample, y at its level-1 output
-// (level i at y + (i-1)*ls).
-__device__ __forceinline__ void real_tile_body(RealTileLds& S, const float* __restrict__ x, float2* __restrict__ y,
-                                               int64_t ls, const float2* __restrict__ t4096, int tid) {
+// One full tile: x points at the tile's first sample (minus xsub's, if given),
+// y at its level-1 output (level i at y + (i-1)*ls).
+template <class O>
+__device__ __forceinline__ void real_tile_body(RealTileLds& S, const float* __restrict__ x,
+                                               const float* __restrict__ xsub, float2* __restrict__ y, int64_t ls,
+                                               const float2* __restrict__ t4096, int tid, O& out) {
     for (int e = tid; e < kRT / 4; e += kRThreads) S.Q[qswz(e)] = t4096[e];   // before any store
-    real_local(x, y, ls, S, tid);
+    real_local<O>(x, xsub, y, ls, S, tid, out);
     __syncthreads();
-    RealLevels<5>::run(S, y, ls, tid);
+    RealLevels<5, O>::run(S, y, ls, tid, out);
 }
 
 }  // namespace mrdft

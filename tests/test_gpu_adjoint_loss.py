@@ -85,7 +85,7 @@ def _loss_case(batch, m, seed):
     return workloads.gaussian_real(rng, (batch, 1 << m)), workloads.gaussian_real(rng, (batch, 1 << m))
 
 
-@pytest.mark.parametrize("m", [3, 10, 14])
+@pytest.mark.parametrize("m", [3, 10, 12, 14, 16, 17])
 def test_spectral_loss_vs_oracle(m):
     need_gpu()
     api = _api()
@@ -122,6 +122,24 @@ def test_spectral_loss_gradient_vs_oracle_and_fd():
             e[p] = h
             fd[p] = 0.75 * (oracle.spectral_loss(xd + e, z[b])[1] - oracle.spectral_loss(xd - e, z[b])[1]) / (2 * h)
         assert rel_l2(g[b], fd) <= GRAD_TOL
+
+
+@pytest.mark.parametrize("m", [12, 13, 16])
+def test_spectral_loss_gradient_fused_orders(m):
+    """Gradient through the one-launch path (levels up to 16 recomputed with
+    their factors folded in) against the oracle's adjoint-based gradient."""
+    need_gpu()
+    api = _api()
+    x, z = _loss_case(2, m, 500 + m)
+    log("loss gradient m=%d" % m)
+    xt = to_dev(x).requires_grad_(True)
+    L = api.spectral_loss(xt, to_dev(z))
+    (1.5 * L).backward()
+    g = xt.grad.cpu().numpy()
+    for b in range(2):
+        nd, _ = oracle.spectral_loss(x[b], z[b])
+        ref = oracle.spectral_loss_grad(x[b], z[b], nd, gL=1.5)
+        assert rel_l2(g[b], ref) <= GRAD_TOL
 
 
 def test_workload5_full_size():

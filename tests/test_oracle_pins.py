@@ -409,3 +409,20 @@ def test_invalid_arguments():
     assert lib.mro_forward_level(2, 3, oracle._dp(x), oracle._dp(y), 0) != 0
     with pytest.raises(ValueError):
         oracle.forward(np.zeros(6))
+
+
+def test_spectral_loss_terms_follow_parseval():
+    """Each level is a block-diagonal DFT of non-overlapping windows, and one
+    window's DFT satisfies E^H E = 2^i I (Section 2, eq. (1)); so the level
+    energies of the loss are num_i = 2^i ||x - z||^2 and den_i = 2^i ||z||^2,
+    and L = ||x - z||^2 / ||z||^2 whatever m is.  A dropped window, a wrong
+    level length or a missing conjugate in the oracle's loss breaks this."""
+    rng = np.random.default_rng(77)
+    for m in (1, 5, 9):
+        x = rng.standard_normal(1 << m)
+        z = rng.standard_normal(1 << m)
+        nd, L = oracle.spectral_loss(x, z)
+        for i in range(1, m + 1):
+            assert nd[i - 1, 0] == pytest.approx((2 ** i) * np.sum((x - z) ** 2), rel=1e-12)
+            assert nd[i - 1, 1] == pytest.approx((2 ** i) * np.sum(z ** 2), rel=1e-12)
+        assert L == pytest.approx(np.sum((x - z) ** 2) / np.sum(z ** 2), rel=1e-12)
