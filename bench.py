@@ -112,12 +112,12 @@ def extra_workloads(steps, warmup, HBM):
     import torch
     from paper_1507_02525_amd import api, workloads
     out = {}
-    for k, name in ((3, "one complex64 signal, N=2^24 (m=24)"),
+    for k, name in ((3, "one complex64 signal, N=2^24 (m=24), tuned plan"),
                     (4, "1000 complex64 signals, m~U{8..18}, int64 offsets, tuned plan, graph replay")):
         d = workloads.make(k)
         if k == 3:
             x = torch.from_numpy(d["x"]).cuda().view(-1)
-            plan = api.Plan(m=d["m"], batch=d["batch"], dtype="c64")
+            plan = api.Plan(m=d["m"], batch=d["batch"], dtype="c64", tune=True)
         else:
             x = torch.from_numpy(d["x"]).cuda()
             plan = api.Plan(offsets=d["offsets"], dtype="c64", tune=True, graph=True)

@@ -102,7 +102,8 @@ struct mrdft_plan {
     int64_t ncjobs = 0;
     TileJob* d_small = nullptr;             // tiles of complex signals of order < 11
     int64_t nsmall = 0;
-    unsigned* d_queue = nullptr;            // persistent launch: next job, workgroups done
+    unsigned* d_queue = nullptr;            // persistent launch: next job per XCD segment, workgroups done
+    unsigned* d_cseg = nullptr;             // starts of the 8 segments of the complex job table
     // adjoint: launch (a) tiles + rows pieces, launch (b) columns jobs, scratch B
     RealJob* d_ajobs = nullptr;
     int64_t najobs = 0;
@@ -184,6 +185,7 @@ void free_plan(mrdft_plan* p) {
     dfree(p->d_cjobs);
     dfree(p->d_small);
     dfree(p->d_queue);
+    dfree(p->d_cseg);
     dfree(p->d_ajobs);
     dfree(p->d_acols);
     dfree(p->d_asmall);
@@ -297,7 +299,8 @@ mrdft_status upload_twiddles(mrdft_plan* p, hipStream_t s) {
 }
 
 std::vector<RealJob> real_jobs(const mrdft_plan* p, int order);
-std::vector<RealJob> complex_jobs(const mrdft_plan* p, int order);
+std::vector<RealJob> complex_jobs(const mrdft_plan* p, int order, std::vector<unsigned>* seg);
+mrdft_status upload_cjobs(mrdft_plan* p, int order, hipStream_t s);
 mrdft_status upload_jobs(const std::vector<RealJob>& v, RealJob** dst, int64_t* n, hipStream_t s);
 
 mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
@@ -334,7 +337,7 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
         mrdft_status st = upload_jobs(real_jobs(p, p->order), &p->d_rjobs, &p->nrjobs, s);
         if (st) return st;
     } else {
-        mrdft_status st = upload_jobs(complex_jobs(p, p->order), &p->d_cjobs, &p->ncjobs, s);
+        mrdft_status st = upload_cjobs(p, p->order, s);
         if (st) return st;
         std::vector<TileJob> small;
         for (int64_t j = 0; j < p->batch; ++j) {
@@ -349,11 +352,14 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
             HIP_TRY(hipMemcpyAsync(p->d_small, small.data(), sizeof(TileJob) * small.size(), hipMemcpyHostToDevice, s));
         }
         if (p->ncjobs > 0) {
-            if (hipMalloc(&p->d_queue, 2 * sizeof(unsigned)) != hipSuccess)
+            if (hipMalloc(&p->d_queue, kC64Queues * sizeof(unsigned)) != hipSuccess)
                 return fail(MRDFT_E_ALLOC, "queue allocation failed");
-            HIP_TRY(hipMemsetAsync(p->d_queue, 0, 2 * sizeof(unsigned), s));   // once; kernels restore it
+            HIP_TRY(hipMemsetAsync(p->d_queue, 0, kC64Queues * sizeof(unsigned), s));   // once; kernels restore it
             p->tile_log = kC64TileLog;
-            p->grid = (int)std::min<int64_t>(p->ncjobs, 4 * (int64_t)p->num_cu);
+            // one workgroup per CU by default: the pieces of a level-16 window
+            // re-read its x columns, and fewer windows in flight per XCD keep
+            // them in L2 (the tuner also tries 2 and 4 per CU)
+            p->grid = (int)std::min<int64_t>(p->ncjobs, (int64_t)p->num_cu);
         }
     }
     {
@@ -478,7 +484,10 @@ struct JobBuckets {
         }
         load[b] += pieces;
     }
-    std::vector<RealJob> deal(int order) {
+    // contiguous: the buckets one after the other, their starts in seg[0..8]
+    // (persistent launch); otherwise interleaved so that block b falls in
+    // bucket b mod 8 (one workgroup per job).
+    std::vector<RealJob> deal(int order, std::vector<unsigned>* seg = nullptr) {
         std::vector<std::vector<RealJob>> bucket(kX);
         for (int b = 0; b < kX; ++b) {
             std::stable_sort(rows[b].begin(), rows[b].end(),
@@ -499,6 +508,15 @@ struct JobBuckets {
             }
         }
         std::vector<RealJob> out;
+        if (seg) {
+            seg->assign(kX + 1, 0);
+            for (int b = 0; b < kX; ++b) {
+                (*seg)[b] = (unsigned)out.size();
+                out.insert(out.end(), bucket[b].begin(), bucket[b].end());
+            }
+            (*seg)[kX] = (unsigned)out.size();
+            return out;
+        }
         for (size_t i = 0;; ++i) {
             bool any = false;
             for (int b = 0; b < kX; ++b)
@@ -535,7 +553,7 @@ std::vector<RealJob> real_jobs(const mrdft_plan* p, int order) {
 
 // Complex signals of order >= 11: 2048-sample tiles and pieces of levels
 // 12..16 (2^(lg-12) pieces of 16 rows per window).
-std::vector<RealJob> complex_jobs(const mrdft_plan* p, int order) {
+std::vector<RealJob> complex_jobs(const mrdft_plan* p, int order, std::vector<unsigned>* seg) {
     JobBuckets jb;
     for (int64_t j = 0; j < p->batch; ++j) {
         const int mj = p->orders[j];
@@ -551,7 +569,19 @@ std::vector<RealJob> complex_jobs(const mrdft_plan* p, int order) {
                               1 << (lg - kCRowsMinLevel));
         }
     }
-    return jb.deal(order);
+    return jb.deal(order, seg);
+}
+
+// Complex job table in per-XCD segments, with its segment starts.
+mrdft_status upload_cjobs(mrdft_plan* p, int order, hipStream_t s) {
+    std::vector<unsigned> seg;
+    mrdft_status st = upload_jobs(complex_jobs(p, order, &seg), &p->d_cjobs, &p->ncjobs, s);
+    if (st) return st;
+    if (!p->d_cseg && hipMalloc(&p->d_cseg, sizeof(unsigned) * seg.size()) != hipSuccess)
+        return fail(MRDFT_E_ALLOC, "segment table allocation failed");
+    HIP_TRY(hipMemcpyAsync(p->d_cseg, seg.data(), sizeof(unsigned) * seg.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return MRDFT_OK;
 }
 
 // Upload a job table (replacing a previous one of the same slot).
@@ -676,7 +706,8 @@ mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, h
         } else if (cjobs_cover) {
             {
                 ProfScope ps(p, MRDFT_KERNEL_FUSED_FWD, s0);
-                HIP_TRY(launch_fwd_c64((const float2*)x, Y, p->d_cjobs, p->ncjobs, p->d_queue, p->grid, tw, s0));
+                HIP_TRY(launch_fwd_c64((const float2*)x, Y, p->d_cjobs, p->ncjobs, p->d_cseg, p->d_queue, p->grid, tw,
+                                       s0));
             }
             if (p->nsmall) {
                 ProfScope ps(p, MRDFT_KERNEL_TILE_FWD, s0);
@@ -831,7 +862,7 @@ mrdft_status tune(mrdft_plan* p, hipStream_t s) {
         if (st) break;
         if (c.tile_log != kTileMaxLog && c.order != cur_order) {
             st = real ? upload_jobs(real_jobs(p, c.order), &p->d_rjobs, &p->nrjobs, s)
-                      : upload_jobs(complex_jobs(p, c.order), &p->d_cjobs, &p->ncjobs, s);
+                      : upload_cjobs(p, c.order, s);
             cur_order = c.order;
             if (st) break;
         }
@@ -846,7 +877,7 @@ mrdft_status tune(mrdft_plan* p, hipStream_t s) {
     }
     if (!st && best.tile_log != kTileMaxLog && best.order != cur_order)
         st = real ? upload_jobs(real_jobs(p, best.order), &p->d_rjobs, &p->nrjobs, s)
-                  : upload_jobs(complex_jobs(p, best.order), &p->d_cjobs, &p->ncjobs, s);
+                  : upload_cjobs(p, best.order, s);
     p->tile_log = best.tile_log;
     p->order = best.tile_log == kTileMaxLog && !real ? cur_order : best.order;
     p->grid = best.grid;
@@ -1039,7 +1070,7 @@ mrdft_status mrdft_plan_set_schedule(mrdft_plan_t plan, int tile_log, int grid, 
     if (!real && tile_log == kC64TileLog && grid < 1) return fail(MRDFT_E_INVALID_ARG, "grid must be >= 1");
     if (order != plan->order) {
         st = real ? upload_jobs(real_jobs(plan, order), &plan->d_rjobs, &plan->nrjobs, stream)
-                  : upload_jobs(complex_jobs(plan, order), &plan->d_cjobs, &plan->ncjobs, stream);
+                  : upload_cjobs(plan, order, stream);
         if (st) return st;
         plan->order = order;
     }

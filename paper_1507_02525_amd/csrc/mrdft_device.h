@@ -104,4 +104,14 @@ __device__ __forceinline__ float2 tw_big(const double2* __restrict__ hi, const d
     return make_float2((float)(a.x * b.x - a.y * b.y), (float)(a.x * b.y + a.y * b.x));
 }
 
+// Same twiddle in FP64 (not rounded).
+__device__ __forceinline__ double2 tw_big64(const double2* __restrict__ hi, const double2* __restrict__ lo, int lg,
+                                            int64_t e) {
+    const int64_t mask = ((int64_t)1 << kMaxOrder) - 1;
+    const int64_t E = (e << (kMaxOrder - lg)) & mask;
+    const double2 a = hi[E >> kTwFineLog];
+    const double2 b = lo[E & ((1 << kTwFineLog) - 1)];
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
 }  // namespace mrdft

@@ -3,6 +3,12 @@
 // 1..11 on chip, mrdft_tile_c64.h) or one 16-row piece of a window of a level
 // 12..16 (mrdft_rows_c64.h).  Signals of any order share the launch; their
 // offsets are int64.
+//
+// The table holds one segment per XCD, with all pieces of a window in one
+// segment.  A workgroup takes jobs from the segment of the XCD it runs on
+// (read from the hardware register), so the pieces of a window share their x
+// columns through that XCD's L2; when its segment is empty it takes jobs from
+// the other segments.
 #include "mrdft_internal.h"
 #include "mrdft_rows_c64.h"
 #include "mrdft_tile_c64.h"
@@ -18,19 +24,40 @@ union FwdC64Lds {
 static_assert(sizeof(FwdC64Lds) <= 40 * 1024, "four workgroups per CU");
 static_assert(kCThreads == kRowsThreads, "one block size for both job kinds");
 
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ unsigned xcc_id() {
+    unsigned v;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(v));
+    return v & (kXcds - 1);
+}
+
+// queue[q] (q < 8): next job of segment q; queue[8]: workgroups done.
 __global__ __launch_bounds__(kCThreads, 4) void fwd_c64_kernel(const float2* __restrict__ x, float2* __restrict__ Y,
-                                                               const RealJob* __restrict__ jobs, int64_t njobs,
-                                                               unsigned* queue, const float2* __restrict__ t4096,
+                                                               const RealJob* __restrict__ jobs,
+                                                               const unsigned* __restrict__ seg, unsigned* queue,
+                                                               const float2* __restrict__ t4096,
                                                                const float2* __restrict__ rowtw,
                                                                const float2* __restrict__ comb) {
     __shared__ FwdC64Lds S;
-    __shared__ unsigned s_job;
+    __shared__ int s_job;
     const int tid = threadIdx.x;
+    const unsigned home = xcc_id();
     for (;;) {
-        if (tid == 0) s_job = atomicAdd(&queue[0], 1u);
+        if (tid == 0) {
+            int found = -1;
+            for (int k = 0; k < kXcds && found < 0; ++k) {
+                const unsigned q = (home + k) & (kXcds - 1);
+                const unsigned len = seg[q + 1] - seg[q];
+                if (__hip_atomic_load(&queue[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= len) continue;
+                const unsigned i = atomicAdd(&queue[q], 1u);
+                if (i < len) found = (int)(seg[q] + i);
+            }
+            s_job = found;
+        }
         __syncthreads();
-        const int64_t j = s_job;
-        if (j >= njobs) break;                        // every workgroup reaches this exit
+        const int j = s_job;
+        if (j < 0) break;                             // every segment is exhausted: every workgroup exits
         const RealJob jb = jobs[j];
         const float2* xj = x + jb.in_off;
         float2* yj = Y + jb.out_off;
@@ -59,21 +86,20 @@ __global__ __launch_bounds__(kCThreads, 4) void fwd_c64_kernel(const float2* __r
     // others have made their final fetch before they counted themselves out.
     if (tid == 0) {
         __threadfence();
-        const unsigned done = atomicAdd(&queue[1], 1u);
+        const unsigned done = atomicAdd(&queue[kXcds], 1u);
         if (done == gridDim.x - 1) {
-            atomicExch(&queue[0], 0u);
-            atomicExch(&queue[1], 0u);
+            for (int q = 0; q <= kXcds; ++q) atomicExch(&queue[q], 0u);
         }
     }
 }
 
 }  // namespace
 
-hipError_t launch_fwd_c64(const float2* x, float2* Y, const RealJob* jobs, int64_t njobs, unsigned* queue, int grid,
-                          const Twiddles& tw, hipStream_t s) {
+hipError_t launch_fwd_c64(const float2* x, float2* Y, const RealJob* jobs, int64_t njobs, const unsigned* seg,
+                          unsigned* queue, int grid, const Twiddles& tw, hipStream_t s) {
     if (njobs <= 0) return hipSuccess;
     if (grid < 1) grid = 1;
-    hipLaunchKernelGGL(fwd_c64_kernel, dim3((unsigned)grid), dim3(kCThreads), 0, s, x, Y, jobs, njobs, queue, tw.tile,
+    hipLaunchKernelGGL(fwd_c64_kernel, dim3((unsigned)grid), dim3(kCThreads), 0, s, x, Y, jobs, seg, queue, tw.tile,
                        tw.rows, tw.crows_comb);
     return hipGetLastError();
 }

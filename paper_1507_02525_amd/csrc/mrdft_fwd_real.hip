@@ -19,6 +19,8 @@ union FwdRealLds {
 static_assert(sizeof(FwdRealLds) <= 40 * 1024, "four workgroups per CU");
 static_assert(kRThreads == kRowsThreads, "one block size for both job kinds");
 
+constexpr int kModeStore = 0, kModeNorms = 1, kModeScaled = 2;
+
 // Sum of v over the 64 lanes of a wave (all lanes receive it).
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -26,14 +28,14 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// RED = false: the level spectra are stored to Y; with `alpha` (spectral-loss
-// gradient) the input is x - xsub and level i of signal b is stored times
-// alpha[b * m + i - 1].  RED = true (spectral loss): the input is x - xsub
-// (xsub may be null) and only the squared magnitudes of every level are
-// summed, into sums[b * m + level - 1]; Y is not touched.  Both need a
-// uniform batch (signal b = in_off / N).
+// MODE kModeStore: the level spectra are stored to Y.  kModeScaled
+// (spectral-loss gradient): the input is x - xsub and level i of signal b is
+// stored times alpha[b * m + i - 1].  kModeNorms (spectral loss): the input is
+// x - xsub (xsub may be null) and only the squared magnitudes of every level
+// are summed, into sums[b * m + level - 1]; Y is not touched.  The last two
+// need a uniform batch (signal b = in_off / N).
 // At least 4 waves per SIMD: 4 workgroups per CU (128 VGPRs).
-template <bool RED>
+template <int MODE>
 __global__ __launch_bounds__(kRThreads, 4) void fwd_real_kernel(const float* __restrict__ x, float2* __restrict__ Y,
                                                                 const RealJob* __restrict__ jobs,
                                                                 const float2* __restrict__ t4096,
@@ -42,31 +44,40 @@ __global__ __launch_bounds__(kRThreads, 4) void fwd_real_kernel(const float* __r
                                                                 const float* __restrict__ xsub,
                                                                 double* __restrict__ sums,
                                                                 const float* __restrict__ alpha, int m) {
+    constexpr bool RED = MODE == kModeNorms;
     __shared__ FwdRealLds S;
     const RealJob jb = jobs[blockIdx.x];
     const int tid = threadIdx.x;
     const float* xj = x + jb.in_off;
-    const float* zj = (RED && xsub) ? xsub + jb.in_off : nullptr;
+    const float* zj = (MODE != kModeStore && xsub) ? xsub + jb.in_off : nullptr;
     float2* yj = RED ? nullptr : Y + jb.out_off;
-    if constexpr (!RED) {
+    if constexpr (MODE == kModeStore) {
         StoreOut out;
-        const float* za = nullptr;
-        float sc = 1.0f;
-        if (alpha) {
-            out.alpha = alpha + (jb.in_off / jb.level_stride) * m;
-            za = xsub ? xsub + jb.in_off : nullptr;
-            if (jb.lg > 0) sc = out.alpha[jb.lg - 1];
-        }
         switch (jb.lg) {
-            case 0: real_tile_body(S.tile, xj, za, yj, jb.level_stride, t4096, tid, out); break;
-            case 13: rows_real_body<5, false>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(13),
-                                              comb + rows_combine_offset(13), tid, za, nullptr, sc); break;
-            case 14: rows_real_body<6, false>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(14),
-                                              comb + rows_combine_offset(14), tid, za, nullptr, sc); break;
-            case 15: rows_real_body<7, false>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(15),
-                                              comb + rows_combine_offset(15), tid, za, nullptr, sc); break;
-            case 16: rows_real_body<8, false>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(16),
-                                              comb + rows_combine_offset(16), tid, za, nullptr, sc); break;
+            case 0: real_tile_body(S.tile, xj, nullptr, yj, jb.level_stride, t4096, tid, out); break;
+            case 13: rows_real_body<5>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(13),
+                                       comb + rows_combine_offset(13), tid); break;
+            case 14: rows_real_body<6>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(14),
+                                       comb + rows_combine_offset(14), tid); break;
+            case 15: rows_real_body<7>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(15),
+                                       comb + rows_combine_offset(15), tid); break;
+            case 16: rows_real_body<8>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(16),
+                                       comb + rows_combine_offset(16), tid); break;
+            default: break;
+        }
+    } else if constexpr (MODE == kModeScaled) {
+        const ScaledOut out{alpha + (jb.in_off / jb.level_stride) * m};
+        const float sc = jb.lg > 0 ? out.alpha[jb.lg - 1] : 1.0f;
+        switch (jb.lg) {
+            case 0: real_tile_body(S.tile, xj, zj, yj, jb.level_stride, t4096, tid, out); break;
+            case 13: rows_real_body<5>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(13),
+                                       comb + rows_combine_offset(13), tid, zj, nullptr, sc); break;
+            case 14: rows_real_body<6>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(14),
+                                       comb + rows_combine_offset(14), tid, zj, nullptr, sc); break;
+            case 15: rows_real_body<7>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(15),
+                                       comb + rows_combine_offset(15), tid, zj, nullptr, sc); break;
+            case 16: rows_real_body<8>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(16),
+                                       comb + rows_combine_offset(16), tid, zj, nullptr, sc); break;
             default: break;
         }
     } else {
@@ -100,7 +111,7 @@ __global__ __launch_bounds__(kRThreads, 4) void fwd_real_kernel(const float* __r
 hipError_t launch_fwd_real(const float* x, float2* Y, const RealJob* jobs, int64_t njobs, const Twiddles& tw,
                            hipStream_t s) {
     if (njobs <= 0) return hipSuccess;
-    hipLaunchKernelGGL(fwd_real_kernel<false>, dim3((unsigned)njobs), dim3(kRThreads), 0, s, x, Y, jobs, tw.tile,
+    hipLaunchKernelGGL(fwd_real_kernel<kModeStore>, dim3((unsigned)njobs), dim3(kRThreads), 0, s, x, Y, jobs, tw.tile,
                        tw.rows, tw.rows_comb, nullptr, nullptr, nullptr, 0);
     return hipGetLastError();
 }
@@ -108,7 +119,7 @@ hipError_t launch_fwd_real(const float* x, float2* Y, const RealJob* jobs, int64
 hipError_t launch_fwd_real_scaled(const float* x, const float* xsub, const float* alpha, int m, float2* Y,
                                   const RealJob* jobs, int64_t njobs, const Twiddles& tw, hipStream_t s) {
     if (njobs <= 0) return hipSuccess;
-    hipLaunchKernelGGL(fwd_real_kernel<false>, dim3((unsigned)njobs), dim3(kRThreads), 0, s, x, Y, jobs, tw.tile,
+    hipLaunchKernelGGL(fwd_real_kernel<kModeScaled>, dim3((unsigned)njobs), dim3(kRThreads), 0, s, x, Y, jobs, tw.tile,
                        tw.rows, tw.rows_comb, xsub, nullptr, alpha, m);
     return hipGetLastError();
 }
@@ -116,7 +127,7 @@ hipError_t launch_fwd_real_scaled(const float* x, const float* xsub, const float
 hipError_t launch_fwd_real_norms(const float* x, const float* xsub, double* sums, int m, const RealJob* jobs,
                                  int64_t njobs, const Twiddles& tw, hipStream_t s) {
     if (njobs <= 0) return hipSuccess;
-    hipLaunchKernelGGL(fwd_real_kernel<true>, dim3((unsigned)njobs), dim3(kRThreads), 0, s, x, nullptr, jobs,
+    hipLaunchKernelGGL(fwd_real_kernel<kModeNorms>, dim3((unsigned)njobs), dim3(kRThreads), 0, s, x, nullptr, jobs,
                        tw.tile, tw.rows, tw.rows_comb, xsub, sums, nullptr, m);
     return hipGetLastError();
 }

@@ -67,9 +67,12 @@ hipError_t launch_fwd_real_norms(const float* x, const float* xsub, double* sums
                                  int64_t njobs, const Twiddles& tw, hipStream_t s);
 // Complex input: 2048-sample tiles (lg = 0, levels 1..11) and pieces of levels
 // 12..16 (mrdft_fwd_c64.hip).  Persistent: `grid` workgroups take jobs from
-// queue[0] until the table is exhausted; the last workgroup out clears
-// queue[0..1] for the next launch (the plan zeroes them once at creation).
+// the table's 8 per-XCD segments [seg[q], seg[q+1]) through the counters
+// queue[0..7] until every segment is exhausted; the last workgroup out
+// (counted in queue[8]) clears queue[0..8] for the next launch (the plan
+// zeroes them once at creation).
 constexpr int kC64TileLog = 11;
+constexpr int kC64Queues = 9;
 // Adjoint (mrdft_adj.hip).  Launch (a): RealJob with in_off = gY offset (the
 // tile's level-1 gradient, or the window's gradient at its level), out_off =
 // gx offset of the tile or scratch offset of the window's block, lg = 0 for a
@@ -85,8 +88,8 @@ hipError_t launch_adj_a(bool real_out, const float2* gY, void* gx, float2* scrat
                         const Twiddles& tw, hipStream_t s);
 hipError_t launch_adj_b(bool real_out, void* gx, const float2* scratch, const AdjColJob* jobs, int64_t njobs,
                         const Twiddles& tw, hipStream_t s);
-hipError_t launch_fwd_c64(const float2* x, float2* Y, const RealJob* jobs, int64_t njobs, unsigned* queue, int grid,
-                          const Twiddles& tw, hipStream_t s);
+hipError_t launch_fwd_c64(const float2* x, float2* Y, const RealJob* jobs, int64_t njobs, const unsigned* seg,
+                          unsigned* queue, int grid, const Twiddles& tw, hipStream_t s);
 hipError_t launch_tile_fwd(bool real_in, const void* x, float2* Y, const TileJob* jobs, int64_t njobs,
                            const Twiddles& tw, hipStream_t s);
 // Real input, 4096-sample tiles (levels 1..12): see mrdft_tile_real.h.

@@ -12,7 +12,9 @@
 // touches 16 consecutive complex64 values (128 bytes); the first pass radix is
 // at least 16 so later passes keep that property.  Twiddles of large windows
 // come from two FP64 tables (coarse and fine exponent), multiplied in FP64 and
-// rounded once.  With INV the conjugate kernel is used (adjoint), and the last
+// rounded once: a thread looks up w^{j s0} and w^{16 j} for its column j and
+// first row s0 and forms its further rows s0 + 16 i by FP64 multiplication
+// (no scattered table reads per element).  With INV the conjugate kernel is used (adjoint), and the last
 // pass can accumulate into the gradient instead of storing.
 #include "mrdft_internal.h"
 #include "mrdft_lds_fft.h"
@@ -21,16 +23,23 @@ namespace mrdft {
 
 constexpr int kColStride(int r) { return r + 1; }   // LDS padding against bank conflicts
 
+// w_{2^lg}^e (lg <= 8) from a table of w_256 in LDS.
+struct TwLds256 {
+    const float2* t;
+    __device__ __forceinline__ float2 operator()(int lg, int e) const { return t[(e << (8 - lg)) & 255]; }
+};
+
 template <bool INV>
-__device__ __forceinline__ void column_fft(float2* B, int rl, const float2* __restrict__ tab, int tid) {
+__device__ __forceinline__ void column_fft(float2* B, int rl, const float2* T, int tid) {
     const int fst = kColStride(1 << rl);
     int lgNs = 0;
     const int rem = rl & 3;
-    if (rem == 1) { lds_step<2, 1, INV>(B, rl, 0, fst, 1, kPassCols, TwGlobal{tab}, tid, kPassThreads); lgNs = 1; }
-    else if (rem == 2) { lds_step<4, 1, INV>(B, rl, 0, fst, 1, kPassCols, TwGlobal{tab}, tid, kPassThreads); lgNs = 2; }
-    else if (rem == 3) { lds_step<8, 1, INV>(B, rl, 0, fst, 1, kPassCols, TwGlobal{tab}, tid, kPassThreads); lgNs = 3; }
+    const TwLds256 tw{T};
+    if (rem == 1) { lds_step<2, 1, INV>(B, rl, 0, fst, 1, kPassCols, tw, tid, kPassThreads); lgNs = 1; }
+    else if (rem == 2) { lds_step<4, 1, INV>(B, rl, 0, fst, 1, kPassCols, tw, tid, kPassThreads); lgNs = 2; }
+    else if (rem == 3) { lds_step<8, 1, INV>(B, rl, 0, fst, 1, kPassCols, tw, tid, kPassThreads); lgNs = 3; }
     while (lgNs < rl) {
-        lds_step<16, 1, INV>(B, rl, lgNs, fst, 1, kPassCols, TwGlobal{tab}, tid, kPassThreads);
+        lds_step<16, 1, INV>(B, rl, lgNs, fst, 1, kPassCols, tw, tid, kPassThreads);
         lgNs += 4;
     }
 }
@@ -41,6 +50,7 @@ __global__ __launch_bounds__(kPassThreads) void pass_kernel(const void* __restri
                                                             const double2* __restrict__ hi,
                                                             const double2* __restrict__ lo) {
     __shared__ float2 B[kPassCols * ((1 << kPassMaxLog) + 1)];
+    __shared__ float2 T[256];                          // w_256^e for the column FFT steps
     const int rl = g.r_log;
     const int r = 1 << rl;
     const int fst = kColStride(r);
@@ -57,22 +67,33 @@ __global__ __launch_bounds__(kPassThreads) void pass_kernel(const void* __restri
     const int ns_log = g.ns_log;
     const int64_t nsm = ((int64_t)1 << ns_log) - 1;
     const int nval = r * kPassCols;
+    T[tid] = tab[tid << (kTileMaxLog - 8)];
 
-    for (int e = tid; e < nval; e += kPassThreads) {
-        const int jj = e & (kPassCols - 1), s = e >> 4;
+    {
+        // thread: column jj = tid & 15, rows s = s0 + 16 i (s0 = tid >> 4)
+        const int jj = tid & (kPassCols - 1), s0 = tid >> 4;
         const int64_t j = j0 + jj;
-        const int64_t idx = ib + j + (int64_t)s * cols;
-        float2 v;
-        if constexpr (IN_KIND == IN_R32) v = make_float2(((const float*)in)[idx], 0.0f);
-        else v = ((const float2*)in)[idx];
-        if (ns_log > 0 && s > 0) {
-            const float2 w = tw_big(hi, lo, ns_log + rl, (j & nsm) * s);
-            v = INV ? cmulc(v, w) : cmul(v, w);
+        const int tlg = ns_log + rl;
+        double2 w = make_double2(1.0, 0.0), step = make_double2(1.0, 0.0);
+        if (ns_log > 0) {
+            w = tw_big64(hi, lo, tlg, (j & nsm) * s0);
+            step = tw_big64(hi, lo, tlg, (j & nsm) * kPassCols);
         }
-        B[jj * fst + s] = v;
+        for (int s = s0; s < r; s += kPassCols) {
+            const int64_t idx = ib + j + (int64_t)s * cols;
+            float2 v;
+            if constexpr (IN_KIND == IN_R32) v = make_float2(((const float*)in)[idx], 0.0f);
+            else v = ((const float2*)in)[idx];
+            if (ns_log > 0) {
+                const float2 wf = make_float2((float)w.x, (float)w.y);
+                v = INV ? cmulc(v, wf) : cmul(v, wf);
+                w = make_double2(w.x * step.x - w.y * step.y, w.x * step.y + w.y * step.x);
+            }
+            B[jj * fst + s] = v;
+        }
     }
     __syncthreads();
-    column_fft<INV>(B, rl, tab, tid);
+    column_fft<INV>(B, rl, T, tid);
 
     for (int e = tid; e < nval; e += kPassThreads) {
         int jj, s;

@@ -51,9 +51,13 @@ __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2
 // squared magnitudes summed per level in FP64, Y never written.
 struct StoreOut {
     static constexpr bool kReduce = false;
-    const float* alpha = nullptr;                  // per-level factors (spectral-loss gradient), or none
+    __device__ __forceinline__ float2 sc(int, float2 v) const { return v; }
+};
+// Stored times a per-level factor (spectral-loss gradient).
+struct ScaledOut {
+    static constexpr bool kReduce = false;
+    const float* alpha;
     __device__ __forceinline__ float2 sc(int level, float2 v) const {
-        if (!alpha) return v;
         const float a = alpha[level - 1];
         return make_float2(a * v.x, a * v.y);
     }
