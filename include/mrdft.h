@@ -92,6 +92,20 @@ mrdft_status mrdft_plan_create(mrdft_plan_t* plan, int m, int64_t batch, const i
                                mrdft_dtype dtype, unsigned flags, hipStream_t stream);
 
 /*
+ * Same, keeping only the levels lo..hi (1 <= lo <= hi <= MRDFT_MAX_ORDER):
+ * signal j stores its levels lo..min(hi, m_j), level i at O_j + (i - lo) N_j
+ * with O_j = sum_{j' < j} max(0, min(hi, m_j') - lo + 1) N_j' (a signal with
+ * m_j < lo stores nothing).  Output bytes shrink in proportion; the levels
+ * above hi inside a tile are not computed, the ones below lo only as far as
+ * the recurrence needs them.  The adjoint takes gY in the same layout (the
+ * missing levels' gradients are zero).  Uniform batches need lo <= m.  The
+ * spectral loss needs the full range.
+ * Errors: as mrdft_plan_create, and MRDFT_E_INVALID_ARG for a bad range.
+ */
+mrdft_status mrdft_plan_create_levels(mrdft_plan_t* plan, int m, int64_t batch, const int64_t* offsets,
+                                      mrdft_dtype dtype, unsigned flags, int lo, int hi, hipStream_t stream);
+
+/*
  * Output offsets of a plan, in complex elements: host int64[batch+1],
  * out[j] = O_j (start of signal j's levels in Y), out[batch] = total outputs.
  */

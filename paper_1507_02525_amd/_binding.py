@@ -33,6 +33,8 @@ _i64p = ctypes.POINTER(ctypes.c_int64)
 SIGNATURES = {
     "mrdft_plan_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, _i64, _i64p, ctypes.c_int,
                                          ctypes.c_uint, _vp]),
+    "mrdft_plan_create_levels": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, _i64, _i64p, ctypes.c_int,
+                                                ctypes.c_uint, ctypes.c_int, ctypes.c_int, _vp]),
     "mrdft_plan_output_offsets": (ctypes.c_int, [_vp, _i64p]),
     "mrdft_plan_sizes": (ctypes.c_int, [_vp, _i64p, _i64p]),
     "mrdft_plan_schedule": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),

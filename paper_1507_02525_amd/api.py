@@ -36,11 +36,12 @@ class Plan:
     Uniform batch: ``Plan(m=m, batch=B, dtype="c64"|"r32")``.
     Ragged batch:  ``Plan(offsets=int64 array [batch+1], dtype=...)``.
     ``tune=True`` times the candidate schedules at creation; ``graph=True``
-    replays mrdft_forward from a captured HIP graph.
+    replays mrdft_forward from a captured HIP graph; ``levels=(lo, hi)`` keeps
+    only those levels (compact output, see mrdft_plan_create_levels).
     """
 
     def __init__(self, m: int = 0, batch: int = 1, offsets=None, dtype: str = "c64", device=None,
-                 tune: bool = False, graph: bool = False):
+                 tune: bool = False, graph: bool = False, levels=None):
         lib = B.lib()
         self.dtype = dtype
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
@@ -58,7 +59,10 @@ class Plan:
         with torch.cuda.device(self.device):
             stream = ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
             flags = (B.MRDFT_FLAG_TUNE if tune else 0) | (B.MRDFT_FLAG_GRAPH if graph else 0)
-            B.check(lib.mrdft_plan_create(ctypes.byref(h), int(m), int(batch), offp, code, flags, stream))
+            lo, hi = (1, B.MRDFT_MAX_ORDER) if levels is None else (int(levels[0]), int(levels[1]))
+            B.check(lib.mrdft_plan_create_levels(ctypes.byref(h), int(m), int(batch), offp, code, flags, lo, hi,
+                                                 stream))
+        self.levels = (lo, hi)
         self.handle = h
         self.m = int(m)
         self.batch = int(batch)
@@ -140,7 +144,8 @@ class Plan:
         Y = torch.empty(self.n_out, dtype=torch.complex64, device=self.device)
         self.mrdft_forward(x.contiguous(), Y)
         if not self.ragged:
-            Y = Y.view(self.batch, self.m, 1 << self.m)
+            kept = min(self.levels[1], self.m) - self.levels[0] + 1
+            Y = Y.view(self.batch, kept, 1 << self.m)
         return Y
 
     def adjoint(self, gY: torch.Tensor) -> torch.Tensor:

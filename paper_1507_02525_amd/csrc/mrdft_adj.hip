@@ -32,7 +32,7 @@ __global__ __launch_bounds__(kCThreads, 4) void adj_a_kernel(const float2* __res
     switch (jb.lg) {
         case 0: {
             void* gxj = REAL ? (void*)((float*)gx + jb.out_off) : (void*)((float2*)gx + jb.out_off);
-            adj_tile_body<REAL>(S.tile, gyj, gxj, jb.level_stride, t4096, tid);
+            adj_tile_body<REAL>(S.tile, gyj, gxj, jb.level_stride, t4096, tid, LevelRange::unpack(jb.g));
             break;
         }
         case 12: adj_rows_body<4>(S.rows, gyj, scratch + jb.out_off, jb.g, t4096, rowtw + rows_twiddle_offset(12), tid); break;
@@ -59,9 +59,12 @@ __global__ __launch_bounds__(kRowsThreads, 4) void adj_b_kernel(void* __restrict
         if constexpr (REAL) acc[s] = 0.0f;
         else acc[s] = make_float2(0.0f, 0.0f);
     }
-    const int c0 = 16 * jb.c;
-    const int top = jb.region_log < kRowsMaxLevel ? jb.region_log : kRowsMaxLevel;
-    for (int lg = kCRowsMinLevel; lg <= top; ++lg) {
+    const int c0 = 16 * (jb.c & 15);
+    const LevelRange lv = LevelRange::unpack(jb.c >> 8);
+    int top = jb.region_log < kRowsMaxLevel ? jb.region_log : kRowsMaxLevel;
+    if (top > lv.hi) top = lv.hi;
+    const int first = lv.lo > kCRowsMinLevel ? lv.lo : kCRowsMinLevel;
+    for (int lg = first; lg <= top; ++lg) {
         const float2* scr = scratch + jb.scr_off + (int64_t)(lg - kCRowsMinLevel) * jb.level_stride;
         // a fresh copy of the thread index per level: nothing derived from it is
         // hoisted out of this loop (five inlined bodies would spill)

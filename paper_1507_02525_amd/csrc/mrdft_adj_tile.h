@@ -14,6 +14,7 @@
 // threads; 28 KB of LDS (real gx) or 36 KB (complex gx).
 #pragma once
 #include "mrdft_device.h"
+#include "mrdft_internal.h"
 #include "mrdft_tile_c64.h"
 
 namespace mrdft {
@@ -84,7 +85,7 @@ __device__ __forceinline__ void adj_acc(AdjTileLds<REAL>& S, int i, float2 v, bo
 // Level I (2 <= I <= 11): P holds G_I on entry and G_{I-1} on exit.
 //   gyl : gY of level I-1 at this tile (level-major, complex64)
 template <int I, bool REAL>
-__device__ __forceinline__ void adj_level(AdjTileLds<REAL>& S, const float2* __restrict__ gyl, int tid) {
+__device__ __forceinline__ void adj_level(AdjTileLds<REAL>& S, const float2* __restrict__ gyl, int tid, bool have) {
     constexpr int L = 1 << I, M = L / 2, LM = I - 1;
     constexpr int PPT = kCT / 2 / kCThreads;            // (w, k) jobs per thread
     constexpr bool FIRST = (I == kCTLog);               // A not yet written
@@ -94,9 +95,10 @@ __device__ __forceinline__ void adj_level(AdjTileLds<REAL>& S, const float2* __r
     for (int c = 0; c < PPT; ++c) {
         const int J = tid + c * kCThreads;               // = w * M + k
         const int w = J / M, k = J % M;
-        // level I-1 gradient inputs of the two children (loaded early)
-        nxt0[c] = gyl[2 * w * M + k];
-        nxt1[c] = gyl[(2 * w + 1) * M + k];
+        // level I-1 gradient inputs of the two children (loaded early; zero
+        // for a level outside the plan's range)
+        nxt0[c] = have ? gyl[2 * w * M + k] : make_float2(0.0f, 0.0f);
+        nxt1[c] = have ? gyl[(2 * w + 1) * M + k] : make_float2(0.0f, 0.0f);
         e[c] = S.P[2 * J];
     }
     float2 d[PPT];
@@ -131,10 +133,10 @@ __device__ __forceinline__ void adj_level(AdjTileLds<REAL>& S, const float2* __r
 template <int I, bool REAL>
 struct AdjLevels {
     static __device__ __forceinline__ void run(AdjTileLds<REAL>& S, const float2* __restrict__ gy, int64_t ls,
-                                               int tid) {
+                                               int tid, LevelRange lv) {
         if constexpr (I >= 2) {
-            adj_level<I, REAL>(S, gy + (int64_t)(I - 2) * ls, tid);
-            AdjLevels<I - 1, REAL>::run(S, gy, ls, tid);
+            adj_level<I, REAL>(S, gy + (int64_t)(I - 2) * ls, tid, lv.in(I - 1));
+            AdjLevels<I - 1, REAL>::run(S, gy, ls, tid, lv);
         }
     }
 };
@@ -144,18 +146,19 @@ struct AdjLevels {
 // overwritten.
 template <bool REAL>
 __device__ __forceinline__ void adj_tile_body(AdjTileLds<REAL>& S, const float2* __restrict__ gy, void* __restrict__ gx,
-                                              int64_t ls, const float2* __restrict__ t4096, int tid) {
+                                              int64_t ls, const float2* __restrict__ t4096, int tid, LevelRange lv) {
     for (int e = tid; e < kCT / 4; e += kCThreads) S.Q[cqswz(e)] = t4096[2 * e];
     {
         const float4* g11 = (const float4*)(gy + (int64_t)(kCTLog - 1) * ls);
+        const bool have = lv.in(kCTLog);
 #pragma unroll
         for (int r = 0; r < kCT / 2 / kCThreads; ++r) {
             const int p = tid + r * kCThreads;
-            *(float4*)(S.P + 2 * p) = g11[p];
+            *(float4*)(S.P + 2 * p) = have ? g11[p] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         }
     }
     __syncthreads();
-    AdjLevels<kCTLog, REAL>::run(S, gy, ls, tid);
+    AdjLevels<kCTLog, REAL>::run(S, gy, ls, tid, lv);
     // level 1: windows of two
 #pragma unroll
     for (int r = 0; r < kCT / 2 / kCThreads; ++r) {

@@ -78,6 +78,13 @@ struct mrdft_plan {
     mrdft_dtype dtype = MRDFT_C64;
     bool ragged = false;
     std::vector<int64_t> in_off, out_off;   // [batch+1]
+    // levels kept: [lo, hi]; signal j stores levels lo..min(hi, m_j) at
+    // out_off[j] + (i - lo) N_j, i.e. at base(j) + (i - 1) N_j
+    int lo = 1, hi = MRDFT_MAX_ORDER;
+    int kept(int order) const { return std::max(0, std::min(hi, order) - lo + 1); }
+    int64_t base(int64_t j) const { return out_off[j] - (int64_t)(lo - 1) * (in_off[j + 1] - in_off[j]); }
+    int32_t range() const { return LevelRange::pack(lo, std::min(hi, 255)); }
+    bool full_range(int order) const { return lo == 1 && hi >= order; }
     std::vector<int> orders;
     int64_t n_in = 0, n_out = 0;
     int max_order = 0;
@@ -314,15 +321,15 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
         for (int64_t tau = 0; tau < N / T; ++tau) {
             TileJob jb;
             jb.in_off = p->in_off[j] + tau * T;
-            jb.out_off = p->out_off[j] + tau * T;
+            jb.out_off = p->base(j) + tau * T;
             jb.level_stride = N;
             jb.t = t;
-            jb.pad = 0;
+            jb.pad = p->range();
             jobs.push_back(jb);
         }
         if (mj > kTileMaxLog) {
             gin[mj].push_back(p->in_off[j]);
-            gout[mj].push_back(p->out_off[j]);
+            gout[mj].push_back(p->base(j));
         }
     }
     // full tiles first: the real-input kernel handles exactly those
@@ -343,7 +350,7 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
         for (int64_t j = 0; j < p->batch; ++j) {
             const int mj = p->orders[j];
             if (mj >= kC64TileLog) continue;
-            small.push_back(TileJob{p->in_off[j], p->out_off[j], int64_t(1) << mj, mj, 0});
+            small.push_back(TileJob{p->in_off[j], p->base(j), int64_t(1) << mj, mj, p->range()});
         }
         p->nsmall = (int64_t)small.size();
         if (!small.empty()) {
@@ -374,24 +381,30 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
             const int mj = p->orders[j];
             const int64_t N = int64_t(1) << mj;
             if (mj < kC64TileLog) {
-                sm.push_back(TileJob{p->in_off[j], p->out_off[j], N, mj, 0});
+                sm.push_back(TileJob{p->in_off[j], p->base(j), N, mj, p->range()});
                 continue;
             }
             for (int64_t tau = 0; tau < (N >> kC64TileLog); ++tau)
-                aj.push_back(RealJob{p->out_off[j] + (tau << kC64TileLog), p->in_off[j] + (tau << kC64TileLog), N, 0, 0});
+                aj.push_back(RealJob{p->base(j) + (tau << kC64TileLog), p->in_off[j] + (tau << kC64TileLog), N, 0,
+                                     p->range()});
             const int top = std::min(mj, kRowsMaxLevel);
+            bool any_upper = false;
             for (int lg = kCRowsMinLevel; lg <= top; ++lg) {
+                if (lg < p->lo || lg > p->hi) continue;
+                any_upper = true;
                 const int64_t L = int64_t(1) << lg;
                 for (int64_t w = 0; w < N / L; ++w)
                     for (int g = 0; g < (1 << (lg - kCRowsMinLevel)); ++g)
-                        aj.push_back(RealJob{p->out_off[j] + (int64_t)(lg - 1) * N + w * L,
+                        aj.push_back(RealJob{p->base(j) + (int64_t)(lg - 1) * N + w * L,
                                              scr + (int64_t)(lg - kCRowsMinLevel) * N + w * L, 0, lg, g});
             }
             if (top >= kCRowsMinLevel) {
                 const int64_t region = int64_t(1) << top;
-                for (int64_t r = 0; r < N / region; ++r)
-                    for (int c = 0; c < 16; ++c)
-                        cj.push_back(AdjColJob{p->in_off[j] + r * region, scr + r * region, N, top, kColOrder[c]});
+                if (any_upper)
+                    for (int64_t r = 0; r < N / region; ++r)
+                        for (int c = 0; c < 16; ++c)
+                            cj.push_back(AdjColJob{p->in_off[j] + r * region, scr + r * region, N, top,
+                                                   kColOrder[c] | (p->range() << 8)});
                 scr += (int64_t)(top - kCRowsMinLevel + 1) * N;
             }
         }
@@ -539,12 +552,13 @@ std::vector<RealJob> real_jobs(const mrdft_plan* p, int order) {
         if (mj < kRealTileLog) continue;
         const int64_t N = int64_t(1) << mj;
         for (int64_t tau = 0; tau < (N >> kRealTileLog); ++tau)
-            jb.add_tile(RealJob{p->in_off[j] + (tau << kRealTileLog), p->out_off[j] + (tau << kRealTileLog), N, 0, 0},
+            jb.add_tile(RealJob{p->in_off[j] + (tau << kRealTileLog), p->base(j) + (tau << kRealTileLog), N, 0,
+                                p->range()},
                         6);                                    // 12 x 32 KB against 64 KB per piece
-        for (int lg = kRowsMinLevel; lg <= std::min(mj, kRowsMaxLevel); ++lg) {
+        for (int lg = std::max(kRowsMinLevel, p->lo); lg <= std::min({mj, kRowsMaxLevel, p->hi}); ++lg) {
             const int64_t L = int64_t(1) << lg;
             for (int64_t w = 0; w < N / L; ++w)
-                jb.add_window(RealJob{p->in_off[j] + w * L, p->out_off[j] + (int64_t)(lg - 1) * N + w * L, N, lg, 0},
+                jb.add_window(RealJob{p->in_off[j] + w * L, p->base(j) + (int64_t)(lg - 1) * N + w * L, N, lg, 0},
                               1 << (lg - kRowsMinLevel));
         }
     }
@@ -560,12 +574,13 @@ std::vector<RealJob> complex_jobs(const mrdft_plan* p, int order, std::vector<un
         if (mj < kC64TileLog) continue;
         const int64_t N = int64_t(1) << mj;
         for (int64_t tau = 0; tau < (N >> kC64TileLog); ++tau)
-            jb.add_tile(RealJob{p->in_off[j] + (tau << kC64TileLog), p->out_off[j] + (tau << kC64TileLog), N, 0, 0},
+            jb.add_tile(RealJob{p->in_off[j] + (tau << kC64TileLog), p->base(j) + (tau << kC64TileLog), N, 0,
+                                p->range()},
                         5);                                    // 11 x 16 KB against 32 KB per piece
-        for (int lg = kCRowsMinLevel; lg <= std::min(mj, kRowsMaxLevel); ++lg) {
+        for (int lg = std::max(kCRowsMinLevel, p->lo); lg <= std::min({mj, kRowsMaxLevel, p->hi}); ++lg) {
             const int64_t L = int64_t(1) << lg;
             for (int64_t w = 0; w < N / L; ++w)
-                jb.add_window(RealJob{p->in_off[j] + w * L, p->out_off[j] + (int64_t)(lg - 1) * N + w * L, 0, lg, 0},
+                jb.add_window(RealJob{p->in_off[j] + w * L, p->base(j) + (int64_t)(lg - 1) * N + w * L, 0, lg, 0},
                               1 << (lg - kCRowsMinLevel));
         }
     }
@@ -633,6 +648,12 @@ struct ProfScope {
     }
 };
 
+// Level i of a group launch: ragged signals address it through their base
+// offsets (already shifted by -(lo-1) N), uniform ones as b * kept * N + (i - lo) N.
+float2* level_ptr(const mrdft_plan* p, float2* Y, int i, int64_t N) {
+    return Y + (int64_t)(p->ragged ? i - 1 : i - p->lo) * N;
+}
+
 // Forward transform of all levels of every signal (x of the plan dtype, or an
 // explicit override of kind `in_kind`).
 mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, hipStream_t s0) {
@@ -649,6 +670,7 @@ mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, h
         const int64_t N = int64_t(1) << g.order;
         for (int i = kTileMaxLog + 1; i <= g.order; ++i) {
             if ((real_jobs_cover || cjobs_cover) && i <= kRowsMaxLevel) continue;     // in the one launch
+            if (i < p->lo || i > p->hi) continue;                                      // level not kept
             // single-pass levels spread over the side streams; the multi-pass
             // levels share one scratch buffer and therefore one stream
             const int si = (i <= kUpperMaxLevel) ? (i - kTileMaxLog - 1) : 0;
@@ -663,9 +685,9 @@ mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, h
                 geo.in_sig = g.d_in_sig;
                 geo.in_stride = N;
                 geo.out_sig = g.d_out_sig;
-                geo.out_stride = (int64_t)g.order * N;
+                geo.out_stride = (int64_t)p->kept(g.order) * N;
                 ProfScope ps(p, MRDFT_KERNEL_PASS_FWD, s);
-                HIP_TRY(launch_upper_fwd(in_kind == IN_R32, x, Y + (int64_t)(i - 1) * N, geo, tw, s));
+                HIP_TRY(launch_upper_fwd(in_kind == IN_R32, x, level_ptr(p, Y, i, N), geo, tw, s));
                 continue;
             }
             const std::vector<int> bits = pass_bits(i);
@@ -681,9 +703,9 @@ mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, h
                 geo.in_sig = first ? g.d_in_sig : nullptr;
                 geo.in_stride = N;
                 geo.out_sig = last ? g.d_out_sig : nullptr;
-                geo.out_stride = last ? (int64_t)g.order * N : N;
+                geo.out_stride = last ? (int64_t)p->kept(g.order) * N : N;
                 const void* in = first ? x : (const void*)p->d_s[(q - 1) & 1];
-                void* out = last ? (void*)(Y + (int64_t)(i - 1) * N) : (void*)p->d_s[q & 1];
+                void* out = last ? (void*)level_ptr(p, Y, i, N) : (void*)p->d_s[q & 1];
                 ProfScope ps(p, MRDFT_KERNEL_PASS_FWD, s);
                 HIP_TRY(launch_pass(false, first ? in_kind : IN_C64, OUT_STORE, in, out, geo, tw, s));
                 ns += bits[q];
@@ -743,6 +765,7 @@ mrdft_status run_adjoint(mrdft_plan* p, const float2* gY, void* gx, bool real_ou
     for (const Group& g : p->groups) {
         const int64_t N = int64_t(1) << g.order;
         for (int i = kRowsMaxLevel + 1; i <= g.order; ++i) {
+            if (i < p->lo || i > p->hi) continue;                                      // level not kept
             const std::vector<int> bits = pass_bits(i);
             int ns = 0;
             for (size_t q = 0; q < bits.size(); ++q) {
@@ -754,10 +777,10 @@ mrdft_status run_adjoint(mrdft_plan* p, const float2* gY, void* gx, bool real_ou
                 geo.nwin = g.count * (N >> i);
                 geo.wps = N >> i;
                 geo.in_sig = first ? g.d_out_sig : nullptr;
-                geo.in_stride = first ? (int64_t)g.order * N : N;
+                geo.in_stride = first ? (int64_t)p->kept(g.order) * N : N;
                 geo.out_sig = last ? g.d_in_sig : nullptr;
                 geo.out_stride = N;
-                const void* in = first ? (const void*)(gY + (int64_t)(i - 1) * N) : (const void*)p->d_s[(q - 1) & 1];
+                const void* in = first ? (const void*)level_ptr(p, (float2*)gY, i, N) : (const void*)p->d_s[(q - 1) & 1];
                 void* out = last ? gx : (void*)p->d_s[q & 1];
                 const int ok = last ? (real_out ? OUT_ADD_R32 : OUT_ADD_C64) : OUT_STORE;
                 ProfScope ps(p, MRDFT_KERNEL_PASS_ADJ, s);
@@ -777,6 +800,7 @@ mrdft_status upper_passes(mrdft_plan* p, const float* x, float2* W, hipStream_t 
     const int top = p->m - kRowsMaxLevel;
     for (const Group& g : p->groups) {
         for (int i = kRowsMaxLevel + 1; i <= g.order; ++i) {
+            if (i < p->lo || i > p->hi) continue;                                      // level not kept
             const std::vector<int> bits = pass_bits(i);
             int ns = 0;
             for (size_t q = 0; q < bits.size(); ++q) {
@@ -957,8 +981,18 @@ const char* mrdft_last_error(void) { return g_last_error.c_str(); }
 
 mrdft_status mrdft_plan_create(mrdft_plan_t* plan, int m, int64_t batch, const int64_t* offsets, mrdft_dtype dtype,
                                unsigned flags, hipStream_t stream) {
+    return mrdft_plan_create_levels(plan, m, batch, offsets, dtype, flags, 1, MRDFT_MAX_ORDER, stream);
+}
+
+mrdft_status mrdft_plan_create_levels(mrdft_plan_t* plan, int m, int64_t batch, const int64_t* offsets,
+                                      mrdft_dtype dtype, unsigned flags, int lo, int hi, hipStream_t stream) {
     if (!plan) return fail(MRDFT_E_INVALID_ARG, "plan output pointer is NULL");
     *plan = nullptr;
+    if (lo < 1 || hi < lo || hi > MRDFT_MAX_ORDER)
+        return fail(MRDFT_E_INVALID_ARG, "level range [%d, %d] must satisfy 1 <= lo <= hi <= %d", lo, hi,
+                    MRDFT_MAX_ORDER);
+    if (!offsets && m >= 1 && lo > m)
+        return fail(MRDFT_E_INVALID_ARG, "level range starts at %d above the order %d", lo, m);
     if (batch < 1) return fail(MRDFT_E_INVALID_ARG, "batch must be >= 1 (got %lld)", (long long)batch);
     if (dtype != MRDFT_C64 && dtype != MRDFT_R32) return fail(MRDFT_E_INVALID_ARG, "unknown dtype %d", (int)dtype);
     if (flags & ~(MRDFT_FLAG_TUNE | MRDFT_FLAG_GRAPH)) return fail(MRDFT_E_INVALID_ARG, "unknown flags 0x%x", flags);
@@ -967,6 +1001,8 @@ mrdft_status mrdft_plan_create(mrdft_plan_t* plan, int m, int64_t batch, const i
     p->batch = batch;
     p->dtype = dtype;
     p->flags = flags;
+    p->lo = lo;
+    p->hi = hi;
     p->in_off.resize(batch + 1);
     p->out_off.resize(batch + 1);
     p->orders.resize(batch);
@@ -1002,7 +1038,7 @@ mrdft_status mrdft_plan_create(mrdft_plan_t* plan, int m, int64_t batch, const i
     for (int64_t j = 0; j < batch; ++j) {
         const int64_t N = int64_t(1) << p->orders[j];
         p->in_off[j + 1] = p->in_off[j] + N;
-        p->out_off[j + 1] = p->out_off[j] + (int64_t)p->orders[j] * N;
+        p->out_off[j + 1] = p->out_off[j] + (int64_t)p->kept(p->orders[j]) * N;
         if (p->orders[j] > p->max_order) p->max_order = p->orders[j];
     }
     p->m = offsets ? 0 : m;
@@ -1109,6 +1145,8 @@ mrdft_status mrdft_spectral_loss_fwd(mrdft_plan_t plan, const float* x, const fl
     if (st) return st;
     if (plan->ragged || plan->dtype != MRDFT_R32)
         return fail(MRDFT_E_UNSUPPORTED, "the spectral loss needs a uniform real (MRDFT_R32) plan");
+    if (!plan->full_range(plan->m))
+        return fail(MRDFT_E_UNSUPPORTED, "the spectral loss needs every level (plan created with a level range)");
     if (!x || !z || !num_den || !L) return fail(MRDFT_E_INVALID_ARG, "x, z, num_den and L must be non-NULL");
     if (misaligned(x, 16) || misaligned(z, 16) || misaligned(num_den, 8) || misaligned(L, 4))
         return fail(MRDFT_E_INVALID_ARG, "x or z is not 16-byte aligned");
@@ -1160,6 +1198,8 @@ mrdft_status mrdft_spectral_loss_bwd(mrdft_plan_t plan, const float* x, const fl
     if (st) return st;
     if (plan->ragged || plan->dtype != MRDFT_R32)
         return fail(MRDFT_E_UNSUPPORTED, "the spectral loss needs a uniform real (MRDFT_R32) plan");
+    if (!plan->full_range(plan->m))
+        return fail(MRDFT_E_UNSUPPORTED, "the spectral loss needs every level (plan created with a level range)");
     if (!x || !z || !num_den || !gL || !gx) return fail(MRDFT_E_INVALID_ARG, "null pointer argument");
     if (misaligned(x, 16) || misaligned(z, 16) || misaligned(gx, 16))
         return fail(MRDFT_E_INVALID_ARG, "x, z or gx is not 16-byte aligned");

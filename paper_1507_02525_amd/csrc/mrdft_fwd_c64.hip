@@ -67,7 +67,7 @@ __global__ __launch_bounds__(kCThreads, 4) void fwd_c64_kernel(const float2* __r
         int t;
         asm volatile("v_mov_b32 %0, %1" : "=v"(t) : "v"(tid));
         switch (jb.lg) {
-            case 0: c64_tile_body(S.tile, xj, yj, jb.level_stride, t4096, t); break;
+            case 0: c64_tile_body(S.tile, xj, yj, jb.level_stride, t4096, t, LevelRange::unpack(jb.g)); break;
             case 12: rows_c64_body<4>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(12),
                                       comb + crows_combine_offset(12), t); break;
             case 13: rows_c64_body<5>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(13),

@@ -52,7 +52,7 @@ __global__ __launch_bounds__(kRThreads, 4) void fwd_real_kernel(const float* __r
     const float* zj = (MODE != kModeStore && xsub) ? xsub + jb.in_off : nullptr;
     float2* yj = RED ? nullptr : Y + jb.out_off;
     if constexpr (MODE == kModeStore) {
-        StoreOut out;
+        StoreOut out{LevelRange::unpack(jb.g)};       // tile jobs carry the plan's level range
         switch (jb.lg) {
             case 0: real_tile_body(S.tile, xj, nullptr, yj, jb.level_stride, t4096, tid, out); break;
             case 13: rows_real_body<5>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(13),

@@ -5,13 +5,22 @@
 
 namespace mrdft {
 
+// Levels kept by a plan: [lo, hi] (1-based).  Outputs of other levels are not
+// stored and their gradients read as zero; packed into one job field.
+struct LevelRange {
+    int lo, hi;
+    __host__ __device__ bool in(int i) const { return i >= lo && i <= hi; }
+    __host__ __device__ static constexpr int32_t pack(int lo, int hi) { return lo | (hi << 8); }
+    __host__ __device__ static LevelRange unpack(int32_t v) { return LevelRange{v & 255, (v >> 8) & 255}; }
+};
+
 // One on-chip tile of 2^t consecutive samples of one signal.
 struct TileJob {
     int64_t in_off;        // element offset of the tile's first sample in x
     int64_t out_off;       // element offset in Y of level 1 at that sample
     int64_t level_stride;  // distance in Y between two levels of this signal (= N)
     int32_t t;             // levels 1..t are computed on chip
-    int32_t pad;
+    int32_t pad;           // LevelRange::pack(lo, hi) of the levels stored
 };
 
 // Geometry of one global Stockham pass over all windows of one level.
@@ -47,7 +56,7 @@ struct RealJob {
     int64_t out_off;       // Y offset of the tile's level-1 output, or of the window's output at its level
     int64_t level_stride;  // tile: distance in Y between two levels (= N); rows piece: unused
     int32_t lg;            // 0: tile of 4096 samples (levels 1..12); 13..16: rows piece of level lg
-    int32_t g;             // rows piece index, 0 <= g < 2^(lg-13)
+    int32_t g;             // rows piece index, 0 <= g < 2^(lg-13); tile: LevelRange::pack of the levels kept
 };
 // Row twiddles w_L^{n1 k2} (n1 < 256, k2 < L/256) of levels 12..16, [k2][n1] per level.
 __host__ __device__ constexpr int64_t rows_twiddle_offset(int lg) {
@@ -82,7 +91,7 @@ struct AdjColJob {
     int64_t scr_off;       // scratch offset of the region in the level-12 block
     int64_t level_stride;  // distance between two levels' scratch blocks (= N)
     int32_t region_log;    // region of 2^region_log samples (12 .. 16)
-    int32_t c;             // columns 16c .. 16c+15
+    int32_t c;             // columns 16 (c & 15) .. +15; c >> 8 = LevelRange::pack of the levels kept
 };
 hipError_t launch_adj_a(bool real_out, const float2* gY, void* gx, float2* scratch, const RealJob* jobs, int64_t njobs,
                         const Twiddles& tw, hipStream_t s);

@@ -39,7 +39,7 @@ __device__ __forceinline__ float2 to_c(float2 v) { return v; }
 // ---------------------------------------------------------------------------
 template <int I, int LC>
 struct LocalFwd {
-    static __device__ __forceinline__ void run(const float2* xv, float2* pv, float2* y, int64_t ls) {
+    static __device__ __forceinline__ void run(const float2* xv, float2* pv, float2* y, int64_t ls, LevelRange lv) {
         if constexpr (I <= LC) {
             constexpr int C = 1 << LC, L = 1 << I, M = L / 2;
             float2 nv[C];
@@ -59,17 +59,19 @@ struct LocalFwd {
             float4* yo = (float4*)(y + (int64_t)(I - 1) * ls);
 #pragma unroll
             for (int e = 0; e < C; ++e) pv[e] = nv[e];
+            if (lv.in(I)) {
 #pragma unroll
-            for (int e = 0; e < C / 2; ++e)
-                yo[e] = make_float4(pv[2 * e].x, pv[2 * e].y, pv[2 * e + 1].x, pv[2 * e + 1].y);
-            LocalFwd<I + 1, LC>::run(xv, pv, y, ls);
+                for (int e = 0; e < C / 2; ++e)
+                    yo[e] = make_float4(pv[2 * e].x, pv[2 * e].y, pv[2 * e + 1].x, pv[2 * e + 1].y);
+            }
+            LocalFwd<I + 1, LC>::run(xv, pv, y, ls, lv);
         }
     }
 };
 
 template <int LC, bool REAL>
 __device__ __forceinline__ void fwd_local(const typename XType<REAL>::T* __restrict__ xin, float2* y, int64_t ls,
-                                          typename XType<REAL>::T* Xs, float2* Ps, int c0, bool keep) {
+                                          typename XType<REAL>::T* Xs, float2* Ps, int c0, bool keep, LevelRange lv) {
     constexpr int C = 1 << LC;
     float2 xv[C], pv[C];
     if constexpr (REAL) {
@@ -95,10 +97,12 @@ __device__ __forceinline__ void fwd_local(const typename XType<REAL>::T* __restr
         pv[2 * b + 1] = csub(xv[2 * b], xv[2 * b + 1]);
     }
     float4* yo = (float4*)y;
+    if (lv.in(1)) {
 #pragma unroll
-    for (int e = 0; e < C / 2; ++e)
-        yo[e] = make_float4(pv[2 * e].x, pv[2 * e].y, pv[2 * e + 1].x, pv[2 * e + 1].y);
-    LocalFwd<2, LC>::run(xv, pv, y, ls);
+        for (int e = 0; e < C / 2; ++e)
+            yo[e] = make_float4(pv[2 * e].x, pv[2 * e].y, pv[2 * e + 1].x, pv[2 * e + 1].y);
+    }
+    LocalFwd<2, LC>::run(xv, pv, y, ls, lv);
     if (keep) {
 #pragma unroll
         for (int e = 0; e < C; ++e) {
@@ -150,24 +154,26 @@ __global__ __launch_bounds__(kTileThreads) void tile_fwd_kernel(const void* __re
     const XT* xin = (const XT*)x + jb.in_off;
     float2* y = Y + jb.out_off;
     const int64_t ls = jb.level_stride;
+    const LevelRange lv = LevelRange::unpack(jb.pad);
+    const int top = t < lv.hi ? t : lv.hi;            // levels above the range are not computed
 
     const int lc = t < 4 ? t : 4;
-    const bool keep = t > 4;
+    const bool keep = top > 4;
     if (keep) load_quarter(Qs, tab, tid, kTileThreads);
     if (tid < (T >> lc)) {
         const int c0 = tid << lc;
         switch (lc) {
-            case 1: fwd_local<1, REAL>(xin + c0, y + c0, ls, Xs, Ps, c0, keep); break;
-            case 2: fwd_local<2, REAL>(xin + c0, y + c0, ls, Xs, Ps, c0, keep); break;
-            case 3: fwd_local<3, REAL>(xin + c0, y + c0, ls, Xs, Ps, c0, keep); break;
-            default: fwd_local<4, REAL>(xin + c0, y + c0, ls, Xs, Ps, c0, keep); break;
+            case 1: fwd_local<1, REAL>(xin + c0, y + c0, ls, Xs, Ps, c0, keep, lv); break;
+            case 2: fwd_local<2, REAL>(xin + c0, y + c0, ls, Xs, Ps, c0, keep, lv); break;
+            case 3: fwd_local<3, REAL>(xin + c0, y + c0, ls, Xs, Ps, c0, keep, lv); break;
+            default: fwd_local<4, REAL>(xin + c0, y + c0, ls, Xs, Ps, c0, keep, lv); break;
         }
     }
     if (!keep) return;
     const TwQuarter tw{Qs};
     __syncthreads();
 
-    for (int i = 5; i <= t; ++i) {
+    for (int i = 5; i <= top; ++i) {
         const int lgM = i - 1, M = 1 << lgM, L = 2 * M;
         const int nw = T >> i;
         const int rem = lgM % 3;
@@ -221,10 +227,12 @@ __global__ __launch_bounds__(kTileThreads) void tile_fwd_kernel(const void* __re
             }
         }
         __syncthreads();
-        float4* yo = (float4*)(y + (int64_t)(i - 1) * ls);
-        for (int e = tid; e < T / 2; e += kTileThreads) {
-            const float2 a = Ps[pad(2 * e)], b = Ps[pad(2 * e + 1)];
-            yo[e] = make_float4(a.x, a.y, b.x, b.y);
+        if (lv.in(i)) {
+            float4* yo = (float4*)(y + (int64_t)(i - 1) * ls);
+            for (int e = tid; e < T / 2; e += kTileThreads) {
+                const float2 a = Ps[pad(2 * e)], b = Ps[pad(2 * e + 1)];
+                yo[e] = make_float4(a.x, a.y, b.x, b.y);
+            }
         }
     }
 }
@@ -236,14 +244,16 @@ template <int I>
 struct LocalAdj {
     // G: level-I gradient (natural order) for a chunk of C values; gx accumulates.
     template <int C>
-    static __device__ __forceinline__ void run(float2* G, float2* gx, const float2* __restrict__ gy, int64_t ls) {
+    static __device__ __forceinline__ void run(float2* G, float2* gx, const float2* __restrict__ gy, int64_t ls,
+                                               LevelRange lv) {
         if constexpr (I >= 2) {
             constexpr int L = 1 << I, M = L / 2;
             float2 gn[C];
             const float4* gl = (const float4*)(gy + (int64_t)(I - 2) * ls);   // gY^(I-1) chunk
+            const bool have = lv.in(I - 1);                                   // levels outside the range: zero
 #pragma unroll
             for (int e = 0; e < C / 2; ++e) {
-                float4 a = gl[e];
+                const float4 a = have ? gl[e] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
                 gn[2 * e] = make_float2(a.x, a.y);
                 gn[2 * e + 1] = make_float2(a.z, a.w);
             }
@@ -268,7 +278,7 @@ struct LocalAdj {
             }
 #pragma unroll
             for (int e = 0; e < C; ++e) G[e] = gn[e];
-            LocalAdj<I - 1>::template run<C>(G, gx, gy, ls);
+            LocalAdj<I - 1>::template run<C>(G, gx, gy, ls, lv);
         } else {
             // Level 1: transpose of I (x) H_2.
 #pragma unroll
@@ -284,7 +294,8 @@ struct LocalAdj {
 template <int LC, bool REAL>
 __device__ __forceinline__ void adj_local(const float2* __restrict__ gy, int64_t ls, typename XType<REAL>::T* gout,
                                           const float2* Gs /* LDS level-LC gradient or null */,
-                                          const typename XType<REAL>::T* Xs /* LDS partial gx or null */, int c0) {
+                                          const typename XType<REAL>::T* Xs /* LDS partial gx or null */, int c0,
+                                          LevelRange lv) {
     constexpr int C = 1 << LC;
     float2 G[C], gx[C];
     if (Gs) {
@@ -292,9 +303,10 @@ __device__ __forceinline__ void adj_local(const float2* __restrict__ gy, int64_t
         for (int e = 0; e < C; ++e) G[e] = Gs[pad(c0 + e)];
     } else {
         const float4* gl = (const float4*)(gy + (int64_t)(LC - 1) * ls);
+        const bool have = lv.in(LC);
 #pragma unroll
         for (int e = 0; e < C / 2; ++e) {
-            float4 a = gl[e];
+            const float4 a = have ? gl[e] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             G[2 * e] = make_float2(a.x, a.y);
             G[2 * e + 1] = make_float2(a.z, a.w);
         }
@@ -304,7 +316,7 @@ __device__ __forceinline__ void adj_local(const float2* __restrict__ gy, int64_t
         if (Xs) gx[e] = to_c(Xs[pad(c0 + e)]);
         else gx[e] = make_float2(0.0f, 0.0f);
     }
-    LocalAdj<LC>::template run<C>(G, gx, gy, ls);
+    LocalAdj<LC>::template run<C>(G, gx, gy, ls, lv);
     if constexpr (REAL) {
 #pragma unroll
         for (int e = 0; e < C / 2; ++e) ((float2*)gout)[e] = make_float2(gx[2 * e].x, gx[2 * e + 1].x);
@@ -351,13 +363,15 @@ __global__ __launch_bounds__(kTileThreads) void tile_adj_kernel(const float2* __
     const float2* gy = gY + jb.out_off;
     XT* gout = (XT*)gx + jb.in_off;
     const int64_t ls = jb.level_stride;
+    const LevelRange lv = LevelRange::unpack(jb.pad);
 
     if (t > 4) {
         const TwQuarter tw{Qs};
         load_quarter(Qs, tab, tid, kTileThreads);
         const float4* g4 = (const float4*)(gy + (int64_t)(t - 1) * ls);
+        const bool have_t = lv.in(t);
         for (int e = tid; e < T / 2; e += kTileThreads) {
-            const float4 a = g4[e];
+            const float4 a = have_t ? g4[e] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             Ps[pad(2 * e)] = make_float2(a.x, a.y);
             Ps[pad(2 * e + 1)] = make_float2(a.z, a.w);
         }
@@ -423,6 +437,8 @@ __global__ __launch_bounds__(kTileThreads) void tile_adj_kernel(const float2* __
             // Push the even-bin gradient to both children (transpose of U^(i)),
             // adding the level i-1 input gradient.
             const float2* gl = gy + (int64_t)(i - 2) * ls;
+            const bool have = lv.in(i - 1);
+            const float2 zero = make_float2(0.0f, 0.0f);
             __syncthreads();
 #pragma unroll
             for (int c = 0; c < 8; ++c) {
@@ -430,8 +446,8 @@ __global__ __launch_bounds__(kTileThreads) void tile_adj_kernel(const float2* __
                 if (e < T / 2) {
                     const int w = e >> lgM, k = e & (M - 1);
                     const int p0 = w * L + k, p1 = p0 + M;
-                    Ps[pad(p0)] = cadd(ge[c], gl[p0]);
-                    Ps[pad(p1)] = cadd(ge[c], gl[p1]);
+                    Ps[pad(p0)] = cadd(ge[c], have ? gl[p0] : zero);
+                    Ps[pad(p1)] = cadd(ge[c], have ? gl[p1] : zero);
                 }
             }
             __syncthreads();
@@ -443,10 +459,10 @@ __global__ __launch_bounds__(kTileThreads) void tile_adj_kernel(const float2* __
         const float2* Gs = (t > 4) ? Ps : nullptr;
         const XT* Xp = (t > 4) ? Xs : nullptr;
         switch (lc) {
-            case 1: adj_local<1, REAL>(gy + c0, ls, gout + c0, Gs, Xp, c0); break;
-            case 2: adj_local<2, REAL>(gy + c0, ls, gout + c0, Gs, Xp, c0); break;
-            case 3: adj_local<3, REAL>(gy + c0, ls, gout + c0, Gs, Xp, c0); break;
-            default: adj_local<4, REAL>(gy + c0, ls, gout + c0, Gs, Xp, c0); break;
+            case 1: adj_local<1, REAL>(gy + c0, ls, gout + c0, Gs, Xp, c0, lv); break;
+            case 2: adj_local<2, REAL>(gy + c0, ls, gout + c0, Gs, Xp, c0, lv); break;
+            case 3: adj_local<3, REAL>(gy + c0, ls, gout + c0, Gs, Xp, c0, lv); break;
+            default: adj_local<4, REAL>(gy + c0, ls, gout + c0, Gs, Xp, c0, lv); break;
         }
     }
 }

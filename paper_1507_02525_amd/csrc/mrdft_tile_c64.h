@@ -14,6 +14,7 @@
 // level spectra.
 #pragma once
 #include "mrdft_device.h"
+#include "mrdft_internal.h"
 #include "mrdft_lds_fft.h"
 
 namespace mrdft {
@@ -107,7 +108,7 @@ struct CtSteps {
 
 // LDS level I (4 <= I <= 11) of the tile; y points at this level's output.
 template <int I>
-__device__ __forceinline__ void ct_level(CTileLds& S, float2* __restrict__ y, int tid) {
+__device__ __forceinline__ void ct_level(CTileLds& S, float2* __restrict__ y, int tid, bool store) {
     constexpr int L = 1 << I, M = L / 2, LM = I - 1;
     constexpr int NW = kCT / L;
     constexpr int PPT = NW * M / kCThreads;              // (w, k) jobs per thread
@@ -164,24 +165,28 @@ __device__ __forceinline__ void ct_level(CTileLds& S, float2* __restrict__ y, in
         const int J = tid + c * kCThreads;          // = w * M + k: the pair (2k, 2k+1) of window w
         const float4 pr = make_float4(u[c].x, u[c].y, d[c].x, d[c].y);
         *(float4*)(S.P + 2 * J) = pr;
-        *(float4*)(y + 2 * J) = pr;
+        if (store) *(float4*)(y + 2 * J) = pr;
     }
     __syncthreads();
 }
 
 template <int I>
 struct CtLevels {
-    static __device__ __forceinline__ void run(CTileLds& S, float2* __restrict__ y, int64_t ls, int tid) {
+    static __device__ __forceinline__ void run(CTileLds& S, float2* __restrict__ y, int64_t ls, int tid,
+                                               LevelRange lv) {
         if constexpr (I <= kCTLog) {
-            ct_level<I>(S, y + (int64_t)(I - 1) * ls, tid);
-            CtLevels<I + 1>::run(S, y, ls, tid);
+            if (I > lv.hi) return;                    // levels above the range are not computed
+            ct_level<I>(S, y + (int64_t)(I - 1) * ls, tid, lv.in(I));
+            CtLevels<I + 1>::run(S, y, ls, tid, lv);
         }
     }
 };
 
 // Writes one register level (8 values per thread, one window each) through
 // the wave's 4 KB of staging (pair e of lane l at 4l + (e ^ (l & 3))).
-__device__ __forceinline__ void ct_stage(const float2* pv, float4* st, float2* __restrict__ yl, int lane) {
+__device__ __forceinline__ void ct_stage(const float2* pv, float4* st, float2* __restrict__ yl, int lane,
+                                         bool store) {
+    if (!store) return;
 #pragma unroll
     for (int e = 0; e < 4; ++e)
         st[4 * lane + (e ^ (lane & 3))] = make_float4(pv[2 * e].x, pv[2 * e].y, pv[2 * e + 1].x, pv[2 * e + 1].y);
@@ -198,7 +203,7 @@ __device__ __forceinline__ void ct_stage(const float2* pv, float4* st, float2* _
 template <int I>
 struct CtLocal {
     static __device__ __forceinline__ void run(const float2* xv, float2* pv, float4* st, float2* y, int64_t ls,
-                                               int lane) {
+                                               int lane, LevelRange lv) {
         if constexpr (I <= 3) {
             constexpr int C = 8, L = 1 << I, M = L / 2;
             float2 nv[C];
@@ -216,8 +221,8 @@ struct CtLocal {
             }
 #pragma unroll
             for (int e = 0; e < C; ++e) pv[e] = nv[e];
-            ct_stage(pv, st, y + (int64_t)(I - 1) * ls, lane);
-            CtLocal<I + 1>::run(xv, pv, st, y, ls, lane);
+            ct_stage(pv, st, y + (int64_t)(I - 1) * ls, lane, lv.in(I));
+            CtLocal<I + 1>::run(xv, pv, st, y, ls, lane, lv);
         }
     }
 };
@@ -225,7 +230,7 @@ struct CtLocal {
 // One tile: x at its first sample, y at its level-1 output (level i at
 // y + (i-1) ls).  Wave v owns samples [512 v, 512 v + 512).
 __device__ __forceinline__ void c64_tile_body(CTileLds& S, const float2* __restrict__ x, float2* __restrict__ y,
-                                              int64_t ls, const float2* __restrict__ t4096, int tid) {
+                                              int64_t ls, const float2* __restrict__ t4096, int tid, LevelRange lv) {
     constexpr int C = 8;
     const int v = tid >> 6, lane = tid & 63;
     for (int e = tid; e < kCT / 4; e += kCThreads) S.Q[cqswz(e)] = t4096[2 * e];   // before any store
@@ -253,14 +258,14 @@ __device__ __forceinline__ void c64_tile_body(CTileLds& S, const float2* __restr
     }
     float4* st = (float4*)S.P + 256 * v;            // the wave's 4 KB of P
     float2* yv = y + 512 * v;
-    ct_stage(pv, st, yv, lane);
-    CtLocal<2>::run(xv, pv, st, yv, ls, lane);
+    ct_stage(pv, st, yv, lane, lv.in(1));
+    CtLocal<2>::run(xv, pv, st, yv, ls, lane, lv);
     // level-3 spectra into P (this wave's own region, after its staging reads)
 #pragma unroll
     for (int e = 0; e < C / 2; ++e)
         *(float4*)(S.P + C * tid + 2 * e) = make_float4(pv[2 * e].x, pv[2 * e].y, pv[2 * e + 1].x, pv[2 * e + 1].y);
     __syncthreads();
-    CtLevels<4>::run(S, y, ls, tid);
+    CtLevels<4>::run(S, y, ls, tid, lv);
 }
 
 }  // namespace mrdft

@@ -51,7 +51,9 @@ __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2
 // squared magnitudes summed per level in FP64, Y never written.
 struct StoreOut {
     static constexpr bool kReduce = false;
+    LevelRange lv;                                 // levels stored
     __device__ __forceinline__ float2 sc(int, float2 v) const { return v; }
+    __device__ __forceinline__ bool keep(int level) const { return lv.in(level); }
 };
 // Stored times a per-level factor (spectral-loss gradient).
 struct ScaledOut {
@@ -61,11 +63,13 @@ struct ScaledOut {
         const float a = alpha[level - 1];
         return make_float2(a * v.x, a * v.y);
     }
+    __device__ __forceinline__ bool keep(int) const { return true; }
 };
 struct NormOut {
     static constexpr bool kReduce = true;
     double* sums;                                   // this signal's per-level sums
     __device__ __forceinline__ float2 sc(int, float2 v) const { return v; }
+    __device__ __forceinline__ bool keep(int) const { return true; }
     // Adds the wave's partial sums of one level (every lane must call it).
     __device__ __forceinline__ void add(int level, float t) {
         double v = (double)t;
@@ -257,7 +261,7 @@ __device__ __forceinline__ void real_level(RealTileLds& S, float2* __restrict__ 
         if constexpr (O::kReduce) {
             nrm += norm2(u0) + norm2(ok[c]) + norm2(uj[c]) + norm2(oj[c]) + norm2(ua) + norm2(oka) + norm2(ub) +
                    norm2(oja);
-        } else {
+        } else if (out.keep(I)) {
             const float2 s0 = out.sc(I, u0), s1 = out.sc(I, ok[c]), s2 = out.sc(I, uj[c]), s3 = out.sc(I, oj[c]);
             const float2 s4 = out.sc(I, ua), s5 = out.sc(I, oka), s6 = out.sc(I, ub), s7 = out.sc(I, oja);
             *(float4*)(yw + 2 * k) = make_float4(s0.x, s0.y, s1.x, s1.y);
@@ -302,6 +306,7 @@ __device__ __forceinline__ void stage_level(const float2* pv, float4* st, float2
         out.add(level, t);
         return;
     }
+    if (!out.keep(level)) return;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
         const float2 a = out.sc(level, pv[2 * e]), b = out.sc(level, pv[2 * e + 1]);

@@ -99,3 +99,12 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(_binding, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError):
         _binding.lib()
+
+
+@pytest.mark.parametrize("lo,hi", [(0, 5), (6, 5), (1, 29), (11, 12)])
+def test_invalid_level_ranges(lo, hi):
+    b = _lib()
+    h = ctypes.c_void_p()
+    st = b.lib().mrdft_plan_create_levels(ctypes.byref(h), 10, 1, None, 0, 0, lo, hi, None)
+    assert st == b.MRDFT_E_INVALID_ARG
+    assert h.value is None

@@ -143,3 +143,63 @@ def test_tuned_plan_matches_oracle():
         ref = oracle.forward(x[offs[j]:offs[j + 1]].astype(np.complex128))
         err = worst_level_err(Yh[oo[j]:oo[j + 1]].reshape(m, 1 << m), ref)
         assert err <= FWD_TOL, (j, m, err)
+
+
+# ---------------------------------------------------------------------------
+# Level-range plans: only levels lo..hi are stored (compact layout).
+
+def _levels_ref(x, lo, hi):
+    ref = oracle.forward(x.astype(np.complex128))
+    m = ref.shape[0]
+    return ref[lo - 1:min(hi, m)]
+
+
+@pytest.mark.parametrize("dtype,orders,lo,hi", [
+    ("r32", [16, 16], 5, 9),            # inside the tile only
+    ("r32", [16, 14, 12, 9], 11, 14),   # tile and rows pieces
+    ("r32", [17, 13], 13, 17),          # pieces and a pass level
+    ("c64", [16, 12, 10], 3, 13),       # complex tile and pieces
+    ("c64", [17, 11, 14], 12, 17),      # pieces and a pass level only
+    ("c64", [8, 13], 1, 4),             # register levels only
+])
+def test_level_range_forward_and_adjoint(dtype, orders, lo, hi):
+    need_gpu()
+    log("levels %s %s [%d, %d]" % (dtype, orders, lo, hi))
+    x, offs = _ragged(orders, 60 + lo, dtype=dtype)
+    plan = api.Plan(offsets=offs, dtype=dtype, levels=(lo, hi))
+    Y = torch.empty(plan.n_out, dtype=torch.complex64, device="cuda")
+    plan.mrdft_forward(to_dev(x), Y)
+    oo = plan.output_offsets()
+    Yh = Y.cpu().numpy()
+    rng = np.random.default_rng(lo * 31 + hi)
+    gys = []
+    for j, m in enumerate(orders):
+        ref = _levels_ref(x[offs[j]:offs[j + 1]], lo, hi)
+        got = Yh[oo[j]:oo[j + 1]].reshape(ref.shape)
+        assert worst_level_err(got, ref) <= FWD_TOL if ref.size else got.size == 0
+        gys.append(workloads.gaussian_complex(rng, ref.shape))
+    # adjoint: gradients of the kept levels only (the others are zero)
+    gy = np.concatenate([g.reshape(-1) for g in gys]).astype(np.complex64)
+    gx = torch.empty(plan.n_in, dtype=torch.complex64 if dtype == "c64" else torch.float32, device="cuda")
+    plan.mrdft_adjoint(to_dev(gy), gx)
+    gxh = gx.cpu().numpy()
+    for j, m in enumerate(orders):
+        full = np.zeros((m, 1 << m), dtype=np.complex128)
+        kept = gys[j]
+        if kept.size:
+            full[lo - 1:lo - 1 + kept.shape[0]] = kept
+        ref = oracle.adjoint(full)
+        if dtype == "r32":
+            ref = ref.real
+        got = gxh[offs[j]:offs[j + 1]]
+        assert np.linalg.norm(got - ref) <= 1e-5 * max(np.linalg.norm(ref), 1e-30), (j, m)
+
+
+def test_level_range_uniform_shape():
+    need_gpu()
+    x = torch.randn(3, 1 << 13, device="cuda")
+    plan = api.Plan(m=13, batch=3, dtype="r32", levels=(4, 20))
+    Y = plan.forward(x)
+    assert Y.shape == (3, 10, 1 << 13)
+    ref = oracle.forward(x[1].cpu().numpy().astype(np.complex128))
+    assert worst_level_err(Y[1].cpu().numpy(), ref[3:]) <= FWD_TOL
