@@ -179,3 +179,56 @@ def spectral_loss_grad(x, z, num_den, gL: float = 1.0, method: int = AUTO) -> np
     _check(_load().mro_spectral_loss_grad(m, _dp(xr), _dp(zr), _dp(nd), float(gL), _dp(gx),
                                           method), "spectral_loss_grad")
     return gx
+
+
+# ---------------------------------------------------------------------------
+# Packed half-spectrum layout of a real signal's levels.  The paper does not
+# treat real input; this is the plain definition of the optional output: a
+# real window's spectrum is Hermitian (Y[L-k] = conj(Y[k])), so window w of a
+# level with L-point windows keeps L/2 values: value 0 = (Re Y[0], Re Y[L/2])
+# packed as one complex number, value k = Y[k] for 0 < k < L/2.
+
+def pack_half(Y) -> np.ndarray:
+    """Full levels (m, N) of a real signal -> packed half spectra (m, N/2)."""
+    Y = _c128(Y)
+    m, n = Y.shape
+    out = np.empty((m, n // 2), dtype=np.complex128)
+    for i in range(1, m + 1):
+        L = 1 << i
+        win = Y[i - 1].reshape(n // L, L)
+        h = out[i - 1].reshape(n // L, L // 2)
+        h[:, 0] = win[:, 0].real + 1j * win[:, L // 2].real
+        h[:, 1:] = win[:, 1:L // 2]
+    return out
+
+
+def unpack_half_zero(gh) -> np.ndarray:
+    """Packed (m, N/2) -> full (m, N): value 0 back to bins 0 and L/2 as real
+    numbers, value k to bin k, every bin above L/2 zero (the transpose of
+    pack_half as a real-linear map)."""
+    gh = _c128(gh)
+    m, h = gh.shape
+    n = 2 * h
+    out = np.zeros((m, n), dtype=np.complex128)
+    for i in range(1, m + 1):
+        L = 1 << i
+        src = gh[i - 1].reshape(n // L, L // 2)
+        dst = out[i - 1].reshape(n // L, L)
+        dst[:, 0] = src[:, 0].real
+        dst[:, L // 2] = src[:, 0].imag
+        dst[:, 1:L // 2] = src[:, 1:]
+    return out
+
+
+def forward_half(x, method: int = AUTO) -> np.ndarray:
+    """Real x (N,) -> packed half spectra of every level, complex128 (m, N/2)."""
+    xr = np.asarray(x)
+    if np.iscomplexobj(xr):
+        raise ValueError("the half-spectrum layout is defined for real signals")
+    return pack_half(forward(xr.astype(np.float64), method))
+
+
+def adjoint_half(gh, method: int = AUTO) -> np.ndarray:
+    """Gradient of a real loss of the packed values with respect to real x:
+    Re(A^H unpack_half_zero(gh)), float64 (N,)."""
+    return adjoint(unpack_half_zero(gh), method).real

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 import torch
 
-# Bars from the benchmark spec: FP32 GPU results vs the FP64 oracle.
+# Parity bars: FP32 GPU results against the FP64 oracle.
 FWD_TOL = 1e-6      # relative L2 per signal and level
 GRAD_TOL = 1e-5     # relative L2 of gradients
 

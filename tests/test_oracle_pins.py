@@ -426,3 +426,66 @@ def test_spectral_loss_terms_follow_parseval():
             assert nd[i - 1, 0] == pytest.approx((2 ** i) * np.sum((x - z) ** 2), rel=1e-12)
             assert nd[i - 1, 1] == pytest.approx((2 ** i) * np.sum(z ** 2), rel=1e-12)
         assert L == pytest.approx(np.sum((x - z) ** 2) / np.sum(z ** 2), rel=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Packed half-spectrum layout of real signals (optional output).
+
+@pytest.mark.parametrize("m", [2, 3, 7, 10])
+def test_half_spectrum_matches_numpy_rfft(m):
+    """For a real window numpy.fft.rfft gives bins 0..L/2 (an independent
+    library routine): value 0 must be (Re bin 0, Re bin L/2), values
+    1..L/2-1 the bins themselves, and bins 0 and L/2 must be real."""
+    rng = np.random.default_rng(100 + m)
+    x = rng.standard_normal(1 << m)
+    h = oracle.forward_half(x)
+    assert h.shape == (m, (1 << m) // 2)
+    for i in range(1, m + 1):
+        L = 1 << i
+        r = np.fft.rfft(x.reshape(-1, L), axis=1)
+        blk = h[i - 1].reshape(-1, L // 2)
+        assert np.max(np.abs(blk[:, 0].real - r[:, 0].real)) < 1e-11
+        assert np.max(np.abs(blk[:, 0].imag - r[:, L // 2].real)) < 1e-11
+        assert np.max(np.abs(r[:, 0].imag)) < 1e-11 and np.max(np.abs(r[:, L // 2].imag)) < 1e-11
+        if L > 2:
+            assert np.max(np.abs(blk[:, 1:] - r[:, 1:L // 2])) < 1e-10
+
+
+def test_half_spectrum_closed_forms():
+    """Level 1 packs (x0 + x1, x0 - x1); a constant c packs (c L, 0) into
+    value 0 of every window and zeros elsewhere; an alternating signal packs
+    (0, L) (all of it at the Nyquist bin)."""
+    x = np.array([3.0, -1.0, 2.0, 5.0])
+    h = oracle.forward_half(x)
+    assert np.allclose(h[0], [2.0 + 4.0j, 7.0 - 3.0j])
+    m = 6
+    c = np.full(1 << m, 1.5)
+    alt = np.array([(-1.0) ** n for n in range(1 << m)])
+    hc, ha = oracle.forward_half(c), oracle.forward_half(alt)
+    for i in range(1, m + 1):
+        L = 1 << i
+        bc, ba = hc[i - 1].reshape(-1, L // 2), ha[i - 1].reshape(-1, L // 2)
+        assert np.allclose(bc[:, 0], 1.5 * L) and np.allclose(bc[:, 1:], 0.0, atol=1e-12)
+        assert np.allclose(ba[:, 0], 1j * L) and np.allclose(ba[:, 1:], 0.0, atol=1e-12)
+
+
+@pytest.mark.parametrize("m", [2, 5, 9])
+def test_half_adjoint_identity(m):
+    """The half-spectrum output is real-linear in real x, so its adjoint G
+    must satisfy Re<h(x), g> = <x, G g> for every real x and complex g (the
+    gradient of the real loss Re<h(x), g>).  A missing factor, a value sent to
+    the wrong bin or a dropped Nyquist term breaks it."""
+    rng = np.random.default_rng(200 + m)
+    n = 1 << m
+    x = rng.standard_normal(n)
+    g = rng.standard_normal((m, n // 2)) + 1j * rng.standard_normal((m, n // 2))
+    lhs = np.real(np.vdot(g.reshape(-1), oracle.forward_half(x).reshape(-1)))
+    rhs = float(np.dot(x, oracle.adjoint_half(g)))
+    assert abs(lhs - rhs) < 1e-10 * max(1.0, abs(lhs))
+    # and by brute force on the basis vectors for the smallest case
+    if m == 2:
+        for p in range(n):
+            e = np.zeros(n)
+            e[p] = 1.0
+            assert oracle.adjoint_half(g)[p] == pytest.approx(
+                np.real(np.vdot(g.reshape(-1), oracle.forward_half(e).reshape(-1))), abs=1e-12)
