@@ -106,8 +106,9 @@ def measured_traffic(kind):
 def extra_workloads(steps, warmup, HBM):
     """Workloads beside the headline: one long complex signal (N = 2^24) and a
     ragged batch of 1000 complex signals (m in 8..18) through a tuned plan with
-    graph replay (forward only), and the spectral loss forward + backward on
-    32 real pairs of 2^18 samples.  Inputs resident in HBM."""
+    graph replay (forward only), the real batch with packed half-spectrum
+    output, and the spectral loss forward + backward on 32 real pairs of 2^18
+    samples.  Inputs resident in HBM."""
     import numpy as np
     import torch
     from paper_1507_02525_amd import api, workloads
@@ -134,6 +135,22 @@ def extra_workloads(steps, warmup, HBM):
                                  "schedule": plan.schedule()}
         del Y, x, plan
         torch.cuda.empty_cache()
+    # the real batch with packed half-spectrum output (half the output bytes)
+    d = workloads.make(2)
+    x = torch.from_numpy(d["x"]).cuda().view(-1)
+    plan = api.Plan(m=d["m"], batch=d["batch"], dtype="r32", half=True)
+    Y = torch.empty(plan.n_out, dtype=torch.complex64, device="cuda")
+    fn = lambda: plan.mrdft_forward(x, Y)   # noqa: E731
+    for _ in range(warmup):
+        fn()
+    ms = timed(fn, steps, torch.cuda.synchronize)
+    byts = int(plan.n_in) * 4 + plan.n_out * 8
+    out["workload2_half"] = {"workload": "64 real float32 signals, N=2^16 (m=16), packed half-spectrum output",
+                             "ms_per_call": round(ms, 4),
+                             "Gsamples_per_s": round(plan.n_in / (ms * 1e-3) / 1e9, 3),
+                             "hbm_frac": round(byts / (ms * 1e-3) / 1e9 / HBM, 4)}
+    del Y, x, plan
+    torch.cuda.empty_cache()
     # spectral loss, forward + backward: 32 real pairs of 2^18 samples
     d = workloads.make(5)
     x = torch.from_numpy(d["x"]).cuda().requires_grad_(True)

@@ -72,6 +72,21 @@ typedef enum {
  * and replay it afterwards (one graph launch per call); a call with other
  * pointers captures again.  Not combinable with kernel timing. */
 #define MRDFT_FLAG_GRAPH 2u
+/* Half-spectrum output, real (MRDFT_R32) plans only.  A real window's
+ * spectrum is Hermitian (Y[L-k] = conj(Y[k])), so each window of L = 2^i
+ * points is stored as L/2 complex values: value 0 = (Y[0], Y[L/2]) (both are
+ * real: DC in the real part, Nyquist in the imaginary part), value k = Y[k]
+ * for 0 < k < L/2.  Every level then holds N/2 complex values per signal and
+ * every length in the layout rules below (N_j per level, m_j * N_j per
+ * signal) is halved; output bytes halve.  Level 1 (L = 2) becomes the single
+ * value (x0 + x1, x0 - x1).  The adjoint takes gY in the same packed layout:
+ * it returns the gradient of a real loss of the packed values, i.e.
+ * Re(sum_i A_i^H g^(i)) with g^(i) the packed gradient unpacked with zeros
+ * (value 0 -> bins 0 and L/2 as real numbers, value k -> bin k, bins above
+ * L/2 zero).  Needs signals of at least 4 samples (m_j >= 2, so that every
+ * signal's output stays 16-byte aligned); the spectral-loss calls return
+ * MRDFT_E_UNSUPPORTED on such a plan. */
+#define MRDFT_FLAG_HALF 4u
 
 /*
  * Create a plan.  Section 2 (problem statement of eq. (1)).
@@ -83,10 +98,13 @@ typedef enum {
  *             offsets, offsets[0] = 0, each length offsets[j+1]-offsets[j] a
  *             power of two 2^m_j with 1 <= m_j <= MRDFT_MAX_ORDER.
  *   dtype   : element type of x (MRDFT_C64 or MRDFT_R32).
- *   flags   : MRDFT_FLAG_NONE or an OR of MRDFT_FLAG_TUNE, MRDFT_FLAG_GRAPH.
+ *   flags   : MRDFT_FLAG_NONE or an OR of MRDFT_FLAG_TUNE, MRDFT_FLAG_GRAPH,
+ *             MRDFT_FLAG_HALF.
  *   stream  : stream used for the plan's one-time uploads (synchronised
  *             before return).
- * Errors: MRDFT_E_INVALID_ARG for any violated rule, MRDFT_E_ALLOC, MRDFT_E_HIP.
+ * Errors: MRDFT_E_INVALID_ARG for any violated rule (MRDFT_FLAG_HALF with
+ * complex input or a signal shorter than 4 samples included), MRDFT_E_ALLOC,
+ * MRDFT_E_HIP.
  */
 mrdft_status mrdft_plan_create(mrdft_plan_t* plan, int m, int64_t batch, const int64_t* offsets,
                                mrdft_dtype dtype, unsigned flags, hipStream_t stream);

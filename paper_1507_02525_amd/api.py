@@ -37,11 +37,13 @@ class Plan:
     Ragged batch:  ``Plan(offsets=int64 array [batch+1], dtype=...)``.
     ``tune=True`` times the candidate schedules at creation; ``graph=True``
     replays mrdft_forward from a captured HIP graph; ``levels=(lo, hi)`` keeps
-    only those levels (compact output, see mrdft_plan_create_levels).
+    only those levels (compact output, see mrdft_plan_create_levels);
+    ``half=True`` (real input) stores each window as its packed half spectrum
+    (L/2 values, value 0 = (Y[0], Y[L/2]); see MRDFT_FLAG_HALF).
     """
 
     def __init__(self, m: int = 0, batch: int = 1, offsets=None, dtype: str = "c64", device=None,
-                 tune: bool = False, graph: bool = False, levels=None):
+                 tune: bool = False, graph: bool = False, levels=None, half: bool = False):
         lib = B.lib()
         self.dtype = dtype
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
@@ -58,11 +60,13 @@ class Plan:
             offp = None
         with torch.cuda.device(self.device):
             stream = ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
-            flags = (B.MRDFT_FLAG_TUNE if tune else 0) | (B.MRDFT_FLAG_GRAPH if graph else 0)
+            flags = (B.MRDFT_FLAG_TUNE if tune else 0) | (B.MRDFT_FLAG_GRAPH if graph else 0) \
+                | (B.MRDFT_FLAG_HALF if half else 0)
             lo, hi = (1, B.MRDFT_MAX_ORDER) if levels is None else (int(levels[0]), int(levels[1]))
             B.check(lib.mrdft_plan_create_levels(ctypes.byref(h), int(m), int(batch), offp, code, flags, lo, hi,
                                                  stream))
         self.levels = (lo, hi)
+        self.half = bool(half)
         self.handle = h
         self.m = int(m)
         self.batch = int(batch)
@@ -145,7 +149,7 @@ class Plan:
         self.mrdft_forward(x.contiguous(), Y)
         if not self.ragged:
             kept = min(self.levels[1], self.m) - self.levels[0] + 1
-            Y = Y.view(self.batch, kept, 1 << self.m)
+            Y = Y.view(self.batch, kept, (1 << self.m) >> (1 if self.half else 0))
         return Y
 
     def adjoint(self, gY: torch.Tensor) -> torch.Tensor:

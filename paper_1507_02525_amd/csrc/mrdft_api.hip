@@ -59,6 +59,7 @@ struct Group {
     int64_t count = 0;
     int64_t* d_in_sig = nullptr;    // x offset of each signal (ragged only)
     int64_t* d_out_sig = nullptr;   // Y offset of each signal (ragged only)
+    int64_t* d_fout_sig = nullptr;  // half-spectrum plans: offset in the full-spectrum gradient layout
 };
 
 // Bit split of the passes for a window of 2^lg points (each pass radix <= 2^8,
@@ -79,10 +80,19 @@ struct mrdft_plan {
     bool ragged = false;
     std::vector<int64_t> in_off, out_off;   // [batch+1]
     // levels kept: [lo, hi]; signal j stores levels lo..min(hi, m_j) at
-    // out_off[j] + (i - lo) N_j, i.e. at base(j) + (i - 1) N_j
+    // out_off[j] + (i - lo) N_j, i.e. at base(j) + (i - 1) N_j (N_j / 2 for
+    // half-spectrum plans, hs = 1)
     int lo = 1, hi = MRDFT_MAX_ORDER;
+    int hs = 0;
     int kept(int order) const { return std::max(0, std::min(hi, order) - lo + 1); }
-    int64_t base(int64_t j) const { return out_off[j] - (int64_t)(lo - 1) * (in_off[j + 1] - in_off[j]); }
+    int64_t base(int64_t j) const { return out_off[j] - (int64_t)(lo - 1) * ((in_off[j + 1] - in_off[j]) >> hs); }
+    // full-spectrum layout of the same levels (the half plans' adjoint works in it)
+    std::vector<int64_t> fout_off;
+    int64_t n_fout = 0;
+    int64_t basef(int64_t j) const { return fout_off[j] - (int64_t)(lo - 1) * (in_off[j + 1] - in_off[j]); }
+    HalfJob* d_hjobs = nullptr;             // half plans: unpacking jobs of the adjoint
+    int64_t nhjobs = 0;
+    float2* d_gfull = nullptr;              // half plans: unpacked gradient, full layout
     int32_t range() const { return LevelRange::pack(lo, std::min(hi, 255)); }
     bool full_range(int order) const { return lo == 1 && hi >= order; }
     std::vector<int> orders;
@@ -180,6 +190,7 @@ void free_plan(mrdft_plan* p) {
     for (auto& g : p->groups) {
         dfree(g.d_in_sig);
         dfree(g.d_out_sig);
+        dfree(g.d_fout_sig);
     }
     dfree(p->d_tw_tile);
     dfree(p->d_tw_hi);
@@ -197,6 +208,8 @@ void free_plan(mrdft_plan* p) {
     dfree(p->d_acols);
     dfree(p->d_asmall);
     dfree(p->d_ascratch);
+    dfree(p->d_hjobs);
+    dfree(p->d_gfull);
     if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
@@ -312,7 +325,7 @@ mrdft_status upload_jobs(const std::vector<RealJob>& v, RealJob** dst, int64_t* 
 
 mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
     std::vector<TileJob> jobs;
-    std::vector<std::vector<int64_t>> gin(kMaxOrder + 1), gout(kMaxOrder + 1);
+    std::vector<std::vector<int64_t>> gin(kMaxOrder + 1), gout(kMaxOrder + 1), gfout(kMaxOrder + 1);
     for (int64_t j = 0; j < p->batch; ++j) {
         const int mj = p->orders[j];
         const int64_t N = int64_t(1) << mj;
@@ -321,8 +334,8 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
         for (int64_t tau = 0; tau < N / T; ++tau) {
             TileJob jb;
             jb.in_off = p->in_off[j] + tau * T;
-            jb.out_off = p->base(j) + tau * T;
-            jb.level_stride = N;
+            jb.out_off = p->base(j) + ((tau * T) >> p->hs);
+            jb.level_stride = N >> p->hs;
             jb.t = t;
             jb.pad = p->range();
             jobs.push_back(jb);
@@ -330,6 +343,7 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
         if (mj > kTileMaxLog) {
             gin[mj].push_back(p->in_off[j]);
             gout[mj].push_back(p->base(j));
+            gfout[mj].push_back(p->basef(j));
         }
     }
     // full tiles first: the real-input kernel handles exactly those
@@ -381,11 +395,11 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
             const int mj = p->orders[j];
             const int64_t N = int64_t(1) << mj;
             if (mj < kC64TileLog) {
-                sm.push_back(TileJob{p->in_off[j], p->base(j), N, mj, p->range()});
+                sm.push_back(TileJob{p->in_off[j], p->basef(j), N, mj, p->range()});
                 continue;
             }
             for (int64_t tau = 0; tau < (N >> kC64TileLog); ++tau)
-                aj.push_back(RealJob{p->base(j) + (tau << kC64TileLog), p->in_off[j] + (tau << kC64TileLog), N, 0,
+                aj.push_back(RealJob{p->basef(j) + (tau << kC64TileLog), p->in_off[j] + (tau << kC64TileLog), N, 0,
                                      p->range()});
             const int top = std::min(mj, kRowsMaxLevel);
             bool any_upper = false;
@@ -395,7 +409,7 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
                 const int64_t L = int64_t(1) << lg;
                 for (int64_t w = 0; w < N / L; ++w)
                     for (int g = 0; g < (1 << (lg - kCRowsMinLevel)); ++g)
-                        aj.push_back(RealJob{p->base(j) + (int64_t)(lg - 1) * N + w * L,
+                        aj.push_back(RealJob{p->basef(j) + (int64_t)(lg - 1) * N + w * L,
                                              scr + (int64_t)(lg - kCRowsMinLevel) * N + w * L, 0, lg, g});
             }
             if (top >= kCRowsMinLevel) {
@@ -422,6 +436,26 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
         if (!sm.empty()) HIP_TRY(hipMemcpyAsync(p->d_asmall, sm.data(), sizeof(TileJob) * sm.size(), hipMemcpyHostToDevice, s));
         HIP_TRY(hipStreamSynchronize(s));
     }
+    if (p->hs) {
+        // adjoint of the packed output: unpacking jobs and the full-layout gradient
+        std::vector<HalfJob> hj;
+        for (int64_t j = 0; j < p->batch; ++j) {
+            const int mj = p->orders[j];
+            const int64_t N = int64_t(1) << mj;
+            for (int i = p->lo; i <= std::min(p->hi, mj); ++i)
+                for (int64_t c0 = 0; c0 < N; c0 += kHalfChunk)
+                    hj.push_back(HalfJob{p->base(j) + (int64_t)(i - 1) * (N / 2), p->basef(j) + (int64_t)(i - 1) * N,
+                                         c0, i, (int32_t)std::min<int64_t>(N, kHalfChunk)});
+        }
+        p->nhjobs = (int64_t)hj.size();
+        if (!hj.empty()) {
+            if (hipMalloc(&p->d_hjobs, sizeof(HalfJob) * hj.size()) != hipSuccess ||
+                hipMalloc(&p->d_gfull, sizeof(float2) * p->n_fout) != hipSuccess)
+                return fail(MRDFT_E_ALLOC, "half-spectrum gradient workspace allocation failed (%lld complex)",
+                            (long long)p->n_fout);
+            HIP_TRY(hipMemcpyAsync(p->d_hjobs, hj.data(), sizeof(HalfJob) * hj.size(), hipMemcpyHostToDevice, s));
+        }
+    }
     int64_t scratch = 0;
     for (int o = kTileMaxLog + 1; o <= kMaxOrder; ++o) {
         if (gin[o].empty()) continue;
@@ -430,13 +464,17 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
         g.count = (int64_t)gin[o].size();
         if (p->ragged) {
             if (hipMalloc(&g.d_in_sig, sizeof(int64_t) * g.count) != hipSuccess ||
-                hipMalloc(&g.d_out_sig, sizeof(int64_t) * g.count) != hipSuccess) {
+                hipMalloc(&g.d_out_sig, sizeof(int64_t) * g.count) != hipSuccess ||
+                (p->hs && hipMalloc(&g.d_fout_sig, sizeof(int64_t) * g.count) != hipSuccess)) {
                 p->groups.push_back(g);
                 return fail(MRDFT_E_ALLOC, "signal table allocation failed");
             }
             p->groups.push_back(g);
             HIP_TRY(hipMemcpyAsync(g.d_in_sig, gin[o].data(), sizeof(int64_t) * g.count, hipMemcpyHostToDevice, s));
             HIP_TRY(hipMemcpyAsync(g.d_out_sig, gout[o].data(), sizeof(int64_t) * g.count, hipMemcpyHostToDevice, s));
+            if (p->hs)
+                HIP_TRY(hipMemcpyAsync(g.d_fout_sig, gfout[o].data(), sizeof(int64_t) * g.count, hipMemcpyHostToDevice,
+                                       s));
         } else {
             p->groups.push_back(g);
         }
@@ -552,13 +590,14 @@ std::vector<RealJob> real_jobs(const mrdft_plan* p, int order) {
         if (mj < kRealTileLog) continue;
         const int64_t N = int64_t(1) << mj;
         for (int64_t tau = 0; tau < (N >> kRealTileLog); ++tau)
-            jb.add_tile(RealJob{p->in_off[j] + (tau << kRealTileLog), p->base(j) + (tau << kRealTileLog), N, 0,
-                                p->range()},
+            jb.add_tile(RealJob{p->in_off[j] + (tau << kRealTileLog), p->base(j) + ((tau << kRealTileLog) >> p->hs),
+                                N >> p->hs, 0, p->range()},
                         6);                                    // 12 x 32 KB against 64 KB per piece
         for (int lg = std::max(kRowsMinLevel, p->lo); lg <= std::min({mj, kRowsMaxLevel, p->hi}); ++lg) {
             const int64_t L = int64_t(1) << lg;
             for (int64_t w = 0; w < N / L; ++w)
-                jb.add_window(RealJob{p->in_off[j] + w * L, p->base(j) + (int64_t)(lg - 1) * N + w * L, N, lg, 0},
+                jb.add_window(RealJob{p->in_off[j] + w * L, p->base(j) + (((int64_t)(lg - 1) * N + w * L) >> p->hs),
+                                      N, lg, 0},
                               1 << (lg - kRowsMinLevel));
         }
     }
@@ -676,6 +715,7 @@ mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, h
             const int si = (i <= kUpperMaxLevel) ? (i - kTileMaxLog - 1) : 0;
             const hipStream_t s = p->nsides ? p->side[si % p->nsides] : s0;
             if (i <= kUpperMaxLevel) {
+                if (p->hs) return fail(MRDFT_E_UNSUPPORTED, "half-spectrum output of level %d without the real launch", i);
                 PassGeom geo;
                 geo.lg = i;
                 geo.r_log = 0;
@@ -703,11 +743,12 @@ mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, h
                 geo.in_sig = first ? g.d_in_sig : nullptr;
                 geo.in_stride = N;
                 geo.out_sig = last ? g.d_out_sig : nullptr;
-                geo.out_stride = last ? (int64_t)p->kept(g.order) * N : N;
+                geo.out_stride = last ? (int64_t)p->kept(g.order) * (N >> p->hs) : N;
                 const void* in = first ? x : (const void*)p->d_s[(q - 1) & 1];
-                void* out = last ? (void*)level_ptr(p, Y, i, N) : (void*)p->d_s[q & 1];
+                void* out = last ? (void*)level_ptr(p, Y, i, N >> p->hs) : (void*)p->d_s[q & 1];
+                const int ok = (last && p->hs) ? OUT_HALF : OUT_STORE;
                 ProfScope ps(p, MRDFT_KERNEL_PASS_FWD, s);
-                HIP_TRY(launch_pass(false, first ? in_kind : IN_C64, OUT_STORE, in, out, geo, tw, s));
+                HIP_TRY(launch_pass(false, first ? in_kind : IN_C64, ok, in, out, geo, tw, s));
                 ns += bits[q];
             }
         }
@@ -716,15 +757,16 @@ mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, h
         if (real_jobs_cover) {
             {
                 ProfScope ps(p, MRDFT_KERNEL_FUSED_FWD, s0);
-                HIP_TRY(launch_fwd_real((const float*)x, Y, p->d_rjobs, p->nrjobs, tw, s0));
+                HIP_TRY(launch_fwd_real((const float*)x, Y, p->d_rjobs, p->nrjobs, tw, s0, p->hs != 0));
             }
             if (p->njobs > p->njobs_full) {
                 ProfScope ps(p, MRDFT_KERNEL_TILE_FWD, s0);
-                HIP_TRY(launch_tile_fwd(true, x, Y, p->d_jobs + p->njobs_full, p->njobs - p->njobs_full, tw, s0));
+                HIP_TRY(launch_tile_fwd(true, x, Y, p->d_jobs + p->njobs_full, p->njobs - p->njobs_full, tw, s0,
+                                        p->hs != 0));
             }
         } else if (in_kind == IN_R32) {
             ProfScope ps(p, MRDFT_KERNEL_TILE_FWD, s0);
-            HIP_TRY(launch_tile_fwd(true, x, Y, p->d_jobs, p->njobs, tw, s0));
+            HIP_TRY(launch_tile_fwd(true, x, Y, p->d_jobs, p->njobs, tw, s0, p->hs != 0));
         } else if (cjobs_cover) {
             {
                 ProfScope ps(p, MRDFT_KERNEL_FUSED_FWD, s0);
@@ -749,6 +791,14 @@ mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, h
 
 mrdft_status run_adjoint(mrdft_plan* p, const float2* gY, void* gx, bool real_out, hipStream_t s) {
     const Twiddles tw = p->tw();
+    if (p->hs) {
+        // packed half-spectrum gradient -> full-spectrum layout, then the full adjoint
+        {
+            ProfScope ps(p, MRDFT_KERNEL_TILE_ADJ, s);
+            HIP_TRY(launch_expand_half(gY, p->d_gfull, p->d_hjobs, p->nhjobs, s));
+        }
+        gY = p->d_gfull;
+    }
     if (p->najobs) {
         ProfScope ps(p, MRDFT_KERNEL_TILE_ADJ, s);
         HIP_TRY(launch_adj_a(real_out, gY, gx, p->d_ascratch, p->d_ajobs, p->najobs, tw, s));
@@ -776,7 +826,7 @@ mrdft_status run_adjoint(mrdft_plan* p, const float2* gY, void* gx, bool real_ou
                 geo.ns_log = ns;
                 geo.nwin = g.count * (N >> i);
                 geo.wps = N >> i;
-                geo.in_sig = first ? g.d_out_sig : nullptr;
+                geo.in_sig = first ? (p->hs ? g.d_fout_sig : g.d_out_sig) : nullptr;
                 geo.in_stride = first ? (int64_t)p->kept(g.order) * N : N;
                 geo.out_sig = last ? g.d_in_sig : nullptr;
                 geo.out_stride = N;
@@ -995,7 +1045,10 @@ mrdft_status mrdft_plan_create_levels(mrdft_plan_t* plan, int m, int64_t batch, 
         return fail(MRDFT_E_INVALID_ARG, "level range starts at %d above the order %d", lo, m);
     if (batch < 1) return fail(MRDFT_E_INVALID_ARG, "batch must be >= 1 (got %lld)", (long long)batch);
     if (dtype != MRDFT_C64 && dtype != MRDFT_R32) return fail(MRDFT_E_INVALID_ARG, "unknown dtype %d", (int)dtype);
-    if (flags & ~(MRDFT_FLAG_TUNE | MRDFT_FLAG_GRAPH)) return fail(MRDFT_E_INVALID_ARG, "unknown flags 0x%x", flags);
+    if (flags & ~(MRDFT_FLAG_TUNE | MRDFT_FLAG_GRAPH | MRDFT_FLAG_HALF))
+        return fail(MRDFT_E_INVALID_ARG, "unknown flags 0x%x", flags);
+    if ((flags & MRDFT_FLAG_HALF) && dtype != MRDFT_R32)
+        return fail(MRDFT_E_INVALID_ARG, "half-spectrum output (MRDFT_FLAG_HALF) needs real (MRDFT_R32) input");
     mrdft_plan* p = new (std::nothrow) mrdft_plan();
     if (!p) return fail(MRDFT_E_ALLOC, "host allocation failed");
     p->batch = batch;
@@ -1003,8 +1056,10 @@ mrdft_status mrdft_plan_create_levels(mrdft_plan_t* plan, int m, int64_t batch, 
     p->flags = flags;
     p->lo = lo;
     p->hi = hi;
+    p->hs = (flags & MRDFT_FLAG_HALF) ? 1 : 0;
     p->in_off.resize(batch + 1);
     p->out_off.resize(batch + 1);
+    p->fout_off.resize(batch + 1);
     p->orders.resize(batch);
     if (offsets) {
         if (m != 0) {
@@ -1034,13 +1089,22 @@ mrdft_status mrdft_plan_create_levels(mrdft_plan_t* plan, int m, int64_t batch, 
         }
         for (int64_t j = 0; j < batch; ++j) p->orders[j] = m;
     }
-    p->in_off[0] = p->out_off[0] = 0;
+    for (int64_t j = 0; j < batch && p->hs; ++j) {
+        if (p->orders[j] < 2) {
+            delete p;
+            return fail(MRDFT_E_INVALID_ARG, "half-spectrum output needs signals of at least 4 samples (signal %lld)",
+                        (long long)j);
+        }
+    }
+    p->in_off[0] = p->out_off[0] = p->fout_off[0] = 0;
     for (int64_t j = 0; j < batch; ++j) {
         const int64_t N = int64_t(1) << p->orders[j];
         p->in_off[j + 1] = p->in_off[j] + N;
-        p->out_off[j + 1] = p->out_off[j] + (int64_t)p->kept(p->orders[j]) * N;
+        p->out_off[j + 1] = p->out_off[j] + (int64_t)p->kept(p->orders[j]) * (N >> p->hs);
+        p->fout_off[j + 1] = p->fout_off[j] + (int64_t)p->kept(p->orders[j]) * N;
         if (p->orders[j] > p->max_order) p->max_order = p->orders[j];
     }
+    p->n_fout = p->fout_off[batch];
     p->m = offsets ? 0 : m;
     p->n_in = p->in_off[batch];
     p->n_out = p->out_off[batch];
@@ -1147,6 +1211,7 @@ mrdft_status mrdft_spectral_loss_fwd(mrdft_plan_t plan, const float* x, const fl
         return fail(MRDFT_E_UNSUPPORTED, "the spectral loss needs a uniform real (MRDFT_R32) plan");
     if (!plan->full_range(plan->m))
         return fail(MRDFT_E_UNSUPPORTED, "the spectral loss needs every level (plan created with a level range)");
+    if (plan->hs) return fail(MRDFT_E_UNSUPPORTED, "the spectral loss needs a full-spectrum plan");
     if (!x || !z || !num_den || !L) return fail(MRDFT_E_INVALID_ARG, "x, z, num_den and L must be non-NULL");
     if (misaligned(x, 16) || misaligned(z, 16) || misaligned(num_den, 8) || misaligned(L, 4))
         return fail(MRDFT_E_INVALID_ARG, "x or z is not 16-byte aligned");
@@ -1200,6 +1265,7 @@ mrdft_status mrdft_spectral_loss_bwd(mrdft_plan_t plan, const float* x, const fl
         return fail(MRDFT_E_UNSUPPORTED, "the spectral loss needs a uniform real (MRDFT_R32) plan");
     if (!plan->full_range(plan->m))
         return fail(MRDFT_E_UNSUPPORTED, "the spectral loss needs every level (plan created with a level range)");
+    if (plan->hs) return fail(MRDFT_E_UNSUPPORTED, "the spectral loss needs a full-spectrum plan");
     if (!x || !z || !num_den || !gL || !gx) return fail(MRDFT_E_INVALID_ARG, "null pointer argument");
     if (misaligned(x, 16) || misaligned(z, 16) || misaligned(gx, 16))
         return fail(MRDFT_E_INVALID_ARG, "x, z or gx is not 16-byte aligned");

@@ -19,7 +19,7 @@ union FwdRealLds {
 static_assert(sizeof(FwdRealLds) <= 40 * 1024, "four workgroups per CU");
 static_assert(kRThreads == kRowsThreads, "one block size for both job kinds");
 
-constexpr int kModeStore = 0, kModeNorms = 1, kModeScaled = 2;
+constexpr int kModeStore = 0, kModeNorms = 1, kModeScaled = 2, kModeHalf = 3;
 
 // Sum of v over the 64 lanes of a wave (all lanes receive it).
 __device__ __forceinline__ double wave_sum(double v) {
@@ -28,7 +28,8 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// MODE kModeStore: the level spectra are stored to Y.  kModeScaled
+// MODE kModeStore: the level spectra are stored to Y (kModeHalf: as packed
+// half spectra, the job offsets and level stride in half-spectrum units).  kModeScaled
 // (spectral-loss gradient): the input is x - xsub and level i of signal b is
 // stored times alpha[b * m + i - 1].  kModeNorms (spectral loss): the input is
 // x - xsub (xsub may be null) and only the squared magnitudes of every level
@@ -51,18 +52,19 @@ __global__ __launch_bounds__(kRThreads, 4) void fwd_real_kernel(const float* __r
     const float* xj = x + jb.in_off;
     const float* zj = (MODE != kModeStore && xsub) ? xsub + jb.in_off : nullptr;
     float2* yj = RED ? nullptr : Y + jb.out_off;
-    if constexpr (MODE == kModeStore) {
-        StoreOut out{LevelRange::unpack(jb.g)};       // tile jobs carry the plan's level range
+    if constexpr (MODE == kModeStore || MODE == kModeHalf) {
+        constexpr bool H = MODE == kModeHalf;
+        StoreOutT<H> out{LevelRange::unpack(jb.g)};   // tile jobs carry the plan's level range
         switch (jb.lg) {
             case 0: real_tile_body(S.tile, xj, nullptr, yj, jb.level_stride, t4096, tid, out); break;
-            case 13: rows_real_body<5>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(13),
-                                       comb + rows_combine_offset(13), tid); break;
-            case 14: rows_real_body<6>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(14),
-                                       comb + rows_combine_offset(14), tid); break;
-            case 15: rows_real_body<7>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(15),
-                                       comb + rows_combine_offset(15), tid); break;
-            case 16: rows_real_body<8>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(16),
-                                       comb + rows_combine_offset(16), tid); break;
+            case 13: rows_real_body<5, false, H>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(13),
+                                                 comb + rows_combine_offset(13), tid); break;
+            case 14: rows_real_body<6, false, H>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(14),
+                                                 comb + rows_combine_offset(14), tid); break;
+            case 15: rows_real_body<7, false, H>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(15),
+                                                 comb + rows_combine_offset(15), tid); break;
+            case 16: rows_real_body<8, false, H>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(16),
+                                                 comb + rows_combine_offset(16), tid); break;
             default: break;
         }
     } else if constexpr (MODE == kModeScaled) {
@@ -109,10 +111,14 @@ __global__ __launch_bounds__(kRThreads, 4) void fwd_real_kernel(const float* __r
 }  // namespace
 
 hipError_t launch_fwd_real(const float* x, float2* Y, const RealJob* jobs, int64_t njobs, const Twiddles& tw,
-                           hipStream_t s) {
+                           hipStream_t s, bool half) {
     if (njobs <= 0) return hipSuccess;
-    hipLaunchKernelGGL(fwd_real_kernel<kModeStore>, dim3((unsigned)njobs), dim3(kRThreads), 0, s, x, Y, jobs, tw.tile,
-                       tw.rows, tw.rows_comb, nullptr, nullptr, nullptr, 0);
+    if (half)
+        hipLaunchKernelGGL(fwd_real_kernel<kModeHalf>, dim3((unsigned)njobs), dim3(kRThreads), 0, s, x, Y, jobs,
+                           tw.tile, tw.rows, tw.rows_comb, nullptr, nullptr, nullptr, 0);
+    else
+        hipLaunchKernelGGL(fwd_real_kernel<kModeStore>, dim3((unsigned)njobs), dim3(kRThreads), 0, s, x, Y, jobs,
+                           tw.tile, tw.rows, tw.rows_comb, nullptr, nullptr, nullptr, 0);
     return hipGetLastError();
 }
 

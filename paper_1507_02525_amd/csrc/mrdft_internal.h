@@ -38,7 +38,8 @@ struct PassGeom {
 };
 
 enum InKind { IN_C64 = 0, IN_R32 = 1 };
-enum OutKind { OUT_STORE = 0, OUT_ADD_C64 = 1, OUT_ADD_R32 = 2 };
+// OUT_HALF: store packed half spectra (window W at W * L/2, slot 0 = (Y[0], Y[L/2])).
+enum OutKind { OUT_STORE = 0, OUT_ADD_C64 = 1, OUT_ADD_R32 = 2, OUT_HALF = 3 };
 
 struct Twiddles {
     const float2* tile;   // w_{4096}^e, e < 4096 (FP32, rounded once from FP64)
@@ -63,8 +64,9 @@ __host__ __device__ constexpr int64_t rows_twiddle_offset(int lg) {
     return lg <= 12 ? 0 : rows_twiddle_offset(lg - 1) + ((int64_t)1 << (lg - 1));
 }
 constexpr int64_t rows_twiddle_entries() { return rows_twiddle_offset(17); }
+// half: packed half-spectrum output (job offsets and level strides in those units).
 hipError_t launch_fwd_real(const float* x, float2* Y, const RealJob* jobs, int64_t njobs, const Twiddles& tw,
-                           hipStream_t s);
+                           hipStream_t s, bool half = false);
 // Same jobs, spectral loss: the input is x - xsub (xsub may be null) and the
 // squared magnitudes of every level are added to sums[b * m + level - 1]
 // (uniform batch; the rows jobs carry level_stride = N).  Y is not written.
@@ -93,14 +95,28 @@ struct AdjColJob {
     int32_t region_log;    // region of 2^region_log samples (12 .. 16)
     int32_t c;             // columns 16 (c & 15) .. +15; c >> 8 = LevelRange::pack of the levels kept
 };
+// Half-spectrum plans: one job unpacks `len` consecutive bins (from bin c0)
+// of one level of one signal from the packed gradient (level at hlev) into the
+// full-spectrum gradient (level at flev), windows of 2^lg bins.
+struct HalfJob {
+    int64_t hlev;
+    int64_t flev;
+    int64_t c0;
+    int32_t lg;
+    int32_t len;
+};
+constexpr int kHalfChunk = 4096;
+hipError_t launch_expand_half(const float2* gh, float2* g, const HalfJob* jobs, int64_t njobs, hipStream_t s);
 hipError_t launch_adj_a(bool real_out, const float2* gY, void* gx, float2* scratch, const RealJob* jobs, int64_t njobs,
                         const Twiddles& tw, hipStream_t s);
 hipError_t launch_adj_b(bool real_out, void* gx, const float2* scratch, const AdjColJob* jobs, int64_t njobs,
                         const Twiddles& tw, hipStream_t s);
 hipError_t launch_fwd_c64(const float2* x, float2* Y, const RealJob* jobs, int64_t njobs, const unsigned* seg,
                           unsigned* queue, int grid, const Twiddles& tw, hipStream_t s);
+// half (real input only): packed half-spectrum output, job offsets and level
+// strides in those units.
 hipError_t launch_tile_fwd(bool real_in, const void* x, float2* Y, const TileJob* jobs, int64_t njobs,
-                           const Twiddles& tw, hipStream_t s);
+                           const Twiddles& tw, hipStream_t s, bool half = false);
 // Real input, 4096-sample tiles (levels 1..12): see mrdft_tile_real.h.
 constexpr int kRealTileLog = 12;
 hipError_t launch_tile_adj(bool real_out, const float2* gY, void* gx, const TileJob* jobs, int64_t njobs,

@@ -62,7 +62,7 @@ __global__ __launch_bounds__(kPassThreads) void pass_kernel(const void* __restri
     const int64_t j0 = (blk - gwin * jblocks) * kPassCols;
     const int64_t b = gwin / g.wps, W = gwin - b * g.wps;
     const int64_t ib = (g.in_sig ? g.in_sig[b] : b * g.in_stride) + W * L;
-    const int64_t ob = (g.out_sig ? g.out_sig[b] : b * g.out_stride) + W * L;
+    const int64_t ob = (g.out_sig ? g.out_sig[b] : b * g.out_stride) + W * (OUT_KIND == OUT_HALF ? L / 2 : L);
     const int tid = threadIdx.x;
     const int ns_log = g.ns_log;
     const int64_t nsm = ((int64_t)1 << ns_log) - 1;
@@ -111,6 +111,14 @@ __global__ __launch_bounds__(kPassThreads) void pass_kernel(const void* __restri
         const float2 v = B[jj * fst + s];
         if constexpr (OUT_KIND == OUT_STORE) {
             ((float2*)out)[o] = v;
+        } else if constexpr (OUT_KIND == OUT_HALF) {
+            // bin k = o - ob of a real window: k < L/2 kept, the DC and
+            // Nyquist real parts share slot 0, the upper half is dropped
+            const int64_t k = o - ob;
+            float* sl = (float*)((float2*)out + ob);
+            if (k == 0) sl[0] = v.x;
+            else if (k == L / 2) sl[1] = v.x;
+            else if (k < L / 2) ((float2*)out)[o] = v;
         } else if constexpr (OUT_KIND == OUT_ADD_C64) {
             float2* p = (float2*)out + o;
             *p = cadd(*p, v);
@@ -132,10 +140,12 @@ static hipError_t launch_pass_t(int in_kind, int out_kind, const void* in, void*
     hipLaunchKernelGGL((pass_kernel<INV, IK, OK>), grid, block, 0, s, in, out, g, tw.tile, tw.hi, tw.lo)
     if (in_kind == IN_R32) {
         if (out_kind == OUT_STORE) MRDFT_PASS(IN_R32, OUT_STORE);
+        else if (out_kind == OUT_HALF) MRDFT_PASS(IN_R32, OUT_HALF);
         else if (out_kind == OUT_ADD_C64) MRDFT_PASS(IN_R32, OUT_ADD_C64);
         else MRDFT_PASS(IN_R32, OUT_ADD_R32);
     } else {
         if (out_kind == OUT_STORE) MRDFT_PASS(IN_C64, OUT_STORE);
+        else if (out_kind == OUT_HALF) MRDFT_PASS(IN_C64, OUT_HALF);
         else if (out_kind == OUT_ADD_C64) MRDFT_PASS(IN_C64, OUT_ADD_C64);
         else MRDFT_PASS(IN_C64, OUT_ADD_R32);
     }

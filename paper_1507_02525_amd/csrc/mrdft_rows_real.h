@@ -111,7 +111,9 @@ constexpr int64_t rows_combine_entries() { return rows_combine_offset(kRowsMaxLe
 //   t4096 : w_4096^e, e < 4096 (FP32, rounded once from FP64)
 //   rowtw : this level's row twiddles, rowtw[k2 * 256 + n1] = w_L^{n1 k2}
 //   comb  : this level's column-combine factors (see rows_combine_offset)
-template <int RL, bool RED = false>
+// HALF: only bins k < L/2 (k1 < 128) are stored, with slot 0 = (Y[0], Y[L/2])
+// (Y[L/2] is row 0 at k1 = 128).
+template <int RL, bool RED = false, bool HALF = false>
 __device__ __forceinline__ void rows_real_body(RowsLds& S, const float* __restrict__ xw, float2* __restrict__ yw,
                                                int g, const float2* __restrict__ t4096,
                                                const float2* __restrict__ rowtw, const float4* __restrict__ comb,
@@ -193,16 +195,18 @@ __device__ __forceinline__ void rows_real_body(RowsLds& S, const float* __restri
         *norm += (double)t;
         return;
     }
+    constexpr int U = HALF ? 4 : 8;                // k1 < 128 for the half spectrum
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < U; ++u) {
         const int e = tid + u * kRowsThreads;
         const int k1 = e >> 3, kp = (e & 7) * 2;
-        const float2 a = S.C[kp * kRowsStride + rpad(k1)];
+        float2 a = S.C[kp * kRowsStride + rpad(k1)];
         const float2 c = S.C[(kp + 1) * kRowsStride + rpad(k1)];
+        if (HALF && u == 0 && tid == 0 && g == 0) a.y = S.C[rpad(kRowsN / 2)].x;   // (DC, Nyquist)
         *(float4*)(yw + k0 + kp + (int64_t)R * k1) = make_float4(scale * a.x, scale * a.y, scale * c.x, scale * c.y);
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < U; ++u) {
         const int e = tid + u * kRowsThreads;
         const int k1 = e >> 3, kp = (e & 7) * 2;
         // bin 16 gm + kp (+1) at k1 = conj(row 16 - kp (15 - kp) at 255 - k1)

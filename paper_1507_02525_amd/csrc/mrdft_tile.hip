@@ -37,7 +37,30 @@ __device__ __forceinline__ float2 to_c(float2 v) { return v; }
 // ---------------------------------------------------------------------------
 // Register phase, forward: levels 2..LC of a chunk of C = 2^LC samples.
 // ---------------------------------------------------------------------------
-template <int I, int LC>
+// One level of a register chunk (C values, windows of L natural-order bins)
+// to y: full spectra, or (HALF) the C/2 packed half-spectrum slots, slot 0 of
+// a window = (Y[0], Y[L/2]).  16-byte stores.
+template <int C, int L, bool HALF>
+__device__ __forceinline__ void store_chunk(const float2* pv, float2* y) {
+    float4* yo = (float4*)y;
+    if constexpr (HALF) {
+        constexpr int M = L / 2;
+        float2 hv[C / 2];
+#pragma unroll
+        for (int w = 0; w < C / L; ++w) {
+            hv[w * M] = make_float2(pv[w * L].x, pv[w * L + M].x);
+#pragma unroll
+            for (int k = 1; k < M; ++k) hv[w * M + k] = pv[w * L + k];
+        }
+#pragma unroll
+        for (int e = 0; e < C / 4; ++e) yo[e] = make_float4(hv[2 * e].x, hv[2 * e].y, hv[2 * e + 1].x, hv[2 * e + 1].y);
+    } else {
+#pragma unroll
+        for (int e = 0; e < C / 2; ++e) yo[e] = make_float4(pv[2 * e].x, pv[2 * e].y, pv[2 * e + 1].x, pv[2 * e + 1].y);
+    }
+}
+
+template <int I, int LC, bool HALF>
 struct LocalFwd {
     static __device__ __forceinline__ void run(const float2* xv, float2* pv, float2* y, int64_t ls, LevelRange lv) {
         if constexpr (I <= LC) {
@@ -56,20 +79,15 @@ struct LocalFwd {
                     nv[w * L + 2 * k + 1] = d[k];
                 }
             }
-            float4* yo = (float4*)(y + (int64_t)(I - 1) * ls);
 #pragma unroll
             for (int e = 0; e < C; ++e) pv[e] = nv[e];
-            if (lv.in(I)) {
-#pragma unroll
-                for (int e = 0; e < C / 2; ++e)
-                    yo[e] = make_float4(pv[2 * e].x, pv[2 * e].y, pv[2 * e + 1].x, pv[2 * e + 1].y);
-            }
-            LocalFwd<I + 1, LC>::run(xv, pv, y, ls, lv);
+            if (lv.in(I)) store_chunk<C, L, HALF>(pv, y + (int64_t)(I - 1) * ls);
+            LocalFwd<I + 1, LC, HALF>::run(xv, pv, y, ls, lv);
         }
     }
 };
 
-template <int LC, bool REAL>
+template <int LC, bool REAL, bool HALF>
 __device__ __forceinline__ void fwd_local(const typename XType<REAL>::T* __restrict__ xin, float2* y, int64_t ls,
                                           typename XType<REAL>::T* Xs, float2* Ps, int c0, bool keep, LevelRange lv) {
     constexpr int C = 1 << LC;
@@ -96,13 +114,8 @@ __device__ __forceinline__ void fwd_local(const typename XType<REAL>::T* __restr
         pv[2 * b] = cadd(xv[2 * b], xv[2 * b + 1]);
         pv[2 * b + 1] = csub(xv[2 * b], xv[2 * b + 1]);
     }
-    float4* yo = (float4*)y;
-    if (lv.in(1)) {
-#pragma unroll
-        for (int e = 0; e < C / 2; ++e)
-            yo[e] = make_float4(pv[2 * e].x, pv[2 * e].y, pv[2 * e + 1].x, pv[2 * e + 1].y);
-    }
-    LocalFwd<2, LC>::run(xv, pv, y, ls, lv);
+    if (lv.in(1)) store_chunk<C, 2, HALF>(pv, y);
+    LocalFwd<2, LC, HALF>::run(xv, pv, y, ls, lv);
     if (keep) {
 #pragma unroll
         for (int e = 0; e < C; ++e) {
@@ -137,7 +150,9 @@ __device__ __forceinline__ void first_load_fwd(const XT* Xs, int i, int nw, cons
     }
 }
 
-template <bool REAL>
+// HALF (real input, tiles of at least 4 samples): packed half-spectrum
+// output, job offsets and level stride in those units.
+template <bool REAL, bool HALF>
 __global__ __launch_bounds__(kTileThreads) void tile_fwd_kernel(const void* __restrict__ x, float2* __restrict__ Y,
                                                                 const TileJob* __restrict__ jobs,
                                                                 const float2* __restrict__ tab) {
@@ -162,11 +177,14 @@ __global__ __launch_bounds__(kTileThreads) void tile_fwd_kernel(const void* __re
     if (keep) load_quarter(Qs, tab, tid, kTileThreads);
     if (tid < (T >> lc)) {
         const int c0 = tid << lc;
+        float2* yc = y + (c0 >> (HALF ? 1 : 0));
         switch (lc) {
-            case 1: fwd_local<1, REAL>(xin + c0, y + c0, ls, Xs, Ps, c0, keep, lv); break;
-            case 2: fwd_local<2, REAL>(xin + c0, y + c0, ls, Xs, Ps, c0, keep, lv); break;
-            case 3: fwd_local<3, REAL>(xin + c0, y + c0, ls, Xs, Ps, c0, keep, lv); break;
-            default: fwd_local<4, REAL>(xin + c0, y + c0, ls, Xs, Ps, c0, keep, lv); break;
+            case 1:
+                if constexpr (!HALF) fwd_local<1, REAL, false>(xin + c0, yc, ls, Xs, Ps, c0, keep, lv);
+                break;
+            case 2: fwd_local<2, REAL, HALF>(xin + c0, yc, ls, Xs, Ps, c0, keep, lv); break;
+            case 3: fwd_local<3, REAL, HALF>(xin + c0, yc, ls, Xs, Ps, c0, keep, lv); break;
+            default: fwd_local<4, REAL, HALF>(xin + c0, yc, ls, Xs, Ps, c0, keep, lv); break;
         }
     }
     if (!keep) return;
@@ -229,9 +247,20 @@ __global__ __launch_bounds__(kTileThreads) void tile_fwd_kernel(const void* __re
         __syncthreads();
         if (lv.in(i)) {
             float4* yo = (float4*)(y + (int64_t)(i - 1) * ls);
-            for (int e = tid; e < T / 2; e += kTileThreads) {
-                const float2 a = Ps[pad(2 * e)], b = Ps[pad(2 * e + 1)];
-                yo[e] = make_float4(a.x, a.y, b.x, b.y);
+            if constexpr (HALF) {
+                // slots 2e, 2e + 1 of window w (M >= 16: one window per pair)
+                for (int e = tid; e < T / 4; e += kTileThreads) {
+                    const int w = (2 * e) >> lgM, k = (2 * e) & (M - 1);
+                    float2 a = Ps[pad(w * L + k)];
+                    if (k == 0) a.y = Ps[pad(w * L + M)].x;
+                    const float2 b = Ps[pad(w * L + k + 1)];
+                    yo[e] = make_float4(a.x, a.y, b.x, b.y);
+                }
+            } else {
+                for (int e = tid; e < T / 2; e += kTileThreads) {
+                    const float2 a = Ps[pad(2 * e)], b = Ps[pad(2 * e + 1)];
+                    yo[e] = make_float4(a.x, a.y, b.x, b.y);
+                }
             }
         }
     }
@@ -468,11 +497,13 @@ __global__ __launch_bounds__(kTileThreads) void tile_adj_kernel(const float2* __
 }
 
 hipError_t launch_tile_fwd(bool real_in, const void* x, float2* Y, const TileJob* jobs, int64_t njobs,
-                           const Twiddles& tw, hipStream_t s) {
+                           const Twiddles& tw, hipStream_t s, bool half) {
     if (njobs <= 0) return hipSuccess;
+    if (half && !real_in) return hipErrorInvalidValue;
     dim3 grid((unsigned)njobs), block(kTileThreads);
-    if (real_in) hipLaunchKernelGGL(tile_fwd_kernel<true>, grid, block, 0, s, x, Y, jobs, tw.tile);
-    else hipLaunchKernelGGL(tile_fwd_kernel<false>, grid, block, 0, s, x, Y, jobs, tw.tile);
+    if (half) hipLaunchKernelGGL((tile_fwd_kernel<true, true>), grid, block, 0, s, x, Y, jobs, tw.tile);
+    else if (real_in) hipLaunchKernelGGL((tile_fwd_kernel<true, false>), grid, block, 0, s, x, Y, jobs, tw.tile);
+    else hipLaunchKernelGGL((tile_fwd_kernel<false, false>), grid, block, 0, s, x, Y, jobs, tw.tile);
     return hipGetLastError();
 }
 

@@ -16,7 +16,8 @@
 //   A = (Z[k] + conj(Z[M/2-1-k]))/2, B = -j (Z[k] - conj(Z[M/2-1-k]))/2,
 //   T = w_L^{2k+1} B:  O[k] = A + T,  O[M/2-1-k] = conj(A - T).
 // * Every level is written out as the full spectrum (the upper half as
-//   conjugates), straight from registers.
+//   conjugates), straight from registers, or (half-spectrum output) as the
+//   packed slots themselves.
 //
 // Everything level-dependent is a compile-time constant (one instantiation per
 // level), so LDS addressing folds into immediate offsets.
@@ -49,15 +50,21 @@ __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2
 
 // Where the level spectra go: stored to Y, or (spectral loss) only their
 // squared magnitudes summed per level in FP64, Y never written.
-struct StoreOut {
+// HALF: each window of L bins is stored as its L/2 packed half-spectrum
+// slots (slot 0 = (Y[0], Y[L/2]), slot k = Y[k]), levels N/2 apart.
+template <bool HALF>
+struct StoreOutT {
     static constexpr bool kReduce = false;
+    static constexpr bool kHalf = HALF;
     LevelRange lv;                                 // levels stored
     __device__ __forceinline__ float2 sc(int, float2 v) const { return v; }
     __device__ __forceinline__ bool keep(int level) const { return lv.in(level); }
 };
+using StoreOut = StoreOutT<false>;
 // Stored times a per-level factor (spectral-loss gradient).
 struct ScaledOut {
     static constexpr bool kReduce = false;
+    static constexpr bool kHalf = false;
     const float* alpha;
     __device__ __forceinline__ float2 sc(int level, float2 v) const {
         const float a = alpha[level - 1];
@@ -67,6 +74,7 @@ struct ScaledOut {
 };
 struct NormOut {
     static constexpr bool kReduce = true;
+    static constexpr bool kHalf = false;
     double* sums;                                   // this signal's per-level sums
     __device__ __forceinline__ float2 sc(int, float2 v) const { return v; }
     __device__ __forceinline__ bool keep(int) const { return true; }
@@ -261,6 +269,12 @@ __device__ __forceinline__ void real_level(RealTileLds& S, float2* __restrict__ 
         if constexpr (O::kReduce) {
             nrm += norm2(u0) + norm2(ok[c]) + norm2(uj[c]) + norm2(oj[c]) + norm2(ua) + norm2(oka) + norm2(ub) +
                    norm2(oja);
+        } else if (O::kHalf) {
+            if (out.keep(I)) {                          // the packed slots themselves (slot 0 = uk at k = 0)
+                float2* yh = y + (int64_t)w * M;
+                *(float4*)(yh + 2 * k) = make_float4(uk[c].x, uk[c].y, ok[c].x, ok[c].y);
+                *(float4*)(yh + 2 * j) = make_float4(uj[c].x, uj[c].y, oj[c].x, oj[c].y);
+            }
         } else if (out.keep(I)) {
             const float2 s0 = out.sc(I, u0), s1 = out.sc(I, ok[c]), s2 = out.sc(I, uj[c]), s3 = out.sc(I, oj[c]);
             const float2 s4 = out.sc(I, ua), s5 = out.sc(I, oka), s6 = out.sc(I, ub), s7 = out.sc(I, oja);
@@ -296,9 +310,12 @@ __device__ __forceinline__ void wave_sync() {
 // each) through the wave's private LDS region, so that every global store
 // instruction covers 1 KB of consecutive output.  Pair e of lane l sits at
 // 8l + (e ^ (l & 7)) (XOR swizzle: conflict-free writes and reads).
-template <class O>
-__device__ __forceinline__ void stage_level(const float2* pv, float4* st, float2* __restrict__ yl, int lane, O& out,
-                                            int level) {
+// Half-spectrum output: the lane's 8 packed slots (slot 0 of each window =
+// (Y[0], Y[L/2])), pair e of lane l at 4l + (e ^ (l & 3)), 512 B per store
+// instruction.
+template <int I, class O>
+__device__ __forceinline__ void stage_level(const float2* pv, float4* st, float2* __restrict__ yl, int lane, O& out) {
+    constexpr int level = I;
     if constexpr (O::kReduce) {
         float t = 0.0f;
 #pragma unroll
@@ -307,6 +324,27 @@ __device__ __forceinline__ void stage_level(const float2* pv, float4* st, float2
         return;
     }
     if (!out.keep(level)) return;
+    if constexpr (O::kHalf) {
+        constexpr int L = 1 << I, M = L / 2;
+        float2 hv[8];
+#pragma unroll
+        for (int w = 0; w < 16 / L; ++w) {
+            hv[w * M] = make_float2(pv[w * L].x, pv[w * L + M].x);
+#pragma unroll
+            for (int k = 1; k < M; ++k) hv[w * M + k] = pv[w * L + k];
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) st[4 * lane + (e ^ (lane & 3))] = make_float4(hv[2 * e].x, hv[2 * e].y,
+                                                                                 hv[2 * e + 1].x, hv[2 * e + 1].y);
+        wave_sync();
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int p = 64 * r + lane, wl = p >> 2, e = p & 3;
+            *(float4*)(yl + 2 * p) = st[4 * wl + (e ^ (wl & 3))];
+        }
+        wave_sync();
+        return;
+    }
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
         const float2 a = out.sc(level, pv[2 * e]), b = out.sc(level, pv[2 * e + 1]);
@@ -344,7 +382,7 @@ struct LocalFwdReal {
             }
 #pragma unroll
             for (int e = 0; e < C; ++e) pv[e] = nv[e];
-            stage_level<O>(pv, st, y + (int64_t)(I - 1) * ls, lane, out, I);
+            stage_level<I, O>(pv, st, y + (int64_t)(I - 1) * ls, lane, out);
             LocalFwdReal<I + 1, O>::run(xv, pv, st, y, ls, lane, out);
         }
     }
@@ -394,8 +432,8 @@ __device__ __forceinline__ void real_local(const float* __restrict__ xin, const 
         pv[2 * b] = cadd(xv[2 * b], xv[2 * b + 1]);
         pv[2 * b + 1] = csub(xv[2 * b], xv[2 * b + 1]);
     }
-    float2* yv = y + 1024 * v;
-    stage_level<O>(pv, st, yv, lane, out, 1);
+    float2* yv = y + (O::kHalf ? 512 : 1024) * v;
+    stage_level<1, O>(pv, st, yv, lane, out);
     LocalFwdReal<2, O>::run(xv, pv, st, yv, ls, lane, out);
     __syncthreads();                             // staging done in every wave
 #pragma unroll

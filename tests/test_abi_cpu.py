@@ -108,3 +108,15 @@ def test_invalid_level_ranges(lo, hi):
     st = b.lib().mrdft_plan_create_levels(ctypes.byref(h), 10, 1, None, 0, 0, lo, hi, None)
     assert st == b.MRDFT_E_INVALID_ARG
     assert h.value is None
+
+
+@pytest.mark.parametrize("m,dtype,offsets", [(10, 0, None),            # complex input
+                                             (1, 1, None),             # N = 2 < 4
+                                             (0, 1, [0, 8, 10, 26])])  # one ragged signal of 2 samples
+def test_invalid_half_spectrum_plans(m, dtype, offsets):
+    b = _lib()
+    st, h = _create(b, m, 1 if offsets is None else len(offsets) - 1, offsets=offsets, dtype=dtype,
+                    flags=b.MRDFT_FLAG_HALF)
+    assert st == b.MRDFT_E_INVALID_ARG
+    assert h.value is None
+    assert "half" in b.last_error()
