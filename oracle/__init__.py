@@ -232,3 +232,43 @@ def adjoint_half(gh, method: int = AUTO) -> np.ndarray:
     """Gradient of a real loss of the packed values with respect to real x:
     Re(A^H unpack_half_zero(gh)), float64 (N,)."""
     return adjoint(unpack_half_zero(gh), method).real
+
+
+# ---------------------------------------------------------------------------
+# Two-dimensional separable MrDFT (the paper names two-dimensional signals as
+# an application and gives no formula).  Reading: for an image x of
+# N1 x N2 = 2^m1 x 2^m2 samples and every pair of levels (i1, i2), the 2-D DFT
+# of every non-overlapping 2^i1 x 2^i2 block,
+#   Y[i1, i2][b1 L1 + k1, b2 L2 + k2] =
+#       sum_{n1 < L1, n2 < L2} x[b1 L1 + n1, b2 L2 + n2] w_L1^{n1 k1} w_L2^{n2 k2},
+# i.e. Y[i1, i2] = A1_i1 x A2_i2^T with A_i the level-i block of eq. (1).
+# Being separable, it is computed here with the 1-D oracle along the rows and
+# then along the columns (the pins check it against the double sum itself).
+
+def forward2d(x, method: int = AUTO) -> np.ndarray:
+    """Image x (N1, N2) -> complex128 (m1, m2, N1, N2)."""
+    xc = _c128(x)
+    if xc.ndim != 2:
+        raise ValueError("x must be a 2-D array")
+    n1, n2 = xc.shape
+    m1, m2 = _order(n1), _order(n2)
+    rows = np.stack([forward(xc[r], method) for r in range(n1)])          # (N1, m2, N2)
+    out = np.empty((m1, m2, n1, n2), dtype=np.complex128)
+    for i2 in range(m2):
+        for c in range(n2):
+            out[:, i2, :, c] = forward(rows[:, i2, c], method)              # (m1, N1)
+    return out
+
+
+def adjoint2d(gy, method: int = AUTO) -> np.ndarray:
+    """gy (m1, m2, N1, N2) -> complex128 (N1, N2): the conjugate transpose of
+    forward2d, sum over level pairs of A1_i1^H gy[i1, i2] conj(A2_i2)."""
+    g = _c128(gy)
+    m1, m2, n1, n2 = g.shape
+    if _order(n1) != m1 or _order(n2) != m2:
+        raise ValueError("gy must have shape (m1, m2, 2^m1, 2^m2)")
+    part = np.empty((m2, n1, n2), dtype=np.complex128)
+    for i2 in range(m2):
+        for c in range(n2):
+            part[i2, :, c] = adjoint(g[:, i2, :, c], method)                # columns first
+    return np.stack([adjoint(part[:, r, :], method) for r in range(n1)])

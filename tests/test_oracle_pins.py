@@ -489,3 +489,82 @@ def test_half_adjoint_identity(m):
             e[p] = 1.0
             assert oracle.adjoint_half(g)[p] == pytest.approx(
                 np.real(np.vdot(g.reshape(-1), oracle.forward_half(e).reshape(-1))), abs=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Two-dimensional separable MrDFT.
+
+def _direct2d(x):
+    """The double sum of every block's 2-D DFT, exponents reduced exactly in
+    integers (brute force, tiny images only)."""
+    n1, n2 = x.shape
+    m1, m2 = n1.bit_length() - 1, n2.bit_length() - 1
+    out = np.zeros((m1, m2, n1, n2), dtype=np.complex128)
+    for i1 in range(1, m1 + 1):
+        L1 = 1 << i1
+        for i2 in range(1, m2 + 1):
+            L2 = 1 << i2
+            for p1 in range(n1):
+                b1, k1 = divmod(p1, L1)
+                for p2 in range(n2):
+                    b2, k2 = divmod(p2, L2)
+                    acc = 0j
+                    for a in range(L1):
+                        for c in range(L2):
+                            e1 = (a * k1) % L1
+                            e2 = (c * k2) % L2
+                            ang = -2.0 * np.pi * (e1 / L1 + e2 / L2)
+                            acc += x[b1 * L1 + a, b2 * L2 + c] * complex(np.cos(ang), np.sin(ang))
+                    out[i1 - 1, i2 - 1, p1, p2] = acc
+    return out
+
+
+@pytest.mark.parametrize("shape", [(2, 2), (4, 8), (8, 4)])
+def test_forward2d_matches_double_sum(shape):
+    rng = np.random.default_rng(300 + shape[0] * 10 + shape[1])
+    x = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    assert np.max(np.abs(oracle.forward2d(x) - _direct2d(x))) < 1e-11
+
+
+def test_forward2d_matches_numpy_fft2_per_block():
+    rng = np.random.default_rng(310)
+    x = rng.standard_normal((16, 32))
+    y = oracle.forward2d(x)
+    for i1 in range(1, 5):
+        for i2 in range(1, 6):
+            L1, L2 = 1 << i1, 1 << i2
+            blocks = x.reshape(16 // L1, L1, 32 // L2, L2).transpose(0, 2, 1, 3)
+            ref = np.fft.fft2(blocks).transpose(0, 2, 1, 3).reshape(16, 32)
+            assert np.max(np.abs(y[i1 - 1, i2 - 1] - ref)) < 1e-10
+
+
+def test_forward2d_parseval_and_impulse():
+    rng = np.random.default_rng(311)
+    x = rng.standard_normal((8, 16)) + 1j * rng.standard_normal((8, 16))
+    y = oracle.forward2d(x)
+    e = np.sum(np.abs(x) ** 2)
+    for i1 in range(1, 4):
+        for i2 in range(1, 5):
+            assert np.sum(np.abs(y[i1 - 1, i2 - 1]) ** 2) == pytest.approx(2 ** (i1 + i2) * e, rel=1e-12)
+    # impulse at (p, q): one block per level pair holds w_L1^{(p mod L1) k1} w_L2^{(q mod L2) k2}
+    d = np.zeros((8, 16))
+    d[5, 11] = 1.0
+    yd = oracle.forward2d(d)
+    for i1 in range(1, 4):
+        for i2 in range(1, 5):
+            L1, L2 = 1 << i1, 1 << i2
+            blk = np.zeros((8, 16), dtype=np.complex128)
+            b1, b2 = 5 // L1, 11 // L2
+            k1, k2 = np.arange(L1), np.arange(L2)
+            blk[b1 * L1:(b1 + 1) * L1, b2 * L2:(b2 + 1) * L2] = np.outer(
+                np.exp(-2j * np.pi * ((5 % L1) * k1 % L1) / L1), np.exp(-2j * np.pi * ((11 % L2) * k2 % L2) / L2))
+            assert np.max(np.abs(yd[i1 - 1, i2 - 1] - blk)) < 1e-12
+
+
+def test_adjoint2d_identity():
+    rng = np.random.default_rng(312)
+    x = rng.standard_normal((8, 4)) + 1j * rng.standard_normal((8, 4))
+    g = rng.standard_normal((3, 2, 8, 4)) + 1j * rng.standard_normal((3, 2, 8, 4))
+    lhs = np.vdot(g.reshape(-1), oracle.forward2d(x).reshape(-1))
+    rhs = np.vdot(oracle.adjoint2d(g), x)
+    assert abs(lhs - rhs) < 1e-10 * abs(lhs)
