@@ -107,8 +107,9 @@ def extra_workloads(steps, warmup, HBM):
     """Workloads beside the headline: one long complex signal (N = 2^24) and a
     ragged batch of 1000 complex signals (m in 8..18) through a tuned plan with
     graph replay (forward only), the real batch with packed half-spectrum
-    output, and the spectral loss forward + backward on 32 real pairs of 2^18
-    samples.  Inputs resident in HBM."""
+    output, the 2-D separable transform of 4 real 1024 x 1024 images, and the
+    spectral loss forward + backward on 32 real pairs of 2^18 samples.  Inputs
+    resident in HBM."""
     import numpy as np
     import torch
     from paper_1507_02525_amd import api, workloads
@@ -150,6 +151,22 @@ def extra_workloads(steps, warmup, HBM):
                              "Gsamples_per_s": round(plan.n_in / (ms * 1e-3) / 1e9, 3),
                              "hbm_frac": round(byts / (ms * 1e-3) / 1e9 / HBM, 4)}
     del Y, x, plan
+    torch.cuda.empty_cache()
+    # two-dimensional separable transform: 4 real images of 1024 x 1024, all 100 level pairs
+    rng = np.random.default_rng(1515)
+    x = torch.from_numpy(workloads.gaussian_real(rng, (4, 1024, 1024))).cuda()
+    plan2 = api.Plan2D(10, 10, batch=4, dtype="r32")
+    Y = torch.empty(plan2.n_out, dtype=torch.complex64, device="cuda")
+    fn = lambda: plan2.mrdft_forward2d(x, Y)   # noqa: E731
+    for _ in range(warmup):
+        fn()
+    ms = timed(fn, steps, torch.cuda.synchronize)
+    byts = plan2.n_in * 4 + plan2.n_out * 8
+    out["workload2d"] = {"workload": "2-D separable, 4 real float32 images 1024 x 1024, 100 level pairs",
+                         "ms_per_call": round(ms, 4),
+                         "Gsamples_per_s": round(plan2.n_in / (ms * 1e-3) / 1e9, 3),
+                         "hbm_frac": round(byts / (ms * 1e-3) / 1e9 / HBM, 4)}
+    del Y, x, plan2
     torch.cuda.empty_cache()
     # spectral loss, forward + backward: 32 real pairs of 2^18 samples
     d = workloads.make(5)

@@ -218,6 +218,45 @@ mrdft_status mrdft_plan_read_profile(mrdft_plan_t plan, int nkinds, double* tota
 /* Destroy a plan (NULL is accepted).  The handle must not be used afterwards. */
 mrdft_status mrdft_plan_destroy(mrdft_plan_t plan);
 
+/*
+ * Two-dimensional separable MrDFT.  Section 6 names two-dimensional signals
+ * as an application of the multiresolution representation; the transform is
+ * the 1-D one of eq. (1) applied along both axes.  For an image x of
+ * N1 x N2 = 2^m1 x 2^m2 samples (row-major: N2 consecutive samples per row)
+ * and every pair of levels (i1, i2), the 2-D DFT of every non-overlapping
+ * 2^i1 x 2^i2 block, L1 = 2^i1, L2 = 2^i2:
+ *
+ *   Y^(i1,i2)[b1 L1 + k1][b2 L2 + k2] =
+ *       sum_{n1 < L1, n2 < L2} x[b1 L1 + n1][b2 L2 + n2] w_L1^{n1 k1} w_L2^{n2 k2},
+ *
+ * w_L = exp(-j 2 pi / L), no normalisation; m1 * m2 * N1 * N2 complex outputs
+ * per image.  Layout of Y (complex64): Y[b][i1-1][n1][i2-1][n2], so the plane
+ * of the level pair (i1, i2) of image b starts at ((b m1 + i1 - 1) N1 m2 +
+ * i2 - 1) N2 with row stride m2 N2.  Computed as a column transform of the
+ * transposed images, a transpose, and a row transform; the plan owns that
+ * workspace (about (2 m1 + 1) N1 N2 complex values per image).
+ *
+ *   mrdft_plan2d_create : 1 <= m1, m2; batch >= 1 images; dtype of x
+ *                         (MRDFT_R32 or MRDFT_C64); uploads on `stream`
+ *                         (synchronised).  Errors: MRDFT_E_INVALID_ARG,
+ *                         MRDFT_E_ALLOC, MRDFT_E_HIP.
+ *   mrdft_plan2d_sizes  : samples in (batch N1 N2) and complex outputs
+ *                         (batch m1 m2 N1 N2).
+ *   mrdft_forward2d     : x device [batch][N1][N2] of the plan dtype ->
+ *                         Y device complex64 (layout above), overwritten.
+ *   mrdft_adjoint2d     : conjugate transpose, gY in Y's layout -> gx of the
+ *                         plan dtype (real plans: the real part), overwritten.
+ * Asynchronous on `stream`; one call at a time per plan (shared workspace).
+ * A handle that is not live gives MRDFT_E_INVALID_ARG.
+ */
+typedef struct mrdft_plan2d* mrdft_plan2d_t;
+mrdft_status mrdft_plan2d_create(mrdft_plan2d_t* plan, int m1, int m2, int64_t batch, mrdft_dtype dtype,
+                                 hipStream_t stream);
+mrdft_status mrdft_plan2d_sizes(mrdft_plan2d_t plan, int64_t* n_in, int64_t* n_out);
+mrdft_status mrdft_forward2d(mrdft_plan2d_t plan, const void* x, void* Y, hipStream_t stream);
+mrdft_status mrdft_adjoint2d(mrdft_plan2d_t plan, const void* gY, void* gx, hipStream_t stream);
+mrdft_status mrdft_plan2d_destroy(mrdft_plan2d_t plan);    /* NULL is accepted */
+
 /* Thread-local message of the last failing call on this thread ("" if none). */
 const char* mrdft_last_error(void);
 

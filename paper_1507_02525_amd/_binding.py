@@ -48,6 +48,11 @@ SIGNATURES = {
     "mrdft_plan_set_profiling": (ctypes.c_int, [_vp, ctypes.c_int]),
     "mrdft_plan_read_profile": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), _i64p]),
     "mrdft_plan_destroy": (ctypes.c_int, [_vp]),
+    "mrdft_plan2d_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _i64, ctypes.c_int, _vp]),
+    "mrdft_plan2d_sizes": (ctypes.c_int, [_vp, _i64p, _i64p]),
+    "mrdft_forward2d": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "mrdft_adjoint2d": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "mrdft_plan2d_destroy": (ctypes.c_int, [_vp]),
     "mrdft_last_error": (ctypes.c_char_p, []),
 }
 

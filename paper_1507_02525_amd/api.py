@@ -172,6 +172,72 @@ class Plan:
             pass
 
 
+class Plan2D:
+    """Owner of one ``mrdft_plan2d_t``: the separable 2-D transform of
+    ``batch`` images of 2^m1 x 2^m2 samples (see mrdft_plan2d_create).
+    ``forward`` returns complex64 of shape (batch, m1, N1, m2, N2): the plane
+    of the level pair (i1, i2) is ``Y[:, i1-1, :, i2-1, :]``."""
+
+    def __init__(self, m1: int, m2: int, batch: int = 1, dtype: str = "c64", device=None):
+        lib = B.lib()
+        self.dtype = dtype
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        code = {"c64": B.MRDFT_C64, "r32": B.MRDFT_R32}.get(dtype)
+        if code is None:
+            raise ValueError("dtype must be 'c64' or 'r32'")
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            stream = ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+            B.check(lib.mrdft_plan2d_create(ctypes.byref(h), int(m1), int(m2), int(batch), code, stream))
+        self.handle = h
+        self.m1, self.m2, self.batch = int(m1), int(m2), int(batch)
+        n_in = ctypes.c_int64()
+        n_out = ctypes.c_int64()
+        B.check(lib.mrdft_plan2d_sizes(h, ctypes.byref(n_in), ctypes.byref(n_out)))
+        self.n_in, self.n_out = n_in.value, n_out.value
+
+    def _want(self):
+        return torch.complex64 if self.dtype == "c64" else torch.float32
+
+    def mrdft_forward2d(self, x: torch.Tensor, Y: torch.Tensor) -> torch.Tensor:
+        if x.dtype != self._want() or not x.is_contiguous() or x.numel() != self.n_in or x.device != self.device:
+            raise ValueError("x must be a contiguous %s tensor of %d elements on %s"
+                             % (self._want(), self.n_in, self.device))
+        if Y.dtype != torch.complex64 or not Y.is_contiguous() or Y.numel() != self.n_out or Y.device != self.device:
+            raise ValueError("Y must be a contiguous complex64 tensor of %d elements" % self.n_out)
+        B.check(B.lib().mrdft_forward2d(self.handle, _ptr(x), _ptr(Y), _stream_ptr(x)))
+        return Y
+
+    def mrdft_adjoint2d(self, gY: torch.Tensor, gx: torch.Tensor) -> torch.Tensor:
+        if gY.dtype != torch.complex64 or not gY.is_contiguous() or gY.numel() != self.n_out:
+            raise ValueError("gY must be a contiguous complex64 tensor of %d elements" % self.n_out)
+        if gx.dtype != self._want() or not gx.is_contiguous() or gx.numel() != self.n_in:
+            raise ValueError("gx must be a contiguous %s tensor of %d elements" % (self._want(), self.n_in))
+        B.check(B.lib().mrdft_adjoint2d(self.handle, _ptr(gY), _ptr(gx), _stream_ptr(gY)))
+        return gx
+
+    def forward(self, x: torch.Tensor) -> torch.Tensor:
+        Y = torch.empty(self.n_out, dtype=torch.complex64, device=self.device)
+        self.mrdft_forward2d(x.contiguous(), Y)
+        return Y.view(self.batch, self.m1, 1 << self.m1, self.m2, 1 << self.m2)
+
+    def adjoint(self, gY: torch.Tensor) -> torch.Tensor:
+        gx = torch.empty(self.n_in, dtype=self._want(), device=self.device)
+        self.mrdft_adjoint2d(gY.contiguous().view(-1), gx)
+        return gx.view(self.batch, 1 << self.m1, 1 << self.m2)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            B.check(B.lib().mrdft_plan2d_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 _cache: dict = {}
 _cache_lock = threading.Lock()
 

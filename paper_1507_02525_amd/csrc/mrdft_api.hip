@@ -1025,6 +1025,12 @@ mrdft_status ensure_loss_workspace(mrdft_plan* p) {
 
 }  // namespace
 
+namespace mrdft {
+// Error reporting for the other host files of the library (thread-local
+// message returned by mrdft_last_error).
+mrdft_status report_error(mrdft_status st, const char* msg) { return fail(st, "%s", msg); }
+}  // namespace mrdft
+
 extern "C" {
 
 const char* mrdft_last_error(void) { return g_last_error.c_str(); }

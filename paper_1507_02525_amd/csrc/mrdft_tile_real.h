@@ -125,6 +125,13 @@ __device__ __forceinline__ float2 wq2(const float2* Q, int e) {
 // slots of P).
 __device__ __forceinline__ int fpad(int i) { return i + (i >> 5); }
 
+// The samples X sit at a swizzled index: within each 64-sample (256-byte)
+// row the sixteen 16-byte slots are XORed with (5 row) mod 16.  The first
+// step of every level reads the window halves of many small windows at once
+// (windows of 64 samples all start on the same banks); the swizzle spreads
+// them over the banks and keeps 16-byte groups (float4) and pairs contiguous.
+__device__ __forceinline__ int xsw(int i) { return i ^ (((5 * (i >> 6)) & 15) << 2); }
+
 // One in-place radix-R Stockham step over NW FFTs of H points in F (contiguous
 // per window), span 2^LNS before the step.  256 threads, R in {2, 4}.
 template <int R, int H, int NW, int LNS>
@@ -210,12 +217,11 @@ __device__ __forceinline__ void real_level(RealTileLds& S, float2* __restrict__ 
         for (int c = 0; c < JPT; ++c) {
             const int J = tid + c * kRThreads;
             const int w = J / PER, j = J % PER;
-            const float* xw = S.X + w * L;
 #pragma unroll
             for (int s = 0; s < R1; ++s) {
                 const int p = j + s * PER;
-                const float2 lo = *(const float2*)(xw + 2 * p);
-                const float2 hi = *(const float2*)(xw + M + 2 * p);
+                const float2 lo = *(const float2*)(S.X + xsw(w * L + 2 * p));
+                const float2 hi = *(const float2*)(S.X + xsw(w * L + M + 2 * p));
                 const float2 z = make_float2(lo.x - hi.x, lo.y - hi.y);
                 v[c][s] = cmul(z, wq2<I - 1>(S.Q, p));                   // w_M^p, p < M/2
             }
@@ -253,11 +259,10 @@ __device__ __forceinline__ void real_level(RealTileLds& S, float2* __restrict__ 
         const int J = tid + c * kRThreads;
         const int w = J / (H / 2), k = J % (H / 2);
         const int j = H - 1 - k;
+        // one 16-byte store per slot pair (lanes 16 bytes apart fill the banks)
         float2* pw = S.P + w * M;
-        pw[2 * k] = uk[c];
-        pw[2 * k + 1] = ok[c];
-        pw[2 * j] = uj[c];
-        pw[2 * j + 1] = oj[c];
+        *(float4*)(pw + 2 * k) = make_float4(uk[c].x, uk[c].y, ok[c].x, ok[c].y);
+        *(float4*)(pw + 2 * j) = make_float4(uj[c].x, uj[c].y, oj[c].x, oj[c].y);
         // Full spectrum: bins 2k, 2k+1 (lower half) and the aligned upper pairs
         // (L/2 + 2t, L/2 + 2t + 1) = (conj u[H-t], conj o[H-1-t]), t = j and t = k;
         // bin 0 is real, bin L/2 (Nyquist) is the second half of slot 0.
@@ -309,10 +314,11 @@ __device__ __forceinline__ void wave_sync() {
 // Writes one register-phase level (16 complex values per thread, one window
 // each) through the wave's private LDS region, so that every global store
 // instruction covers 1 KB of consecutive output.  Pair e of lane l sits at
-// 8l + (e ^ (l & 7)) (XOR swizzle: conflict-free writes and reads).
+// 8l + (e ^ ((l / 2) mod 8)): the 16 lanes served per LDS cycle (16 bytes
+// each) then fall on distinct banks, for the writes and for the reads.
 // Half-spectrum output: the lane's 8 packed slots (slot 0 of each window =
-// (Y[0], Y[L/2])), pair e of lane l at 4l + (e ^ (l & 3)), 512 B per store
-// instruction.
+// (Y[0], Y[L/2])), pair e of lane l at 4l + (e ^ ((l / 4) mod 4)), 512 B per
+// store instruction.
 template <int I, class O>
 __device__ __forceinline__ void stage_level(const float2* pv, float4* st, float2* __restrict__ yl, int lane, O& out) {
     constexpr int level = I;
@@ -334,13 +340,13 @@ __device__ __forceinline__ void stage_level(const float2* pv, float4* st, float2
             for (int k = 1; k < M; ++k) hv[w * M + k] = pv[w * L + k];
         }
 #pragma unroll
-        for (int e = 0; e < 4; ++e) st[4 * lane + (e ^ (lane & 3))] = make_float4(hv[2 * e].x, hv[2 * e].y,
-                                                                                 hv[2 * e + 1].x, hv[2 * e + 1].y);
+        for (int e = 0; e < 4; ++e)
+            st[4 * lane + (e ^ ((lane >> 2) & 3))] = make_float4(hv[2 * e].x, hv[2 * e].y, hv[2 * e + 1].x, hv[2 * e + 1].y);
         wave_sync();
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int p = 64 * r + lane, wl = p >> 2, e = p & 3;
-            *(float4*)(yl + 2 * p) = st[4 * wl + (e ^ (wl & 3))];
+            *(float4*)(yl + 2 * p) = st[4 * wl + (e ^ ((wl >> 2) & 3))];
         }
         wave_sync();
         return;
@@ -348,13 +354,13 @@ __device__ __forceinline__ void stage_level(const float2* pv, float4* st, float2
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
         const float2 a = out.sc(level, pv[2 * e]), b = out.sc(level, pv[2 * e + 1]);
-        st[8 * lane + (e ^ (lane & 7))] = make_float4(a.x, a.y, b.x, b.y);
+        st[8 * lane + (e ^ ((lane >> 1) & 7))] = make_float4(a.x, a.y, b.x, b.y);
     }
     wave_sync();
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
         const int p = 64 * r + lane, wl = p >> 3, e = p & 7;
-        *(float4*)(yl + 2 * p) = st[8 * wl + (e ^ (wl & 7))];
+        *(float4*)(yl + 2 * p) = st[8 * wl + (e ^ ((wl >> 1) & 7))];
     }
     wave_sync();
 }
@@ -412,14 +418,20 @@ __device__ __forceinline__ void real_local(const float* __restrict__ xin, const 
                 a[r] = make_float2(a[r].x - b.x, a[r].y - b.y);
             }
         }
+        // pair q goes to lane q / 8, 16-byte slot ((q / 2) mod 4) XOR ((q / 32) mod 4)
+        // of that lane's 64 bytes: the lanes' 16-byte reads below then cover
+        // all banks
 #pragma unroll
-        for (int r = 0; r < 8; ++r) *(float2*)(xs + 2 * (64 * r + lane)) = a[r];
+        for (int r = 0; r < 8; ++r) {
+            const int q = 64 * r + lane, ol = q >> 3, e = q & 7;
+            *(float2*)(xs + C * ol + 4 * ((e >> 1) ^ ((ol >> 2) & 3)) + 2 * (e & 1)) = a[r];
+        }
     }
     wave_sync();
     float2 xv[C], pv[C];
 #pragma unroll
     for (int e = 0; e < C / 4; ++e) {
-        const float4 a = *(const float4*)(xs + C * lane + 4 * e);
+        const float4 a = *(const float4*)(xs + C * lane + 4 * (e ^ ((lane >> 2) & 3)));
         xv[4 * e] = make_float2(a.x, 0.0f);
         xv[4 * e + 1] = make_float2(a.y, 0.0f);
         xv[4 * e + 2] = make_float2(a.z, 0.0f);
@@ -438,11 +450,20 @@ __device__ __forceinline__ void real_local(const float* __restrict__ xin, const 
     __syncthreads();                             // staging done in every wave
 #pragma unroll
     for (int e = 0; e < C / 4; ++e)
-        *(float4*)(S.X + C * tid + 4 * e) = make_float4(xv[4 * e].x, xv[4 * e + 1].x, xv[4 * e + 2].x, xv[4 * e + 3].x);
-    float2* pd = S.P + tid * 8;
-    pd[0] = make_float2(pv[0].x, pv[8].x);
+        *(float4*)(S.X + xsw(C * tid + 4 * e)) =
+            make_float4(xv[4 * e].x, xv[4 * e + 1].x, xv[4 * e + 2].x, xv[4 * e + 3].x);
+    // the 8 slots as four 16-byte pairs, pair c written at step c XOR ((tid / 4)
+    // mod 4), so that the 16 lanes of one step cover all banks
+    pv[0].y = pv[8].x;
+    float4* pd = (float4*)(S.P + tid * 8);
+    const int rot = (tid >> 2) & 3;
 #pragma unroll
-    for (int s = 1; s < 8; ++s) pd[s] = pv[s];
+    for (int c = 0; c < 4; ++c) {
+        const int cc = c ^ rot;
+        const float2 a = cc == 0 ? pv[0] : cc == 1 ? pv[2] : cc == 2 ? pv[4] : pv[6];
+        const float2 b = cc == 0 ? pv[1] : cc == 1 ? pv[3] : cc == 2 ? pv[5] : pv[7];
+        pd[cc] = make_float4(a.x, a.y, b.x, b.y);
+    }
 }
 
 // One full tile: x points at the tile's first sample (minus xsub's, if given),

@@ -22,7 +22,7 @@ def _lib():
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(mrdft_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(mrdft_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_header_declares_the_expected_calls():
@@ -120,3 +120,25 @@ def test_invalid_half_spectrum_plans(m, dtype, offsets):
     assert st == b.MRDFT_E_INVALID_ARG
     assert h.value is None
     assert "half" in b.last_error()
+
+
+@pytest.mark.parametrize("m1,m2,batch,dtype", [(0, 4, 1, 0), (4, 0, 1, 1), (29, 2, 1, 0), (24, 20, 1, 0),
+                                               (4, 4, 0, 0), (4, 4, 1, 9)])
+def test_invalid_2d_plans(m1, m2, batch, dtype):
+    b = _lib()
+    h = ctypes.c_void_p()
+    assert b.lib().mrdft_plan2d_create(ctypes.byref(h), m1, m2, batch, dtype, None) == b.MRDFT_E_INVALID_ARG
+    assert h.value is None
+    assert b.last_error() != ""
+
+
+def test_2d_bogus_handles():
+    b = _lib()
+    lib = b.lib()
+    bogus = ctypes.c_void_p(0x1234)
+    n = ctypes.c_int64()
+    assert lib.mrdft_plan2d_sizes(bogus, ctypes.byref(n), ctypes.byref(n)) == b.MRDFT_E_INVALID_ARG
+    assert lib.mrdft_forward2d(bogus, None, None, None) == b.MRDFT_E_INVALID_ARG
+    assert lib.mrdft_adjoint2d(bogus, None, None, None) == b.MRDFT_E_INVALID_ARG
+    assert lib.mrdft_plan2d_destroy(bogus) == b.MRDFT_E_INVALID_ARG
+    assert lib.mrdft_plan2d_destroy(None) == b.MRDFT_OK
