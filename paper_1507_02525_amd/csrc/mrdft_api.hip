@@ -101,6 +101,8 @@ struct mrdft_plan {
     TileJob* d_jobs = nullptr;
     int64_t njobs = 0;
     int64_t njobs_full = 0;                 // leading jobs with t = 12 (full 4096-sample tiles)
+    int jobs_tmax = 1, tail_tmax = 1;       // largest t of all tile jobs / of those after njobs_full
+    int small_tmax = 1, asmall_tmax = 1;    // largest t of d_small / d_asmall
     std::vector<Group> groups;
     float2* d_tw_tile = nullptr;
     double2* d_tw_hi = nullptr;
@@ -351,6 +353,10 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
     p->njobs = (int64_t)jobs.size();
     p->njobs_full = 0;
     while (p->njobs_full < p->njobs && jobs[p->njobs_full].t == kRealTileLog) ++p->njobs_full;
+    for (int64_t q = 0; q < p->njobs; ++q) {
+        p->jobs_tmax = std::max(p->jobs_tmax, (int)jobs[q].t);
+        if (q >= p->njobs_full) p->tail_tmax = std::max(p->tail_tmax, (int)jobs[q].t);
+    }
     if (hipMalloc(&p->d_jobs, sizeof(TileJob) * jobs.size()) != hipSuccess)
         return fail(MRDFT_E_ALLOC, "tile table allocation failed (%zu bytes)", sizeof(TileJob) * jobs.size());
     HIP_TRY(hipMemcpyAsync(p->d_jobs, jobs.data(), sizeof(TileJob) * jobs.size(), hipMemcpyHostToDevice, s));
@@ -367,6 +373,7 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
             small.push_back(TileJob{p->in_off[j], p->base(j), int64_t(1) << mj, mj, p->range()});
         }
         p->nsmall = (int64_t)small.size();
+        for (const TileJob& t : small) p->small_tmax = std::max(p->small_tmax, (int)t.t);
         if (!small.empty()) {
             if (hipMalloc(&p->d_small, sizeof(TileJob) * small.size()) != hipSuccess)
                 return fail(MRDFT_E_ALLOC, "tile table allocation failed");
@@ -425,6 +432,7 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
         p->najobs = (int64_t)aj.size();
         p->nacols = (int64_t)cj.size();
         p->nasmall = (int64_t)sm.size();
+        for (const TileJob& t : sm) p->asmall_tmax = std::max(p->asmall_tmax, (int)t.t);
         if ((!aj.empty() && hipMalloc(&p->d_ajobs, sizeof(RealJob) * aj.size()) != hipSuccess) ||
             (!cj.empty() && hipMalloc(&p->d_acols, sizeof(AdjColJob) * cj.size()) != hipSuccess) ||
             (!sm.empty() && hipMalloc(&p->d_asmall, sizeof(TileJob) * sm.size()) != hipSuccess) ||
@@ -761,12 +769,12 @@ mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, h
             }
             if (p->njobs > p->njobs_full) {
                 ProfScope ps(p, MRDFT_KERNEL_TILE_FWD, s0);
-                HIP_TRY(launch_tile_fwd(true, x, Y, p->d_jobs + p->njobs_full, p->njobs - p->njobs_full, tw, s0,
+                HIP_TRY(launch_tile_fwd(true, x, Y, p->d_jobs + p->njobs_full, p->njobs - p->njobs_full, p->tail_tmax, tw, s0,
                                         p->hs != 0));
             }
         } else if (in_kind == IN_R32) {
             ProfScope ps(p, MRDFT_KERNEL_TILE_FWD, s0);
-            HIP_TRY(launch_tile_fwd(true, x, Y, p->d_jobs, p->njobs, tw, s0, p->hs != 0));
+            HIP_TRY(launch_tile_fwd(true, x, Y, p->d_jobs, p->njobs, p->jobs_tmax, tw, s0, p->hs != 0));
         } else if (cjobs_cover) {
             {
                 ProfScope ps(p, MRDFT_KERNEL_FUSED_FWD, s0);
@@ -775,11 +783,11 @@ mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, h
             }
             if (p->nsmall) {
                 ProfScope ps(p, MRDFT_KERNEL_TILE_FWD, s0);
-                HIP_TRY(launch_tile_fwd(false, x, Y, p->d_small, p->nsmall, tw, s0));
+                HIP_TRY(launch_tile_fwd(false, x, Y, p->d_small, p->nsmall, p->small_tmax, tw, s0));
             }
         } else {
             ProfScope ps(p, MRDFT_KERNEL_TILE_FWD, s0);
-            HIP_TRY(launch_tile_fwd(false, x, Y, p->d_jobs, p->njobs, tw, s0));
+            HIP_TRY(launch_tile_fwd(false, x, Y, p->d_jobs, p->njobs, p->jobs_tmax, tw, s0));
         }
     }
     for (int k = 0; k < p->nsides; ++k) {
@@ -805,7 +813,7 @@ mrdft_status run_adjoint(mrdft_plan* p, const float2* gY, void* gx, bool real_ou
     }
     if (p->nasmall) {
         ProfScope ps(p, MRDFT_KERNEL_TILE_ADJ, s);
-        HIP_TRY(launch_tile_adj(real_out, gY, gx, p->d_asmall, p->nasmall, tw, s));
+        HIP_TRY(launch_tile_adj(real_out, gY, gx, p->d_asmall, p->nasmall, p->asmall_tmax, tw, s));
     }
     if (p->nacols) {
         ProfScope ps(p, MRDFT_KERNEL_PASS_ADJ, s);

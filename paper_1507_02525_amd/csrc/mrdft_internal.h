@@ -115,11 +115,12 @@ hipError_t launch_fwd_c64(const float2* x, float2* Y, const RealJob* jobs, int64
                           unsigned* queue, int grid, const Twiddles& tw, hipStream_t s);
 // half (real input only): packed half-spectrum output, job offsets and level
 // strides in those units.
-hipError_t launch_tile_fwd(bool real_in, const void* x, float2* Y, const TileJob* jobs, int64_t njobs,
+// tmax: the largest tile order t among the jobs (sizes the launch's LDS).
+hipError_t launch_tile_fwd(bool real_in, const void* x, float2* Y, const TileJob* jobs, int64_t njobs, int tmax,
                            const Twiddles& tw, hipStream_t s, bool half = false);
 // Real input, 4096-sample tiles (levels 1..12): see mrdft_tile_real.h.
 constexpr int kRealTileLog = 12;
-hipError_t launch_tile_adj(bool real_out, const float2* gY, void* gx, const TileJob* jobs, int64_t njobs,
+hipError_t launch_tile_adj(bool real_out, const float2* gY, void* gx, const TileJob* jobs, int64_t njobs, int tmax,
                            const Twiddles& tw, hipStream_t s);
 // Single-pass levels with window 2^(10 + rl), 1 <= rl <= 6 (see mrdft_upper.hip).
 constexpr int kUpperMaxLevel = 16;

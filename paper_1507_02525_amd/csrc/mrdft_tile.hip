@@ -31,6 +31,32 @@ struct XType<true> {
     using T = float;
 };
 
+// LDS of one launch, sized for its largest tile 2^tmax (dynamic shared
+// memory): small tiles leave room for more workgroups per CU.
+extern __shared__ __align__(16) unsigned char g_tile_lds[];
+template <typename XT>
+struct TileLds {
+    XT* X;
+    float2* P;
+    float2* F;
+    float2* Q;
+};
+__host__ __device__ constexpr size_t align16(size_t b) { return (b + 15) & ~size_t(15); }
+template <typename XT>
+__host__ __device__ constexpr size_t tile_lds_bytes(int tmax) {
+    return align16(sizeof(XT) * padded_size(1 << tmax)) + sizeof(float2) * padded_size(1 << tmax) +
+           sizeof(float2) * padded_size((1 << tmax) / 2) + sizeof(float2) * kQuarter;
+}
+template <typename XT>
+__device__ __forceinline__ TileLds<XT> tile_lds(int tmax) {
+    TileLds<XT> L;
+    L.X = (XT*)g_tile_lds;
+    L.P = (float2*)(g_tile_lds + align16(sizeof(XT) * padded_size(1 << tmax)));
+    L.F = L.P + padded_size(1 << tmax);
+    L.Q = L.F + padded_size((1 << tmax) / 2);
+    return L;
+}
+
 __device__ __forceinline__ float2 to_c(float v) { return make_float2(v, 0.0f); }
 __device__ __forceinline__ float2 to_c(float2 v) { return v; }
 
@@ -155,12 +181,13 @@ __device__ __forceinline__ void first_load_fwd(const XT* Xs, int i, int nw, cons
 template <bool REAL, bool HALF>
 __global__ __launch_bounds__(kTileThreads) void tile_fwd_kernel(const void* __restrict__ x, float2* __restrict__ Y,
                                                                 const TileJob* __restrict__ jobs,
-                                                                const float2* __restrict__ tab) {
+                                                                const float2* __restrict__ tab, int tmax) {
     using XT = typename XType<REAL>::T;
-    __shared__ XT Xs[padded_size(kTileMax)];          // x tile
-    __shared__ float2 Ps[padded_size(kTileMax)];      // previous level, natural bin order
-    __shared__ float2 Fs[padded_size(kTileMax / 2)];  // odd-bin FFT work space
-    __shared__ float2 Qs[kQuarter];                   // twiddle quarter table
+    const TileLds<XT> L = tile_lds<XT>(tmax);
+    XT* Xs = L.X;                                     // x tile
+    float2* Ps = L.P;                                 // previous level, natural bin order
+    float2* Fs = L.F;                                 // odd-bin FFT work space
+    float2* Qs = L.Q;                                 // twiddle quarter table
 
     const TileJob jb = jobs[blockIdx.x];
     const int t = jb.t;
@@ -378,12 +405,13 @@ __device__ __forceinline__ void first_load_adj(const float2* Ps, int i, int nw, 
 template <bool REAL>
 __global__ __launch_bounds__(kTileThreads) void tile_adj_kernel(const float2* __restrict__ gY, void* __restrict__ gx,
                                                                 const TileJob* __restrict__ jobs,
-                                                                const float2* __restrict__ tab) {
+                                                                const float2* __restrict__ tab, int tmax) {
     using XT = typename XType<REAL>::T;
-    __shared__ XT Xs[padded_size(kTileMax)];          // gx accumulator (real part only for real x)
-    __shared__ float2 Ps[padded_size(kTileMax)];      // current level gradient G
-    __shared__ float2 Fs[padded_size(kTileMax / 2)];
-    __shared__ float2 Qs[kQuarter];
+    const TileLds<XT> L = tile_lds<XT>(tmax);
+    XT* Xs = L.X;                                     // gx accumulator (real part only for real x)
+    float2* Ps = L.P;                                 // current level gradient G
+    float2* Fs = L.F;
+    float2* Qs = L.Q;
 
     const TileJob jb = jobs[blockIdx.x];
     const int t = jb.t;
@@ -496,23 +524,44 @@ __global__ __launch_bounds__(kTileThreads) void tile_adj_kernel(const float2* __
     }
 }
 
-hipError_t launch_tile_fwd(bool real_in, const void* x, float2* Y, const TileJob* jobs, int64_t njobs,
+// Allow the largest tile's dynamic LDS (above the 64 KB default) once per kernel.
+template <typename XT, typename K>
+void allow_tile_lds(K kernel) {
+    (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)tile_lds_bytes<XT>(kTileMaxLog));
+}
+struct TileLdsInit {
+    TileLdsInit() {
+        allow_tile_lds<float>(tile_fwd_kernel<true, true>);
+        allow_tile_lds<float>(tile_fwd_kernel<true, false>);
+        allow_tile_lds<float2>(tile_fwd_kernel<false, false>);
+        allow_tile_lds<float>(tile_adj_kernel<true>);
+        allow_tile_lds<float2>(tile_adj_kernel<false>);
+    }
+};
+
+hipError_t launch_tile_fwd(bool real_in, const void* x, float2* Y, const TileJob* jobs, int64_t njobs, int tmax,
                            const Twiddles& tw, hipStream_t s, bool half) {
     if (njobs <= 0) return hipSuccess;
-    if (half && !real_in) return hipErrorInvalidValue;
+    if ((half && !real_in) || tmax < 1 || tmax > kTileMaxLog) return hipErrorInvalidValue;
+    static TileLdsInit once;
     dim3 grid((unsigned)njobs), block(kTileThreads);
-    if (half) hipLaunchKernelGGL((tile_fwd_kernel<true, true>), grid, block, 0, s, x, Y, jobs, tw.tile);
-    else if (real_in) hipLaunchKernelGGL((tile_fwd_kernel<true, false>), grid, block, 0, s, x, Y, jobs, tw.tile);
-    else hipLaunchKernelGGL((tile_fwd_kernel<false, false>), grid, block, 0, s, x, Y, jobs, tw.tile);
+    const size_t lds = real_in ? tile_lds_bytes<float>(tmax) : tile_lds_bytes<float2>(tmax);
+    if (half) hipLaunchKernelGGL((tile_fwd_kernel<true, true>), grid, block, lds, s, x, Y, jobs, tw.tile, tmax);
+    else if (real_in) hipLaunchKernelGGL((tile_fwd_kernel<true, false>), grid, block, lds, s, x, Y, jobs, tw.tile, tmax);
+    else hipLaunchKernelGGL((tile_fwd_kernel<false, false>), grid, block, lds, s, x, Y, jobs, tw.tile, tmax);
     return hipGetLastError();
 }
 
-hipError_t launch_tile_adj(bool real_out, const float2* gY, void* gx, const TileJob* jobs, int64_t njobs,
+hipError_t launch_tile_adj(bool real_out, const float2* gY, void* gx, const TileJob* jobs, int64_t njobs, int tmax,
                            const Twiddles& tw, hipStream_t s) {
     if (njobs <= 0) return hipSuccess;
+    if (tmax < 1 || tmax > kTileMaxLog) return hipErrorInvalidValue;
+    static TileLdsInit once;
     dim3 grid((unsigned)njobs), block(kTileThreads);
-    if (real_out) hipLaunchKernelGGL(tile_adj_kernel<true>, grid, block, 0, s, gY, gx, jobs, tw.tile);
-    else hipLaunchKernelGGL(tile_adj_kernel<false>, grid, block, 0, s, gY, gx, jobs, tw.tile);
+    const size_t lds = real_out ? tile_lds_bytes<float>(tmax) : tile_lds_bytes<float2>(tmax);
+    if (real_out) hipLaunchKernelGGL(tile_adj_kernel<true>, grid, block, lds, s, gY, gx, jobs, tw.tile, tmax);
+    else hipLaunchKernelGGL(tile_adj_kernel<false>, grid, block, lds, s, gY, gx, jobs, tw.tile, tmax);
     return hipGetLastError();
 }
 
