@@ -138,7 +138,8 @@ mrdft_status mrdft_plan_sizes(mrdft_plan_t plan, int64_t* n_in, int64_t* n_out);
  *   tile_log : levels computed per on-chip tile (11 or 12 for complex plans,
  *              12 for real plans); the levels above come from the upper-level
  *              jobs and passes.
- *   grid     : workgroups of the persistent complex launch (0: not used).
+ *   grid     : workgroups of the persistent complex launch (0: one
+ *              workgroup per job, or not used).
  *   order    : job order, MRDFT_ORDER_*.
  * Any output pointer may be NULL.
  */
@@ -150,7 +151,8 @@ mrdft_status mrdft_plan_schedule(mrdft_plan_t plan, int* tile_log, int* grid, in
 /*
  * Pin the forward schedule (e.g. one saved from an earlier tuning run) instead
  * of tuning again.  tile_log: 11 or 12 for complex plans, 12 for real plans;
- * grid: workgroups of the persistent complex launch (>= 1, ignored otherwise);
+ * grid: workgroups of the persistent complex launch (>= 1; 0: one workgroup
+ * per job; ignored for real plans and tile_log 12);
  * order: MRDFT_ORDER_*.  Drops a captured forward graph.  Synchronises
  * `stream` (the job table is re-uploaded).
  * Errors: MRDFT_E_INVALID_ARG for values outside these sets.

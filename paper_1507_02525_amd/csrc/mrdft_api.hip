@@ -119,6 +119,7 @@ struct mrdft_plan {
     // tiles and one launch per upper level (tile_log 12)
     RealJob* d_cjobs = nullptr;
     int64_t ncjobs = 0;
+    bool cjobs_direct = false;              // d_cjobs dealt for one workgroup per job (grid 0)
     TileJob* d_small = nullptr;             // tiles of complex signals of order < 11
     int64_t nsmall = 0;
     unsigned* d_queue = nullptr;            // persistent launch: next job per XCD segment, workgroups done
@@ -322,7 +323,7 @@ mrdft_status upload_twiddles(mrdft_plan* p, hipStream_t s) {
 
 std::vector<RealJob> real_jobs(const mrdft_plan* p, int order);
 std::vector<RealJob> complex_jobs(const mrdft_plan* p, int order, std::vector<unsigned>* seg);
-mrdft_status upload_cjobs(mrdft_plan* p, int order, hipStream_t s);
+mrdft_status upload_cjobs(mrdft_plan* p, int order, hipStream_t s, bool direct);
 mrdft_status upload_jobs(const std::vector<RealJob>& v, RealJob** dst, int64_t* n, hipStream_t s);
 
 mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
@@ -364,7 +365,7 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
         mrdft_status st = upload_jobs(real_jobs(p, p->order), &p->d_rjobs, &p->nrjobs, s);
         if (st) return st;
     } else {
-        mrdft_status st = upload_cjobs(p, p->order, s);
+        mrdft_status st = upload_cjobs(p, p->order, s, true);   // default: one workgroup per job
         if (st) return st;
         std::vector<TileJob> small;
         for (int64_t j = 0; j < p->batch; ++j) {
@@ -380,14 +381,11 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
             HIP_TRY(hipMemcpyAsync(p->d_small, small.data(), sizeof(TileJob) * small.size(), hipMemcpyHostToDevice, s));
         }
         if (p->ncjobs > 0) {
-            if (hipMalloc(&p->d_queue, kC64Queues * sizeof(unsigned)) != hipSuccess)
+            if (!p->d_queue && hipMalloc(&p->d_queue, kC64Queues * sizeof(unsigned)) != hipSuccess)
                 return fail(MRDFT_E_ALLOC, "queue allocation failed");
             HIP_TRY(hipMemsetAsync(p->d_queue, 0, kC64Queues * sizeof(unsigned), s));   // once; kernels restore it
             p->tile_log = kC64TileLog;
-            // one workgroup per CU by default: the pieces of a level-16 window
-            // re-read its x columns, and fewer windows in flight per XCD keep
-            // them in L2 (the tuner also tries 2 and 4 per CU)
-            p->grid = (int)std::min<int64_t>(p->ncjobs, (int64_t)p->num_cu);
+            p->grid = 0;      // one workgroup per job (the tuner also tries persistent grids)
         }
     }
     {
@@ -635,10 +633,12 @@ std::vector<RealJob> complex_jobs(const mrdft_plan* p, int order, std::vector<un
 }
 
 // Complex job table in per-XCD segments, with its segment starts.
-mrdft_status upload_cjobs(mrdft_plan* p, int order, hipStream_t s) {
+mrdft_status upload_cjobs(mrdft_plan* p, int order, hipStream_t s, bool direct) {
     std::vector<unsigned> seg;
-    mrdft_status st = upload_jobs(complex_jobs(p, order, &seg), &p->d_cjobs, &p->ncjobs, s);
+    mrdft_status st = upload_jobs(complex_jobs(p, order, direct ? nullptr : &seg), &p->d_cjobs, &p->ncjobs, s);
     if (st) return st;
+    p->cjobs_direct = direct;
+    if (direct) return MRDFT_OK;
     if (!p->d_cseg && hipMalloc(&p->d_cseg, sizeof(unsigned) * seg.size()) != hipSuccess)
         return fail(MRDFT_E_ALLOC, "segment table allocation failed");
     HIP_TRY(hipMemcpyAsync(p->d_cseg, seg.data(), sizeof(unsigned) * seg.size(), hipMemcpyHostToDevice, s));
@@ -778,6 +778,9 @@ mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, h
         } else if (cjobs_cover) {
             {
                 ProfScope ps(p, MRDFT_KERNEL_FUSED_FWD, s0);
+                if (p->grid == 0)
+                    HIP_TRY(launch_fwd_c64_direct((const float2*)x, Y, p->d_cjobs, p->ncjobs, tw, s0));
+                else
                 HIP_TRY(launch_fwd_c64((const float2*)x, Y, p->d_cjobs, p->ncjobs, p->d_cseg, p->d_queue, p->grid, tw,
                                        s0));
             }
@@ -932,6 +935,7 @@ mrdft_status tune(mrdft_plan* p, hipStream_t s) {
         if (real) {
             cands.push_back({kRealTileLog, order, 0});
         } else {
+            cands.push_back({kC64TileLog, order, 0});
             for (int per = 1; per <= 4; per *= 2)
                 cands.push_back({kC64TileLog, order, (int)std::min<int64_t>(p->ncjobs, (int64_t)per * p->num_cu)});
         }
@@ -942,9 +946,9 @@ mrdft_status tune(mrdft_plan* p, hipStream_t s) {
     int cur_order = p->order;
     for (const Cand& c : cands) {
         if (st) break;
-        if (c.tile_log != kTileMaxLog && c.order != cur_order) {
+        if (c.tile_log != kTileMaxLog && (c.order != cur_order || (!real && (c.grid == 0) != p->cjobs_direct))) {
             st = real ? upload_jobs(real_jobs(p, c.order), &p->d_rjobs, &p->nrjobs, s)
-                      : upload_cjobs(p, c.order, s);
+                      : upload_cjobs(p, c.order, s, c.grid == 0);
             cur_order = c.order;
             if (st) break;
         }
@@ -957,9 +961,10 @@ mrdft_status tune(mrdft_plan* p, hipStream_t s) {
             best = c;
         }
     }
-    if (!st && best.tile_log != kTileMaxLog && best.order != cur_order)
+    if (!st && best.tile_log != kTileMaxLog &&
+        (best.order != cur_order || (!real && (best.grid == 0) != p->cjobs_direct)))
         st = real ? upload_jobs(real_jobs(p, best.order), &p->d_rjobs, &p->nrjobs, s)
-                  : upload_cjobs(p, best.order, s);
+                  : upload_cjobs(p, best.order, s, best.grid == 0);
     p->tile_log = best.tile_log;
     p->order = best.tile_log == kTileMaxLog && !real ? cur_order : best.order;
     p->grid = best.grid;
@@ -1181,10 +1186,11 @@ mrdft_status mrdft_plan_set_schedule(mrdft_plan_t plan, int tile_log, int grid, 
         return fail(MRDFT_E_INVALID_ARG, "unknown job order %d", order);
     if (real ? tile_log != kRealTileLog : (tile_log != kC64TileLog && tile_log != kTileMaxLog))
         return fail(MRDFT_E_INVALID_ARG, "tile_log %d is not available for this plan", tile_log);
-    if (!real && tile_log == kC64TileLog && grid < 1) return fail(MRDFT_E_INVALID_ARG, "grid must be >= 1");
-    if (order != plan->order) {
+    if (!real && tile_log == kC64TileLog && grid < 0) return fail(MRDFT_E_INVALID_ARG, "grid must be >= 0");
+    const bool direct = !real && tile_log == kC64TileLog && grid == 0;
+    if (order != plan->order || (!real && plan->ncjobs > 0 && direct != plan->cjobs_direct)) {
         st = real ? upload_jobs(real_jobs(plan, order), &plan->d_rjobs, &plan->nrjobs, stream)
-                  : upload_cjobs(plan, order, stream);
+                  : upload_cjobs(plan, order, stream, direct);
         if (st) return st;
         plan->order = order;
     }

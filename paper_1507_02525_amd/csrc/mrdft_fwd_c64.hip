@@ -1,14 +1,14 @@
-// Forward MrDFT of complex signals in one persistent launch: each workgroup
-// repeatedly takes the next job of a table, either a 2048-sample tile (levels
-// 1..11 on chip, mrdft_tile_c64.h) or one 16-row piece of a window of a level
-// 12..16 (mrdft_rows_c64.h).  Signals of any order share the launch; their
-// offsets are int64.
+// Forward MrDFT of complex signals in one launch, each job either a
+// 2048-sample tile (levels 1..11 on chip, mrdft_tile_c64.h) or one 16-row
+// piece of a window of a level 12..16 (mrdft_rows_c64.h).  Signals of any
+// order share the launch; their offsets are int64.
 //
-// The table holds one segment per XCD, with all pieces of a window in one
+// Persistent form: each workgroup repeatedly takes the next job of a table
+// that holds one segment per XCD, with all pieces of a window in one
 // segment.  A workgroup takes jobs from the segment of the XCD it runs on
 // (read from the hardware register), so the pieces of a window share their x
 // columns through that XCD's L2; when its segment is empty it takes jobs from
-// the other segments.
+// the other segments.  Direct form: one workgroup per job.
 #include "mrdft_internal.h"
 #include "mrdft_rows_c64.h"
 #include "mrdft_tile_c64.h"
@@ -93,7 +93,45 @@ __global__ __launch_bounds__(kCThreads, 4) void fwd_c64_kernel(const float2* __r
     }
 }
 
+// One workgroup per job (the table dealt so that block b, which runs on XCD
+// b mod 8, holds a job of that XCD's bucket).  In the persistent form the
+// loads of a workgroup's next job queue behind the stores of its previous one
+// (one in-order vector memory counter); here every job starts fresh.
+__global__ __launch_bounds__(kCThreads, 4) void fwd_c64_direct(const float2* __restrict__ x, float2* __restrict__ Y,
+                                                               const RealJob* __restrict__ jobs,
+                                                               const float2* __restrict__ t4096,
+                                                               const float2* __restrict__ rowtw,
+                                                               const float2* __restrict__ comb) {
+    __shared__ FwdC64Lds S;
+    const int tid = threadIdx.x;
+    const RealJob jb = jobs[blockIdx.x];
+    const float2* xj = x + jb.in_off;
+    float2* yj = Y + jb.out_off;
+    switch (jb.lg) {
+        case 0: c64_tile_body(S.tile, xj, yj, jb.level_stride, t4096, tid, LevelRange::unpack(jb.g)); break;
+        case 12: rows_c64_body<4>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(12),
+                                  comb + crows_combine_offset(12), tid); break;
+        case 13: rows_c64_body<5>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(13),
+                                  comb + crows_combine_offset(13), tid); break;
+        case 14: rows_c64_body<6>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(14),
+                                  comb + crows_combine_offset(14), tid); break;
+        case 15: rows_c64_body<7>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(15),
+                                  comb + crows_combine_offset(15), tid); break;
+        case 16: rows_c64_body<8>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(16),
+                                  comb + crows_combine_offset(16), tid); break;
+        default: break;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_fwd_c64_direct(const float2* x, float2* Y, const RealJob* jobs, int64_t njobs, const Twiddles& tw,
+                                 hipStream_t s) {
+    if (njobs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fwd_c64_direct, dim3((unsigned)njobs), dim3(kCThreads), 0, s, x, Y, jobs, tw.tile, tw.rows,
+                       tw.crows_comb);
+    return hipGetLastError();
+}
 
 hipError_t launch_fwd_c64(const float2* x, float2* Y, const RealJob* jobs, int64_t njobs, const unsigned* seg,
                           unsigned* queue, int grid, const Twiddles& tw, hipStream_t s) {

@@ -1,6 +1,7 @@
 """Schedules of the forward launch against the FP64 oracle (GPU).
 
-Covers the persistent complex launch (any grid, including a single workgroup
+Covers the complex launch (one workgroup per job, or persistent with any
+grid, including a single workgroup
 that takes every job), each job order, the tile kernel with one launch per
 upper level, the tuner's choice, the queue that the persistent launch leaves
 cleared for the next call, and graph replay against eager calls.
@@ -45,7 +46,8 @@ def _check_ragged(Y, x, offs, orders, plan):
 C_ORDERS = [11, 12, 9, 13, 14, 16, 17, 15, 5, 12]
 
 
-@pytest.mark.parametrize("tile_log,grid,order", [(11, 1, "tiles_first"), (11, 7, "rows_first"),
+@pytest.mark.parametrize("tile_log,grid,order", [(11, 0, "tiles_first"), (11, 0, "interleaved"),
+                                                 (11, 1, "tiles_first"), (11, 7, "rows_first"),
                                                  (11, 1024, "interleaved"), (11, 256, "tiles_first"),
                                                  (12, 0, "tiles_first")])
 def test_complex_schedules_match_oracle(tile_log, grid, order):
