@@ -9,8 +9,8 @@ import pytest
 import torch
 
 import oracle
-from paper_1507_02525_amd import workloads
-from tests.gpu_util import FWD_TOL, log, need_gpu, rel_l2, to_dev, worst_level_err
+from paper_1507_02525_amd import api, workloads
+from tests.gpu_util import FWD_TOL, GRAD_TOL, log, need_gpu, rel_l2, to_dev, worst_level_err
 
 pytestmark = pytest.mark.gpu
 
@@ -186,3 +186,44 @@ def test_repeat_runs_bitwise_identical():
     a = api.forward(xt)
     b = api.forward(xt)
     assert torch.equal(a, b)
+
+
+def test_maximum_order_sampled():
+    """One real signal of 2^28 samples (the largest order; 60 GB of output):
+    direct-sum bins of the top level, windows of lower levels against the
+    oracle's FFT route, per-level Parseval, and A^H A x = (2^(m+1) - 2) x
+    through the adjoint."""
+    need_gpu()
+    m = 28
+    log("maximum order: r32 m=28")
+    rng = np.random.default_rng(1528)
+    x = rng.standard_normal(1 << m, dtype=np.float32)
+    xd = to_dev(x)
+    plan = api.Plan(m=m, batch=1, dtype="r32")
+    Y = torch.empty(plan.n_out, dtype=torch.complex64, device="cuda")
+    plan.mrdft_forward(xd, Y)
+    torch.cuda.synchronize()
+    Yl = Y.view(m, 1 << m)
+    rms = float(np.sqrt(np.mean(x.astype(np.float64) ** 2)))
+    for i, w, k in ((m, 0, 1), (m, 0, (1 << m) - 3), (m - 1, 1, 12345), (20, 77, 999)):
+        L = 1 << i
+        seg = x[w * L:(w + 1) * L].astype(np.float64)
+        v = oracle.forward_bin(seg, i, 0, k)
+        g = complex(Yl[i - 1, w * L + k].item())
+        assert abs(g - v) <= 1e-5 * np.sqrt(L) * rms, (i, w, k, g, v)
+    for i, w in ((1, 5), (12, 3), (13, 1000), (16, 4095), (17, 7), (20, 100)):
+        L = 1 << i
+        seg = x[w * L:(w + 1) * L].astype(np.complex128)
+        ref = oracle.forward_level(seg, i, oracle.FFT) if i > 1 else np.array([seg[0] + seg[1], seg[0] - seg[1]])
+        got = Yl[i - 1, w * L:(w + 1) * L].cpu().numpy()
+        assert rel_l2(got, ref) <= FWD_TOL, (i, w, rel_l2(got, ref))
+    ex = float(torch.sum(xd.double() ** 2).item())
+    for i in range(1, m + 1):
+        ey = float(torch.sum(Yl[i - 1].abs().double() ** 2).item())
+        assert abs(ey / ((1 << i) * ex) - 1) < 1e-5, i
+    gx = torch.empty_like(xd)
+    plan.mrdft_adjoint(Y, gx)
+    del Y, Yl
+    scale = float((1 << (m + 1)) - 2)
+    err = torch.linalg.vector_norm((gx.double() - scale * xd.double())).item() / (scale * np.sqrt(ex))
+    assert err <= GRAD_TOL, err
