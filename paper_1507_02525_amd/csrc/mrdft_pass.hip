@@ -67,29 +67,42 @@ __global__ __launch_bounds__(kPassThreads) void pass_kernel(const void* __restri
     const int ns_log = g.ns_log;
     const int64_t nsm = ((int64_t)1 << ns_log) - 1;
     const int nval = r * kPassCols;
-    T[tid] = tab[tid << (kTileMaxLog - 8)];
 
     {
-        // thread: column jj = tid & 15, rows s = s0 + 16 i (s0 = tid >> 4)
+        // thread: column jj = tid & 15, rows s = s0 + 16 i (s0 = tid >> 4); all
+        // of the thread's loads are issued before the first one is used
+        constexpr int kRowsPerThread = (1 << kPassMaxLog) / kPassCols;
         const int jj = tid & (kPassCols - 1), s0 = tid >> 4;
         const int64_t j = j0 + jj;
         const int tlg = ns_log + rl;
+        float2 v[kRowsPerThread];
+#pragma unroll
+        for (int i = 0; i < kRowsPerThread; ++i) {
+            const int s = s0 + kPassCols * i;
+            if (s < r) {
+                const int64_t idx = ib + j + (int64_t)s * cols;
+                if constexpr (IN_KIND == IN_R32) v[i] = make_float2(((const float*)in)[idx], 0.0f);
+                else v[i] = ((const float2*)in)[idx];
+            }
+        }
+        T[tid] = tab[tid << (kTileMaxLog - 8)];      // after the data loads: its wait covers them
         double2 w = make_double2(1.0, 0.0), step = make_double2(1.0, 0.0);
         if (ns_log > 0) {
             w = tw_big64(hi, lo, tlg, (j & nsm) * s0);
             step = tw_big64(hi, lo, tlg, (j & nsm) * kPassCols);
         }
-        for (int s = s0; s < r; s += kPassCols) {
-            const int64_t idx = ib + j + (int64_t)s * cols;
-            float2 v;
-            if constexpr (IN_KIND == IN_R32) v = make_float2(((const float*)in)[idx], 0.0f);
-            else v = ((const float2*)in)[idx];
-            if (ns_log > 0) {
-                const float2 wf = make_float2((float)w.x, (float)w.y);
-                v = INV ? cmulc(v, wf) : cmul(v, wf);
-                w = make_double2(w.x * step.x - w.y * step.y, w.x * step.y + w.y * step.x);
+#pragma unroll
+        for (int i = 0; i < kRowsPerThread; ++i) {
+            const int s = s0 + kPassCols * i;
+            if (s < r) {
+                float2 u = v[i];
+                if (ns_log > 0) {
+                    const float2 wf = make_float2((float)w.x, (float)w.y);
+                    u = INV ? cmulc(u, wf) : cmul(u, wf);
+                    w = make_double2(w.x * step.x - w.y * step.y, w.x * step.y + w.y * step.x);
+                }
+                B[jj * fst + s] = u;
             }
-            B[jj * fst + s] = v;
         }
     }
     __syncthreads();
