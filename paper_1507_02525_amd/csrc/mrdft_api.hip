@@ -854,8 +854,11 @@ mrdft_status run_adjoint(mrdft_plan* p, const float2* gY, void* gx, bool real_ou
 }
 
 // Levels above 16 of a uniform plan through the global passes, written to
-// W[b][i - 17][n] (compact) or to the plan's output layout W[b][i - 1][n].
-mrdft_status upper_passes(mrdft_plan* p, const float* x, float2* W, hipStream_t s, bool full_layout = false) {
+// W[b][i - 17][n] (compact) or to the plan's output layout W[b][i - 1][n];
+// with `norms`, nothing is written and the squared magnitudes of signal b's
+// level i are added to norms[b * m + i - 1].
+mrdft_status upper_passes(mrdft_plan* p, const float* x, float2* W, hipStream_t s, bool full_layout = false,
+                          double* norms = nullptr) {
     const Twiddles tw = p->tw();
     const int64_t N = int64_t(1) << p->m;
     const int top = p->m - kRowsMaxLevel;
@@ -878,9 +881,17 @@ mrdft_status upper_passes(mrdft_plan* p, const float* x, float2* W, hipStream_t 
                 geo.out_stride = last ? (int64_t)(full_layout ? p->m : top) * N : N;
                 const int slot = full_layout ? i - 1 : i - kRowsMaxLevel - 1;
                 const void* in = first ? (const void*)x : (const void*)p->d_s[(q - 1) & 1];
-                void* out = last ? (void*)(W + (int64_t)slot * N) : (void*)p->d_s[q & 1];
+                void* out = (void*)p->d_s[q & 1];
+                int ok = OUT_STORE;
+                if (last && norms) {
+                    out = norms;
+                    geo.out_stride = p->m;
+                    ok = OUT_NORM;
+                } else if (last) {
+                    out = (void*)(W + (int64_t)slot * N);
+                }
                 ProfScope ps(p, MRDFT_KERNEL_PASS_FWD, s);
-                HIP_TRY(launch_pass(false, first ? IN_R32 : IN_C64, OUT_STORE, in, out, geo, tw, s));
+                HIP_TRY(launch_pass(false, first ? IN_R32 : IN_C64, ok, in, out, geo, tw, s));
                 ns += bits[q];
             }
         }
@@ -1253,14 +1264,12 @@ mrdft_status mrdft_spectral_loss_fwd(mrdft_plan_t plan, const float* x, const fl
             HIP_TRY(launch_fwd_real_norms(z, nullptr, sden, plan->m, plan->d_rjobs, plan->nrjobs, tw, stream));
         }
         if (plan->m > kRowsMaxLevel) {
+            // levels above 16: the last pass of each level adds the squared
+            // magnitudes straight into the level sums
             HIP_TRY(launch_sub_real(x, z, plan->d_v, plan->n_in, stream));
-            const int top = plan->m - kRowsMaxLevel;                   // levels above 16 per signal
             for (int pass = 0; pass < 2; ++pass) {
-                st = upper_passes(plan, pass == 0 ? plan->d_v : z, plan->d_Yv, stream);
+                st = upper_passes(plan, pass == 0 ? plan->d_v : z, nullptr, stream, false, pass == 0 ? snum : sden);
                 if (st) return st;
-                HIP_TRY(launch_sumsq(plan->d_Yv, plan->d_part, plan->batch * top, N, stream));
-                HIP_TRY(launch_add_rows(plan->d_part, loss_chunks(N), pass == 0 ? snum : sden, plan->batch, plan->m,
-                                        kRowsMaxLevel, stream));
             }
         }
         HIP_TRY(launch_finalize(snum, sden, num_den, L, plan->batch, plan->m, 1, stream));

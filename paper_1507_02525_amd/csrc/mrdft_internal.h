@@ -39,7 +39,9 @@ struct PassGeom {
 
 enum InKind { IN_C64 = 0, IN_R32 = 1 };
 // OUT_HALF: store packed half spectra (window W at W * L/2, slot 0 = (Y[0], Y[L/2])).
-enum OutKind { OUT_STORE = 0, OUT_ADD_C64 = 1, OUT_ADD_R32 = 2, OUT_HALF = 3 };
+// OUT_NORM: nothing stored; the squared magnitudes of signal b's level lg are
+// added (FP64) to ((double*)out)[b * out_stride + lg - 1].
+enum OutKind { OUT_STORE = 0, OUT_ADD_C64 = 1, OUT_ADD_R32 = 2, OUT_HALF = 3, OUT_NORM = 4 };
 
 struct Twiddles {
     const float2* tile;   // w_{4096}^e, e < 4096 (FP32, rounded once from FP64)

@@ -4,7 +4,7 @@
 
 namespace mrdft {
 
-constexpr int64_t kLossChunk = 65536;   // elements reduced by one block
+constexpr int64_t kLossChunk = 8192;    // elements reduced by one block
 
 int loss_chunks(int64_t N);
 hipError_t launch_sub_real(const float* x, const float* z, float* v, int64_t n, hipStream_t s);

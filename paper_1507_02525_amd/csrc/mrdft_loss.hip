@@ -29,9 +29,25 @@ __global__ __launch_bounds__(kRedThreads) void sumsq_kernel(const float2* __rest
     const int c = blockIdx.x - (int)(row * nchunks);
     const float2* p = Y + row * N + (int64_t)c * chunk;
     const int64_t n = (N - (int64_t)c * chunk) < chunk ? (N - (int64_t)c * chunk) : chunk;
+    // pairs of values (16-byte loads), four loads in flight per thread
     double acc = 0.0;
-    for (int64_t e = threadIdx.x; e < n; e += kRedThreads) {
-        const float2 v = p[e];
+    const int64_t npair = n >> 1;
+    const float4* p4 = (const float4*)p;          // rows and chunks start at even elements
+    int64_t e = threadIdx.x;
+    for (; e + 3 * kRedThreads < npair; e += 4 * kRedThreads) {
+        float4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = p4[e + u * kRedThreads];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            acc += ((double)v[u].x * v[u].x + (double)v[u].y * v[u].y) + ((double)v[u].z * v[u].z + (double)v[u].w * v[u].w);
+    }
+    for (; e < npair; e += kRedThreads) {
+        const float4 v = p4[e];
+        acc += ((double)v.x * v.x + (double)v.y * v.y) + ((double)v.z * v.z + (double)v.w * v.w);
+    }
+    if ((n & 1) && threadIdx.x == 0) {
+        const float2 v = p[n - 1];
         acc += (double)v.x * v.x + (double)v.y * v.y;
     }
     __shared__ double red[kRedThreads];
@@ -44,28 +60,33 @@ __global__ __launch_bounds__(kRedThreads) void sumsq_kernel(const float2* __rest
     if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-// num_den[row] = (sum of num partials, sum of den partials); then L.
-__global__ void finalize_kernel(const double* __restrict__ pnum, const double* __restrict__ pden,
-                                double* __restrict__ num_den, float* __restrict__ L, int64_t batch, int m,
-                                int nchunks) {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
-    double total = 0.0;
-    for (int64_t b = 0; b < batch; ++b) {
-        double lb = 0.0;
-        for (int i = 0; i < m; ++i) {
-            const int64_t row = b * m + i;
-            double num = 0.0, den = 0.0;
-            for (int c = 0; c < nchunks; ++c) {
-                num += pnum[row * nchunks + c];
-                den += pden[row * nchunks + c];
-            }
-            num_den[2 * row] = num;
-            num_den[2 * row + 1] = den;
-            lb += num / den;
+// num_den[row] = (sum of num partials, sum of den partials); then
+// L = (1/m) sum over rows of num / den.  One block; thread t takes rows
+// t, t + 256, ... and the block sums in a fixed tree (deterministic).
+__global__ __launch_bounds__(kRedThreads) void finalize_kernel(const double* __restrict__ pnum,
+                                                               const double* __restrict__ pden,
+                                                               double* __restrict__ num_den, float* __restrict__ L,
+                                                               int64_t batch, int m, int nchunks) {
+    const int64_t rows = batch * m;
+    double acc = 0.0;
+    for (int64_t row = threadIdx.x; row < rows; row += kRedThreads) {
+        double num = 0.0, den = 0.0;
+        for (int c = 0; c < nchunks; ++c) {
+            num += pnum[row * nchunks + c];
+            den += pden[row * nchunks + c];
         }
-        total += lb / (double)m;
+        num_den[2 * row] = num;
+        num_den[2 * row + 1] = den;
+        acc += num / den;
     }
-    *L = (float)total;
+    __shared__ double red[kRedThreads];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *L = (float)(red[0] / (double)m);
 }
 
 // Y[b][i][:] *= gL * 2 / (m * den_{b,i})
@@ -122,7 +143,8 @@ hipError_t launch_sumsq(const float2* Y, double* part, int64_t rows, int64_t N, 
 
 hipError_t launch_finalize(const double* pnum, const double* pden, double* num_den, float* L, int64_t batch, int m,
                            int64_t N, hipStream_t s) {
-    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(64), 0, s, pnum, pden, num_den, L, batch, m, loss_chunks(N));
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kRedThreads), 0, s, pnum, pden, num_den, L, batch, m,
+                       loss_chunks(N));
     return hipGetLastError();
 }
 

@@ -108,6 +108,7 @@ __global__ __launch_bounds__(kPassThreads) void pass_kernel(const void* __restri
     __syncthreads();
     column_fft<INV>(B, rl, T, tid);
 
+    double nacc = 0.0;                                 // OUT_NORM: this thread's squared magnitudes
     for (int e = tid; e < nval; e += kPassThreads) {
         int jj, s;
         int64_t o;
@@ -124,6 +125,9 @@ __global__ __launch_bounds__(kPassThreads) void pass_kernel(const void* __restri
         const float2 v = B[jj * fst + s];
         if constexpr (OUT_KIND == OUT_STORE) {
             ((float2*)out)[o] = v;
+        } else if constexpr (OUT_KIND == OUT_NORM) {
+            (void)o;
+            nacc += (double)v.x * v.x + (double)v.y * v.y;
         } else if constexpr (OUT_KIND == OUT_HALF) {
             // bin k = o - ob of a real window: k < L/2 kept, the DC and
             // Nyquist real parts share slot 0, the upper half is dropped
@@ -140,6 +144,18 @@ __global__ __launch_bounds__(kPassThreads) void pass_kernel(const void* __restri
             *p += v.x;
         }
     }
+    if constexpr (OUT_KIND == OUT_NORM) {
+        // block sum, then one FP64 atomic per workgroup into sums[b * out_stride + lg - 1]
+        __syncthreads();                               // B is free again
+        double* red = reinterpret_cast<double*>(B);
+        red[tid] = nacc;
+        __syncthreads();
+        for (int h = kPassThreads / 2; h > 0; h >>= 1) {
+            if (tid < h) red[tid] += red[tid + h];
+            __syncthreads();
+        }
+        if (tid == 0) atomicAdd((double*)out + b * g.out_stride + g.lg - 1, red[0]);
+    }
 }
 
 template <bool INV>
@@ -154,11 +170,13 @@ static hipError_t launch_pass_t(int in_kind, int out_kind, const void* in, void*
     if (in_kind == IN_R32) {
         if (out_kind == OUT_STORE) MRDFT_PASS(IN_R32, OUT_STORE);
         else if (out_kind == OUT_HALF) MRDFT_PASS(IN_R32, OUT_HALF);
+        else if (out_kind == OUT_NORM) MRDFT_PASS(IN_R32, OUT_NORM);
         else if (out_kind == OUT_ADD_C64) MRDFT_PASS(IN_R32, OUT_ADD_C64);
         else MRDFT_PASS(IN_R32, OUT_ADD_R32);
     } else {
         if (out_kind == OUT_STORE) MRDFT_PASS(IN_C64, OUT_STORE);
         else if (out_kind == OUT_HALF) MRDFT_PASS(IN_C64, OUT_HALF);
+        else if (out_kind == OUT_NORM) MRDFT_PASS(IN_C64, OUT_NORM);
         else if (out_kind == OUT_ADD_C64) MRDFT_PASS(IN_C64, OUT_ADD_C64);
         else MRDFT_PASS(IN_C64, OUT_ADD_R32);
     }
