@@ -367,12 +367,7 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
     } else {
         mrdft_status st = upload_cjobs(p, p->order, s, true);   // default: one workgroup per job
         if (st) return st;
-        std::vector<TileJob> small;
-        for (int64_t j = 0; j < p->batch; ++j) {
-            const int mj = p->orders[j];
-            if (mj >= kC64TileLog) continue;
-            small.push_back(TileJob{p->in_off[j], p->base(j), int64_t(1) << mj, mj, p->range()});
-        }
+        std::vector<TileJob> small;      // signals below 2^11 go into multi-signal tiles of the one launch
         p->nsmall = (int64_t)small.size();
         for (const TileJob& t : small) p->small_tmax = std::max(p->small_tmax, (int)t.t);
         if (!small.empty()) {
@@ -616,7 +611,21 @@ std::vector<RealJob> complex_jobs(const mrdft_plan* p, int order, std::vector<un
     JobBuckets jb;
     for (int64_t j = 0; j < p->batch; ++j) {
         const int mj = p->orders[j];
-        if (mj < kC64TileLog) continue;
+        if (mj < kC64TileLog) {
+            // a run of consecutive signals of this order (x and outputs are
+            // contiguous), 2^(11 - m) of them per tile; signals that keep no
+            // level are skipped
+            if (mj < p->lo) continue;
+            const int64_t N = int64_t(1) << mj, per = int64_t(1) << (kC64TileLog - mj);
+            int64_t n = 1;
+            while (j + n < p->batch && p->orders[j + n] == mj && n < per) ++n;
+            const int64_t vlen = n * N;
+            jb.add_tile(RealJob{p->in_off[j], p->base(j), N | (vlen << 32), kMultiTileLg + mj,
+                                LevelRange::pack(p->lo, std::min(p->hi, mj))},
+                        5);
+            j += n - 1;
+            continue;
+        }
         const int64_t N = int64_t(1) << mj;
         for (int64_t tau = 0; tau < (N >> kC64TileLog); ++tau)
             jb.add_tile(RealJob{p->in_off[j] + (tau << kC64TileLog), p->base(j) + (tau << kC64TileLog), N, 0,

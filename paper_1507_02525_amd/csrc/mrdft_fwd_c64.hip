@@ -26,6 +26,17 @@ static_assert(kCThreads == kRowsThreads, "one block size for both job kinds");
 
 constexpr int kXcds = 8;
 
+// A tile of several consecutive signals of 2^m samples (m < 11): job lg =
+// kMultiTileLg + m, level_stride = 2^m | (valid samples << 32).
+__device__ __forceinline__ void multi_tile(CTileLds& S, const float2* x, float2* y, const RealJob& jb,
+                                           const float2* t4096, int tid) {
+    const int m = jb.lg - kMultiTileLg;
+    const int64_t N = jb.level_stride & 0xffffffffLL;
+    const LevelRange lv = LevelRange::unpack(jb.g);
+    const SubMap sm{m, (int)(jb.level_stride >> 32), (int64_t)(lv.hi - lv.lo + 1) * N};
+    c64_tile_body<true>(S, x, y, N, t4096, tid, lv, sm);
+}
+
 __device__ __forceinline__ unsigned xcc_id() {
     unsigned v;
     asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(v));
@@ -78,7 +89,9 @@ __global__ __launch_bounds__(kCThreads, 4) void fwd_c64_kernel(const float2* __r
                                       comb + crows_combine_offset(15), t); break;
             case 16: rows_c64_body<8>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(16),
                                       comb + crows_combine_offset(16), t); break;
-            default: break;
+            default:
+                if (jb.lg >= kMultiTileLg) multi_tile(S.tile, xj, yj, jb, t4096, t);
+                break;
         }
         __syncthreads();                              // LDS and s_job reuse
     }
@@ -119,7 +132,9 @@ __global__ __launch_bounds__(kCThreads, 4) void fwd_c64_direct(const float2* __r
                                   comb + crows_combine_offset(15), tid); break;
         case 16: rows_c64_body<8>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(16),
                                   comb + crows_combine_offset(16), tid); break;
-        default: break;
+        default:
+            if (jb.lg >= kMultiTileLg) multi_tile(S.tile, xj, yj, jb, t4096, tid);
+            break;
     }
 }
 

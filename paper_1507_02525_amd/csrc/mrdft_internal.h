@@ -85,6 +85,10 @@ hipError_t launch_fwd_real_norms(const float* x, const float* xsub, double* sums
 // (counted in queue[8]) clears queue[0..8] for the next launch (the plan
 // zeroes them once at creation).
 constexpr int kC64TileLog = 11;
+// Job kind of a 2048-sample tile holding several consecutive signals of
+// 2^m samples, m < 11: lg = kMultiTileLg + m, level_stride = 2^m | (valid
+// samples << 32), g = LevelRange::pack(lo, min(hi, m)).
+constexpr int kMultiTileLg = 32;
 constexpr int kC64Queues = 9;
 // Adjoint (mrdft_adj.hip).  Launch (a): RealJob with in_off = gY offset (the
 // tile's level-1 gradient, or the window's gradient at its level), out_off =

@@ -54,6 +54,21 @@ struct TwQ2048 {
 // strided Stockham accesses); 1024 points need 1056 slots of P.
 __device__ __forceinline__ int cfpad(int i) { return i + (i >> 5); }
 
+// Where position t of a tile level goes, relative to the level's base: the
+// tile lies inside one signal (MULTI false: t itself), or it holds several
+// consecutive signals of 2^m samples (signal t >> m at output stride S,
+// position t mod 2^m) of which the first vlen samples are valid.
+struct SubMap {
+    int m;
+    int vlen;
+    int64_t S;
+    template <bool MULTI>
+    __device__ __forceinline__ int64_t off(int t) const {
+        if constexpr (MULTI) return (int64_t)(t >> m) * S + (t & ((1 << m) - 1));
+        else return t;
+    }
+};
+
 __device__ __forceinline__ void ct_wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -107,8 +122,8 @@ struct CtSteps {
 };
 
 // LDS level I (4 <= I <= 11) of the tile; y points at this level's output.
-template <int I>
-__device__ __forceinline__ void ct_level(CTileLds& S, float2* __restrict__ y, int tid, bool store) {
+template <int I, bool MULTI>
+__device__ __forceinline__ void ct_level(CTileLds& S, float2* __restrict__ y, int tid, bool store, const SubMap& sm) {
     constexpr int L = 1 << I, M = L / 2, LM = I - 1;
     constexpr int NW = kCT / L;
     constexpr int PPT = NW * M / kCThreads;              // (w, k) jobs per thread
@@ -165,27 +180,29 @@ __device__ __forceinline__ void ct_level(CTileLds& S, float2* __restrict__ y, in
         const int J = tid + c * kCThreads;          // = w * M + k: the pair (2k, 2k+1) of window w
         const float4 pr = make_float4(u[c].x, u[c].y, d[c].x, d[c].y);
         *(float4*)(S.P + 2 * J) = pr;
-        if (store) *(float4*)(y + 2 * J) = pr;
+        if (store && (!MULTI || 2 * J < sm.vlen)) *(float4*)(y + sm.off<MULTI>(2 * J)) = pr;
     }
     __syncthreads();
 }
 
-template <int I>
+template <int I, bool MULTI>
 struct CtLevels {
     static __device__ __forceinline__ void run(CTileLds& S, float2* __restrict__ y, int64_t ls, int tid,
-                                               LevelRange lv) {
+                                               LevelRange lv, const SubMap& sm) {
         if constexpr (I <= kCTLog) {
             if (I > lv.hi) return;                    // levels above the range are not computed
-            ct_level<I>(S, y + (int64_t)(I - 1) * ls, tid, lv.in(I));
-            CtLevels<I + 1>::run(S, y, ls, tid, lv);
+            ct_level<I, MULTI>(S, y + (int64_t)(I - 1) * ls, tid, lv.in(I), sm);
+            CtLevels<I + 1, MULTI>::run(S, y, ls, tid, lv, sm);
         }
     }
 };
 
 // Writes one register level (8 values per thread, one window each) through
 // the wave's 4 KB of staging (pair e of lane l at 4l + (e ^ (l & 3))).
-__device__ __forceinline__ void ct_stage(const float2* pv, float4* st, float2* __restrict__ yl, int lane,
-                                         bool store) {
+//   yl: the level's base; t0: the wave's first tile position (512 v)
+template <bool MULTI>
+__device__ __forceinline__ void ct_stage(const float2* pv, float4* st, float2* __restrict__ yl, int t0, int lane,
+                                         bool store, const SubMap& sm) {
     if (!store) return;
 #pragma unroll
     for (int e = 0; e < 4; ++e)
@@ -194,16 +211,17 @@ __device__ __forceinline__ void ct_stage(const float2* pv, float4* st, float2* _
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int p = 64 * r + lane, wl = p >> 2, e = p & 3;
-        *(float4*)(yl + 2 * p) = st[4 * wl + (e ^ (wl & 3))];
+        const int t = t0 + 2 * p;
+        if (!MULTI || t < sm.vlen) *(float4*)(yl + sm.off<MULTI>(t)) = st[4 * wl + (e ^ (wl & 3))];
     }
     ct_wave_sync();
 }
 
 // Register levels I..3 of an 8-sample window (full spectra, natural order).
-template <int I>
+template <int I, bool MULTI>
 struct CtLocal {
-    static __device__ __forceinline__ void run(const float2* xv, float2* pv, float4* st, float2* y, int64_t ls,
-                                               int lane, LevelRange lv) {
+    static __device__ __forceinline__ void run(const float2* xv, float2* pv, float4* st, float2* y, int t0, int64_t ls,
+                                               int lane, LevelRange lv, const SubMap& sm) {
         if constexpr (I <= 3) {
             constexpr int C = 8, L = 1 << I, M = L / 2;
             float2 nv[C];
@@ -221,16 +239,20 @@ struct CtLocal {
             }
 #pragma unroll
             for (int e = 0; e < C; ++e) pv[e] = nv[e];
-            ct_stage(pv, st, y + (int64_t)(I - 1) * ls, lane, lv.in(I));
-            CtLocal<I + 1>::run(xv, pv, st, y, ls, lane, lv);
+            ct_stage<MULTI>(pv, st, y + (int64_t)(I - 1) * ls, t0, lane, lv.in(I), sm);
+            CtLocal<I + 1, MULTI>::run(xv, pv, st, y, t0, ls, lane, lv, sm);
         }
     }
 };
 
 // One tile: x at its first sample, y at its level-1 output (level i at
-// y + (i-1) ls).  Wave v owns samples [512 v, 512 v + 512).
+// y + (i-1) ls).  Wave v owns samples [512 v, 512 v + 512).  MULTI: the tile
+// holds consecutive signals of 2^sm.m samples (ls = 2^sm.m, lv.hi <= sm.m),
+// samples past sm.vlen are not read and their outputs not written.
+template <bool MULTI = false>
 __device__ __forceinline__ void c64_tile_body(CTileLds& S, const float2* __restrict__ x, float2* __restrict__ y,
-                                              int64_t ls, const float2* __restrict__ t4096, int tid, LevelRange lv) {
+                                              int64_t ls, const float2* __restrict__ t4096, int tid, LevelRange lv,
+                                              const SubMap& sm = SubMap{31, kCT, 0}) {
     constexpr int C = 8;
     const int v = tid >> 6, lane = tid & 63;
     for (int e = tid; e < kCT / 4; e += kCThreads) S.Q[cqswz(e)] = t4096[2 * e];   // before any store
@@ -239,7 +261,10 @@ __device__ __forceinline__ void c64_tile_body(CTileLds& S, const float2* __restr
         const float4* xg = (const float4*)(x + 512 * v);
         float4 a[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) a[r] = xg[64 * r + lane];
+        for (int r = 0; r < 4; ++r) {
+            if (!MULTI || 512 * v + 2 * (64 * r + lane) < sm.vlen) a[r] = xg[64 * r + lane];
+            else a[r] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        }
 #pragma unroll
         for (int r = 0; r < 4; ++r) *(float4*)(S.X + 512 * v + 2 * (64 * r + lane)) = a[r];
     }
@@ -257,15 +282,14 @@ __device__ __forceinline__ void c64_tile_body(CTileLds& S, const float2* __restr
         pv[2 * b + 1] = csub(xv[2 * b], xv[2 * b + 1]);
     }
     float4* st = (float4*)S.P + 256 * v;            // the wave's 4 KB of P
-    float2* yv = y + 512 * v;
-    ct_stage(pv, st, yv, lane, lv.in(1));
-    CtLocal<2>::run(xv, pv, st, yv, ls, lane, lv);
+    ct_stage<MULTI>(pv, st, y, 512 * v, lane, lv.in(1), sm);
+    CtLocal<2, MULTI>::run(xv, pv, st, y, 512 * v, ls, lane, lv, sm);
     // level-3 spectra into P (this wave's own region, after its staging reads)
 #pragma unroll
     for (int e = 0; e < C / 2; ++e)
         *(float4*)(S.P + C * tid + 2 * e) = make_float4(pv[2 * e].x, pv[2 * e].y, pv[2 * e + 1].x, pv[2 * e + 1].y);
     __syncthreads();
-    CtLevels<4>::run(S, y, ls, tid, lv);
+    CtLevels<4, MULTI>::run(S, y, ls, tid, lv, sm);
 }
 
 }  // namespace mrdft

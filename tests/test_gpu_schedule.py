@@ -205,3 +205,32 @@ def test_level_range_uniform_shape():
     assert Y.shape == (3, 10, 1 << 13)
     ref = oracle.forward(x[1].cpu().numpy().astype(np.complex128))
     assert worst_level_err(Y[1].cpu().numpy(), ref[3:]) <= FWD_TOL
+
+
+@pytest.mark.parametrize("lo,hi", [(1, 28), (3, 9)])
+def test_complex_small_signal_runs(lo, hi):
+    """Signals below 2^11 share 2048-sample tiles in runs of equal order:
+    runs longer than a tile holds (300 signals of 8 samples), runs that end
+    mid-tile, single signals between runs, signals that keep no level
+    (order below lo) and the same through the persistent form."""
+    need_gpu()
+    orders = [3] * 300 + [5, 5, 10, 10, 10, 2, 2, 2, 2, 2, 11, 4] + [1] * 7 + [9, 13, 8, 8, 6]
+    x, offs = _ragged(orders, 49 + lo)
+    plan = api.Plan(offsets=offs, dtype="c64", levels=(lo, hi))
+    xd = to_dev(x)
+    for grid in (0, 5):
+        plan.set_schedule(11, grid, "tiles_first")
+        Y = torch.full((plan.n_out,), float("nan"), dtype=torch.complex64, device="cuda")
+        plan.mrdft_forward(xd, Y)
+        oo = plan.output_offsets()
+        Yh = Y.cpu().numpy()
+        assert not np.isnan(Yh).any(), "output not fully written"
+        worst = 0.0
+        for j, m in enumerate(orders):
+            ref = oracle.forward(x[offs[j]:offs[j + 1]].astype(np.complex128))[lo - 1:min(hi, m)]
+            got = Yh[oo[j]:oo[j + 1]]
+            assert got.size == ref.size, (j, m)
+            if ref.size:
+                worst = max(worst, worst_level_err(got.reshape(ref.shape), ref))
+        log("  grid %d worst rel err %.3e" % (grid, worst))
+        assert worst <= FWD_TOL
