@@ -144,11 +144,23 @@ __device__ __forceinline__ void adj_cols_level(AdjColsLds& S, const float2* __re
     constexpr int R = 1 << RL, L = R * kRowsN;
     const int nwin = 1 << (region_log - RL - kRowsLog);          // windows of this level in the region
     const int rows = nwin * R;                                    // = region / 256
-    // load B[w][k2][c0 + col] (128-byte chunks) into FFT f = w * 16 + col, point k2
-    for (int e = tid; e < rows * 16; e += kRowsThreads) {
+    // load B[w][k2][c0 + col] (128-byte chunks) into FFT f = w * 16 + col, point
+    // k2; all of a thread's loads are issued before the first LDS store
+    constexpr int kPer = kAdjColsPoints / kRowsThreads;
+    float2 v[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int e = tid + u * kRowsThreads;
         const int col = e & 15, rr = e >> 4;                      // rr = w * R + k2
         const int w = rr / R, k2 = rr % R;
-        S.V[cpad((w * 16 + col) * R + k2)] = scr[(int64_t)w * L + k2 * kRowsN + c0 + col];
+        if (e < rows * 16) v[u] = scr[(int64_t)w * L + k2 * kRowsN + c0 + col];
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int e = tid + u * kRowsThreads;
+        const int col = e & 15, rr = e >> 4;
+        const int w = rr / R, k2 = rr % R;
+        if (e < rows * 16) S.V[cpad((w * 16 + col) * R + k2)] = v[u];
     }
     __syncthreads();
     // all 4096 points go through the steps; with a region below 2^16 the FFTs
