@@ -294,6 +294,21 @@ def main():
     except Exception as exc:  # the oracle is optional here; report why it is missing
         rel = "unavailable: %s" % exc
 
+    # --- attainable HBM rates on this machine (context for the roofline fraction) -------
+    big = torch.empty(1 << 28, dtype=torch.float32, device="cuda")     # 1 GiB
+    big2 = torch.empty_like(big)
+    for _ in range(3):
+        big.fill_(1.0)
+        big2.copy_(big)
+    ms_fill = timed(lambda: big.fill_(1.0), 10, sync)
+    ms_copy = timed(lambda: big2.copy_(big), 10, sync)
+    attainable = {"write_GBps": round(big.numel() * 4 / (ms_fill * 1e-3) / 1e9, 1),
+                  "copy_GBps": round(2 * big.numel() * 4 / (ms_copy * 1e-3) / 1e9, 1),
+                  "how": "torch fill_ (write) and copy_ (read + write) of 1 GiB, 3 warm-up and 10 timed reps"}
+    attainable["achieved_over_write"] = round(roofline["achieved"] / attainable["write_GBps"], 4)
+    del big, big2
+    torch.cuda.empty_cache()
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(d["x"], args.cpu_seconds)
@@ -319,6 +334,7 @@ def main():
         "hbm_frac_step": round(frac_step, 4),
         "algorithmic_bytes_per_step": alg_bytes,
         "roofline": roofline,
+        "attainable_hbm": attainable,
         "fwd_bwd": {"ms_per_step": round(ms_fb, 4), "value": round(samples / (ms_fb * 1e-3) / 1e9, 3),
                     "unit": "Gsamples/s",
                     "hbm_frac": round((2 * alg_bytes) / (ms_fb * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
