@@ -189,7 +189,7 @@ def extra_workloads(steps, warmup, HBM):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (the transform shards by signal; "
+        print("bench.py: this benchmark measures one GPU only (the transform shards by signal; "
               "multi-GPU runs are not part of it). Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
     import numpy as np

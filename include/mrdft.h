@@ -49,7 +49,7 @@ typedef struct mrdft_plan* mrdft_plan_t;
 typedef enum {
     MRDFT_OK = 0,
     MRDFT_E_INVALID_ARG = 1, /* bad order, length, offsets, pointer, alignment or dtype */
-    MRDFT_E_UNSUPPORTED = 2, /* valid request this build does not handle */
+    MRDFT_E_UNSUPPORTED = 2, /* valid request the library does not handle */
     MRDFT_E_ALLOC = 3,       /* device or host allocation failed */
     MRDFT_E_HIP = 4          /* a HIP runtime call failed (message has the HIP error) */
 } mrdft_status;
