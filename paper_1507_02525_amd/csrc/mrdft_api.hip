@@ -102,7 +102,7 @@ struct mrdft_plan {
     int64_t njobs = 0;
     int64_t njobs_full = 0;                 // leading jobs with t = 12 (full 4096-sample tiles)
     int jobs_tmax = 1, tail_tmax = 1;       // largest t of all tile jobs / of those after njobs_full
-    int small_tmax = 1, asmall_tmax = 1;    // largest t of d_small / d_asmall
+    int asmall_tmax = 1;                    // largest t of d_asmall
     std::vector<Group> groups;
     float2* d_tw_tile = nullptr;
     double2* d_tw_hi = nullptr;
@@ -114,14 +114,13 @@ struct mrdft_plan {
     // real input: tiles of 4096 samples and rows pieces of levels 13..16, one launch
     RealJob* d_rjobs = nullptr;
     int64_t nrjobs = 0;
-    // complex input: tiles of 2048 samples and rows pieces of levels 12..16 in
-    // one persistent launch (tile_log 11), or the tile kernel with 4096-sample
+    // complex input: tiles of 2048 samples (several signals of order < 11 per
+    // tile) and rows pieces of levels 12..16 in one launch (tile_log 11: one
+    // workgroup per job, or persistent), or the tile kernel with 4096-sample
     // tiles and one launch per upper level (tile_log 12)
     RealJob* d_cjobs = nullptr;
     int64_t ncjobs = 0;
     bool cjobs_direct = false;              // d_cjobs dealt for one workgroup per job (grid 0)
-    TileJob* d_small = nullptr;             // tiles of complex signals of order < 11
-    int64_t nsmall = 0;
     unsigned* d_queue = nullptr;            // persistent launch: next job per XCD segment, workgroups done
     unsigned* d_cseg = nullptr;             // starts of the 8 segments of the complex job table
     // adjoint: launch (a) tiles + rows pieces, launch (b) columns jobs, scratch B
@@ -204,7 +203,6 @@ void free_plan(mrdft_plan* p) {
     dfree(p->d_tw_ccomb);
     dfree(p->d_rjobs);
     dfree(p->d_cjobs);
-    dfree(p->d_small);
     dfree(p->d_queue);
     dfree(p->d_cseg);
     dfree(p->d_ajobs);
@@ -367,14 +365,6 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
     } else {
         mrdft_status st = upload_cjobs(p, p->order, s, true);   // default: one workgroup per job
         if (st) return st;
-        std::vector<TileJob> small;      // signals below 2^11 go into multi-signal tiles of the one launch
-        p->nsmall = (int64_t)small.size();
-        for (const TileJob& t : small) p->small_tmax = std::max(p->small_tmax, (int)t.t);
-        if (!small.empty()) {
-            if (hipMalloc(&p->d_small, sizeof(TileJob) * small.size()) != hipSuccess)
-                return fail(MRDFT_E_ALLOC, "tile table allocation failed");
-            HIP_TRY(hipMemcpyAsync(p->d_small, small.data(), sizeof(TileJob) * small.size(), hipMemcpyHostToDevice, s));
-        }
         if (p->ncjobs > 0) {
             if (!p->d_queue && hipMalloc(&p->d_queue, kC64Queues * sizeof(unsigned)) != hipSuccess)
                 return fail(MRDFT_E_ALLOC, "queue allocation failed");
@@ -790,12 +780,8 @@ mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, h
                 if (p->grid == 0)
                     HIP_TRY(launch_fwd_c64_direct((const float2*)x, Y, p->d_cjobs, p->ncjobs, tw, s0));
                 else
-                HIP_TRY(launch_fwd_c64((const float2*)x, Y, p->d_cjobs, p->ncjobs, p->d_cseg, p->d_queue, p->grid, tw,
-                                       s0));
-            }
-            if (p->nsmall) {
-                ProfScope ps(p, MRDFT_KERNEL_TILE_FWD, s0);
-                HIP_TRY(launch_tile_fwd(false, x, Y, p->d_small, p->nsmall, p->small_tmax, tw, s0));
+                    HIP_TRY(launch_fwd_c64((const float2*)x, Y, p->d_cjobs, p->ncjobs, p->d_cseg, p->d_queue, p->grid,
+                                           tw, s0));
             }
         } else {
             ProfScope ps(p, MRDFT_KERNEL_TILE_FWD, s0);
@@ -933,8 +919,8 @@ mrdft_status time_forward(mrdft_plan* p, const void* x, float2* Y, hipStream_t s
 
 // Autotuner: time the candidate schedules on zero-filled scratch buffers and
 // keep the fastest.  Complex plans: tile depth 12 (tile kernel, one launch per
-// upper level) or 11 (one persistent launch) with each job order and grid of
-// 1, 2 or 4 workgroups per CU; real plans: the job order.
+// upper level) or 11 (one launch: one workgroup per job, or persistent with 1,
+// 2 or 4 workgroups per CU) with each job order; real plans: the job order.
 mrdft_status tune(mrdft_plan* p, hipStream_t s) {
     const bool real = p->dtype == MRDFT_R32;
     if (real ? p->nrjobs == 0 : p->ncjobs == 0) return MRDFT_OK;
