@@ -8,9 +8,10 @@
 // (j / Ns)*Ns*r + (j mod Ns) + s*Ns.  The last pass leaves every window in
 // natural bin order, i.e. already permuted as Gamma asks.
 //
-// A workgroup handles 16 consecutive columns, so every global load and store
-// touches 16 consecutive complex64 values (128 bytes); the first pass radix is
-// at least 16 so later passes keep that property.  Twiddles of large windows
+// A workgroup handles 4096 points: 4096 / r consecutive columns (at least 16,
+// so every global load and store touches at least 128 consecutive bytes; a
+// small radix gets more columns, i.e. longer runs, instead of more
+// workgroups); the first pass radix is at least 16.  Twiddles of large windows
 // come from two FP64 tables (coarse and fine exponent), multiplied in FP64 and
 // rounded once: a thread looks up w^{j s0} and w^{16 j} for its column j and
 // first row s0 and forms its further rows s0 + 16 i by FP64 multiplication
@@ -29,17 +30,23 @@ struct TwLds256 {
     __device__ __forceinline__ float2 operator()(int lg, int e) const { return t[(e << (8 - lg)) & 255]; }
 };
 
+// The r-point FFTs (r = 2^rl) of the workgroup's 4096 / r columns: a first
+// step of radix 2, 4 or 8 if rl is not a multiple of 4, then radix 16; every
+// step has 4096 / radix jobs over the 256 threads.
+constexpr int kPassPoints = 4096;
 template <bool INV>
 __device__ __forceinline__ void column_fft(float2* B, int rl, const float2* T, int tid) {
     const int fst = kColStride(1 << rl);
+    const int nc = kPassPoints >> rl;
     int lgNs = 0;
     const int rem = rl & 3;
     const TwLds256 tw{T};
-    if (rem == 1) { lds_step<2, 1, INV>(B, rl, 0, fst, 1, kPassCols, tw, tid, kPassThreads); lgNs = 1; }
-    else if (rem == 2) { lds_step<4, 1, INV>(B, rl, 0, fst, 1, kPassCols, tw, tid, kPassThreads); lgNs = 2; }
-    else if (rem == 3) { lds_step<8, 1, INV>(B, rl, 0, fst, 1, kPassCols, tw, tid, kPassThreads); lgNs = 3; }
+    constexpr int J = kPassPoints / kPassThreads;     // jobs per thread of a radix-1 step
+    if (rem == 1) { lds_step<2, J / 2, INV>(B, rl, 0, fst, 1, nc, tw, tid, kPassThreads); lgNs = 1; }
+    else if (rem == 2) { lds_step<4, J / 4, INV>(B, rl, 0, fst, 1, nc, tw, tid, kPassThreads); lgNs = 2; }
+    else if (rem == 3) { lds_step<8, J / 8, INV>(B, rl, 0, fst, 1, nc, tw, tid, kPassThreads); lgNs = 3; }
     while (lgNs < rl) {
-        lds_step<16, 1, INV>(B, rl, lgNs, fst, 1, kPassCols, tw, tid, kPassThreads);
+        lds_step<16, J / 16, INV>(B, rl, lgNs, fst, 1, nc, tw, tid, kPassThreads);
         lgNs += 4;
     }
 }
@@ -49,60 +56,60 @@ __global__ __launch_bounds__(kPassThreads) void pass_kernel(const void* __restri
                                                             PassGeom g, const float2* __restrict__ tab,
                                                             const double2* __restrict__ hi,
                                                             const double2* __restrict__ lo) {
-    __shared__ float2 B[kPassCols * ((1 << kPassMaxLog) + 1)];
+    __shared__ float2 B[kPassPoints + (kPassPoints >> 4)];   // nc columns of r + 1 (nc <= 256)
     __shared__ float2 T[256];                          // w_256^e for the column FFT steps
     const int rl = g.r_log;
     const int r = 1 << rl;
     const int fst = kColStride(r);
+    const int lnc = 12 - rl;                           // log2 of the columns per workgroup
+    const int nc = 1 << lnc;
     const int64_t L = (int64_t)1 << g.lg;
     const int64_t cols = L >> rl;                      // columns j per window
-    const int64_t jblocks = cols / kPassCols;
+    const int64_t jblocks = cols >> lnc;
     const int64_t blk = blockIdx.x;
     const int64_t gwin = blk / jblocks;
-    const int64_t j0 = (blk - gwin * jblocks) * kPassCols;
+    const int64_t j0 = (blk - gwin * jblocks) << lnc;
     const int64_t b = gwin / g.wps, W = gwin - b * g.wps;
     const int64_t ib = (g.in_sig ? g.in_sig[b] : b * g.in_stride) + W * L;
     const int64_t ob = (g.out_sig ? g.out_sig[b] : b * g.out_stride) + W * (OUT_KIND == OUT_HALF ? L / 2 : L);
     const int tid = threadIdx.x;
     const int ns_log = g.ns_log;
     const int64_t nsm = ((int64_t)1 << ns_log) - 1;
-    const int nval = r * kPassCols;
+    const int nval = kPassPoints;
 
     {
-        // thread: column jj = tid & 15, rows s = s0 + 16 i (s0 = tid >> 4); all
-        // of the thread's loads are issued before the first one is used
-        constexpr int kRowsPerThread = (1 << kPassMaxLog) / kPassCols;
-        const int jj = tid & (kPassCols - 1), s0 = tid >> 4;
+        // thread: column jj = tid mod nc, rows s = s0 + (256 / nc) i (s0 = tid / nc),
+        // 16 rows per thread; all of the thread's loads are issued before the
+        // first one is used
+        constexpr int kRowsPerThread = kPassPoints / kPassThreads;
+        const int jj = tid & (nc - 1), s0 = tid >> lnc;
+        const int rstep = kPassThreads >> lnc;
         const int64_t j = j0 + jj;
         const int tlg = ns_log + rl;
         float2 v[kRowsPerThread];
 #pragma unroll
         for (int i = 0; i < kRowsPerThread; ++i) {
-            const int s = s0 + kPassCols * i;
-            if (s < r) {
-                const int64_t idx = ib + j + (int64_t)s * cols;
-                if constexpr (IN_KIND == IN_R32) v[i] = make_float2(((const float*)in)[idx], 0.0f);
-                else v[i] = ((const float2*)in)[idx];
-            }
+            const int s = s0 + rstep * i;
+            const int64_t idx = ib + j + (int64_t)s * cols;
+            if constexpr (IN_KIND == IN_R32) v[i] = make_float2(((const float*)in)[idx], 0.0f);
+            else v[i] = ((const float2*)in)[idx];
         }
         T[tid] = tab[tid << (kTileMaxLog - 8)];      // after the data loads: its wait covers them
         double2 w = make_double2(1.0, 0.0), step = make_double2(1.0, 0.0);
         if (ns_log > 0) {
             w = tw_big64(hi, lo, tlg, (j & nsm) * s0);
-            step = tw_big64(hi, lo, tlg, (j & nsm) * kPassCols);
+            step = tw_big64(hi, lo, tlg, (j & nsm) * rstep);
         }
 #pragma unroll
         for (int i = 0; i < kRowsPerThread; ++i) {
-            const int s = s0 + kPassCols * i;
-            if (s < r) {
-                float2 u = v[i];
-                if (ns_log > 0) {
-                    const float2 wf = make_float2((float)w.x, (float)w.y);
-                    u = INV ? cmulc(u, wf) : cmul(u, wf);
-                    w = make_double2(w.x * step.x - w.y * step.y, w.x * step.y + w.y * step.x);
-                }
-                B[jj * fst + s] = u;
+            const int s = s0 + rstep * i;
+            float2 u = v[i];
+            if (ns_log > 0) {
+                const float2 wf = make_float2((float)w.x, (float)w.y);
+                u = INV ? cmulc(u, wf) : cmul(u, wf);
+                w = make_double2(w.x * step.x - w.y * step.y, w.x * step.y + w.y * step.x);
             }
+            B[jj * fst + s] = u;
         }
     }
     __syncthreads();
@@ -116,9 +123,9 @@ __global__ __launch_bounds__(kPassThreads) void pass_kernel(const void* __restri
             jj = e >> rl;
             s = e & (r - 1);
             o = ob + (j0 + jj) * r + s;
-        } else {                    // 16 consecutive columns -> 16 consecutive outputs per s
-            jj = e & (kPassCols - 1);
-            s = e >> 4;
+        } else {                    // consecutive columns -> consecutive outputs per s (within a span)
+            jj = e & (nc - 1);
+            s = e >> lnc;
             const int64_t j = j0 + jj;
             o = ob + ((j >> ns_log) << (ns_log + rl)) + (j & nsm) + ((int64_t)s << ns_log);
         }
@@ -161,8 +168,8 @@ __global__ __launch_bounds__(kPassThreads) void pass_kernel(const void* __restri
 template <bool INV>
 static hipError_t launch_pass_t(int in_kind, int out_kind, const void* in, void* out, const PassGeom& g,
                                 const Twiddles& tw, hipStream_t s) {
-    const int64_t cols = ((int64_t)1 << g.lg) >> g.r_log;
-    const int64_t nblk = g.nwin * (cols / kPassCols);
+    if (g.r_log < 4 || g.r_log > kPassMaxLog || g.lg < 12) return hipErrorInvalidValue;
+    const int64_t nblk = g.nwin << (g.lg - 12);         // 4096 points per workgroup
     if (nblk <= 0) return hipSuccess;
     dim3 grid((unsigned)nblk), block(kPassThreads);
 #define MRDFT_PASS(IK, OK) \
