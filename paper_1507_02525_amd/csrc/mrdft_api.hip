@@ -143,7 +143,8 @@ struct mrdft_plan {
     hipGraphExec_t gexec = nullptr;
     const void* gkey_x = nullptr;
     void* gkey_y = nullptr;
-    float2* d_s[2] = {nullptr, nullptr};    // pass ping-pong scratch
+    float2* d_s[2] = {nullptr, nullptr};    // pass ping-pong scratch of the caller's stream / side stream 0
+    float2* d_ss[3][2] = {};                // ping-pong scratch of side streams 1..3
     // spectral loss workspace
     float* d_v = nullptr;
     float2* d_Yv = nullptr;
@@ -216,6 +217,10 @@ void free_plan(mrdft_plan* p) {
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
     dfree(p->d_s[0]);
     dfree(p->d_s[1]);
+    for (auto& pr : p->d_ss) {
+        dfree(pr[0]);
+        dfree(pr[1]);
+    }
     dfree(p->d_v);
     dfree(p->d_Yv);
     dfree(p->d_Yz);
@@ -476,10 +481,11 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
     bool need_side = false;
     for (const Group& g : p->groups) need_side |= p->dtype != MRDFT_R32 || g.order > kRowsMaxLevel;
     if (need_side && !(serial && serial[0] == '1')) {
-        // one side stream per level above the tile (up to kSides), default priority
+        // one side stream per level above the tile (up to kSides), default priority;
+        // the real launch covers the levels up to 16
         int levels = 0;
-        for (const Group& g : p->groups) levels = std::max(levels, g.order - kTileMaxLog);
-        if (p->dtype == MRDFT_R32) levels = std::min(levels, 1);     // the real launch covers levels <= 16
+        for (const Group& g : p->groups)
+            levels = std::max(levels, g.order - (p->dtype == MRDFT_R32 ? kRowsMaxLevel : kTileMaxLog));
         HIP_TRY(hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming));
         for (int k = 0; k < std::min(levels, (int)mrdft_plan::kSides); ++k) {
             HIP_TRY(hipStreamCreateWithFlags(&p->side[k], hipStreamNonBlocking));
@@ -488,9 +494,16 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
         }
     }
     if (scratch > 0) {
+        // one ping-pong pair per side stream: chains of passes of different
+        // levels run concurrently
         if (hipMalloc(&p->d_s[0], sizeof(float2) * scratch) != hipSuccess ||
             hipMalloc(&p->d_s[1], sizeof(float2) * scratch) != hipSuccess)
             return fail(MRDFT_E_ALLOC, "pass workspace allocation failed (2 x %lld complex)", (long long)scratch);
+        for (int k = 1; k < p->nsides; ++k)
+            if (hipMalloc(&p->d_ss[k - 1][0], sizeof(float2) * scratch) != hipSuccess ||
+                hipMalloc(&p->d_ss[k - 1][1], sizeof(float2) * scratch) != hipSuccess)
+                return fail(MRDFT_E_ALLOC, "pass workspace allocation failed (%d x 2 x %lld complex)", p->nsides,
+                            (long long)scratch);
     }
     HIP_TRY(hipStreamSynchronize(s));
     return MRDFT_OK;
@@ -712,15 +725,18 @@ mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, h
     }
     const bool real_jobs_cover = in_kind == IN_R32 && p->d_rjobs;
     const bool cjobs_cover = in_kind == IN_C64 && p->d_cjobs && p->tile_log == kC64TileLog;
+    int chain = 0;                                    // multi-pass levels, dealt over the side streams
     for (const Group& g : p->groups) {
         const int64_t N = int64_t(1) << g.order;
         for (int i = kTileMaxLog + 1; i <= g.order; ++i) {
             if ((real_jobs_cover || cjobs_cover) && i <= kRowsMaxLevel) continue;     // in the one launch
             if (i < p->lo || i > p->hi) continue;                                      // level not kept
-            // single-pass levels spread over the side streams; the multi-pass
-            // levels share one scratch buffer and therefore one stream
-            const int si = (i <= kUpperMaxLevel) ? (i - kTileMaxLog - 1) : 0;
-            const hipStream_t s = p->nsides ? p->side[si % p->nsides] : s0;
+            // levels spread over the side streams; the passes of one level run
+            // in order on one stream with that stream's scratch pair
+            const int si = (i <= kUpperMaxLevel) ? (i - kTileMaxLog - 1) : chain++;
+            const int k = p->nsides ? si % p->nsides : 0;
+            const hipStream_t s = p->nsides ? p->side[k] : s0;
+            float2* const* ds = k == 0 ? p->d_s : p->d_ss[k - 1];
             if (i <= kUpperMaxLevel) {
                 if (p->hs) return fail(MRDFT_E_UNSUPPORTED, "half-spectrum output of level %d without the real launch", i);
                 PassGeom geo;
@@ -751,8 +767,8 @@ mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, h
                 geo.in_stride = N;
                 geo.out_sig = last ? g.d_out_sig : nullptr;
                 geo.out_stride = last ? (int64_t)p->kept(g.order) * (N >> p->hs) : N;
-                const void* in = first ? x : (const void*)p->d_s[(q - 1) & 1];
-                void* out = last ? (void*)level_ptr(p, Y, i, N >> p->hs) : (void*)p->d_s[q & 1];
+                const void* in = first ? x : (const void*)ds[(q - 1) & 1];
+                void* out = last ? (void*)level_ptr(p, Y, i, N >> p->hs) : (void*)ds[q & 1];
                 const int ok = (last && p->hs) ? OUT_HALF : OUT_STORE;
                 ProfScope ps(p, MRDFT_KERNEL_PASS_FWD, s);
                 HIP_TRY(launch_pass(false, first ? in_kind : IN_C64, ok, in, out, geo, tw, s));
