@@ -19,6 +19,7 @@ import sys
 import time
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
+EXTRA_NAMES = ("workload3", "workload4", "workload2_half", "workload2d", "workload5")
 
 
 def parse():
@@ -32,6 +33,8 @@ def parse():
                     help="first run a plain 256 MiB device copy (reference for HBM byte counters)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the complex workloads reported beside the headline line")
+    ap.add_argument("--extra", default=",".join(EXTRA_NAMES),
+                    help="comma-separated subset of the workloads beside the headline (%s)" % ",".join(EXTRA_NAMES))
     return ap.parse_args()
 
 
@@ -103,7 +106,7 @@ def measured_traffic(kind):
     return None
 
 
-def extra_workloads(steps, warmup, HBM):
+def extra_workloads(steps, warmup, HBM, names=EXTRA_NAMES):
     """Workloads beside the headline: one long complex signal (N = 2^24) and a
     ragged batch of 1000 complex signals (m in 8..18) through a tuned plan with
     graph replay (forward only), the real batch with packed half-spectrum
@@ -116,6 +119,8 @@ def extra_workloads(steps, warmup, HBM):
     out = {}
     for k, name in ((3, "one complex64 signal, N=2^24 (m=24), tuned plan"),
                     (4, "1000 complex64 signals, m~U{8..18}, int64 offsets, tuned plan, graph replay")):
+        if "workload%d" % k not in names:
+            continue
         d = workloads.make(k)
         if k == 3:
             x = torch.from_numpy(d["x"]).cuda().view(-1)
@@ -137,52 +142,55 @@ def extra_workloads(steps, warmup, HBM):
         del Y, x, plan
         torch.cuda.empty_cache()
     # the real batch with packed half-spectrum output (half the output bytes)
-    d = workloads.make(2)
-    x = torch.from_numpy(d["x"]).cuda().view(-1)
-    plan = api.Plan(m=d["m"], batch=d["batch"], dtype="r32", half=True)
-    Y = torch.empty(plan.n_out, dtype=torch.complex64, device="cuda")
-    fn = lambda: plan.mrdft_forward(x, Y)   # noqa: E731
-    for _ in range(warmup):
-        fn()
-    ms = timed(fn, steps, torch.cuda.synchronize)
-    byts = int(plan.n_in) * 4 + plan.n_out * 8
-    out["workload2_half"] = {"workload": "64 real float32 signals, N=2^16 (m=16), packed half-spectrum output",
-                             "ms_per_call": round(ms, 4),
-                             "Gsamples_per_s": round(plan.n_in / (ms * 1e-3) / 1e9, 3),
-                             "hbm_frac": round(byts / (ms * 1e-3) / 1e9 / HBM, 4)}
-    del Y, x, plan
-    torch.cuda.empty_cache()
+    if "workload2_half" in names:
+        d = workloads.make(2)
+        x = torch.from_numpy(d["x"]).cuda().view(-1)
+        plan = api.Plan(m=d["m"], batch=d["batch"], dtype="r32", half=True)
+        Y = torch.empty(plan.n_out, dtype=torch.complex64, device="cuda")
+        fn = lambda: plan.mrdft_forward(x, Y)   # noqa: E731
+        for _ in range(warmup):
+            fn()
+        ms = timed(fn, steps, torch.cuda.synchronize)
+        byts = int(plan.n_in) * 4 + plan.n_out * 8
+        out["workload2_half"] = {"workload": "64 real float32 signals, N=2^16 (m=16), packed half-spectrum output",
+                                 "ms_per_call": round(ms, 4),
+                                 "Gsamples_per_s": round(plan.n_in / (ms * 1e-3) / 1e9, 3),
+                                 "hbm_frac": round(byts / (ms * 1e-3) / 1e9 / HBM, 4)}
+        del Y, x, plan
+        torch.cuda.empty_cache()
     # two-dimensional separable transform: 4 real images of 1024 x 1024, all 100 level pairs
-    rng = np.random.default_rng(1515)
-    x = torch.from_numpy(workloads.gaussian_real(rng, (4, 1024, 1024))).cuda()
-    plan2 = api.Plan2D(10, 10, batch=4, dtype="r32")
-    Y = torch.empty(plan2.n_out, dtype=torch.complex64, device="cuda")
-    fn = lambda: plan2.mrdft_forward2d(x, Y)   # noqa: E731
-    for _ in range(warmup):
-        fn()
-    ms = timed(fn, steps, torch.cuda.synchronize)
-    byts = plan2.n_in * 4 + plan2.n_out * 8
-    out["workload2d"] = {"workload": "2-D separable, 4 real float32 images 1024 x 1024, 100 level pairs",
-                         "ms_per_call": round(ms, 4),
-                         "Gsamples_per_s": round(plan2.n_in / (ms * 1e-3) / 1e9, 3),
-                         "hbm_frac": round(byts / (ms * 1e-3) / 1e9 / HBM, 4)}
-    del Y, x, plan2
-    torch.cuda.empty_cache()
+    if "workload2d" in names:
+        rng = np.random.default_rng(1515)
+        x = torch.from_numpy(workloads.gaussian_real(rng, (4, 1024, 1024))).cuda()
+        plan2 = api.Plan2D(10, 10, batch=4, dtype="r32")
+        Y = torch.empty(plan2.n_out, dtype=torch.complex64, device="cuda")
+        fn = lambda: plan2.mrdft_forward2d(x, Y)   # noqa: E731
+        for _ in range(warmup):
+            fn()
+        ms = timed(fn, steps, torch.cuda.synchronize)
+        byts = plan2.n_in * 4 + plan2.n_out * 8
+        out["workload2d"] = {"workload": "2-D separable, 4 real float32 images 1024 x 1024, 100 level pairs",
+                             "ms_per_call": round(ms, 4),
+                             "Gsamples_per_s": round(plan2.n_in / (ms * 1e-3) / 1e9, 3),
+                             "hbm_frac": round(byts / (ms * 1e-3) / 1e9 / HBM, 4)}
+        del Y, x, plan2
+        torch.cuda.empty_cache()
     # spectral loss, forward + backward: 32 real pairs of 2^18 samples
-    d = workloads.make(5)
-    x = torch.from_numpy(d["x"]).cuda().requires_grad_(True)
-    z = torch.from_numpy(d["z"]).cuda()
+    if "workload5" in names:
+        d = workloads.make(5)
+        x = torch.from_numpy(d["x"]).cuda().requires_grad_(True)
+        z = torch.from_numpy(d["z"]).cuda()
 
-    def loss_step():
-        x.grad = None
-        api.spectral_loss(x, z).backward()
+        def loss_step():
+            x.grad = None
+            api.spectral_loss(x, z).backward()
 
-    for _ in range(warmup):
-        loss_step()
-    ms = timed(loss_step, steps, torch.cuda.synchronize)
-    out["workload5"] = {"workload": "spectral loss forward + backward, 32 real float32 pairs, N=2^18 (m=18)",
-                        "ms_per_call": round(ms, 4),
-                        "Gsamples_per_s": round(x.numel() / (ms * 1e-3) / 1e9, 3)}
+        for _ in range(warmup):
+            loss_step()
+        ms = timed(loss_step, steps, torch.cuda.synchronize)
+        out["workload5"] = {"workload": "spectral loss forward + backward, 32 real float32 pairs, N=2^18 (m=18)",
+                            "ms_per_call": round(ms, 4),
+                            "Gsamples_per_s": round(x.numel() / (ms * 1e-3) / 1e9, 3)}
     return out
 
 
@@ -191,6 +199,11 @@ def main():
     if args.gpus != 1:
         print("bench.py: this benchmark measures one GPU only (the transform shards by signal; "
               "multi-GPU runs are not part of it). Use --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    names = [n for n in args.extra.split(",") if n]
+    unknown = sorted(set(names) - set(EXTRA_NAMES))
+    if unknown:
+        print("bench.py: unknown workload(s) %s; choose from %s" % (unknown, ",".join(EXTRA_NAMES)), file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
@@ -313,7 +326,7 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(d["x"], args.cpu_seconds)
 
-    extra = None if args.no_extra else extra_workloads(max(5, args.steps // 4), 2, HBM_PEAK_GBS)
+    extra = None if args.no_extra else extra_workloads(max(5, args.steps // 4), 2, HBM_PEAK_GBS, names)
 
     out = {
         "metric": "MrDFT Gsamples/s & % HBM peak, fwd and fwd+bwd, vs per-level form, rel err<=1e-6",

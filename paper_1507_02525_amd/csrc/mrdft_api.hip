@@ -337,7 +337,7 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
         const int64_t N = int64_t(1) << mj;
         const int t = mj < kTileMaxLog ? mj : kTileMaxLog;
         const int64_t T = int64_t(1) << t;
-        for (int64_t tau = 0; tau < N / T; ++tau) {
+        for (int64_t tau = 0; p->lo <= t && tau < N / T; ++tau) {     // a tile below the range stores nothing
             TileJob jb;
             jb.in_off = p->in_off[j] + tau * T;
             jb.out_off = p->base(j) + ((tau * T) >> p->hs);
@@ -361,9 +361,11 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
         p->jobs_tmax = std::max(p->jobs_tmax, (int)jobs[q].t);
         if (q >= p->njobs_full) p->tail_tmax = std::max(p->tail_tmax, (int)jobs[q].t);
     }
-    if (hipMalloc(&p->d_jobs, sizeof(TileJob) * jobs.size()) != hipSuccess)
-        return fail(MRDFT_E_ALLOC, "tile table allocation failed (%zu bytes)", sizeof(TileJob) * jobs.size());
-    HIP_TRY(hipMemcpyAsync(p->d_jobs, jobs.data(), sizeof(TileJob) * jobs.size(), hipMemcpyHostToDevice, s));
+    if (!jobs.empty()) {
+        if (hipMalloc(&p->d_jobs, sizeof(TileJob) * jobs.size()) != hipSuccess)
+            return fail(MRDFT_E_ALLOC, "tile table allocation failed (%zu bytes)", sizeof(TileJob) * jobs.size());
+        HIP_TRY(hipMemcpyAsync(p->d_jobs, jobs.data(), sizeof(TileJob) * jobs.size(), hipMemcpyHostToDevice, s));
+    }
     if (p->dtype == MRDFT_R32) {
         mrdft_status st = upload_jobs(real_jobs(p, p->order), &p->d_rjobs, &p->nrjobs, s);
         if (st) return st;
@@ -593,7 +595,7 @@ std::vector<RealJob> real_jobs(const mrdft_plan* p, int order) {
         const int mj = p->orders[j];
         if (mj < kRealTileLog) continue;
         const int64_t N = int64_t(1) << mj;
-        for (int64_t tau = 0; tau < (N >> kRealTileLog); ++tau)
+        for (int64_t tau = 0; p->lo <= kRealTileLog && tau < (N >> kRealTileLog); ++tau)   // tiles keep a level
             jb.add_tile(RealJob{p->in_off[j] + (tau << kRealTileLog), p->base(j) + ((tau << kRealTileLog) >> p->hs),
                                 N >> p->hs, 0, p->range()},
                         6);                                    // 12 x 32 KB against 64 KB per piece
@@ -630,7 +632,7 @@ std::vector<RealJob> complex_jobs(const mrdft_plan* p, int order, std::vector<un
             continue;
         }
         const int64_t N = int64_t(1) << mj;
-        for (int64_t tau = 0; tau < (N >> kC64TileLog); ++tau)
+        for (int64_t tau = 0; p->lo <= kC64TileLog && tau < (N >> kC64TileLog); ++tau)     // tiles keep a level
             jb.add_tile(RealJob{p->in_off[j] + (tau << kC64TileLog), p->base(j) + (tau << kC64TileLog), N, 0,
                                 p->range()},
                         5);                                    // 11 x 16 KB against 32 KB per piece

@@ -163,6 +163,8 @@ def _levels_ref(x, lo, hi):
     ("c64", [16, 12, 10], 3, 13),       # complex tile and pieces
     ("c64", [17, 11, 14], 12, 17),      # pieces and a pass level only
     ("c64", [8, 13], 1, 4),             # register levels only
+    ("c64", [16, 15, 9], 14, 16),       # upper pieces only: no tile job is launched
+    ("r32", [16, 12, 5], 14, 16),       # the same for real input; two signals keep no level
 ])
 def test_level_range_forward_and_adjoint(dtype, orders, lo, hi):
     need_gpu()
