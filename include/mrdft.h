@@ -146,6 +146,7 @@ mrdft_status mrdft_plan_sizes(mrdft_plan_t plan, int64_t* n_in, int64_t* n_out);
 #define MRDFT_ORDER_TILES_FIRST 0 /* tiles, then upper-level pieces from the highest level down */
 #define MRDFT_ORDER_ROWS_FIRST 1  /* upper-level pieces (highest level first), then tiles */
 #define MRDFT_ORDER_INTERLEAVED 2 /* tiles and pieces alternate in proportion */
+#define MRDFT_ORDER_BLOCKS 3      /* per block of 2^16 samples: its tiles and the pieces inside it, together */
 mrdft_status mrdft_plan_schedule(mrdft_plan_t plan, int* tile_log, int* grid, int* order);
 
 /*

@@ -24,7 +24,7 @@ MRDFT_FLAG_NONE = 0
 MRDFT_FLAG_TUNE = 1
 MRDFT_FLAG_GRAPH = 2
 MRDFT_FLAG_HALF = 4
-ORDERS = ("tiles_first", "rows_first", "interleaved")
+ORDERS = ("tiles_first", "rows_first", "interleaved", "blocks")
 KERNEL_KINDS = ("tile_fwd", "pass_fwd", "tile_adj", "pass_adj", "fused_fwd", "loss")
 
 # Every symbol the header declares, with (restype, argtypes).

@@ -135,7 +135,7 @@ struct mrdft_plan {
     unsigned flags = 0;
     int tile_log = kTileMaxLog;
     int grid = 0;
-    int order = MRDFT_ORDER_TILES_FIRST;
+    int order = MRDFT_ORDER_BLOCKS;
     int num_cu = 0;
     // graph replay of the forward
     hipStream_t cap_stream = nullptr;
@@ -519,7 +519,11 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
 //                 the pieces from the highest level down (longest first, the
 //                 short ones fill the tail);
 //   rows first  : the pieces (highest level first), then the tiles;
-//   interleaved : tiles and pieces alternate in proportion.
+//   interleaved : tiles and pieces alternate in proportion;
+//   blocks      : every block of 2^16 samples (or the whole signal if shorter)
+//                 goes whole to one bucket, its tiles and the pieces of the
+//                 windows inside it alternating: the block's samples are read
+//                 from HBM about once and then served by the XCD's L2.
 struct JobBuckets {
     static constexpr int kX = 8;
     std::vector<std::vector<RealJob>> tiles = std::vector<std::vector<RealJob>>(kX);
@@ -541,6 +545,21 @@ struct JobBuckets {
         }
         load[b] += pieces;
     }
+    // t and r alternate in proportion (r first on a tie)
+    static void alternate(std::vector<RealJob>& out, const std::vector<RealJob>& t, const std::vector<RealJob>& r) {
+        const size_t nt = t.size(), nr = r.size();
+        size_t it = 0, ir = 0;
+        while (it < nt || ir < nr) {
+            if (ir < nr && (it >= nt || ir * nt <= it * nr)) out.push_back(r[ir++]);
+            else out.push_back(t[it++]);
+        }
+    }
+    std::vector<std::vector<RealJob>> blocks = std::vector<std::vector<RealJob>>(kX);
+    void add_block(const std::vector<RealJob>& t, const std::vector<RealJob>& r, int64_t cost) {
+        const int b = lightest();
+        alternate(blocks[b], t, r);
+        load[b] += cost;
+    }
     // contiguous: the buckets one after the other, their starts in seg[0..8]
     // (persistent launch); otherwise interleaved so that block b falls in
     // bucket b mod 8 (one workgroup per job).
@@ -549,16 +568,13 @@ struct JobBuckets {
         for (int b = 0; b < kX; ++b) {
             std::stable_sort(rows[b].begin(), rows[b].end(),
                              [](const RealJob& a, const RealJob& c) { return a.lg > c.lg; });
-            if (order == MRDFT_ORDER_ROWS_FIRST) {
+            if (order == MRDFT_ORDER_BLOCKS) {
+                bucket[b] = blocks[b];
+            } else if (order == MRDFT_ORDER_ROWS_FIRST) {
                 bucket[b] = rows[b];
                 bucket[b].insert(bucket[b].end(), tiles[b].begin(), tiles[b].end());
             } else if (order == MRDFT_ORDER_INTERLEAVED) {
-                const size_t nt = tiles[b].size(), nr = rows[b].size();
-                size_t it = 0, ir = 0;
-                while (it < nt || ir < nr) {
-                    if (ir < nr && (it >= nt || ir * nt <= it * nr)) bucket[b].push_back(rows[b][ir++]);
-                    else bucket[b].push_back(tiles[b][it++]);
-                }
+                alternate(bucket[b], tiles[b], rows[b]);
             } else {
                 bucket[b] = tiles[b];
                 bucket[b].insert(bucket[b].end(), rows[b].begin(), rows[b].end());
@@ -591,21 +607,40 @@ struct JobBuckets {
 // (2^(lg-13) pieces per window).
 std::vector<RealJob> real_jobs(const mrdft_plan* p, int order) {
     JobBuckets jb;
+    constexpr int64_t kTileCost = 6;                           // 12 x 32 KB against 64 KB per piece
     for (int64_t j = 0; j < p->batch; ++j) {
         const int mj = p->orders[j];
         if (mj < kRealTileLog) continue;
         const int64_t N = int64_t(1) << mj;
-        for (int64_t tau = 0; p->lo <= kRealTileLog && tau < (N >> kRealTileLog); ++tau)   // tiles keep a level
-            jb.add_tile(RealJob{p->in_off[j] + (tau << kRealTileLog), p->base(j) + ((tau << kRealTileLog) >> p->hs),
-                                N >> p->hs, 0, p->range()},
-                        6);                                    // 12 x 32 KB against 64 KB per piece
-        for (int lg = std::max(kRowsMinLevel, p->lo); lg <= std::min({mj, kRowsMaxLevel, p->hi}); ++lg) {
+        const bool tiles = p->lo <= kRealTileLog;              // tiles keep a level
+        const int plo = std::max(kRowsMinLevel, p->lo), phi = std::min({mj, kRowsMaxLevel, p->hi});
+        auto tile = [&](int64_t tau) {
+            return RealJob{p->in_off[j] + (tau << kRealTileLog), p->base(j) + ((tau << kRealTileLog) >> p->hs),
+                           N >> p->hs, 0, p->range()};
+        };
+        auto window = [&](int lg, int64_t w) {                 // piece 0 of window w of level lg
             const int64_t L = int64_t(1) << lg;
-            for (int64_t w = 0; w < N / L; ++w)
-                jb.add_window(RealJob{p->in_off[j] + w * L, p->base(j) + (((int64_t)(lg - 1) * N + w * L) >> p->hs),
-                                      N, lg, 0},
-                              1 << (lg - kRowsMinLevel));
+            return RealJob{p->in_off[j] + w * L, p->base(j) + (((int64_t)(lg - 1) * N + w * L) >> p->hs), N, lg, 0};
+        };
+        if (order == MRDFT_ORDER_BLOCKS) {
+            const int64_t U = int64_t(1) << std::min(mj, kRowsMaxLevel);   // holds whole windows of every piece level
+            for (int64_t u0 = 0; u0 < N; u0 += U) {
+                std::vector<RealJob> t, r;
+                for (int64_t tau = u0 >> kRealTileLog; tiles && tau < (u0 + U) >> kRealTileLog; ++tau) t.push_back(tile(tau));
+                for (int lg = phi; lg >= plo; --lg)            // highest level first
+                    for (int64_t w = u0 >> lg; w < (u0 + U) >> lg; ++w)
+                        for (int g = 0; g < (1 << (lg - kRowsMinLevel)); ++g) {
+                            RealJob jb1 = window(lg, w);
+                            jb1.g = g;
+                            r.push_back(jb1);
+                        }
+                jb.add_block(t, r, kTileCost * (int64_t)t.size() + (int64_t)r.size());
+            }
+            continue;
         }
+        for (int64_t tau = 0; tiles && tau < (N >> kRealTileLog); ++tau) jb.add_tile(tile(tau), kTileCost);
+        for (int lg = plo; lg <= phi; ++lg)
+            for (int64_t w = 0; w < (N >> lg); ++w) jb.add_window(window(lg, w), 1 << (lg - kRowsMinLevel));
     }
     return jb.deal(order);
 }
@@ -614,6 +649,7 @@ std::vector<RealJob> real_jobs(const mrdft_plan* p, int order) {
 // 12..16 (2^(lg-12) pieces of 16 rows per window).
 std::vector<RealJob> complex_jobs(const mrdft_plan* p, int order, std::vector<unsigned>* seg) {
     JobBuckets jb;
+    constexpr int64_t kTileCost = 5;                           // 11 x 16 KB against 32 KB per piece
     for (int64_t j = 0; j < p->batch; ++j) {
         const int mj = p->orders[j];
         if (mj < kC64TileLog) {
@@ -625,23 +661,42 @@ std::vector<RealJob> complex_jobs(const mrdft_plan* p, int order, std::vector<un
             int64_t n = 1;
             while (j + n < p->batch && p->orders[j + n] == mj && n < per) ++n;
             const int64_t vlen = n * N;
-            jb.add_tile(RealJob{p->in_off[j], p->base(j), N | (vlen << 32), kMultiTileLg + mj,
-                                LevelRange::pack(p->lo, std::min(p->hi, mj))},
-                        5);
+            const RealJob mt{p->in_off[j], p->base(j), N | (vlen << 32), kMultiTileLg + mj,
+                             LevelRange::pack(p->lo, std::min(p->hi, mj))};
+            if (order == MRDFT_ORDER_BLOCKS) jb.add_block({mt}, {}, kTileCost);
+            else jb.add_tile(mt, kTileCost);
             j += n - 1;
             continue;
         }
         const int64_t N = int64_t(1) << mj;
-        for (int64_t tau = 0; p->lo <= kC64TileLog && tau < (N >> kC64TileLog); ++tau)     // tiles keep a level
-            jb.add_tile(RealJob{p->in_off[j] + (tau << kC64TileLog), p->base(j) + (tau << kC64TileLog), N, 0,
-                                p->range()},
-                        5);                                    // 11 x 16 KB against 32 KB per piece
-        for (int lg = std::max(kCRowsMinLevel, p->lo); lg <= std::min({mj, kRowsMaxLevel, p->hi}); ++lg) {
+        const bool tiles = p->lo <= kC64TileLog;               // tiles keep a level
+        const int plo = std::max(kCRowsMinLevel, p->lo), phi = std::min({mj, kRowsMaxLevel, p->hi});
+        auto tile = [&](int64_t tau) {
+            return RealJob{p->in_off[j] + (tau << kC64TileLog), p->base(j) + (tau << kC64TileLog), N, 0, p->range()};
+        };
+        auto window = [&](int lg, int64_t w) {                 // piece 0 of window w of level lg
             const int64_t L = int64_t(1) << lg;
-            for (int64_t w = 0; w < N / L; ++w)
-                jb.add_window(RealJob{p->in_off[j] + w * L, p->base(j) + (int64_t)(lg - 1) * N + w * L, 0, lg, 0},
-                              1 << (lg - kCRowsMinLevel));
+            return RealJob{p->in_off[j] + w * L, p->base(j) + (int64_t)(lg - 1) * N + w * L, 0, lg, 0};
+        };
+        if (order == MRDFT_ORDER_BLOCKS) {
+            const int64_t U = int64_t(1) << std::min(mj, kRowsMaxLevel);
+            for (int64_t u0 = 0; u0 < N; u0 += U) {
+                std::vector<RealJob> t, r;
+                for (int64_t tau = u0 >> kC64TileLog; tiles && tau < (u0 + U) >> kC64TileLog; ++tau) t.push_back(tile(tau));
+                for (int lg = phi; lg >= plo; --lg)
+                    for (int64_t w = u0 >> lg; w < (u0 + U) >> lg; ++w)
+                        for (int g = 0; g < (1 << (lg - kCRowsMinLevel)); ++g) {
+                            RealJob jb1 = window(lg, w);
+                            jb1.g = g;
+                            r.push_back(jb1);
+                        }
+                jb.add_block(t, r, kTileCost * (int64_t)t.size() + (int64_t)r.size());
+            }
+            continue;
         }
+        for (int64_t tau = 0; tiles && tau < (N >> kC64TileLog); ++tau) jb.add_tile(tile(tau), kTileCost);
+        for (int lg = plo; lg <= phi; ++lg)
+            for (int64_t w = 0; w < (N >> lg); ++w) jb.add_window(window(lg, w), 1 << (lg - kCRowsMinLevel));
     }
     return jb.deal(order, seg);
 }
@@ -955,7 +1010,7 @@ mrdft_status tune(mrdft_plan* p, hipStream_t s) {
         int tile_log, order, grid;
     };
     std::vector<Cand> cands;
-    for (int order = 0; order < 3; ++order) {
+    for (int order = 0; order <= MRDFT_ORDER_BLOCKS; ++order) {
         if (real) {
             cands.push_back({kRealTileLog, order, 0});
         } else {
@@ -1206,7 +1261,7 @@ mrdft_status mrdft_plan_set_schedule(mrdft_plan_t plan, int tile_log, int grid, 
     mrdft_status st = check_plan(plan);
     if (st) return st;
     const bool real = plan->dtype == MRDFT_R32;
-    if (order < MRDFT_ORDER_TILES_FIRST || order > MRDFT_ORDER_INTERLEAVED)
+    if (order < MRDFT_ORDER_TILES_FIRST || order > MRDFT_ORDER_BLOCKS)
         return fail(MRDFT_E_INVALID_ARG, "unknown job order %d", order);
     if (real ? tile_log != kRealTileLog : (tile_log != kC64TileLog && tile_log != kTileMaxLog))
         return fail(MRDFT_E_INVALID_ARG, "tile_log %d is not available for this plan", tile_log);

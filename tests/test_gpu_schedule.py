@@ -16,7 +16,7 @@ from tests.gpu_util import FWD_TOL, log, need_gpu, to_dev, worst_level_err
 
 pytestmark = pytest.mark.gpu
 
-ORDERS = ("tiles_first", "rows_first", "interleaved")
+ORDERS = ("tiles_first", "rows_first", "interleaved", "blocks")
 
 
 def _ragged(orders, seed, dtype="c64"):
@@ -49,7 +49,7 @@ C_ORDERS = [11, 12, 9, 13, 14, 16, 17, 15, 5, 12]
 @pytest.mark.parametrize("tile_log,grid,order", [(11, 0, "tiles_first"), (11, 0, "interleaved"),
                                                  (11, 1, "tiles_first"), (11, 7, "rows_first"),
                                                  (11, 1024, "interleaved"), (11, 256, "tiles_first"),
-                                                 (12, 0, "tiles_first")])
+                                                 (12, 0, "tiles_first"), (11, 0, "blocks"), (11, 512, "blocks")])
 def test_complex_schedules_match_oracle(tile_log, grid, order):
     need_gpu()
     log("complex schedule tile_log=%d grid=%d order=%s" % (tile_log, grid, order))
