@@ -1,7 +1,8 @@
 // Adjoint MrDFT (gx = sum_i A_i^H gY^(i)) in two launches.
 //   (a) one workgroup per job: 2048-sample tiles (levels 11..1 by the
 //       transposed recurrence, mrdft_adj_tile.h; gx of the tile is written)
-//       and rows pieces of the levels 12..16 (scratch B, mrdft_adj_rows.h);
+//       and rows pieces of the levels 12..16 (scratch B, mrdft_adj_rows.h;
+//       for real output the levels 13..16 form only the Hermitian half of B);
 //   (b) one workgroup per (region, 16 columns): the column DFTs of the levels
 //       12..16, summed and added to gx.
 // Real plans accumulate Re(gx) only.
@@ -17,7 +18,9 @@ template <bool REAL>
 union AdjALds {
     AdjTileLds<REAL> tile;
     CRowsLds rows;
+    RowsLds hrows;                                    // Hermitian rows pieces (real output)
 };
+static_assert(sizeof(AdjALds<true>) <= 40 * 1024 && sizeof(AdjALds<false>) <= 40 * 1024, "four workgroups per CU");
 
 template <bool REAL>
 __global__ __launch_bounds__(kCThreads, 4) void adj_a_kernel(const float2* __restrict__ gY, void* __restrict__ gx,
@@ -36,10 +39,20 @@ __global__ __launch_bounds__(kCThreads, 4) void adj_a_kernel(const float2* __res
             break;
         }
         case 12: adj_rows_body<4>(S.rows, gyj, scratch + jb.out_off, jb.g, t4096, rowtw + rows_twiddle_offset(12), tid); break;
-        case 13: adj_rows_body<5>(S.rows, gyj, scratch + jb.out_off, jb.g, t4096, rowtw + rows_twiddle_offset(13), tid); break;
-        case 14: adj_rows_body<6>(S.rows, gyj, scratch + jb.out_off, jb.g, t4096, rowtw + rows_twiddle_offset(14), tid); break;
-        case 15: adj_rows_body<7>(S.rows, gyj, scratch + jb.out_off, jb.g, t4096, rowtw + rows_twiddle_offset(15), tid); break;
-        case 16: adj_rows_body<8>(S.rows, gyj, scratch + jb.out_off, jb.g, t4096, rowtw + rows_twiddle_offset(16), tid); break;
+        // real output: Hermitian pieces of 17 rows (half the rows of B)
+#define MRDFT_ADJ_ROWS(LG, RL)                                                                                   \
+    case LG:                                                                                                    \
+        if constexpr (REAL)                                                                                     \
+            adj_rows_real_body<RL>(S.hrows, gyj, scratch + jb.out_off, jb.g, t4096, rowtw + rows_twiddle_offset(LG), \
+                                   tid);                                                                        \
+        else                                                                                                    \
+            adj_rows_body<RL>(S.rows, gyj, scratch + jb.out_off, jb.g, t4096, rowtw + rows_twiddle_offset(LG), tid); \
+        break;
+        MRDFT_ADJ_ROWS(13, 5)
+        MRDFT_ADJ_ROWS(14, 6)
+        MRDFT_ADJ_ROWS(15, 7)
+        MRDFT_ADJ_ROWS(16, 8)
+#undef MRDFT_ADJ_ROWS
         default: break;
     }
 }

@@ -76,6 +76,73 @@ __device__ __forceinline__ void adj_rows_body(CRowsLds& S, const float2* __restr
     }
 }
 
+// Rows piece g (g < R/32) of one window of level lg = RL + 8 (13 <= lg <= 16)
+// for real output.  Only Re(A^H gY) is wanted, which is A^H h for the
+// Hermitian part h[k] = (gY[k] + conj(gY[L - k])) / 2, so B is Hermitian in
+// k2 as well (B[R - k2][n1] = conj(B[k2][n1])) and only its rows
+// k2 = 0 .. R/2 are formed: piece g takes the rows 16g .. 16g+16.  The
+// partners of rows 16g+1 .. 16g+16 are the 16 rows of group R/16 - 1 - g at
+// k1' = 255 - k1 (the mirror of the forward's Hermitian store); the partner of
+// row 16g is row R - 16g at 255 - k1, or row 0 at -k1 mod 256 when g = 0.
+// Rows 16g .. 16g+15 are written, and row R/2 by the last piece.
+template <int RL>
+__device__ __forceinline__ void adj_rows_real_body(RowsLds& S, const float2* __restrict__ gyw,
+                                                   float2* __restrict__ scw, int g, const float2* __restrict__ t4096,
+                                                   const float2* __restrict__ rowtw, int tid) {
+    constexpr int R = 1 << RL, NG = R / 16;
+    static_assert(NG >= 2, "levels 13..16");
+    const int k0 = 16 * g, gm = NG - 1 - g;
+    S.T[tid] = t4096[tid << (kTileMaxLog - kRowsLog)];
+    float4 dv[8], pv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int e = tid + u * kRowsThreads;
+        const int k1 = e >> 3, kp = (e & 7) * 2;
+        dv[u] = *(const float4*)(gyw + k0 + kp + (int64_t)R * k1);          // rows k0 + kp, +1 at k1
+        pv[u] = *(const float4*)(gyw + 16 * gm + kp + (int64_t)R * k1);     // rows 16 gm + kp, +1 at k1
+    }
+    const int k1 = tid;
+    const float2 d16 = gyw[k0 + 16 + (int64_t)R * k1];                         // row k0 + 16
+    const float2 p0 = gyw[((R - k0) & (R - 1)) + (int64_t)R * k1];              // partner of row k0
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int e = tid + u * kRowsThreads;
+        const int c = e >> 3, kp = (e & 7) * 2;
+        S.C[kp * kRowsStride + rpad(c)] = make_float2(dv[u].x, dv[u].y);
+        S.C[(kp + 1) * kRowsStride + rpad(c)] = make_float2(dv[u].z, dv[u].w);
+    }
+    S.C[16 * kRowsStride + rpad(k1)] = d16;
+    __syncthreads();
+    // h = (direct + conj(partner)) / 2; every slot is updated by one thread
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int e = tid + u * kRowsThreads;
+        const int c = 255 - (e >> 3), kp = (e & 7) * 2;
+        float2* a = &S.C[(16 - kp) * kRowsStride + rpad(c)];                   // partner row 16 gm + kp
+        float2* b = &S.C[(15 - kp) * kRowsStride + rpad(c)];                   // partner row 16 gm + kp + 1
+        *a = make_float2(0.5f * (a->x + pv[u].x), 0.5f * (a->y - pv[u].y));
+        *b = make_float2(0.5f * (b->x + pv[u].z), 0.5f * (b->y - pv[u].w));
+    }
+    {
+        const int c = g == 0 ? ((kRowsN - k1) & (kRowsN - 1)) : kRowsN - 1 - k1;
+        float2* a = &S.C[rpad(c)];
+        *a = make_float2(0.5f * (a->x + p0.x), 0.5f * (a->y - p0.y));
+    }
+    __syncthreads();
+    rows_step<0, true>(S, tid);
+    rows_step<4, true>(S, tid);
+    __syncthreads();                                  // row 16 (wave 0) before the outputs
+    const int n1 = tid;
+    const int nq = (g == NG / 2 - 1) ? 17 : 16;       // row R/2 by the last piece
+#pragma unroll
+    for (int q = 0; q < 17; ++q) {
+        if (q < nq) {
+            const int k2 = k0 + q;
+            scw[k2 * kRowsN + n1] = cmulc(S.C[q * kRowsStride + rpad(n1)], rowtw[k2 * kRowsN + n1]);
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Columns phase.
 
@@ -138,10 +205,13 @@ __device__ __forceinline__ void adj_cols_fft(AdjColsLds& S, int tid) {
 // multiple of L), columns c0 .. c0+15; acc[s] is the contribution to the
 // thread's gx values at region row rho = (tid >> 4) + 16 s, column tid & 15.
 //   scr : the scratch block of this level at the region's first sample
+// HERM (real output, levels 13..16): only the rows k2 <= R/2 are in the
+// scratch; the others are their conjugates (B[R - k2] = conj(B[k2])).
 template <int RL, bool REAL, class ACC>
 __device__ __forceinline__ void adj_cols_level(AdjColsLds& S, const float2* __restrict__ scr, int region_log, int c0,
                                                ACC* acc, int tid) {
     constexpr int R = 1 << RL, L = R * kRowsN;
+    constexpr bool HERM = REAL && RL >= 5;
     const int nwin = 1 << (region_log - RL - kRowsLog);          // windows of this level in the region
     const int rows = nwin * R;                                    // = region / 256
     // load B[w][k2][c0 + col] (128-byte chunks) into FFT f = w * 16 + col, point
@@ -153,14 +223,17 @@ __device__ __forceinline__ void adj_cols_level(AdjColsLds& S, const float2* __re
         const int e = tid + u * kRowsThreads;
         const int col = e & 15, rr = e >> 4;                      // rr = w * R + k2
         const int w = rr / R, k2 = rr % R;
-        if (e < rows * 16) v[u] = scr[(int64_t)w * L + k2 * kRowsN + c0 + col];
+        if (e < rows * 16 && (!HERM || k2 <= R / 2)) v[u] = scr[(int64_t)w * L + k2 * kRowsN + c0 + col];
     }
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
         const int e = tid + u * kRowsThreads;
         const int col = e & 15, rr = e >> 4;
         const int w = rr / R, k2 = rr % R;
-        if (e < rows * 16) S.V[cpad((w * 16 + col) * R + k2)] = v[u];
+        if (e < rows * 16 && (!HERM || k2 <= R / 2)) {
+            S.V[cpad((w * 16 + col) * R + k2)] = v[u];
+            if (HERM && k2 > 0 && k2 < R / 2) S.V[cpad((w * 16 + col) * R + R - k2)] = cconj(v[u]);
+        }
     }
     __syncthreads();
     // all 4096 points go through the steps; with a region below 2^16 the FFTs

@@ -404,8 +404,11 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
                 if (lg < p->lo || lg > p->hi) continue;
                 any_upper = true;
                 const int64_t L = int64_t(1) << lg;
+                // real plans: 17-row Hermitian pieces above level 12 (half as many)
+                const int pieces = (p->dtype == MRDFT_R32 && lg > kCRowsMinLevel) ? 1 << (lg - kCRowsMinLevel - 1)
+                                                                                   : 1 << (lg - kCRowsMinLevel);
                 for (int64_t w = 0; w < N / L; ++w)
-                    for (int g = 0; g < (1 << (lg - kCRowsMinLevel)); ++g)
+                    for (int g = 0; g < pieces; ++g)
                         aj.push_back(RealJob{p->basef(j) + (int64_t)(lg - 1) * N + w * L,
                                              scr + (int64_t)(lg - kCRowsMinLevel) * N + w * L, 0, lg, g});
             }
@@ -870,6 +873,8 @@ mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, h
 
 mrdft_status run_adjoint(mrdft_plan* p, const float2* gY, void* gx, bool real_out, hipStream_t s) {
     const Twiddles tw = p->tw();
+    // the job tables of a real plan hold Hermitian pieces: real output only
+    if (real_out != (p->dtype == MRDFT_R32)) return fail(MRDFT_E_UNSUPPORTED, "adjoint output type differs from the plan's");
     if (p->hs) {
         // packed half-spectrum gradient -> full-spectrum layout, then the full adjoint
         {

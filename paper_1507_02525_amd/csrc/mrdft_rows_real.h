@@ -44,7 +44,8 @@ __device__ __forceinline__ int rpad(int i) { return i + (i >> 4); }
 
 // One radix-16 job of a Stockham step with span 2^LNS (LNS = 0 or 4) on row
 // r: 16 points j + 16 s in, positions (j / NS) * 16 NS + (j mod NS) + s NS out.
-template <int LNS>
+// INV: the conjugate transform (the adjoint's rows).
+template <int LNS, bool INV = false>
 __device__ __forceinline__ void rows_job_load(const RowsLds& S, int r, int j, float2* v) {
     constexpr int NS = 1 << LNS;
     const float2* src = S.C + r * kRowsStride;
@@ -53,9 +54,12 @@ __device__ __forceinline__ void rows_job_load(const RowsLds& S, int r, int j, fl
     if constexpr (LNS > 0) {
         const int jm = j & (NS - 1);
 #pragma unroll
-        for (int s = 1; s < 16; ++s) v[s] = cmul(v[s], S.T[(jm * s) << (kRowsLog - LNS - 4)]);
+        for (int s = 1; s < 16; ++s) {
+            const float2 w = S.T[(jm * s) << (kRowsLog - LNS - 4)];
+            v[s] = INV ? cmulc(v[s], w) : cmul(v[s], w);
+        }
     }
-    dft_reg<16, false>(v);
+    dft_reg<16, INV>(v);
 }
 template <int LNS>
 __device__ __forceinline__ void rows_job_store(RowsLds& S, int r, int j, const float2* v) {
@@ -77,18 +81,18 @@ __device__ __forceinline__ void rows_wave_sync() {
 // One radix-16 Stockham step: rows 0..15 with one job per thread, then row 16
 // by lanes 0..15 of wave 0 alone (no other wave touches that row, so a wave
 // sync separates its reads from its writes).
-template <int LNS>
+template <int LNS, bool INV = false>
 __device__ __forceinline__ void rows_step(RowsLds& S, int tid) {
     {
         float2 v[16];
-        rows_job_load<LNS>(S, tid >> 4, tid & 15, v);
+        rows_job_load<LNS, INV>(S, tid >> 4, tid & 15, v);
         __syncthreads();
         rows_job_store<LNS>(S, tid >> 4, tid & 15, v);
         __syncthreads();
     }
     if (tid < 16) {
         float2 v[16];
-        rows_job_load<LNS>(S, 16, tid, v);
+        rows_job_load<LNS, INV>(S, 16, tid, v);
         rows_wave_sync();
         rows_job_store<LNS>(S, 16, tid, v);
         rows_wave_sync();
