@@ -105,7 +105,20 @@ __global__ __launch_bounds__(kRowsThreads, 4) void adj_b_kernel(void* __restrict
     }
 }
 
+__global__ __launch_bounds__(256) void zero_kernel(float* __restrict__ p, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0.0f;
+}
+
 }  // namespace
+
+hipError_t launch_zero(void* p, int64_t bytes, hipStream_t s) {
+    const int64_t n = bytes / (int64_t)sizeof(float);
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(zero_kernel, dim3((unsigned)blocks), dim3(256), 0, s, (float*)p, n);
+    return hipGetLastError();
+}
 
 hipError_t launch_adj_a(bool real_out, const float2* gY, void* gx, float2* scratch, const RealJob* jobs, int64_t njobs,
                         const Twiddles& tw, hipStream_t s) {

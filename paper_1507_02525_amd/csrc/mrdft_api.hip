@@ -130,6 +130,7 @@ struct mrdft_plan {
     int64_t nacols = 0;
     TileJob* d_asmall = nullptr;            // signals of order < 11: tile adjoint kernel
     int64_t nasmall = 0;
+    bool adj_zero = false;                  // no tile level kept: gx is cleared instead of running the tiles
     float2* d_ascratch = nullptr;
     // schedule (tuned or default)
     unsigned flags = 0;
@@ -388,14 +389,17 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
         std::vector<TileJob> sm;
         int64_t scr = 0;
         static const int kColOrder[16] = {0, 2, 4, 6, 8, 10, 12, 14, 1, 3, 5, 7, 9, 11, 13, 15};
+        // with no tile level kept the tiles would only write zeros: gx is
+        // cleared by one fill before the columns phase adds to it
+        p->adj_zero = p->lo > kC64TileLog;
         for (int64_t j = 0; j < p->batch; ++j) {
             const int mj = p->orders[j];
             const int64_t N = int64_t(1) << mj;
             if (mj < kC64TileLog) {
-                sm.push_back(TileJob{p->in_off[j], p->basef(j), N, mj, p->range()});
+                if (!p->adj_zero) sm.push_back(TileJob{p->in_off[j], p->basef(j), N, mj, p->range()});
                 continue;
             }
-            for (int64_t tau = 0; tau < (N >> kC64TileLog); ++tau)
+            for (int64_t tau = 0; !p->adj_zero && tau < (N >> kC64TileLog); ++tau)
                 aj.push_back(RealJob{p->basef(j) + (tau << kC64TileLog), p->in_off[j] + (tau << kC64TileLog), N, 0,
                                      p->range()});
             const int top = std::min(mj, kRowsMaxLevel);
@@ -882,6 +886,10 @@ mrdft_status run_adjoint(mrdft_plan* p, const float2* gY, void* gx, bool real_ou
             HIP_TRY(launch_expand_half(gY, p->d_gfull, p->d_hjobs, p->nhjobs, s));
         }
         gY = p->d_gfull;
+    }
+    if (p->adj_zero) {
+        ProfScope ps(p, MRDFT_KERNEL_TILE_ADJ, s);
+        HIP_TRY(launch_zero(gx, p->n_in * (int64_t)(real_out ? sizeof(float) : sizeof(float2)), s));
     }
     if (p->najobs) {
         ProfScope ps(p, MRDFT_KERNEL_TILE_ADJ, s);

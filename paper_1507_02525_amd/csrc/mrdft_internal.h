@@ -115,6 +115,8 @@ constexpr int kHalfChunk = 4096;
 hipError_t launch_expand_half(const float2* gh, float2* g, const HalfJob* jobs, int64_t njobs, hipStream_t s);
 hipError_t launch_adj_a(bool real_out, const float2* gY, void* gx, float2* scratch, const RealJob* jobs, int64_t njobs,
                         const Twiddles& tw, hipStream_t s);
+// Clears `bytes` (a multiple of 4) at p (4-byte aligned) with vector stores.
+hipError_t launch_zero(void* p, int64_t bytes, hipStream_t s);
 hipError_t launch_adj_b(bool real_out, void* gx, const float2* scratch, const AdjColJob* jobs, int64_t njobs,
                         const Twiddles& tw, hipStream_t s);
 hipError_t launch_fwd_c64(const float2* x, float2* Y, const RealJob* jobs, int64_t njobs, const unsigned* seg,
