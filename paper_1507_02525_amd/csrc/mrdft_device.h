@@ -12,9 +12,10 @@ namespace mrdft {
 constexpr int kTileMaxLog = 12;                 // largest on-chip tile, 2^12 samples
 constexpr int kTileMax = 1 << kTileMaxLog;
 constexpr int kTileThreads = 256;
-constexpr int kPassThreads = 256;               // global Stockham pass
-constexpr int kPassCols = 16;                   // consecutive columns per pass workgroup (128 B)
-constexpr int kPassMaxLog = 8;                  // radix of one global pass <= 2^8
+constexpr int kPassSmallLog = 12;               // global Stockham pass: 4096-point workgroups ...
+constexpr int kPassSmallMaxLog = 8;             // ... for radices up to 2^8
+constexpr int kPassBigLog = 13;                 // 8192-point workgroups for radix 2^9
+constexpr int kPassMaxLog = 9;                  // radix of one global pass <= 2^9
 constexpr int kTwFineLog = 14;                  // FP64 twiddle split: 2^28 = 2^14 * 2^14
 constexpr int kMaxOrder = 28;
 

@@ -8,10 +8,15 @@
 // (j / Ns)*Ns*r + (j mod Ns) + s*Ns.  The last pass leaves every window in
 // natural bin order, i.e. already permuted as Gamma asks.
 //
-// A workgroup handles 4096 points: 4096 / r consecutive columns (at least 16,
-// so every global load and store touches at least 128 consecutive bytes; a
-// small radix gets more columns, i.e. longer runs, instead of more
-// workgroups); the first pass radix is at least 16.  Twiddles of large windows
+// A workgroup handles 2^LP points with 2^LP / 16 threads: 2^LP / r consecutive
+// columns (at least 16, so every global load and store touches at least 128
+// consecutive bytes; a small radix gets more columns, i.e. longer runs,
+// instead of more workgroups); the first pass radix is at least 16.  Radices
+// up to 2^8 use 4096-point workgroups (four per CU), radix 2^9 8192-point
+// workgroups (two per CU, 74 KB of LDS), so that levels 17 and 18 take two
+// passes instead of three.  (16384-point workgroups for radix 2^10, one per
+// CU, moved 2.5 TB/s against 3.4 TB/s here and 3.9 TB/s for the 4096-point
+// form: two of them cost more than three small passes.)  Twiddles of large windows
 // come from two FP64 tables (coarse and fine exponent), multiplied in FP64 and
 // rounded once: a thread looks up w^{j s0} and w^{16 j} for its column j and
 // first row s0 and forms its further rows s0 + 16 i by FP64 multiplication
@@ -24,44 +29,63 @@ namespace mrdft {
 
 constexpr int kColStride(int r) { return r + 1; }   // LDS padding against bank conflicts
 
-// w_{2^lg}^e (lg <= 8) from a table of w_256 in LDS.
-struct TwLds256 {
-    const float2* t;
-    __device__ __forceinline__ float2 operator()(int lg, int e) const { return t[(e << (8 - lg)) & 255]; }
+// Points, threads and LDS of a pass workgroup of 2^LP points.
+template <int LP>
+struct PassShape {
+    static constexpr int kPoints = 1 << LP;
+    static constexpr int kThreads = kPoints / 16;     // 16 points per thread
+    static constexpr int kTwLog = LP - 4;             // largest radix (16 columns); w_{2^kTwLog} in LDS
+    static constexpr int kLdsFloat2 = kPoints + kPoints / 16 + (1 << kTwLog);
+    static constexpr size_t kLdsBytes = sizeof(float2) * kLdsFloat2;
 };
 
-// The r-point FFTs (r = 2^rl) of the workgroup's 4096 / r columns: a first
+// w_{2^lg}^e (lg <= TL) from a table of w_{2^TL} in LDS.
+template <int TL>
+struct TwLds {
+    const float2* t;
+    __device__ __forceinline__ float2 operator()(int lg, int e) const {
+        return t[(e << (TL - lg)) & ((1 << TL) - 1)];
+    }
+};
+
+// The r-point FFTs (r = 2^rl) of the workgroup's 2^LP / r columns: a first
 // step of radix 2, 4 or 8 if rl is not a multiple of 4, then radix 16; every
-// step has 4096 / radix jobs over the 256 threads.
-constexpr int kPassPoints = 4096;
-template <bool INV>
+// step has 2^LP / radix jobs over the threads.
+template <int LP, bool INV>
 __device__ __forceinline__ void column_fft(float2* B, int rl, const float2* T, int tid) {
+    using Sh = PassShape<LP>;
     const int fst = kColStride(1 << rl);
-    const int nc = kPassPoints >> rl;
+    const int nc = Sh::kPoints >> rl;
     int lgNs = 0;
     const int rem = rl & 3;
-    const TwLds256 tw{T};
-    constexpr int J = kPassPoints / kPassThreads;     // jobs per thread of a radix-1 step
-    if (rem == 1) { lds_step<2, J / 2, INV>(B, rl, 0, fst, 1, nc, tw, tid, kPassThreads); lgNs = 1; }
-    else if (rem == 2) { lds_step<4, J / 4, INV>(B, rl, 0, fst, 1, nc, tw, tid, kPassThreads); lgNs = 2; }
-    else if (rem == 3) { lds_step<8, J / 8, INV>(B, rl, 0, fst, 1, nc, tw, tid, kPassThreads); lgNs = 3; }
+    const TwLds<Sh::kTwLog> tw{T};
+    constexpr int J = Sh::kPoints / Sh::kThreads;     // jobs per thread of a radix-1 step
+    constexpr int NT = Sh::kThreads;
+    if (rem == 1) { lds_step<2, J / 2, INV>(B, rl, 0, fst, 1, nc, tw, tid, NT); lgNs = 1; }
+    else if (rem == 2) { lds_step<4, J / 4, INV>(B, rl, 0, fst, 1, nc, tw, tid, NT); lgNs = 2; }
+    else if (rem == 3) { lds_step<8, J / 8, INV>(B, rl, 0, fst, 1, nc, tw, tid, NT); lgNs = 3; }
     while (lgNs < rl) {
-        lds_step<16, J / 16, INV>(B, rl, lgNs, fst, 1, nc, tw, tid, kPassThreads);
+        lds_step<16, J / 16, INV>(B, rl, lgNs, fst, 1, nc, tw, tid, NT);
         lgNs += 4;
     }
 }
 
-template <bool INV, int IN_KIND, int OUT_KIND>
-__global__ __launch_bounds__(kPassThreads) void pass_kernel(const void* __restrict__ in, void* __restrict__ out,
-                                                            PassGeom g, const float2* __restrict__ tab,
-                                                            const double2* __restrict__ hi,
-                                                            const double2* __restrict__ lo) {
-    __shared__ float2 B[kPassPoints + (kPassPoints >> 4)];   // nc columns of r + 1 (nc <= 256)
-    __shared__ float2 T[256];                          // w_256^e for the column FFT steps
+extern __shared__ float2 g_pass_lds[];
+
+template <int LP, bool INV, int IN_KIND, int OUT_KIND>
+__global__ __launch_bounds__(PassShape<LP>::kThreads) void pass_kernel(const void* __restrict__ in,
+                                                                       void* __restrict__ out, PassGeom g,
+                                                                       const float2* __restrict__ tab,
+                                                                       const double2* __restrict__ hi,
+                                                                       const double2* __restrict__ lo) {
+    using Sh = PassShape<LP>;
+    constexpr int kPassPoints = Sh::kPoints, kPassThreads = Sh::kThreads;
+    float2* const B = g_pass_lds;                      // nc columns of r + 1
+    float2* const T = g_pass_lds + kPassPoints + (kPassPoints >> 4);   // w_{2^(LP-4)}^e for the column FFT steps
     const int rl = g.r_log;
     const int r = 1 << rl;
     const int fst = kColStride(r);
-    const int lnc = 12 - rl;                           // log2 of the columns per workgroup
+    const int lnc = LP - rl;                           // log2 of the columns per workgroup
     const int nc = 1 << lnc;
     const int64_t L = (int64_t)1 << g.lg;
     const int64_t cols = L >> rl;                      // columns j per window
@@ -94,7 +118,7 @@ __global__ __launch_bounds__(kPassThreads) void pass_kernel(const void* __restri
             if constexpr (IN_KIND == IN_R32) v[i] = make_float2(((const float*)in)[idx], 0.0f);
             else v[i] = ((const float2*)in)[idx];
         }
-        T[tid] = tab[tid << (kTileMaxLog - 8)];      // after the data loads: its wait covers them
+        T[tid] = tab[tid << (kTileMaxLog - Sh::kTwLog)];   // after the data loads: its wait covers them
         double2 w = make_double2(1.0, 0.0), step = make_double2(1.0, 0.0);
         if (ns_log > 0) {
             w = tw_big64(hi, lo, tlg, (j & nsm) * s0);
@@ -113,7 +137,7 @@ __global__ __launch_bounds__(kPassThreads) void pass_kernel(const void* __restri
         }
     }
     __syncthreads();
-    column_fft<INV>(B, rl, T, tid);
+    column_fft<LP, INV>(B, rl, T, tid);
 
     double nacc = 0.0;                                 // OUT_NORM: this thread's squared magnitudes
     for (int e = tid; e < nval; e += kPassThreads) {
@@ -165,15 +189,36 @@ __global__ __launch_bounds__(kPassThreads) void pass_kernel(const void* __restri
     }
 }
 
-template <bool INV>
+// Lets every large-workgroup instantiation use its dynamic LDS (above 64 KB).
+template <int LP, bool INV, int IK>
+static void allow_pass_lds() {
+    const size_t b = PassShape<LP>::kLdsBytes;
+    (void)hipFuncSetAttribute((const void*)pass_kernel<LP, INV, IK, OUT_STORE>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    (void)hipFuncSetAttribute((const void*)pass_kernel<LP, INV, IK, OUT_HALF>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    (void)hipFuncSetAttribute((const void*)pass_kernel<LP, INV, IK, OUT_NORM>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    (void)hipFuncSetAttribute((const void*)pass_kernel<LP, INV, IK, OUT_ADD_C64>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    (void)hipFuncSetAttribute((const void*)pass_kernel<LP, INV, IK, OUT_ADD_R32>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+}
+struct PassLdsInit {
+    PassLdsInit() {
+        allow_pass_lds<kPassBigLog, false, IN_R32>();
+        allow_pass_lds<kPassBigLog, false, IN_C64>();
+        allow_pass_lds<kPassBigLog, true, IN_R32>();
+        allow_pass_lds<kPassBigLog, true, IN_C64>();
+    }
+};
+
+template <int LP, bool INV>
 static hipError_t launch_pass_t(int in_kind, int out_kind, const void* in, void* out, const PassGeom& g,
                                 const Twiddles& tw, hipStream_t s) {
-    if (g.r_log < 4 || g.r_log > kPassMaxLog || g.lg < 12) return hipErrorInvalidValue;
-    const int64_t nblk = g.nwin << (g.lg - 12);         // 4096 points per workgroup
+    using Sh = PassShape<LP>;
+    if (g.lg < LP) return hipErrorInvalidValue;        // a workgroup's points lie in one window
+    const int64_t nblk = g.nwin << (g.lg - LP);
     if (nblk <= 0) return hipSuccess;
-    dim3 grid((unsigned)nblk), block(kPassThreads);
-#define MRDFT_PASS(IK, OK) \
-    hipLaunchKernelGGL((pass_kernel<INV, IK, OK>), grid, block, 0, s, in, out, g, tw.tile, tw.hi, tw.lo)
+    dim3 grid((unsigned)nblk), block(Sh::kThreads);
+#define MRDFT_PASS(IK, OK)                                                                                      \
+    hipLaunchKernelGGL((pass_kernel<LP, INV, IK, OK>), grid, block, Sh::kLdsBytes, s, in, out, g, tw.tile, tw.hi, \
+                       tw.lo)
     if (in_kind == IN_R32) {
         if (out_kind == OUT_STORE) MRDFT_PASS(IN_R32, OUT_STORE);
         else if (out_kind == OUT_HALF) MRDFT_PASS(IN_R32, OUT_HALF);
@@ -193,8 +238,13 @@ static hipError_t launch_pass_t(int in_kind, int out_kind, const void* in, void*
 
 hipError_t launch_pass(bool inv, int in_kind, int out_kind, const void* in, void* out, const PassGeom& g,
                        const Twiddles& tw, hipStream_t s) {
-    return inv ? launch_pass_t<true>(in_kind, out_kind, in, out, g, tw, s)
-               : launch_pass_t<false>(in_kind, out_kind, in, out, g, tw, s);
+    if (g.r_log < 4 || g.r_log > kPassMaxLog) return hipErrorInvalidValue;
+    if (g.r_log <= kPassSmallMaxLog)
+        return inv ? launch_pass_t<kPassSmallLog, true>(in_kind, out_kind, in, out, g, tw, s)
+                   : launch_pass_t<kPassSmallLog, false>(in_kind, out_kind, in, out, g, tw, s);
+    static PassLdsInit once;
+    return inv ? launch_pass_t<kPassBigLog, true>(in_kind, out_kind, in, out, g, tw, s)
+               : launch_pass_t<kPassBigLog, false>(in_kind, out_kind, in, out, g, tw, s);
 }
 
 }  // namespace mrdft
