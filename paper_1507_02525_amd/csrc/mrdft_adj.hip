@@ -22,7 +22,8 @@ union AdjALds {
 };
 static_assert(sizeof(AdjALds<true>) <= 40 * 1024 && sizeof(AdjALds<false>) <= 40 * 1024, "four workgroups per CU");
 
-template <bool REAL>
+// HALF (real output): gY holds the packed half spectra of a half-spectrum plan.
+template <bool REAL, bool HALF>
 __global__ __launch_bounds__(kCThreads, 4) void adj_a_kernel(const float2* __restrict__ gY, void* __restrict__ gx,
                                                              float2* __restrict__ scratch,
                                                              const RealJob* __restrict__ jobs,
@@ -35,16 +36,18 @@ __global__ __launch_bounds__(kCThreads, 4) void adj_a_kernel(const float2* __res
     switch (jb.lg) {
         case 0: {
             void* gxj = REAL ? (void*)((float*)gx + jb.out_off) : (void*)((float2*)gx + jb.out_off);
-            adj_tile_body<REAL>(S.tile, gyj, gxj, jb.level_stride, t4096, tid, LevelRange::unpack(jb.g));
+            adj_tile_body<REAL, HALF>(S.tile, gyj, gxj, jb.level_stride, t4096, tid, LevelRange::unpack(jb.g));
             break;
         }
-        case 12: adj_rows_body<4>(S.rows, gyj, scratch + jb.out_off, jb.g, t4096, rowtw + rows_twiddle_offset(12), tid); break;
+        case 12:
+            adj_rows_body<4, HALF>(S.rows, gyj, scratch + jb.out_off, jb.g, t4096, rowtw + rows_twiddle_offset(12), tid);
+            break;
         // real output: Hermitian pieces of 17 rows (half the rows of B)
 #define MRDFT_ADJ_ROWS(LG, RL)                                                                                   \
     case LG:                                                                                                    \
         if constexpr (REAL)                                                                                     \
-            adj_rows_real_body<RL>(S.hrows, gyj, scratch + jb.out_off, jb.g, t4096, rowtw + rows_twiddle_offset(LG), \
-                                   tid);                                                                        \
+            adj_rows_real_body<RL, HALF>(S.hrows, gyj, scratch + jb.out_off, jb.g, t4096,                      \
+                                         rowtw + rows_twiddle_offset(LG), tid);                                 \
         else                                                                                                    \
             adj_rows_body<RL>(S.rows, gyj, scratch + jb.out_off, jb.g, t4096, rowtw + rows_twiddle_offset(LG), tid); \
         break;
@@ -120,15 +123,19 @@ hipError_t launch_zero(void* p, int64_t bytes, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_adj_a(bool real_out, const float2* gY, void* gx, float2* scratch, const RealJob* jobs, int64_t njobs,
-                        const Twiddles& tw, hipStream_t s) {
+hipError_t launch_adj_a(bool real_out, bool half, const float2* gY, void* gx, float2* scratch, const RealJob* jobs,
+                        int64_t njobs, const Twiddles& tw, hipStream_t s) {
     if (njobs <= 0) return hipSuccess;
-    if (real_out)
-        hipLaunchKernelGGL(adj_a_kernel<true>, dim3((unsigned)njobs), dim3(kCThreads), 0, s, gY, gx, scratch, jobs,
-                           tw.tile, tw.rows);
+    if (half && !real_out) return hipErrorInvalidValue;
+    if (half)
+        hipLaunchKernelGGL((adj_a_kernel<true, true>), dim3((unsigned)njobs), dim3(kCThreads), 0, s, gY, gx, scratch,
+                           jobs, tw.tile, tw.rows);
+    else if (real_out)
+        hipLaunchKernelGGL((adj_a_kernel<true, false>), dim3((unsigned)njobs), dim3(kCThreads), 0, s, gY, gx, scratch,
+                           jobs, tw.tile, tw.rows);
     else
-        hipLaunchKernelGGL(adj_a_kernel<false>, dim3((unsigned)njobs), dim3(kCThreads), 0, s, gY, gx, scratch, jobs,
-                           tw.tile, tw.rows);
+        hipLaunchKernelGGL((adj_a_kernel<false, false>), dim3((unsigned)njobs), dim3(kCThreads), 0, s, gY, gx, scratch,
+                           jobs, tw.tile, tw.rows);
     return hipGetLastError();
 }
 

@@ -50,18 +50,27 @@ __device__ __forceinline__ void adj_rows_step(CRowsLds& S, int tid) {
 // Rows piece g of one window of level lg = RL + 8.
 //   gyw   : the window's gradient at its level       scw: the window's scratch block (L values)
 //   rowtw : this level's row twiddles rowtw[k2 * 256 + n1] = w_L^{n1 k2}
-template <int RL>
+// HALF: gyw holds the window's packed half spectrum (L/2 slots, half_bin).
+template <int RL, bool HALF = false>
 __device__ __forceinline__ void adj_rows_body(CRowsLds& S, const float2* __restrict__ gyw, float2* __restrict__ scw,
                                               int g, const float2* __restrict__ t4096,
                                               const float2* __restrict__ rowtw, int tid) {
     constexpr int R = 1 << RL;
+    constexpr int64_t L = (int64_t)R * kRowsN;
     const int k0 = 16 * g;
     S.T[tid] = t4096[tid << (kTileMaxLog - kRowsLog)];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
         const int e = tid + u * kRowsThreads;
         const int k1 = e >> 3, kp = (e & 7) * 2;
-        const float4 v = *(const float4*)(gyw + k0 + kp + (int64_t)R * k1);
+        float4 v;
+        if constexpr (HALF) {
+            const float2 a = half_bin(gyw, k0 + kp + (int64_t)R * k1, L);
+            const float2 b = half_bin(gyw, k0 + kp + 1 + (int64_t)R * k1, L);
+            v = make_float4(a.x, a.y, b.x, b.y);
+        } else {
+            v = *(const float4*)(gyw + k0 + kp + (int64_t)R * k1);
+        }
         S.C[kp * kRowsStride + rpad(k1)] = make_float2(v.x, v.y);
         S.C[(kp + 1) * kRowsStride + rpad(k1)] = make_float2(v.z, v.w);
     }
@@ -85,50 +94,66 @@ __device__ __forceinline__ void adj_rows_body(CRowsLds& S, const float2* __restr
 // k1' = 255 - k1 (the mirror of the forward's Hermitian store); the partner of
 // row 16g is row R - 16g at 255 - k1, or row 0 at -k1 mod 256 when g = 0.
 // Rows 16g .. 16g+15 are written, and row R/2 by the last piece.
-template <int RL>
+// HALF: gyw holds the window's packed half spectrum, whose half_bin reading is
+// Hermitian already: h is read directly.
+template <int RL, bool HALF = false>
 __device__ __forceinline__ void adj_rows_real_body(RowsLds& S, const float2* __restrict__ gyw,
                                                    float2* __restrict__ scw, int g, const float2* __restrict__ t4096,
                                                    const float2* __restrict__ rowtw, int tid) {
     constexpr int R = 1 << RL, NG = R / 16;
     static_assert(NG >= 2, "levels 13..16");
-    const int k0 = 16 * g, gm = NG - 1 - g;
+    const int k0 = 16 * g;
     S.T[tid] = t4096[tid << (kTileMaxLog - kRowsLog)];
-    float4 dv[8], pv[8];
+    if constexpr (HALF) {
+        constexpr int64_t L = (int64_t)R * kRowsN;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-        const int e = tid + u * kRowsThreads;
-        const int k1 = e >> 3, kp = (e & 7) * 2;
-        dv[u] = *(const float4*)(gyw + k0 + kp + (int64_t)R * k1);          // rows k0 + kp, +1 at k1
-        pv[u] = *(const float4*)(gyw + 16 * gm + kp + (int64_t)R * k1);     // rows 16 gm + kp, +1 at k1
-    }
-    const int k1 = tid;
-    const float2 d16 = gyw[k0 + 16 + (int64_t)R * k1];                         // row k0 + 16
-    const float2 p0 = gyw[((R - k0) & (R - 1)) + (int64_t)R * k1];              // partner of row k0
+        for (int u = 0; u < 8; ++u) {
+            const int e = tid + u * kRowsThreads;
+            const int c = e >> 3, kp = (e & 7) * 2;
+            S.C[kp * kRowsStride + rpad(c)] = half_bin(gyw, k0 + kp + (int64_t)R * c, L);
+            S.C[(kp + 1) * kRowsStride + rpad(c)] = half_bin(gyw, k0 + kp + 1 + (int64_t)R * c, L);
+        }
+        S.C[16 * kRowsStride + rpad(tid)] = half_bin(gyw, k0 + 16 + (int64_t)R * tid, L);
+        __syncthreads();
+    } else {
+        const int gm = NG - 1 - g;
+        float4 dv[8], pv[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-        const int e = tid + u * kRowsThreads;
-        const int c = e >> 3, kp = (e & 7) * 2;
-        S.C[kp * kRowsStride + rpad(c)] = make_float2(dv[u].x, dv[u].y);
-        S.C[(kp + 1) * kRowsStride + rpad(c)] = make_float2(dv[u].z, dv[u].w);
-    }
-    S.C[16 * kRowsStride + rpad(k1)] = d16;
-    __syncthreads();
-    // h = (direct + conj(partner)) / 2; every slot is updated by one thread
+        for (int u = 0; u < 8; ++u) {
+            const int e = tid + u * kRowsThreads;
+            const int k1 = e >> 3, kp = (e & 7) * 2;
+            dv[u] = *(const float4*)(gyw + k0 + kp + (int64_t)R * k1);          // rows k0 + kp, +1 at k1
+            pv[u] = *(const float4*)(gyw + 16 * gm + kp + (int64_t)R * k1);     // rows 16 gm + kp, +1 at k1
+        }
+        const int k1 = tid;
+        const float2 d16 = gyw[k0 + 16 + (int64_t)R * k1];                         // row k0 + 16
+        const float2 p0 = gyw[((R - k0) & (R - 1)) + (int64_t)R * k1];              // partner of row k0
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-        const int e = tid + u * kRowsThreads;
-        const int c = 255 - (e >> 3), kp = (e & 7) * 2;
-        float2* a = &S.C[(16 - kp) * kRowsStride + rpad(c)];                   // partner row 16 gm + kp
-        float2* b = &S.C[(15 - kp) * kRowsStride + rpad(c)];                   // partner row 16 gm + kp + 1
-        *a = make_float2(0.5f * (a->x + pv[u].x), 0.5f * (a->y - pv[u].y));
-        *b = make_float2(0.5f * (b->x + pv[u].z), 0.5f * (b->y - pv[u].w));
+        for (int u = 0; u < 8; ++u) {
+            const int e = tid + u * kRowsThreads;
+            const int c = e >> 3, kp = (e & 7) * 2;
+            S.C[kp * kRowsStride + rpad(c)] = make_float2(dv[u].x, dv[u].y);
+            S.C[(kp + 1) * kRowsStride + rpad(c)] = make_float2(dv[u].z, dv[u].w);
+        }
+        S.C[16 * kRowsStride + rpad(k1)] = d16;
+        __syncthreads();
+        // h = (direct + conj(partner)) / 2; every slot is updated by one thread
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = tid + u * kRowsThreads;
+            const int c = 255 - (e >> 3), kp = (e & 7) * 2;
+            float2* a = &S.C[(16 - kp) * kRowsStride + rpad(c)];                   // partner row 16 gm + kp
+            float2* b = &S.C[(15 - kp) * kRowsStride + rpad(c)];                   // partner row 16 gm + kp + 1
+            *a = make_float2(0.5f * (a->x + pv[u].x), 0.5f * (a->y - pv[u].y));
+            *b = make_float2(0.5f * (b->x + pv[u].z), 0.5f * (b->y - pv[u].w));
+        }
+        {
+            const int c = g == 0 ? ((kRowsN - k1) & (kRowsN - 1)) : kRowsN - 1 - k1;
+            float2* a = &S.C[rpad(c)];
+            *a = make_float2(0.5f * (a->x + p0.x), 0.5f * (a->y - p0.y));
+        }
+        __syncthreads();
     }
-    {
-        const int c = g == 0 ? ((kRowsN - k1) & (kRowsN - 1)) : kRowsN - 1 - k1;
-        float2* a = &S.C[rpad(c)];
-        *a = make_float2(0.5f * (a->x + p0.x), 0.5f * (a->y - p0.y));
-    }
-    __syncthreads();
     rows_step<0, true>(S, tid);
     rows_step<4, true>(S, tid);
     __syncthreads();                                  // row 16 (wave 0) before the outputs

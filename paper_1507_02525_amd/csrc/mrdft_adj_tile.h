@@ -83,8 +83,9 @@ __device__ __forceinline__ void adj_acc(AdjTileLds<REAL>& S, int i, float2 v, bo
 }
 
 // Level I (2 <= I <= 11): P holds G_I on entry and G_{I-1} on exit.
-//   gyl : gY of level I-1 at this tile (level-major, complex64)
-template <int I, bool REAL>
+//   gyl : gY of level I-1 at this tile (level-major, complex64; HALF: the
+//         packed half spectra, 2^(I-2) slots per window, read by half_bin)
+template <int I, bool REAL, bool HALF = false>
 __device__ __forceinline__ void adj_level(AdjTileLds<REAL>& S, const float2* __restrict__ gyl, int tid, bool have) {
     constexpr int L = 1 << I, M = L / 2, LM = I - 1;
     constexpr int PPT = kCT / 2 / kCThreads;            // (w, k) jobs per thread
@@ -97,8 +98,13 @@ __device__ __forceinline__ void adj_level(AdjTileLds<REAL>& S, const float2* __r
         const int w = J / M, k = J % M;
         // level I-1 gradient inputs of the two children (loaded early; zero
         // for a level outside the plan's range)
-        nxt0[c] = have ? gyl[2 * w * M + k] : make_float2(0.0f, 0.0f);
-        nxt1[c] = have ? gyl[(2 * w + 1) * M + k] : make_float2(0.0f, 0.0f);
+        if constexpr (HALF) {
+            nxt0[c] = have ? half_bin(gyl + 2 * w * (M / 2), k, M) : make_float2(0.0f, 0.0f);
+            nxt1[c] = have ? half_bin(gyl + (2 * w + 1) * (M / 2), k, M) : make_float2(0.0f, 0.0f);
+        } else {
+            nxt0[c] = have ? gyl[2 * w * M + k] : make_float2(0.0f, 0.0f);
+            nxt1[c] = have ? gyl[(2 * w + 1) * M + k] : make_float2(0.0f, 0.0f);
+        }
         e[c] = S.P[2 * J];
     }
     float2 d[PPT];
@@ -130,35 +136,45 @@ __device__ __forceinline__ void adj_level(AdjTileLds<REAL>& S, const float2* __r
     __syncthreads();
 }
 
-template <int I, bool REAL>
+template <int I, bool REAL, bool HALF>
 struct AdjLevels {
     static __device__ __forceinline__ void run(AdjTileLds<REAL>& S, const float2* __restrict__ gy, int64_t ls,
                                                int tid, LevelRange lv) {
         if constexpr (I >= 2) {
-            adj_level<I, REAL>(S, gy + (int64_t)(I - 2) * ls, tid, lv.in(I - 1));
-            AdjLevels<I - 1, REAL>::run(S, gy, ls, tid, lv);
+            adj_level<I, REAL, HALF>(S, gy + (int64_t)(I - 2) * ls, tid, lv.in(I - 1));
+            AdjLevels<I - 1, REAL, HALF>::run(S, gy, ls, tid, lv);
         }
     }
 };
 
 // One tile: gy at the tile's level-1 gradient (level i at gy + (i-1) ls),
 // gx at the tile's first sample (float for REAL, float2 otherwise); gx is
-// overwritten.
-template <bool REAL>
+// overwritten.  HALF (real output): gy holds packed half spectra, the tile's
+// 1024 slots per level.
+template <bool REAL, bool HALF = false>
 __device__ __forceinline__ void adj_tile_body(AdjTileLds<REAL>& S, const float2* __restrict__ gy, void* __restrict__ gx,
                                               int64_t ls, const float2* __restrict__ t4096, int tid, LevelRange lv) {
     for (int e = tid; e < kCT / 4; e += kCThreads) S.Q[cqswz(e)] = t4096[2 * e];
     {
-        const float4* g11 = (const float4*)(gy + (int64_t)(kCTLog - 1) * ls);
+        const float2* g11 = gy + (int64_t)(kCTLog - 1) * ls;
         const bool have = lv.in(kCTLog);
 #pragma unroll
         for (int r = 0; r < kCT / 2 / kCThreads; ++r) {
             const int p = tid + r * kCThreads;
-            *(float4*)(S.P + 2 * p) = have ? g11[p] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (have) {
+                if constexpr (HALF) {
+                    const float2 a = half_bin(g11, 2 * p, kCT), b = half_bin(g11, 2 * p + 1, kCT);
+                    v = make_float4(a.x, a.y, b.x, b.y);
+                } else {
+                    v = ((const float4*)g11)[p];
+                }
+            }
+            *(float4*)(S.P + 2 * p) = v;
         }
     }
     __syncthreads();
-    AdjLevels<kCTLog, REAL>::run(S, gy, ls, tid, lv);
+    AdjLevels<kCTLog, REAL, HALF>::run(S, gy, ls, tid, lv);
     // level 1: windows of two
 #pragma unroll
     for (int r = 0; r < kCT / 2 / kCThreads; ++r) {

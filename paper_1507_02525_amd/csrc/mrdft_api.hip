@@ -59,7 +59,6 @@ struct Group {
     int64_t count = 0;
     int64_t* d_in_sig = nullptr;    // x offset of each signal (ragged only)
     int64_t* d_out_sig = nullptr;   // Y offset of each signal (ragged only)
-    int64_t* d_fout_sig = nullptr;  // half-spectrum plans: offset in the full-spectrum gradient layout
 };
 
 // Bit split of the passes for a window of 2^lg points (each pass radix <= 2^8,
@@ -194,7 +193,6 @@ void free_plan(mrdft_plan* p) {
     for (auto& g : p->groups) {
         dfree(g.d_in_sig);
         dfree(g.d_out_sig);
-        dfree(g.d_fout_sig);
     }
     dfree(p->d_tw_tile);
     dfree(p->d_tw_hi);
@@ -332,7 +330,7 @@ mrdft_status upload_jobs(const std::vector<RealJob>& v, RealJob** dst, int64_t* 
 
 mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
     std::vector<TileJob> jobs;
-    std::vector<std::vector<int64_t>> gin(kMaxOrder + 1), gout(kMaxOrder + 1), gfout(kMaxOrder + 1);
+    std::vector<std::vector<int64_t>> gin(kMaxOrder + 1), gout(kMaxOrder + 1);
     for (int64_t j = 0; j < p->batch; ++j) {
         const int mj = p->orders[j];
         const int64_t N = int64_t(1) << mj;
@@ -350,7 +348,6 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
         if (mj > kTileMaxLog) {
             gin[mj].push_back(p->in_off[j]);
             gout[mj].push_back(p->base(j));
-            gfout[mj].push_back(p->basef(j));
         }
     }
     // full tiles first: the real-input kernel handles exactly those
@@ -399,8 +396,12 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
                 if (!p->adj_zero) sm.push_back(TileJob{p->in_off[j], p->basef(j), N, mj, p->range()});
                 continue;
             }
+            // gradient offsets: packed half spectra for half plans (read through
+            // half_bin), the full layout otherwise
+            const int64_t gb = p->hs ? p->base(j) : p->basef(j);
+            const int hs = p->hs;
             for (int64_t tau = 0; !p->adj_zero && tau < (N >> kC64TileLog); ++tau)
-                aj.push_back(RealJob{p->basef(j) + (tau << kC64TileLog), p->in_off[j] + (tau << kC64TileLog), N, 0,
+                aj.push_back(RealJob{gb + ((tau << kC64TileLog) >> hs), p->in_off[j] + (tau << kC64TileLog), N >> hs, 0,
                                      p->range()});
             const int top = std::min(mj, kRowsMaxLevel);
             bool any_upper = false;
@@ -413,7 +414,7 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
                                                                                    : 1 << (lg - kCRowsMinLevel);
                 for (int64_t w = 0; w < N / L; ++w)
                     for (int g = 0; g < pieces; ++g)
-                        aj.push_back(RealJob{p->basef(j) + (int64_t)(lg - 1) * N + w * L,
+                        aj.push_back(RealJob{gb + (((int64_t)(lg - 1) * N + w * L) >> hs),
                                              scr + (int64_t)(lg - kCRowsMinLevel) * N + w * L, 0, lg, g});
             }
             if (top >= kCRowsMinLevel) {
@@ -442,10 +443,13 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
         HIP_TRY(hipStreamSynchronize(s));
     }
     if (p->hs) {
-        // adjoint of the packed output: unpacking jobs and the full-layout gradient
+        // adjoint of the packed output: the tiles, pieces and passes read the
+        // packed gradient directly; signals below the 2048-sample tile (tile
+        // adjoint kernel) are unpacked into the full layout first
         std::vector<HalfJob> hj;
         for (int64_t j = 0; j < p->batch; ++j) {
             const int mj = p->orders[j];
+            if (mj >= kC64TileLog) continue;
             const int64_t N = int64_t(1) << mj;
             for (int i = p->lo; i <= std::min(p->hi, mj); ++i)
                 for (int64_t c0 = 0; c0 < N; c0 += kHalfChunk)
@@ -469,17 +473,13 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
         g.count = (int64_t)gin[o].size();
         if (p->ragged) {
             if (hipMalloc(&g.d_in_sig, sizeof(int64_t) * g.count) != hipSuccess ||
-                hipMalloc(&g.d_out_sig, sizeof(int64_t) * g.count) != hipSuccess ||
-                (p->hs && hipMalloc(&g.d_fout_sig, sizeof(int64_t) * g.count) != hipSuccess)) {
+                hipMalloc(&g.d_out_sig, sizeof(int64_t) * g.count) != hipSuccess) {
                 p->groups.push_back(g);
                 return fail(MRDFT_E_ALLOC, "signal table allocation failed");
             }
             p->groups.push_back(g);
             HIP_TRY(hipMemcpyAsync(g.d_in_sig, gin[o].data(), sizeof(int64_t) * g.count, hipMemcpyHostToDevice, s));
             HIP_TRY(hipMemcpyAsync(g.d_out_sig, gout[o].data(), sizeof(int64_t) * g.count, hipMemcpyHostToDevice, s));
-            if (p->hs)
-                HIP_TRY(hipMemcpyAsync(g.d_fout_sig, gfout[o].data(), sizeof(int64_t) * g.count, hipMemcpyHostToDevice,
-                                       s));
         } else {
             p->groups.push_back(g);
         }
@@ -879,13 +879,10 @@ mrdft_status run_adjoint(mrdft_plan* p, const float2* gY, void* gx, bool real_ou
     const Twiddles tw = p->tw();
     // the job tables of a real plan hold Hermitian pieces: real output only
     if (real_out != (p->dtype == MRDFT_R32)) return fail(MRDFT_E_UNSUPPORTED, "adjoint output type differs from the plan's");
-    if (p->hs) {
-        // packed half-spectrum gradient -> full-spectrum layout, then the full adjoint
-        {
-            ProfScope ps(p, MRDFT_KERNEL_TILE_ADJ, s);
-            HIP_TRY(launch_expand_half(gY, p->d_gfull, p->d_hjobs, p->nhjobs, s));
-        }
-        gY = p->d_gfull;
+    if (p->hs && p->nhjobs) {
+        // signals below the tile: packed gradient -> full-spectrum layout
+        ProfScope ps(p, MRDFT_KERNEL_TILE_ADJ, s);
+        HIP_TRY(launch_expand_half(gY, p->d_gfull, p->d_hjobs, p->nhjobs, s));
     }
     if (p->adj_zero) {
         ProfScope ps(p, MRDFT_KERNEL_TILE_ADJ, s);
@@ -893,11 +890,11 @@ mrdft_status run_adjoint(mrdft_plan* p, const float2* gY, void* gx, bool real_ou
     }
     if (p->najobs) {
         ProfScope ps(p, MRDFT_KERNEL_TILE_ADJ, s);
-        HIP_TRY(launch_adj_a(real_out, gY, gx, p->d_ascratch, p->d_ajobs, p->najobs, tw, s));
+        HIP_TRY(launch_adj_a(real_out, p->hs != 0, gY, gx, p->d_ascratch, p->d_ajobs, p->najobs, tw, s));
     }
     if (p->nasmall) {
         ProfScope ps(p, MRDFT_KERNEL_TILE_ADJ, s);
-        HIP_TRY(launch_tile_adj(real_out, gY, gx, p->d_asmall, p->nasmall, p->asmall_tmax, tw, s));
+        HIP_TRY(launch_tile_adj(real_out, p->hs ? p->d_gfull : gY, gx, p->d_asmall, p->nasmall, p->asmall_tmax, tw, s));
     }
     if (p->nacols) {
         ProfScope ps(p, MRDFT_KERNEL_PASS_ADJ, s);
@@ -918,15 +915,17 @@ mrdft_status run_adjoint(mrdft_plan* p, const float2* gY, void* gx, bool real_ou
                 geo.ns_log = ns;
                 geo.nwin = g.count * (N >> i);
                 geo.wps = N >> i;
-                geo.in_sig = first ? (p->hs ? g.d_fout_sig : g.d_out_sig) : nullptr;
-                geo.in_stride = first ? (int64_t)p->kept(g.order) * N : N;
+                // the first pass reads the level's gradient (packed for half plans)
+                geo.in_sig = first ? g.d_out_sig : nullptr;
+                geo.in_stride = first ? (int64_t)p->kept(g.order) * (N >> p->hs) : N;
                 geo.out_sig = last ? g.d_in_sig : nullptr;
                 geo.out_stride = N;
-                const void* in = first ? (const void*)level_ptr(p, (float2*)gY, i, N) : (const void*)p->d_s[(q - 1) & 1];
+                const void* in = first ? (const void*)level_ptr(p, (float2*)gY, i, N >> p->hs)
+                                       : (const void*)p->d_s[(q - 1) & 1];
                 void* out = last ? gx : (void*)p->d_s[q & 1];
                 const int ok = last ? (real_out ? OUT_ADD_R32 : OUT_ADD_C64) : OUT_STORE;
                 ProfScope ps(p, MRDFT_KERNEL_PASS_ADJ, s);
-                HIP_TRY(launch_pass(true, IN_C64, ok, in, out, geo, tw, s));
+                HIP_TRY(launch_pass(true, (first && p->hs) ? IN_HALF : IN_C64, ok, in, out, geo, tw, s));
                 ns += bits[q];
             }
         }

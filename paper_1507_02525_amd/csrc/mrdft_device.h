@@ -105,6 +105,23 @@ __device__ __forceinline__ float2 tw_big(const double2* __restrict__ hi, const d
     return make_float2((float)(a.x * b.x - a.y * b.y), (float)(a.x * b.y + a.y * b.x));
 }
 
+// Bin k (0 <= k < Lw) of one window of a real plan's packed half-spectrum
+// gradient (Lw/2 slots: slot 0 = (bin 0, bin Lw/2), slot k = bin k), read as
+// the Hermitian extension halved whose real adjoint is the packed adjoint:
+// bins 0 and Lw/2 the real numbers of slot 0, bin k < Lw/2 slot k / 2, bin
+// k > Lw/2 conj(slot Lw - k) / 2.
+__device__ __forceinline__ float2 half_bin(const float2* __restrict__ hw, int64_t k, int64_t Lw) {
+    const int64_t M = Lw >> 1;
+    if (k == 0) return make_float2(hw[0].x, 0.0f);
+    if (k == M) return make_float2(hw[0].y, 0.0f);
+    if (k < M) {
+        const float2 v = hw[k];
+        return make_float2(0.5f * v.x, 0.5f * v.y);
+    }
+    const float2 v = hw[Lw - k];
+    return make_float2(0.5f * v.x, -0.5f * v.y);
+}
+
 // Same twiddle in FP64 (not rounded).
 __device__ __forceinline__ double2 tw_big64(const double2* __restrict__ hi, const double2* __restrict__ lo, int lg,
                                             int64_t e) {

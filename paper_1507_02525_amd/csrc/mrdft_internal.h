@@ -37,7 +37,9 @@ struct PassGeom {
     int64_t out_stride;
 };
 
-enum InKind { IN_C64 = 0, IN_R32 = 1 };
+// IN_HALF: a real plan's packed half-spectrum gradient (window W at W * L/2),
+// read through half_bin; first passes of the adjoint only (OUT_STORE).
+enum InKind { IN_C64 = 0, IN_R32 = 1, IN_HALF = 2 };
 // OUT_HALF: store packed half spectra (window W at W * L/2, slot 0 = (Y[0], Y[L/2])).
 // OUT_NORM: nothing stored; the squared magnitudes of signal b's level lg are
 // added (FP64) to ((double*)out)[b * out_stride + lg - 1].
@@ -113,8 +115,9 @@ struct HalfJob {
 };
 constexpr int kHalfChunk = 4096;
 hipError_t launch_expand_half(const float2* gh, float2* g, const HalfJob* jobs, int64_t njobs, hipStream_t s);
-hipError_t launch_adj_a(bool real_out, const float2* gY, void* gx, float2* scratch, const RealJob* jobs, int64_t njobs,
-                        const Twiddles& tw, hipStream_t s);
+// half: gY holds packed half spectra (real output only); the job offsets are packed ones.
+hipError_t launch_adj_a(bool real_out, bool half, const float2* gY, void* gx, float2* scratch, const RealJob* jobs,
+                        int64_t njobs, const Twiddles& tw, hipStream_t s);
 // Clears `bytes` (a multiple of 4) at p (4-byte aligned) with vector stores.
 hipError_t launch_zero(void* p, int64_t bytes, hipStream_t s);
 hipError_t launch_adj_b(bool real_out, void* gx, const float2* scratch, const AdjColJob* jobs, int64_t njobs,

@@ -94,7 +94,7 @@ __global__ __launch_bounds__(PassShape<LP>::kThreads) void pass_kernel(const voi
     const int64_t gwin = blk / jblocks;
     const int64_t j0 = (blk - gwin * jblocks) << lnc;
     const int64_t b = gwin / g.wps, W = gwin - b * g.wps;
-    const int64_t ib = (g.in_sig ? g.in_sig[b] : b * g.in_stride) + W * L;
+    const int64_t ib = (g.in_sig ? g.in_sig[b] : b * g.in_stride) + W * (IN_KIND == IN_HALF ? L / 2 : L);
     const int64_t ob = (g.out_sig ? g.out_sig[b] : b * g.out_stride) + W * (OUT_KIND == OUT_HALF ? L / 2 : L);
     const int tid = threadIdx.x;
     const int ns_log = g.ns_log;
@@ -116,6 +116,7 @@ __global__ __launch_bounds__(PassShape<LP>::kThreads) void pass_kernel(const voi
             const int s = s0 + rstep * i;
             const int64_t idx = ib + j + (int64_t)s * cols;
             if constexpr (IN_KIND == IN_R32) v[i] = make_float2(((const float*)in)[idx], 0.0f);
+            else if constexpr (IN_KIND == IN_HALF) v[i] = half_bin((const float2*)in + ib, idx - ib, L);   // first pass: bin idx - ib
             else v[i] = ((const float2*)in)[idx];
         }
         T[tid] = tab[tid << (kTileMaxLog - Sh::kTwLog)];   // after the data loads: its wait covers them
@@ -205,6 +206,8 @@ struct PassLdsInit {
         allow_pass_lds<kPassBigLog, false, IN_C64>();
         allow_pass_lds<kPassBigLog, true, IN_R32>();
         allow_pass_lds<kPassBigLog, true, IN_C64>();
+        (void)hipFuncSetAttribute((const void*)pass_kernel<kPassBigLog, true, IN_HALF, OUT_STORE>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, PassShape<kPassBigLog>::kLdsBytes);
     }
 };
 
@@ -219,7 +222,14 @@ static hipError_t launch_pass_t(int in_kind, int out_kind, const void* in, void*
 #define MRDFT_PASS(IK, OK)                                                                                      \
     hipLaunchKernelGGL((pass_kernel<LP, INV, IK, OK>), grid, block, Sh::kLdsBytes, s, in, out, g, tw.tile, tw.hi, \
                        tw.lo)
-    if (in_kind == IN_R32) {
+    if (in_kind == IN_HALF) {
+        if constexpr (INV) {                          // first adjoint passes only
+            if (out_kind != OUT_STORE) return hipErrorInvalidValue;
+            MRDFT_PASS(IN_HALF, OUT_STORE);
+        } else {
+            return hipErrorInvalidValue;
+        }
+    } else if (in_kind == IN_R32) {
         if (out_kind == OUT_STORE) MRDFT_PASS(IN_R32, OUT_STORE);
         else if (out_kind == OUT_HALF) MRDFT_PASS(IN_R32, OUT_HALF);
         else if (out_kind == OUT_NORM) MRDFT_PASS(IN_R32, OUT_NORM);
