@@ -28,26 +28,29 @@ __global__ __launch_bounds__(kCThreads, 4) void adj_a_kernel(const float2* __res
                                                              float2* __restrict__ scratch,
                                                              const RealJob* __restrict__ jobs,
                                                              const float2* __restrict__ t4096,
-                                                             const float2* __restrict__ rowtw) {
+                                                             const float2* __restrict__ rowtw, int gshift,
+                                                             float hsc) {
     __shared__ AdjALds<REAL> S;
     const RealJob jb = jobs[blockIdx.x];
     const int tid = threadIdx.x;
-    const float2* gyj = gY + jb.in_off;
+    const float2* gyj = gY + (jb.in_off >> gshift);
     switch (jb.lg) {
         case 0: {
             void* gxj = REAL ? (void*)((float*)gx + jb.out_off) : (void*)((float2*)gx + jb.out_off);
-            adj_tile_body<REAL, HALF>(S.tile, gyj, gxj, jb.level_stride, t4096, tid, LevelRange::unpack(jb.g));
+            adj_tile_body<REAL, HALF>(S.tile, gyj, gxj, jb.level_stride >> gshift, t4096, tid, LevelRange::unpack(jb.g),
+                                      hsc);
             break;
         }
         case 12:
-            adj_rows_body<4, HALF>(S.rows, gyj, scratch + jb.out_off, jb.g, t4096, rowtw + rows_twiddle_offset(12), tid);
+            adj_rows_body<4, HALF>(S.rows, gyj, scratch + jb.out_off, jb.g, t4096, rowtw + rows_twiddle_offset(12), tid,
+                                   hsc);
             break;
         // real output: Hermitian pieces of 17 rows (half the rows of B)
 #define MRDFT_ADJ_ROWS(LG, RL)                                                                                   \
     case LG:                                                                                                    \
         if constexpr (REAL)                                                                                     \
             adj_rows_real_body<RL, HALF>(S.hrows, gyj, scratch + jb.out_off, jb.g, t4096,                      \
-                                         rowtw + rows_twiddle_offset(LG), tid);                                 \
+                                         rowtw + rows_twiddle_offset(LG), tid, hsc);                            \
         else                                                                                                    \
             adj_rows_body<RL>(S.rows, gyj, scratch + jb.out_off, jb.g, t4096, rowtw + rows_twiddle_offset(LG), tid); \
         break;
@@ -123,19 +126,19 @@ hipError_t launch_zero(void* p, int64_t bytes, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_adj_a(bool real_out, bool half, const float2* gY, void* gx, float2* scratch, const RealJob* jobs,
-                        int64_t njobs, const Twiddles& tw, hipStream_t s) {
+hipError_t launch_adj_a(bool real_out, bool half, int gshift, float hsc, const float2* gY, void* gx, float2* scratch,
+                        const RealJob* jobs, int64_t njobs, const Twiddles& tw, hipStream_t s) {
     if (njobs <= 0) return hipSuccess;
-    if (half && !real_out) return hipErrorInvalidValue;
+    if ((half && !real_out) || gshift < 0 || gshift > 1) return hipErrorInvalidValue;
     if (half)
         hipLaunchKernelGGL((adj_a_kernel<true, true>), dim3((unsigned)njobs), dim3(kCThreads), 0, s, gY, gx, scratch,
-                           jobs, tw.tile, tw.rows);
+                           jobs, tw.tile, tw.rows, gshift, hsc);
     else if (real_out)
         hipLaunchKernelGGL((adj_a_kernel<true, false>), dim3((unsigned)njobs), dim3(kCThreads), 0, s, gY, gx, scratch,
-                           jobs, tw.tile, tw.rows);
+                           jobs, tw.tile, tw.rows, gshift, hsc);
     else
         hipLaunchKernelGGL((adj_a_kernel<false, false>), dim3((unsigned)njobs), dim3(kCThreads), 0, s, gY, gx, scratch,
-                           jobs, tw.tile, tw.rows);
+                           jobs, tw.tile, tw.rows, gshift, hsc);
     return hipGetLastError();
 }
 

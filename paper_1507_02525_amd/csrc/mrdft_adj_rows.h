@@ -50,11 +50,11 @@ __device__ __forceinline__ void adj_rows_step(CRowsLds& S, int tid) {
 // Rows piece g of one window of level lg = RL + 8.
 //   gyw   : the window's gradient at its level       scw: the window's scratch block (L values)
 //   rowtw : this level's row twiddles rowtw[k2 * 256 + n1] = w_L^{n1 k2}
-// HALF: gyw holds the window's packed half spectrum (L/2 slots, half_bin).
+// HALF: gyw holds the window's packed half spectrum (L/2 slots, half_bin with scale hsc).
 template <int RL, bool HALF = false>
 __device__ __forceinline__ void adj_rows_body(CRowsLds& S, const float2* __restrict__ gyw, float2* __restrict__ scw,
                                               int g, const float2* __restrict__ t4096,
-                                              const float2* __restrict__ rowtw, int tid) {
+                                              const float2* __restrict__ rowtw, int tid, float hsc = 0.5f) {
     constexpr int R = 1 << RL;
     constexpr int64_t L = (int64_t)R * kRowsN;
     const int k0 = 16 * g;
@@ -65,8 +65,8 @@ __device__ __forceinline__ void adj_rows_body(CRowsLds& S, const float2* __restr
         const int k1 = e >> 3, kp = (e & 7) * 2;
         float4 v;
         if constexpr (HALF) {
-            const float2 a = half_bin(gyw, k0 + kp + (int64_t)R * k1, L);
-            const float2 b = half_bin(gyw, k0 + kp + 1 + (int64_t)R * k1, L);
+            const float2 a = half_bin(gyw, k0 + kp + (int64_t)R * k1, L, hsc);
+            const float2 b = half_bin(gyw, k0 + kp + 1 + (int64_t)R * k1, L, hsc);
             v = make_float4(a.x, a.y, b.x, b.y);
         } else {
             v = *(const float4*)(gyw + k0 + kp + (int64_t)R * k1);
@@ -94,12 +94,12 @@ __device__ __forceinline__ void adj_rows_body(CRowsLds& S, const float2* __restr
 // k1' = 255 - k1 (the mirror of the forward's Hermitian store); the partner of
 // row 16g is row R - 16g at 255 - k1, or row 0 at -k1 mod 256 when g = 0.
 // Rows 16g .. 16g+15 are written, and row R/2 by the last piece.
-// HALF: gyw holds the window's packed half spectrum, whose half_bin reading is
-// Hermitian already: h is read directly.
+// HALF: gyw holds the window's packed half spectrum, whose half_bin reading
+// (scale hsc) is Hermitian already: h is read directly.
 template <int RL, bool HALF = false>
 __device__ __forceinline__ void adj_rows_real_body(RowsLds& S, const float2* __restrict__ gyw,
                                                    float2* __restrict__ scw, int g, const float2* __restrict__ t4096,
-                                                   const float2* __restrict__ rowtw, int tid) {
+                                                   const float2* __restrict__ rowtw, int tid, float hsc = 0.5f) {
     constexpr int R = 1 << RL, NG = R / 16;
     static_assert(NG >= 2, "levels 13..16");
     const int k0 = 16 * g;
@@ -110,10 +110,10 @@ __device__ __forceinline__ void adj_rows_real_body(RowsLds& S, const float2* __r
         for (int u = 0; u < 8; ++u) {
             const int e = tid + u * kRowsThreads;
             const int c = e >> 3, kp = (e & 7) * 2;
-            S.C[kp * kRowsStride + rpad(c)] = half_bin(gyw, k0 + kp + (int64_t)R * c, L);
-            S.C[(kp + 1) * kRowsStride + rpad(c)] = half_bin(gyw, k0 + kp + 1 + (int64_t)R * c, L);
+            S.C[kp * kRowsStride + rpad(c)] = half_bin(gyw, k0 + kp + (int64_t)R * c, L, hsc);
+            S.C[(kp + 1) * kRowsStride + rpad(c)] = half_bin(gyw, k0 + kp + 1 + (int64_t)R * c, L, hsc);
         }
-        S.C[16 * kRowsStride + rpad(tid)] = half_bin(gyw, k0 + 16 + (int64_t)R * tid, L);
+        S.C[16 * kRowsStride + rpad(tid)] = half_bin(gyw, k0 + 16 + (int64_t)R * tid, L, hsc);
         __syncthreads();
     } else {
         const int gm = NG - 1 - g;

@@ -24,6 +24,7 @@ struct AdjTileLds {
     float2 P[kCT];                                   // G_i; the FFT work space overlays it
     typename std::conditional<REAL, float, float2>::type A[kCT];   // gx accumulator
     float2 Q[kCT / 4];                               // w_2048^e, e < 512 (swizzled)
+    float2 H[REAL ? kCT / 2 : 1];                    // packed input: one level's slots of the tile
 };
 
 // conj(w_{2^lg}^e)
@@ -86,22 +87,29 @@ __device__ __forceinline__ void adj_acc(AdjTileLds<REAL>& S, int i, float2 v, bo
 //   gyl : gY of level I-1 at this tile (level-major, complex64; HALF: the
 //         packed half spectra, 2^(I-2) slots per window, read by half_bin)
 template <int I, bool REAL, bool HALF = false>
-__device__ __forceinline__ void adj_level(AdjTileLds<REAL>& S, const float2* __restrict__ gyl, int tid, bool have) {
+__device__ __forceinline__ void adj_level(AdjTileLds<REAL>& S, const float2* __restrict__ gyl, int tid, bool have,
+                                          float hsc) {
     constexpr int L = 1 << I, M = L / 2, LM = I - 1;
     constexpr int PPT = kCT / 2 / kCThreads;            // (w, k) jobs per thread
     constexpr bool FIRST = (I == kCTLog);               // A not yet written
     float2* F = S.P;
     float2 e[PPT], nxt0[PPT], nxt1[PPT];
+    if constexpr (HALF) {
+        // the level's packed slots of this tile (contiguous) into H, coalesced;
+        // read back through half_bin after the next barrier
+#pragma unroll
+        for (int r = 0; r < kCT / 4 / kCThreads; ++r) {
+            const int p = tid + r * kCThreads;
+            *(float4*)(S.H + 2 * p) = have ? ((const float4*)gyl)[p] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        }
+    }
 #pragma unroll
     for (int c = 0; c < PPT; ++c) {
         const int J = tid + c * kCThreads;               // = w * M + k
         const int w = J / M, k = J % M;
         // level I-1 gradient inputs of the two children (loaded early; zero
         // for a level outside the plan's range)
-        if constexpr (HALF) {
-            nxt0[c] = have ? half_bin(gyl + 2 * w * (M / 2), k, M) : make_float2(0.0f, 0.0f);
-            nxt1[c] = have ? half_bin(gyl + (2 * w + 1) * (M / 2), k, M) : make_float2(0.0f, 0.0f);
-        } else {
+        if constexpr (!HALF) {
             nxt0[c] = have ? gyl[2 * w * M + k] : make_float2(0.0f, 0.0f);
             nxt1[c] = have ? gyl[(2 * w + 1) * M + k] : make_float2(0.0f, 0.0f);
         }
@@ -130,6 +138,10 @@ __device__ __forceinline__ void adj_level(AdjTileLds<REAL>& S, const float2* __r
     for (int c = 0; c < PPT; ++c) {
         const int J = tid + c * kCThreads;
         const int w = J / M, k = J % M;
+        if constexpr (HALF) {
+            nxt0[c] = half_bin(S.H + 2 * w * (M / 2), k, M, hsc);
+            nxt1[c] = half_bin(S.H + (2 * w + 1) * (M / 2), k, M, hsc);
+        }
         S.P[2 * w * M + k] = cadd(nxt0[c], e[c]);
         S.P[(2 * w + 1) * M + k] = cadd(nxt1[c], e[c]);
     }
@@ -139,10 +151,10 @@ __device__ __forceinline__ void adj_level(AdjTileLds<REAL>& S, const float2* __r
 template <int I, bool REAL, bool HALF>
 struct AdjLevels {
     static __device__ __forceinline__ void run(AdjTileLds<REAL>& S, const float2* __restrict__ gy, int64_t ls,
-                                               int tid, LevelRange lv) {
+                                               int tid, LevelRange lv, float hsc) {
         if constexpr (I >= 2) {
-            adj_level<I, REAL, HALF>(S, gy + (int64_t)(I - 2) * ls, tid, lv.in(I - 1));
-            AdjLevels<I - 1, REAL, HALF>::run(S, gy, ls, tid, lv);
+            adj_level<I, REAL, HALF>(S, gy + (int64_t)(I - 2) * ls, tid, lv.in(I - 1), hsc);
+            AdjLevels<I - 1, REAL, HALF>::run(S, gy, ls, tid, lv, hsc);
         }
     }
 };
@@ -150,31 +162,39 @@ struct AdjLevels {
 // One tile: gy at the tile's level-1 gradient (level i at gy + (i-1) ls),
 // gx at the tile's first sample (float for REAL, float2 otherwise); gx is
 // overwritten.  HALF (real output): gy holds packed half spectra, the tile's
-// 1024 slots per level.
+// 1024 slots per level, read by half_bin with scale hsc.
 template <bool REAL, bool HALF = false>
 __device__ __forceinline__ void adj_tile_body(AdjTileLds<REAL>& S, const float2* __restrict__ gy, void* __restrict__ gx,
-                                              int64_t ls, const float2* __restrict__ t4096, int tid, LevelRange lv) {
+                                              int64_t ls, const float2* __restrict__ t4096, int tid, LevelRange lv,
+                                              float hsc = 0.5f) {
     for (int e = tid; e < kCT / 4; e += kCThreads) S.Q[cqswz(e)] = t4096[2 * e];
     {
         const float2* g11 = gy + (int64_t)(kCTLog - 1) * ls;
         const bool have = lv.in(kCTLog);
+        if constexpr (HALF) {
+            // the top level's 1024 packed slots into H, then unpacked into P
 #pragma unroll
-        for (int r = 0; r < kCT / 2 / kCThreads; ++r) {
-            const int p = tid + r * kCThreads;
-            float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            if (have) {
-                if constexpr (HALF) {
-                    const float2 a = half_bin(g11, 2 * p, kCT), b = half_bin(g11, 2 * p + 1, kCT);
-                    v = make_float4(a.x, a.y, b.x, b.y);
-                } else {
-                    v = ((const float4*)g11)[p];
-                }
+            for (int r = 0; r < kCT / 4 / kCThreads; ++r) {
+                const int p = tid + r * kCThreads;
+                *(float4*)(S.H + 2 * p) = have ? ((const float4*)g11)[p] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             }
-            *(float4*)(S.P + 2 * p) = v;
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < kCT / 2 / kCThreads; ++r) {
+                const int p = tid + r * kCThreads;
+                const float2 a = half_bin(S.H, 2 * p, kCT, hsc), b = half_bin(S.H, 2 * p + 1, kCT, hsc);
+                *(float4*)(S.P + 2 * p) = make_float4(a.x, a.y, b.x, b.y);
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < kCT / 2 / kCThreads; ++r) {
+                const int p = tid + r * kCThreads;
+                *(float4*)(S.P + 2 * p) = have ? ((const float4*)g11)[p] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            }
         }
     }
     __syncthreads();
-    AdjLevels<kCTLog, REAL, HALF>::run(S, gy, ls, tid, lv);
+    AdjLevels<kCTLog, REAL, HALF>::run(S, gy, ls, tid, lv, hsc);
     // level 1: windows of two
 #pragma unroll
     for (int r = 0; r < kCT / 2 / kCThreads; ++r) {

@@ -875,8 +875,15 @@ mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, h
     return MRDFT_OK;
 }
 
-mrdft_status run_adjoint(mrdft_plan* p, const float2* gY, void* gx, bool real_out, hipStream_t s) {
+// packed_from_full: gY holds packed half spectra of a full-spectrum (real,
+// uniform) plan's levels, read with the plan's full-layout tables halved
+// (the spectral-loss gradient).
+mrdft_status run_adjoint(mrdft_plan* p, const float2* gY, void* gx, bool real_out, hipStream_t s,
+                         bool packed_from_full = false) {
     const Twiddles tw = p->tw();
+    const int half = (p->hs || packed_from_full) ? 1 : 0;
+    if (packed_from_full && (p->hs || p->ragged || !real_out || p->nasmall))
+        return fail(MRDFT_E_UNSUPPORTED, "packed gradient of a full-spectrum plan: uniform real plans of order >= 11 only");
     // the job tables of a real plan hold Hermitian pieces: real output only
     if (real_out != (p->dtype == MRDFT_R32)) return fail(MRDFT_E_UNSUPPORTED, "adjoint output type differs from the plan's");
     if (p->hs && p->nhjobs) {
@@ -890,7 +897,10 @@ mrdft_status run_adjoint(mrdft_plan* p, const float2* gY, void* gx, bool real_ou
     }
     if (p->najobs) {
         ProfScope ps(p, MRDFT_KERNEL_TILE_ADJ, s);
-        HIP_TRY(launch_adj_a(real_out, p->hs != 0, gY, gx, p->d_ascratch, p->d_ajobs, p->najobs, tw, s));
+        // a half plan's packed gradient is read as its Hermitian extension
+        // halved, packed spectra of real signals (the loss) whole
+        HIP_TRY(launch_adj_a(real_out, half != 0, packed_from_full ? 1 : 0, packed_from_full ? 1.0f : 0.5f, gY, gx,
+                             p->d_ascratch, p->d_ajobs, p->najobs, tw, s));
     }
     if (p->nasmall) {
         ProfScope ps(p, MRDFT_KERNEL_TILE_ADJ, s);
@@ -917,15 +927,16 @@ mrdft_status run_adjoint(mrdft_plan* p, const float2* gY, void* gx, bool real_ou
                 geo.wps = N >> i;
                 // the first pass reads the level's gradient (packed for half plans)
                 geo.in_sig = first ? g.d_out_sig : nullptr;
-                geo.in_stride = first ? (int64_t)p->kept(g.order) * (N >> p->hs) : N;
+                geo.in_stride = first ? (int64_t)p->kept(g.order) * (N >> half) : N;
                 geo.out_sig = last ? g.d_in_sig : nullptr;
                 geo.out_stride = N;
-                const void* in = first ? (const void*)level_ptr(p, (float2*)gY, i, N >> p->hs)
+                geo.half_scale = packed_from_full ? 1.0f : 0.5f;
+                const void* in = first ? (const void*)level_ptr(p, (float2*)gY, i, N >> half)
                                        : (const void*)p->d_s[(q - 1) & 1];
                 void* out = last ? gx : (void*)p->d_s[q & 1];
                 const int ok = last ? (real_out ? OUT_ADD_R32 : OUT_ADD_C64) : OUT_STORE;
                 ProfScope ps(p, MRDFT_KERNEL_PASS_ADJ, s);
-                HIP_TRY(launch_pass(true, (first && p->hs) ? IN_HALF : IN_C64, ok, in, out, geo, tw, s));
+                HIP_TRY(launch_pass(true, (first && half) ? IN_HALF : IN_C64, ok, in, out, geo, tw, s));
                 ns += bits[q];
             }
         }
@@ -934,11 +945,12 @@ mrdft_status run_adjoint(mrdft_plan* p, const float2* gY, void* gx, bool real_ou
 }
 
 // Levels above 16 of a uniform plan through the global passes, written to
-// W[b][i - 17][n] (compact) or to the plan's output layout W[b][i - 1][n];
-// with `norms`, nothing is written and the squared magnitudes of signal b's
-// level i are added to norms[b * m + i - 1].
+// W[b][i - 17][n] (compact) or to the plan's output layout W[b][i - 1][n]
+// (half: as packed half spectra, N/2 values per level); with `norms`, nothing
+// is written and the squared magnitudes of signal b's level i are added to
+// norms[b * m + i - 1].
 mrdft_status upper_passes(mrdft_plan* p, const float* x, float2* W, hipStream_t s, bool full_layout = false,
-                          double* norms = nullptr) {
+                          double* norms = nullptr, bool half = false) {
     const Twiddles tw = p->tw();
     const int64_t N = int64_t(1) << p->m;
     const int top = p->m - kRowsMaxLevel;
@@ -958,7 +970,7 @@ mrdft_status upper_passes(mrdft_plan* p, const float* x, float2* W, hipStream_t 
                 geo.in_sig = nullptr;
                 geo.in_stride = N;
                 geo.out_sig = nullptr;
-                geo.out_stride = last ? (int64_t)(full_layout ? p->m : top) * N : N;
+                geo.out_stride = last ? (int64_t)(full_layout ? p->m : top) * (N >> (half ? 1 : 0)) : N;
                 const int slot = full_layout ? i - 1 : i - kRowsMaxLevel - 1;
                 const void* in = first ? (const void*)x : (const void*)p->d_s[(q - 1) & 1];
                 void* out = (void*)p->d_s[q & 1];
@@ -968,7 +980,8 @@ mrdft_status upper_passes(mrdft_plan* p, const float* x, float2* W, hipStream_t 
                     geo.out_stride = p->m;
                     ok = OUT_NORM;
                 } else if (last) {
-                    out = (void*)(W + (int64_t)slot * N);
+                    out = (void*)(W + (int64_t)slot * (N >> (half ? 1 : 0)));
+                    if (half) ok = OUT_HALF;
                 }
                 ProfScope ps(p, MRDFT_KERNEL_PASS_FWD, s);
                 HIP_TRY(launch_pass(false, first ? IN_R32 : IN_C64, ok, in, out, geo, tw, s));
@@ -1384,21 +1397,23 @@ mrdft_status mrdft_spectral_loss_bwd(mrdft_plan_t plan, const float* x, const fl
     const int64_t rows = plan->batch * plan->m;
     if (plan->d_rjobs) {
         // Recompute the spectra of x - z with each level already scaled by its
-        // gradient factor (levels 1..16 in the one-launch forward), then the adjoint.
+        // gradient factor (levels 1..16 in the one-launch forward), as packed
+        // half spectra (x - z is real: its level spectra are Hermitian, and
+        // the real adjoint of the packed values is the gradient), then the adjoint.
         HIP_TRY(launch_loss_alpha(num_den, gL, plan->d_alpha, rows, plan->m, stream));
         {
             ProfScope ps(plan, MRDFT_KERNEL_LOSS, stream);
             HIP_TRY(launch_fwd_real_scaled(x, z, plan->d_alpha, plan->m, plan->d_Yv, plan->d_rjobs, plan->nrjobs,
-                                           plan->tw(), stream));
+                                           plan->tw(), stream, true));
         }
         if (plan->m > kRowsMaxLevel) {
             HIP_TRY(launch_sub_real(x, z, plan->d_v, plan->n_in, stream));
-            st = upper_passes(plan, plan->d_v, plan->d_Yv, stream, true);
+            st = upper_passes(plan, plan->d_v, plan->d_Yv, stream, true, nullptr, true);
             if (st) return st;
-            HIP_TRY(launch_scale_levels(plan->d_Yv, num_den, gL, plan->m, N, plan->batch * (plan->m - kRowsMaxLevel),
-                                        stream, kRowsMaxLevel));
+            HIP_TRY(launch_scale_levels(plan->d_Yv, num_den, gL, plan->m, N / 2,
+                                        plan->batch * (plan->m - kRowsMaxLevel), stream, kRowsMaxLevel));
         }
-        return run_adjoint(plan, plan->d_Yv, gx, true, stream);
+        return run_adjoint(plan, plan->d_Yv, gx, true, stream, true);
     }
     HIP_TRY(launch_sub_real(x, z, plan->d_v, plan->n_in, stream));
     st = run_forward(plan, plan->d_v, IN_R32, plan->d_Yv, stream);

@@ -105,21 +105,22 @@ __device__ __forceinline__ float2 tw_big(const double2* __restrict__ hi, const d
     return make_float2((float)(a.x * b.x - a.y * b.y), (float)(a.x * b.y + a.y * b.x));
 }
 
-// Bin k (0 <= k < Lw) of one window of a real plan's packed half-spectrum
-// gradient (Lw/2 slots: slot 0 = (bin 0, bin Lw/2), slot k = bin k), read as
-// the Hermitian extension halved whose real adjoint is the packed adjoint:
-// bins 0 and Lw/2 the real numbers of slot 0, bin k < Lw/2 slot k / 2, bin
-// k > Lw/2 conj(slot Lw - k) / 2.
-__device__ __forceinline__ float2 half_bin(const float2* __restrict__ hw, int64_t k, int64_t Lw) {
+// Bin k (0 <= k < Lw) of one window held as packed half spectra (Lw/2 slots:
+// slot 0 = (bin 0, bin Lw/2), slot k = bin k), read as a Hermitian spectrum:
+// bins 0 and Lw/2 the real numbers of slot 0, bin k < Lw/2 hs * slot k, bin
+// k > Lw/2 hs * conj(slot Lw - k).  hs = 1/2 reads a half plan's packed
+// gradient as the Hermitian extension halved, whose real adjoint is the
+// packed adjoint; hs = 1 reads packed spectra of real signals back whole.
+// One load per bin and no branches (selects), so that a thread's loads can
+// all be in flight together.
+__device__ __forceinline__ float2 half_bin(const float2* __restrict__ hw, int64_t k, int64_t Lw, float hs) {
     const int64_t M = Lw >> 1;
-    if (k == 0) return make_float2(hw[0].x, 0.0f);
-    if (k == M) return make_float2(hw[0].y, 0.0f);
-    if (k < M) {
-        const float2 v = hw[k];
-        return make_float2(0.5f * v.x, 0.5f * v.y);
-    }
-    const float2 v = hw[Lw - k];
-    return make_float2(0.5f * v.x, -0.5f * v.y);
+    const bool up = k > M;
+    const int64_t slot = up ? Lw - k : (k == M ? 0 : k);
+    const float2 v = hw[slot];
+    const float re = (k == 0) ? v.x : (k == M) ? v.y : hs * v.x;
+    const float im = (k == 0 || k == M) ? 0.0f : (up ? -hs * v.y : hs * v.y);
+    return make_float2(re, im);
 }
 
 // Same twiddle in FP64 (not rounded).

@@ -19,7 +19,7 @@ union FwdRealLds {
 static_assert(sizeof(FwdRealLds) <= 40 * 1024, "four workgroups per CU");
 static_assert(kRThreads == kRowsThreads, "one block size for both job kinds");
 
-constexpr int kModeStore = 0, kModeNorms = 1, kModeScaled = 2, kModeHalf = 3;
+constexpr int kModeStore = 0, kModeNorms = 1, kModeScaled = 2, kModeHalf = 3, kModeScaledHalf = 4;
 
 // Sum of v over the 64 lanes of a wave (all lanes receive it).
 __device__ __forceinline__ double wave_sum(double v) {
@@ -67,19 +67,23 @@ __global__ __launch_bounds__(kRThreads, 4) void fwd_real_kernel(const float* __r
                                                  comb + rows_combine_offset(16), tid); break;
             default: break;
         }
-    } else if constexpr (MODE == kModeScaled) {
-        const ScaledOut out{alpha + (jb.in_off / jb.level_stride) * m};
+    } else if constexpr (MODE == kModeScaled || MODE == kModeScaledHalf) {
+        // kModeScaledHalf: packed half spectra from a full-spectrum job table
+        // (every output offset and the tiles' level stride halved)
+        constexpr bool H = MODE == kModeScaledHalf;
+        const ScaledOutT<H> out{alpha + (jb.in_off / jb.level_stride) * m};
         const float sc = jb.lg > 0 ? out.alpha[jb.lg - 1] : 1.0f;
+        float2* const yo = H ? Y + (jb.out_off >> 1) : yj;
         switch (jb.lg) {
-            case 0: real_tile_body(S.tile, xj, zj, yj, jb.level_stride, t4096, tid, out); break;
-            case 13: rows_real_body<5>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(13),
-                                       comb + rows_combine_offset(13), tid, zj, nullptr, sc); break;
-            case 14: rows_real_body<6>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(14),
-                                       comb + rows_combine_offset(14), tid, zj, nullptr, sc); break;
-            case 15: rows_real_body<7>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(15),
-                                       comb + rows_combine_offset(15), tid, zj, nullptr, sc); break;
-            case 16: rows_real_body<8>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(16),
-                                       comb + rows_combine_offset(16), tid, zj, nullptr, sc); break;
+            case 0: real_tile_body(S.tile, xj, zj, yo, jb.level_stride >> (H ? 1 : 0), t4096, tid, out); break;
+            case 13: rows_real_body<5, false, H>(S.rows, xj, yo, jb.g, t4096, rowtw + rows_twiddle_offset(13),
+                                                 comb + rows_combine_offset(13), tid, zj, nullptr, sc); break;
+            case 14: rows_real_body<6, false, H>(S.rows, xj, yo, jb.g, t4096, rowtw + rows_twiddle_offset(14),
+                                                 comb + rows_combine_offset(14), tid, zj, nullptr, sc); break;
+            case 15: rows_real_body<7, false, H>(S.rows, xj, yo, jb.g, t4096, rowtw + rows_twiddle_offset(15),
+                                                 comb + rows_combine_offset(15), tid, zj, nullptr, sc); break;
+            case 16: rows_real_body<8, false, H>(S.rows, xj, yo, jb.g, t4096, rowtw + rows_twiddle_offset(16),
+                                                 comb + rows_combine_offset(16), tid, zj, nullptr, sc); break;
             default: break;
         }
     } else {
@@ -123,10 +127,14 @@ hipError_t launch_fwd_real(const float* x, float2* Y, const RealJob* jobs, int64
 }
 
 hipError_t launch_fwd_real_scaled(const float* x, const float* xsub, const float* alpha, int m, float2* Y,
-                                  const RealJob* jobs, int64_t njobs, const Twiddles& tw, hipStream_t s) {
+                                  const RealJob* jobs, int64_t njobs, const Twiddles& tw, hipStream_t s, bool half) {
     if (njobs <= 0) return hipSuccess;
-    hipLaunchKernelGGL(fwd_real_kernel<kModeScaled>, dim3((unsigned)njobs), dim3(kRThreads), 0, s, x, Y, jobs, tw.tile,
-                       tw.rows, tw.rows_comb, xsub, nullptr, alpha, m);
+    if (half)
+        hipLaunchKernelGGL(fwd_real_kernel<kModeScaledHalf>, dim3((unsigned)njobs), dim3(kRThreads), 0, s, x, Y, jobs,
+                           tw.tile, tw.rows, tw.rows_comb, xsub, nullptr, alpha, m);
+    else
+        hipLaunchKernelGGL(fwd_real_kernel<kModeScaled>, dim3((unsigned)njobs), dim3(kRThreads), 0, s, x, Y, jobs,
+                           tw.tile, tw.rows, tw.rows_comb, xsub, nullptr, alpha, m);
     return hipGetLastError();
 }
 

@@ -35,6 +35,7 @@ struct PassGeom {
     int64_t in_stride;
     const int64_t* out_sig;
     int64_t out_stride;
+    float half_scale = 0.5f;   // IN_HALF: scale of half_bin
 };
 
 // IN_HALF: a real plan's packed half-spectrum gradient (window W at W * L/2),
@@ -75,9 +76,11 @@ hipError_t launch_fwd_real(const float* x, float2* Y, const RealJob* jobs, int64
 // squared magnitudes of every level are added to sums[b * m + level - 1]
 // (uniform batch; the rows jobs carry level_stride = N).  Y is not written.
 // Same jobs, spectral-loss gradient: input x - xsub, level i of signal b
-// stored times alpha[b * m + i - 1] (uniform batch).
+// stored times alpha[b * m + i - 1] (uniform batch); half: as packed half
+// spectra (offsets of the full-spectrum job table halved).
 hipError_t launch_fwd_real_scaled(const float* x, const float* xsub, const float* alpha, int m, float2* Y,
-                                  const RealJob* jobs, int64_t njobs, const Twiddles& tw, hipStream_t s);
+                                  const RealJob* jobs, int64_t njobs, const Twiddles& tw, hipStream_t s,
+                                  bool half = false);
 hipError_t launch_fwd_real_norms(const float* x, const float* xsub, double* sums, int m, const RealJob* jobs,
                                  int64_t njobs, const Twiddles& tw, hipStream_t s);
 // Complex input: 2048-sample tiles (lg = 0, levels 1..11) and pieces of levels
@@ -115,9 +118,11 @@ struct HalfJob {
 };
 constexpr int kHalfChunk = 4096;
 hipError_t launch_expand_half(const float2* gh, float2* g, const HalfJob* jobs, int64_t njobs, hipStream_t s);
-// half: gY holds packed half spectra (real output only); the job offsets are packed ones.
-hipError_t launch_adj_a(bool real_out, bool half, const float2* gY, void* gx, float2* scratch, const RealJob* jobs,
-                        int64_t njobs, const Twiddles& tw, hipStream_t s);
+// half: gY holds packed half spectra (real output only), read by half_bin
+// with scale hsc; the jobs' gradient offsets and tile level strides are
+// shifted right by gshift (1: a full-spectrum job table over a packed gradient).
+hipError_t launch_adj_a(bool real_out, bool half, int gshift, float hsc, const float2* gY, void* gx, float2* scratch,
+                        const RealJob* jobs, int64_t njobs, const Twiddles& tw, hipStream_t s);
 // Clears `bytes` (a multiple of 4) at p (4-byte aligned) with vector stores.
 hipError_t launch_zero(void* p, int64_t bytes, hipStream_t s);
 hipError_t launch_adj_b(bool real_out, void* gx, const float2* scratch, const AdjColJob* jobs, int64_t njobs,

@@ -116,7 +116,8 @@ __global__ __launch_bounds__(PassShape<LP>::kThreads) void pass_kernel(const voi
             const int s = s0 + rstep * i;
             const int64_t idx = ib + j + (int64_t)s * cols;
             if constexpr (IN_KIND == IN_R32) v[i] = make_float2(((const float*)in)[idx], 0.0f);
-            else if constexpr (IN_KIND == IN_HALF) v[i] = half_bin((const float2*)in + ib, idx - ib, L);   // first pass: bin idx - ib
+            else if constexpr (IN_KIND == IN_HALF)
+                v[i] = half_bin((const float2*)in + ib, idx - ib, L, g.half_scale);   // first pass: bin idx - ib
             else v[i] = ((const float2*)in)[idx];
         }
         T[tid] = tab[tid << (kTileMaxLog - Sh::kTwLog)];   // after the data loads: its wait covers them

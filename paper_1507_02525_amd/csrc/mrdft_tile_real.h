@@ -62,9 +62,10 @@ struct StoreOutT {
 };
 using StoreOut = StoreOutT<false>;
 // Stored times a per-level factor (spectral-loss gradient).
-struct ScaledOut {
+template <bool HALF>
+struct ScaledOutT {
     static constexpr bool kReduce = false;
-    static constexpr bool kHalf = false;
+    static constexpr bool kHalf = HALF;
     const float* alpha;
     __device__ __forceinline__ float2 sc(int level, float2 v) const {
         const float a = alpha[level - 1];
@@ -72,6 +73,7 @@ struct ScaledOut {
     }
     __device__ __forceinline__ bool keep(int) const { return true; }
 };
+using ScaledOut = ScaledOutT<false>;
 struct NormOut {
     static constexpr bool kReduce = true;
     static constexpr bool kHalf = false;
@@ -277,8 +279,9 @@ __device__ __forceinline__ void real_level(RealTileLds& S, float2* __restrict__ 
         } else if (O::kHalf) {
             if (out.keep(I)) {                          // the packed slots themselves (slot 0 = uk at k = 0)
                 float2* yh = y + (int64_t)w * M;
-                *(float4*)(yh + 2 * k) = make_float4(uk[c].x, uk[c].y, ok[c].x, ok[c].y);
-                *(float4*)(yh + 2 * j) = make_float4(uj[c].x, uj[c].y, oj[c].x, oj[c].y);
+                const float2 s0 = out.sc(I, uk[c]), s1 = out.sc(I, ok[c]), s2 = out.sc(I, uj[c]), s3 = out.sc(I, oj[c]);
+                *(float4*)(yh + 2 * k) = make_float4(s0.x, s0.y, s1.x, s1.y);
+                *(float4*)(yh + 2 * j) = make_float4(s2.x, s2.y, s3.x, s3.y);
             }
         } else if (out.keep(I)) {
             const float2 s0 = out.sc(I, u0), s1 = out.sc(I, ok[c]), s2 = out.sc(I, uj[c]), s3 = out.sc(I, oj[c]);
@@ -335,9 +338,9 @@ __device__ __forceinline__ void stage_level(const float2* pv, float4* st, float2
         float2 hv[8];
 #pragma unroll
         for (int w = 0; w < 16 / L; ++w) {
-            hv[w * M] = make_float2(pv[w * L].x, pv[w * L + M].x);
+            hv[w * M] = out.sc(level, make_float2(pv[w * L].x, pv[w * L + M].x));
 #pragma unroll
-            for (int k = 1; k < M; ++k) hv[w * M + k] = pv[w * L + k];
+            for (int k = 1; k < M; ++k) hv[w * M + k] = out.sc(level, pv[w * L + k]);
         }
 #pragma unroll
         for (int e = 0; e < 4; ++e)
