@@ -113,6 +113,8 @@ struct mrdft_plan {
     // real input: tiles of 4096 samples and rows pieces of levels 13..16, one launch
     RealJob* d_rjobs = nullptr;
     int64_t nrjobs = 0;
+    RealJob* d_sjobs = nullptr;             // real full-spectrum plans: signals below 4096 samples
+    int64_t nsjobs = 0;                     // (complex-launch tiles reading real input)
     // complex input: tiles of 2048 samples (several signals of order < 11 per
     // tile) and rows pieces of levels 12..16 in one launch (tile_log 11: one
     // workgroup per job, or persistent), or the tile kernel with 4096-sample
@@ -202,6 +204,7 @@ void free_plan(mrdft_plan* p) {
     dfree(p->d_tw_comb);
     dfree(p->d_tw_ccomb);
     dfree(p->d_rjobs);
+    dfree(p->d_sjobs);
     dfree(p->d_cjobs);
     dfree(p->d_queue);
     dfree(p->d_cseg);
@@ -325,6 +328,7 @@ mrdft_status upload_twiddles(mrdft_plan* p, hipStream_t s) {
 
 std::vector<RealJob> real_jobs(const mrdft_plan* p, int order);
 std::vector<RealJob> complex_jobs(const mrdft_plan* p, int order, std::vector<unsigned>* seg);
+std::vector<RealJob> small_real_jobs(const mrdft_plan* p);
 mrdft_status upload_cjobs(mrdft_plan* p, int order, hipStream_t s, bool direct);
 mrdft_status upload_jobs(const std::vector<RealJob>& v, RealJob** dst, int64_t* n, hipStream_t s);
 
@@ -367,6 +371,10 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
     if (p->dtype == MRDFT_R32) {
         mrdft_status st = upload_jobs(real_jobs(p, p->order), &p->d_rjobs, &p->nrjobs, s);
         if (st) return st;
+        if (!p->hs) {
+            st = upload_jobs(small_real_jobs(p), &p->d_sjobs, &p->nsjobs, s);
+            if (st) return st;
+        }
     } else {
         mrdft_status st = upload_cjobs(p, p->order, s, true);   // default: one workgroup per job
         if (st) return st;
@@ -652,6 +660,31 @@ std::vector<RealJob> real_jobs(const mrdft_plan* p, int order) {
     return jb.deal(order);
 }
 
+// Real signals below 4096 samples (full-spectrum plans): the complex launch's
+// 2048-sample tiles (order 11) and multi-signal tiles (orders below 11),
+// reading real input; several short signals share one workgroup.
+std::vector<RealJob> small_real_jobs(const mrdft_plan* p) {
+    JobBuckets jb;
+    for (int64_t j = 0; j < p->batch; ++j) {
+        const int mj = p->orders[j];
+        if (mj >= kRealTileLog || mj < p->lo) continue;    // the real launch / no level kept
+        const int64_t N = int64_t(1) << mj;
+        if (mj < kC64TileLog) {
+            const int64_t per = int64_t(1) << (kC64TileLog - mj);
+            int64_t n = 1;
+            while (j + n < p->batch && p->orders[j + n] == mj && n < per) ++n;
+            const int64_t vlen = n * N;
+            jb.add_block({RealJob{p->in_off[j], p->base(j), N | (vlen << 32), kMultiTileLg + mj,
+                                  LevelRange::pack(p->lo, std::min(p->hi, mj))}},
+                         {}, 1);
+            j += n - 1;
+            continue;
+        }
+        jb.add_block({RealJob{p->in_off[j], p->base(j), N, 0, p->range()}}, {}, 1);
+    }
+    return jb.deal(MRDFT_ORDER_BLOCKS);
+}
+
 // Complex signals of order >= 11: 2048-sample tiles and pieces of levels
 // 12..16 (2^(lg-12) pieces of 16 rows per window).
 std::vector<RealJob> complex_jobs(const mrdft_plan* p, int order, std::vector<unsigned>* seg) {
@@ -846,14 +879,18 @@ mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, h
                 ProfScope ps(p, MRDFT_KERNEL_FUSED_FWD, s0);
                 HIP_TRY(launch_fwd_real((const float*)x, Y, p->d_rjobs, p->nrjobs, tw, s0, p->hs != 0));
             }
-            if (p->njobs > p->njobs_full) {
+            if (p->nsjobs) {                          // signals below 4096 samples
+                ProfScope ps(p, MRDFT_KERNEL_TILE_FWD, s0);
+                HIP_TRY(launch_fwd_c64_direct(x, Y, p->d_sjobs, p->nsjobs, tw, s0, true));
+            } else if (p->njobs > p->njobs_full) {
                 ProfScope ps(p, MRDFT_KERNEL_TILE_FWD, s0);
                 HIP_TRY(launch_tile_fwd(true, x, Y, p->d_jobs + p->njobs_full, p->njobs - p->njobs_full, p->tail_tmax, tw, s0,
                                         p->hs != 0));
             }
         } else if (in_kind == IN_R32) {
             ProfScope ps(p, MRDFT_KERNEL_TILE_FWD, s0);
-            HIP_TRY(launch_tile_fwd(true, x, Y, p->d_jobs, p->njobs, p->jobs_tmax, tw, s0, p->hs != 0));
+            if (p->nsjobs) HIP_TRY(launch_fwd_c64_direct(x, Y, p->d_sjobs, p->nsjobs, tw, s0, true));
+            else HIP_TRY(launch_tile_fwd(true, x, Y, p->d_jobs, p->njobs, p->jobs_tmax, tw, s0, p->hs != 0));
         } else if (cjobs_cover) {
             {
                 ProfScope ps(p, MRDFT_KERNEL_FUSED_FWD, s0);

@@ -28,13 +28,14 @@ constexpr int kXcds = 8;
 
 // A tile of several consecutive signals of 2^m samples (m < 11): job lg =
 // kMultiTileLg + m, level_stride = 2^m | (valid samples << 32).
-__device__ __forceinline__ void multi_tile(CTileLds& S, const float2* x, float2* y, const RealJob& jb,
+template <bool REALIN = false>
+__device__ __forceinline__ void multi_tile(CTileLds& S, const void* x, float2* y, const RealJob& jb,
                                            const float2* t4096, int tid) {
     const int m = jb.lg - kMultiTileLg;
     const int64_t N = jb.level_stride & 0xffffffffLL;
     const LevelRange lv = LevelRange::unpack(jb.g);
     const SubMap sm{m, (int)(jb.level_stride >> 32), (int64_t)(lv.hi - lv.lo + 1) * N};
-    c64_tile_body<true>(S, x, y, N, t4096, tid, lv, sm);
+    c64_tile_body<true, REALIN>(S, x, y, N, t4096, tid, lv, sm);
 }
 
 __device__ __forceinline__ unsigned xcc_id() {
@@ -110,7 +111,10 @@ __global__ __launch_bounds__(kCThreads, 4) void fwd_c64_kernel(const float2* __r
 // b mod 8, holds a job of that XCD's bucket).  In the persistent form the
 // loads of a workgroup's next job queue behind the stores of its previous one
 // (one in-order vector memory counter); here every job starts fresh.
-__global__ __launch_bounds__(kCThreads, 4) void fwd_c64_direct(const float2* __restrict__ x, float2* __restrict__ Y,
+// REALIN: real float32 signals below 4096 samples of a real plan (tiles and
+// multi-signal tiles only; the full complex spectra are written).
+template <bool REALIN>
+__global__ __launch_bounds__(kCThreads, 4) void fwd_c64_direct(const void* __restrict__ x, float2* __restrict__ Y,
                                                                const RealJob* __restrict__ jobs,
                                                                const float2* __restrict__ t4096,
                                                                const float2* __restrict__ rowtw,
@@ -118,8 +122,14 @@ __global__ __launch_bounds__(kCThreads, 4) void fwd_c64_direct(const float2* __r
     __shared__ FwdC64Lds S;
     const int tid = threadIdx.x;
     const RealJob jb = jobs[blockIdx.x];
-    const float2* xj = x + jb.in_off;
     float2* yj = Y + jb.out_off;
+    if constexpr (REALIN) {
+        const float* xj = (const float*)x + jb.in_off;
+        if (jb.lg == 0) c64_tile_body<false, true>(S.tile, xj, yj, jb.level_stride, t4096, tid, LevelRange::unpack(jb.g));
+        else if (jb.lg >= kMultiTileLg) multi_tile<true>(S.tile, xj, yj, jb, t4096, tid);
+        return;
+    }
+    const float2* xj = (const float2*)x + jb.in_off;
     switch (jb.lg) {
         case 0: c64_tile_body(S.tile, xj, yj, jb.level_stride, t4096, tid, LevelRange::unpack(jb.g)); break;
         case 12: rows_c64_body<4>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(12),
@@ -140,11 +150,15 @@ __global__ __launch_bounds__(kCThreads, 4) void fwd_c64_direct(const float2* __r
 
 }  // namespace
 
-hipError_t launch_fwd_c64_direct(const float2* x, float2* Y, const RealJob* jobs, int64_t njobs, const Twiddles& tw,
-                                 hipStream_t s) {
+hipError_t launch_fwd_c64_direct(const void* x, float2* Y, const RealJob* jobs, int64_t njobs, const Twiddles& tw,
+                                 hipStream_t s, bool real_in) {
     if (njobs <= 0) return hipSuccess;
-    hipLaunchKernelGGL(fwd_c64_direct, dim3((unsigned)njobs), dim3(kCThreads), 0, s, x, Y, jobs, tw.tile, tw.rows,
-                       tw.crows_comb);
+    if (real_in)
+        hipLaunchKernelGGL(fwd_c64_direct<true>, dim3((unsigned)njobs), dim3(kCThreads), 0, s, x, Y, jobs, tw.tile,
+                           tw.rows, tw.crows_comb);
+    else
+        hipLaunchKernelGGL(fwd_c64_direct<false>, dim3((unsigned)njobs), dim3(kCThreads), 0, s, x, Y, jobs, tw.tile,
+                           tw.rows, tw.crows_comb);
     return hipGetLastError();
 }
 

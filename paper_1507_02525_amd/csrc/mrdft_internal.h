@@ -130,8 +130,10 @@ hipError_t launch_adj_b(bool real_out, void* gx, const float2* scratch, const Ad
 hipError_t launch_fwd_c64(const float2* x, float2* Y, const RealJob* jobs, int64_t njobs, const unsigned* seg,
                           unsigned* queue, int grid, const Twiddles& tw, hipStream_t s);
 // Same jobs, one workgroup per job (table dealt round-robin over the XCDs).
-hipError_t launch_fwd_c64_direct(const float2* x, float2* Y, const RealJob* jobs, int64_t njobs, const Twiddles& tw,
-                                 hipStream_t s);
+// real_in: float32 signals below 4096 samples of a real plan (tile and
+// multi-signal tile jobs only), written as full complex spectra.
+hipError_t launch_fwd_c64_direct(const void* x, float2* Y, const RealJob* jobs, int64_t njobs, const Twiddles& tw,
+                                 hipStream_t s, bool real_in = false);
 // half (real input only): packed half-spectrum output, job offsets and level
 // strides in those units.
 // tmax: the largest tile order t among the jobs (sizes the launch's LDS).

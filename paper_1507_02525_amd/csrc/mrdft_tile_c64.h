@@ -248,9 +248,10 @@ struct CtLocal {
 // One tile: x at its first sample, y at its level-1 output (level i at
 // y + (i-1) ls).  Wave v owns samples [512 v, 512 v + 512).  MULTI: the tile
 // holds consecutive signals of 2^sm.m samples (ls = 2^sm.m, lv.hi <= sm.m),
-// samples past sm.vlen are not read and their outputs not written.
-template <bool MULTI = false>
-__device__ __forceinline__ void c64_tile_body(CTileLds& S, const float2* __restrict__ x, float2* __restrict__ y,
+// samples past sm.vlen are not read and their outputs not written.  REALIN:
+// x is float32 (real samples, imaginary parts zero).
+template <bool MULTI = false, bool REALIN = false>
+__device__ __forceinline__ void c64_tile_body(CTileLds& S, const void* __restrict__ x, float2* __restrict__ y,
                                               int64_t ls, const float2* __restrict__ t4096, int tid, LevelRange lv,
                                               const SubMap& sm = SubMap{31, kCT, 0}) {
     constexpr int C = 8;
@@ -258,12 +259,19 @@ __device__ __forceinline__ void c64_tile_body(CTileLds& S, const float2* __restr
     for (int e = tid; e < kCT / 4; e += kCThreads) S.Q[cqswz(e)] = t4096[2 * e];   // before any store
     // coalesced load of the wave's samples into X (their final place)
     {
-        const float4* xg = (const float4*)(x + 512 * v);
         float4 a[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            if (!MULTI || 512 * v + 2 * (64 * r + lane) < sm.vlen) a[r] = xg[64 * r + lane];
-            else a[r] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (!MULTI || 512 * v + 2 * (64 * r + lane) < sm.vlen) {
+                if constexpr (REALIN) {
+                    const float2 f = ((const float2*)((const float*)x + 512 * v))[64 * r + lane];
+                    a[r] = make_float4(f.x, 0.0f, f.y, 0.0f);
+                } else {
+                    a[r] = ((const float4*)((const float2*)x + 512 * v))[64 * r + lane];
+                }
+            } else {
+                a[r] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            }
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) *(float4*)(S.X + 512 * v + 2 * (64 * r + lane)) = a[r];
