@@ -685,8 +685,12 @@ std::vector<RealJob> small_real_jobs(const mrdft_plan* p) {
     return jb.deal(MRDFT_ORDER_BLOCKS);
 }
 
+// Pieces per window of a complex level 12..16: one of 16 rows at level 12,
+// 2^(lg-13) of 32 rows above.
+int cpieces(int lg) { return lg == kCRowsMinLevel ? 1 : 1 << (lg - kCRowsMinLevel - 1); }
+
 // Complex signals of order >= 11: 2048-sample tiles and pieces of levels
-// 12..16 (2^(lg-12) pieces of 16 rows per window).
+// 12..16 (cpieces per window).
 std::vector<RealJob> complex_jobs(const mrdft_plan* p, int order, std::vector<unsigned>* seg) {
     JobBuckets jb;
     constexpr int64_t kTileCost = 5;                           // 11 x 16 KB against 32 KB per piece
@@ -725,7 +729,7 @@ std::vector<RealJob> complex_jobs(const mrdft_plan* p, int order, std::vector<un
                 for (int64_t tau = u0 >> kC64TileLog; tiles && tau < (u0 + U) >> kC64TileLog; ++tau) t.push_back(tile(tau));
                 for (int lg = phi; lg >= plo; --lg)
                     for (int64_t w = u0 >> lg; w < (u0 + U) >> lg; ++w)
-                        for (int g = 0; g < (1 << (lg - kCRowsMinLevel)); ++g) {
+                        for (int g = 0; g < cpieces(lg); ++g) {
                             RealJob jb1 = window(lg, w);
                             jb1.g = g;
                             r.push_back(jb1);
@@ -736,7 +740,7 @@ std::vector<RealJob> complex_jobs(const mrdft_plan* p, int order, std::vector<un
         }
         for (int64_t tau = 0; tiles && tau < (N >> kC64TileLog); ++tau) jb.add_tile(tile(tau), kTileCost);
         for (int lg = plo; lg <= phi; ++lg)
-            for (int64_t w = 0; w < (N >> lg); ++w) jb.add_window(window(lg, w), 1 << (lg - kCRowsMinLevel));
+            for (int64_t w = 0; w < (N >> lg); ++w) jb.add_window(window(lg, w), cpieces(lg));
     }
     return jb.deal(order, seg);
 }

@@ -82,14 +82,14 @@ __global__ __launch_bounds__(kCThreads, 4) void fwd_c64_kernel(const float2* __r
             case 0: c64_tile_body(S.tile, xj, yj, jb.level_stride, t4096, t, LevelRange::unpack(jb.g)); break;
             case 12: rows_c64_body<4>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(12),
                                       comb + crows_combine_offset(12), t); break;
-            case 13: rows_c64_body<5>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(13),
-                                      comb + crows_combine_offset(13), t); break;
-            case 14: rows_c64_body<6>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(14),
-                                      comb + crows_combine_offset(14), t); break;
-            case 15: rows_c64_body<7>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(15),
-                                      comb + crows_combine_offset(15), t); break;
-            case 16: rows_c64_body<8>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(16),
-                                      comb + crows_combine_offset(16), t); break;
+            case 13: rows_c64_body2<5>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(13),
+                                       comb + crows_combine_offset(13), t); break;
+            case 14: rows_c64_body2<6>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(14),
+                                       comb + crows_combine_offset(14), t); break;
+            case 15: rows_c64_body2<7>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(15),
+                                       comb + crows_combine_offset(15), t); break;
+            case 16: rows_c64_body2<8>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(16),
+                                       comb + crows_combine_offset(16), t); break;
             default:
                 if (jb.lg >= kMultiTileLg) multi_tile(S.tile, xj, yj, jb, t4096, t);
                 break;
@@ -134,14 +134,14 @@ __global__ __launch_bounds__(kCThreads, 4) void fwd_c64_direct(const void* __res
         case 0: c64_tile_body(S.tile, xj, yj, jb.level_stride, t4096, tid, LevelRange::unpack(jb.g)); break;
         case 12: rows_c64_body<4>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(12),
                                   comb + crows_combine_offset(12), tid); break;
-        case 13: rows_c64_body<5>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(13),
-                                  comb + crows_combine_offset(13), tid); break;
-        case 14: rows_c64_body<6>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(14),
-                                  comb + crows_combine_offset(14), tid); break;
-        case 15: rows_c64_body<7>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(15),
-                                  comb + crows_combine_offset(15), tid); break;
-        case 16: rows_c64_body<8>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(16),
-                                  comb + crows_combine_offset(16), tid); break;
+        case 13: rows_c64_body2<5>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(13),
+                                   comb + crows_combine_offset(13), tid); break;
+        case 14: rows_c64_body2<6>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(14),
+                                   comb + crows_combine_offset(14), tid); break;
+        case 15: rows_c64_body2<7>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(15),
+                                   comb + crows_combine_offset(15), tid); break;
+        case 16: rows_c64_body2<8>(S.rows, xj, yj, jb.g, t4096, rowtw + rows_twiddle_offset(16),
+                                   comb + crows_combine_offset(16), tid); break;
         default:
             if (jb.lg >= kMultiTileLg) multi_tile(S.tile, xj, yj, jb, t4096, tid);
             break;

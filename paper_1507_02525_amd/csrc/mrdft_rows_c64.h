@@ -122,4 +122,70 @@ __device__ __forceinline__ void rows_c64_body(CRowsLds& S, const float2* __restr
     }
 }
 
+// Piece g of one window of level lg = RL + 8 (13 <= lg <= 16) with the 32
+// rows k2 = 32g .. 32g+31 (groups 2g and 2g+1): the sub-DFTs of the columns
+// are computed once for both groups (half of them per window against two
+// 16-row pieces), the two groups' sums stay in registers, and the row FFTs
+// run one group after the other in the same LDS.  No loads are issued ahead:
+// the registers hold the second group's sums instead.
+template <int RL>
+__device__ __forceinline__ void rows_c64_body2(CRowsLds& S, const float2* __restrict__ xw, float2* __restrict__ yw,
+                                               int g, const float2* __restrict__ t4096,
+                                               const float2* __restrict__ rowtw, const float2* __restrict__ comb,
+                                               int tid) {
+    constexpr int R = 1 << RL, P = R / 16;
+    static_assert(P >= 2 && P <= 16, "two groups of 16 rows: windows of 2^13 .. 2^16");
+    const int k0 = 32 * g;
+    const int n1 = tid;
+    S.T[tid] = t4096[tid << (kTileMaxLog - kRowsLog)];
+    const __amdgpu_buffer_rsrc_t xr =
+        __builtin_amdgcn_make_buffer_rsrc((void*)xw, (short)0, R * kRowsN * (int)sizeof(float2), kBufferWord3);
+    const int vo = n1 * (int)sizeof(float2);
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    auto xload = [&](int n2) {
+        const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(xr, vo, n2 * kRowsN * (int)sizeof(float2), 0);
+        return make_float2(__uint_as_float(v.x), __uint_as_float(v.y));
+    };
+    const float2* cb0 = comb + (int64_t)(2 * g) * P * 16;        // group 2g
+    const float2* cb1 = comb + (int64_t)(2 * g + 1) * P * 16;    // group 2g + 1
+    float2 acc[32];
+#pragma unroll 1
+    for (int r = 0; r < P; ++r) {
+        float2 z[16];
+#pragma unroll
+        for (int b = 0; b < 16; ++b) z[b] = xload(r + P * b);
+        dft_reg<16, false>(z);
+        if (r == 0) {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc[q] = acc[16 + q] = z[q];     // factor 1
+        } else {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                acc[q] = cadd(acc[q], cmul(z[q], cb0[r * 16 + q]));    // wave-uniform: scalar loads
+                acc[16 + q] = cadd(acc[16 + q], cmul(z[q], cb1[r * 16 + q]));
+            }
+        }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int kh = k0 + 16 * h;
+        if (h) __syncthreads();                                    // the first group's outputs are read
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            S.C[q * kRowsStride + rpad(n1)] = cmul(acc[16 * h + q], rowtw[(kh + q) * kRowsN + n1]);
+        __syncthreads();
+        crows_step<0>(S, tid);
+        crows_step<4>(S, tid);
+        // outputs: 16 consecutive bins kh .. kh+15 at every k1
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = tid + u * kRowsThreads;
+            const int k1 = e >> 3, kp = (e & 7) * 2;
+            const float2 a = S.C[kp * kRowsStride + rpad(k1)];
+            const float2 c = S.C[(kp + 1) * kRowsStride + rpad(k1)];
+            *(float4*)(yw + kh + kp + (int64_t)R * k1) = make_float4(a.x, a.y, c.x, c.y);
+        }
+    }
+}
+
 }  // namespace mrdft
