@@ -165,6 +165,7 @@ def _levels_ref(x, lo, hi):
     ("c64", [8, 13], 1, 4),             # register levels only
     ("c64", [16, 15, 9], 14, 16),       # upper pieces only: no tile job is launched
     ("r32", [16, 12, 5], 14, 16),       # the same for real input; two signals keep no level
+    ("r32", [10, 11, 9, 9, 9, 13], 3, 10),   # short real signals in the complex launch (one multi tile of 9s)
 ])
 def test_level_range_forward_and_adjoint(dtype, orders, lo, hi):
     need_gpu()
