@@ -1391,7 +1391,8 @@ mrdft_status mrdft_spectral_loss_fwd(mrdft_plan_t plan, const float* x, const fl
         const Twiddles tw = plan->tw();
         double* snum = plan->d_sums;
         double* sden = plan->d_sums + rows;
-        HIP_TRY(hipMemsetAsync(plan->d_sums, 0, sizeof(double) * 2 * rows, stream));
+        // a fill kernel, not a memset node: the call may be captured into a graph
+        HIP_TRY(launch_zero(plan->d_sums, (int64_t)sizeof(double) * 2 * rows, stream));
         {
             ProfScope ps(plan, MRDFT_KERNEL_LOSS, stream);
             HIP_TRY(launch_fwd_real_norms(x, z, snum, plan->m, plan->d_rjobs, plan->nrjobs, tw, stream));

@@ -169,3 +169,38 @@ def test_workload5_full_size():
         ref = oracle.spectral_loss_grad(x[b], z[b], ndr)
         assert rel_l2(g[b], ref) <= GRAD_TOL
     assert abs(L.item() / Lsum - 1) <= 1e-5
+
+
+@pytest.mark.parametrize("m", [13, 18])
+def test_spectral_loss_fwd_graph_replay(m):
+    """The loss forward captured into a HIP graph (it clears its sums with a
+    fill kernel, no memset node) gives the eager result on every replay, with
+    eager work on the stream between the replays."""
+    need_gpu()
+    api = _api()
+    x, z = _loss_case(3, m, 900 + m)
+    log("loss forward graph m=%d" % m)
+    xd, zd = to_dev(x), to_dev(z)
+    plan = api.Plan(m=m, batch=3, dtype="r32")
+    nd = torch.empty(3, m, 2, dtype=torch.float64, device="cuda")
+    L = torch.empty(1, dtype=torch.float32, device="cuda")
+    plan.mrdft_spectral_loss_fwd(xd, zd, nd, L)            # eager (allocates the workspace)
+    torch.cuda.synchronize()
+    nd0, L0 = nd.clone(), L.clone()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            plan.mrdft_spectral_loss_fwd(xd, zd, nd, L)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    junk = torch.zeros(1 << 20, device="cuda")
+    for r in range(3):
+        nd.fill_(-1.0)
+        L.fill_(-1.0)
+        junk.add_(float(r))                                  # eager work between the replays
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.allclose(nd, nd0, rtol=1e-12, atol=0.0), r
+        assert torch.allclose(L, L0, rtol=1e-6, atol=0.0), r
