@@ -919,6 +919,39 @@ mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, h
 // packed_from_full: gY holds packed half spectra of a full-spectrum (real,
 // uniform) plan's levels, read with the plan's full-layout tables halved
 // (the spectral-loss gradient).
+// Passes q0 .. q1-1 of the adjoint chain of level i of group g on stream s
+// with the ping-pong scratch ds: the first pass reads the level's gradient
+// (packed for half plans), the last adds its result into gx.
+mrdft_status adj_chain(mrdft_plan* p, const Group& g, int i, const float2* gY, void* gx, bool real_out, int half,
+                       bool packed_from_full, size_t q0, size_t q1, float2* const* ds, hipStream_t s) {
+    const Twiddles tw = p->tw();
+    const int64_t N = int64_t(1) << g.order;
+    const std::vector<int> bits = pass_bits(i);
+    int ns = 0;
+    for (size_t q = 0; q < q0; ++q) ns += bits[q];
+    for (size_t q = q0; q < q1; ++q) {
+        const bool first = q == 0, last = q + 1 == bits.size();
+        PassGeom geo;
+        geo.lg = i;
+        geo.r_log = bits[q];
+        geo.ns_log = ns;
+        geo.nwin = g.count * (N >> i);
+        geo.wps = N >> i;
+        geo.in_sig = first ? g.d_out_sig : nullptr;
+        geo.in_stride = first ? (int64_t)p->kept(g.order) * (N >> half) : N;
+        geo.out_sig = last ? g.d_in_sig : nullptr;
+        geo.out_stride = N;
+        geo.half_scale = packed_from_full ? 1.0f : 0.5f;
+        const void* in = first ? (const void*)level_ptr(p, (float2*)gY, i, N >> half) : (const void*)ds[(q - 1) & 1];
+        void* out = last ? gx : (void*)ds[q & 1];
+        const int ok = last ? (real_out ? OUT_ADD_R32 : OUT_ADD_C64) : OUT_STORE;
+        ProfScope ps(p, MRDFT_KERNEL_PASS_ADJ, s);
+        HIP_TRY(launch_pass(true, (first && half) ? IN_HALF : IN_C64, ok, in, out, geo, tw, s));
+        ns += bits[q];
+    }
+    return MRDFT_OK;
+}
+
 mrdft_status run_adjoint(mrdft_plan* p, const float2* gY, void* gx, bool real_out, hipStream_t s,
                          bool packed_from_full = false) {
     const Twiddles tw = p->tw();
@@ -927,6 +960,29 @@ mrdft_status run_adjoint(mrdft_plan* p, const float2* gY, void* gx, bool real_ou
         return fail(MRDFT_E_UNSUPPORTED, "packed gradient of a full-spectrum plan: uniform real plans of order >= 11 only");
     // the job tables of a real plan hold Hermitian pieces: real output only
     if (real_out != (p->dtype == MRDFT_R32)) return fail(MRDFT_E_UNSUPPORTED, "adjoint output type differs from the plan's");
+    // Levels above 16 run as chains of global passes whose last pass adds into
+    // gx.  With a side stream per chain, every pass but the last runs on the
+    // chain's side stream (with its own scratch) beside the tile and column
+    // launches below; the last passes follow those launches on s, one chain
+    // after another, so the additions into gx never overlap.
+    std::vector<std::pair<const Group*, int>> chains;
+    for (const Group& g : p->groups)
+        for (int i = kRowsMaxLevel + 1; i <= g.order; ++i)
+            if (i >= p->lo && i <= p->hi) chains.push_back({&g, i});
+    const bool par = !chains.empty() && (int)chains.size() <= p->nsides;
+    auto scratch_of = [&](size_t c) -> float2* const* { return !par || c == 0 ? p->d_s : p->d_ss[c - 1]; };
+    if (par) {
+        HIP_TRY(hipEventRecord(p->fork_ev, s));
+        for (size_t c = 0; c < chains.size(); ++c) {
+            const hipStream_t sk = p->side[c];
+            HIP_TRY(hipStreamWaitEvent(sk, p->fork_ev, 0));
+            const size_t nb = pass_bits(chains[c].second).size();
+            mrdft_status st = adj_chain(p, *chains[c].first, chains[c].second, gY, gx, real_out, half, packed_from_full,
+                                        0, nb - 1, scratch_of(c), sk);
+            if (st) return st;
+            HIP_TRY(hipEventRecord(p->join_ev[c], sk));
+        }
+    }
     if (p->hs && p->nhjobs) {
         // signals below the tile: packed gradient -> full-spectrum layout
         ProfScope ps(p, MRDFT_KERNEL_TILE_ADJ, s);
@@ -951,36 +1007,12 @@ mrdft_status run_adjoint(mrdft_plan* p, const float2* gY, void* gx, bool real_ou
         ProfScope ps(p, MRDFT_KERNEL_PASS_ADJ, s);
         HIP_TRY(launch_adj_b(real_out, gx, p->d_ascratch, p->d_acols, p->nacols, tw, s));
     }
-    // levels above 16: global passes accumulating into gx
-    for (const Group& g : p->groups) {
-        const int64_t N = int64_t(1) << g.order;
-        for (int i = kRowsMaxLevel + 1; i <= g.order; ++i) {
-            if (i < p->lo || i > p->hi) continue;                                      // level not kept
-            const std::vector<int> bits = pass_bits(i);
-            int ns = 0;
-            for (size_t q = 0; q < bits.size(); ++q) {
-                const bool first = q == 0, last = q + 1 == bits.size();
-                PassGeom geo;
-                geo.lg = i;
-                geo.r_log = bits[q];
-                geo.ns_log = ns;
-                geo.nwin = g.count * (N >> i);
-                geo.wps = N >> i;
-                // the first pass reads the level's gradient (packed for half plans)
-                geo.in_sig = first ? g.d_out_sig : nullptr;
-                geo.in_stride = first ? (int64_t)p->kept(g.order) * (N >> half) : N;
-                geo.out_sig = last ? g.d_in_sig : nullptr;
-                geo.out_stride = N;
-                geo.half_scale = packed_from_full ? 1.0f : 0.5f;
-                const void* in = first ? (const void*)level_ptr(p, (float2*)gY, i, N >> half)
-                                       : (const void*)p->d_s[(q - 1) & 1];
-                void* out = last ? gx : (void*)p->d_s[q & 1];
-                const int ok = last ? (real_out ? OUT_ADD_R32 : OUT_ADD_C64) : OUT_STORE;
-                ProfScope ps(p, MRDFT_KERNEL_PASS_ADJ, s);
-                HIP_TRY(launch_pass(true, (first && half) ? IN_HALF : IN_C64, ok, in, out, geo, tw, s));
-                ns += bits[q];
-            }
-        }
+    for (size_t c = 0; c < chains.size(); ++c) {
+        const size_t nb = pass_bits(chains[c].second).size();
+        if (par) HIP_TRY(hipStreamWaitEvent(s, p->join_ev[c], 0));
+        mrdft_status st = adj_chain(p, *chains[c].first, chains[c].second, gY, gx, real_out, half, packed_from_full,
+                                    par ? nb - 1 : 0, nb, scratch_of(c), s);
+        if (st) return st;
     }
     return MRDFT_OK;
 }
@@ -989,15 +1021,19 @@ mrdft_status run_adjoint(mrdft_plan* p, const float2* gY, void* gx, bool real_ou
 // W[b][i - 17][n] (compact) or to the plan's output layout W[b][i - 1][n]
 // (half: as packed half spectra, N/2 values per level); with `norms`, nothing
 // is written and the squared magnitudes of signal b's level i are added to
-// norms[b * m + i - 1].
+// norms[b * m + i - 1].  scr: the ping-pong scratch of the stream s (default:
+// the plan's own); only: that one level (0: every level).
 mrdft_status upper_passes(mrdft_plan* p, const float* x, float2* W, hipStream_t s, bool full_layout = false,
-                          double* norms = nullptr, bool half = false) {
+                          double* norms = nullptr, bool half = false, float2* const* scr = nullptr,
+                          int only = 0) {
+    float2* const* ds = scr ? scr : p->d_s;           // ping-pong scratch of the stream s
     const Twiddles tw = p->tw();
     const int64_t N = int64_t(1) << p->m;
     const int top = p->m - kRowsMaxLevel;
     for (const Group& g : p->groups) {
         for (int i = kRowsMaxLevel + 1; i <= g.order; ++i) {
             if (i < p->lo || i > p->hi) continue;                                      // level not kept
+            if (only && i != only) continue;                                           // one level asked for
             const std::vector<int> bits = pass_bits(i);
             int ns = 0;
             for (size_t q = 0; q < bits.size(); ++q) {
@@ -1013,8 +1049,8 @@ mrdft_status upper_passes(mrdft_plan* p, const float* x, float2* W, hipStream_t 
                 geo.out_sig = nullptr;
                 geo.out_stride = last ? (int64_t)(full_layout ? p->m : top) * (N >> (half ? 1 : 0)) : N;
                 const int slot = full_layout ? i - 1 : i - kRowsMaxLevel - 1;
-                const void* in = first ? (const void*)x : (const void*)p->d_s[(q - 1) & 1];
-                void* out = (void*)p->d_s[q & 1];
+                const void* in = first ? (const void*)x : (const void*)ds[(q - 1) & 1];
+                void* out = (void*)ds[q & 1];
                 int ok = OUT_STORE;
                 if (last && norms) {
                     out = norms;
@@ -1393,19 +1429,40 @@ mrdft_status mrdft_spectral_loss_fwd(mrdft_plan_t plan, const float* x, const fl
         double* sden = plan->d_sums + rows;
         // a fill kernel, not a memset node: the call may be captured into a graph
         HIP_TRY(launch_zero(plan->d_sums, (int64_t)sizeof(double) * 2 * rows, stream));
+        // Levels above 16: the last pass of each level adds the squared
+        // magnitudes straight into the level sums.  With two side streams the
+        // sums of z run on the second one (with its own pass scratch) in the
+        // opposite order, passes first: the HBM-bound passes of one stream then
+        // overlap the arithmetic-bound one-launch forward of the other.
+        const bool upper = plan->m > kRowsMaxLevel;
+        const bool par = upper && plan->nsides >= 2;
+        const hipStream_t s2 = par ? plan->side[1] : stream;
+        if (par) {
+            HIP_TRY(hipEventRecord(plan->fork_ev, stream));
+            HIP_TRY(hipStreamWaitEvent(s2, plan->fork_ev, 0));
+            st = upper_passes(plan, z, nullptr, s2, false, sden, false, plan->d_ss[0]);
+            if (st) return st;
+        }
         {
             ProfScope ps(plan, MRDFT_KERNEL_LOSS, stream);
             HIP_TRY(launch_fwd_real_norms(x, z, snum, plan->m, plan->d_rjobs, plan->nrjobs, tw, stream));
-            HIP_TRY(launch_fwd_real_norms(z, nullptr, sden, plan->m, plan->d_rjobs, plan->nrjobs, tw, stream));
         }
-        if (plan->m > kRowsMaxLevel) {
-            // levels above 16: the last pass of each level adds the squared
-            // magnitudes straight into the level sums
+        {
+            ProfScope ps(plan, MRDFT_KERNEL_LOSS, s2);
+            HIP_TRY(launch_fwd_real_norms(z, nullptr, sden, plan->m, plan->d_rjobs, plan->nrjobs, tw, s2));
+        }
+        if (upper) {
             HIP_TRY(launch_sub_real(x, z, plan->d_v, plan->n_in, stream));
-            for (int pass = 0; pass < 2; ++pass) {
-                st = upper_passes(plan, pass == 0 ? plan->d_v : z, nullptr, stream, false, pass == 0 ? snum : sden);
+            st = upper_passes(plan, plan->d_v, nullptr, stream, false, snum);
+            if (st) return st;
+            if (!par) {
+                st = upper_passes(plan, z, nullptr, stream, false, sden);
                 if (st) return st;
             }
+        }
+        if (par) {
+            HIP_TRY(hipEventRecord(plan->join_ev[1], s2));
+            HIP_TRY(hipStreamWaitEvent(stream, plan->join_ev[1], 0));
         }
         HIP_TRY(launch_finalize(snum, sden, num_den, L, plan->batch, plan->m, 1, stream));
         return MRDFT_OK;
@@ -1442,16 +1499,40 @@ mrdft_status mrdft_spectral_loss_bwd(mrdft_plan_t plan, const float* x, const fl
         // gradient factor (levels 1..16 in the one-launch forward), as packed
         // half spectra (x - z is real: its level spectra are Hermitian, and
         // the real adjoint of the packed values is the gradient), then the adjoint.
+        // Levels above 16 (unscaled, scaled afterwards) run on side streams
+        // when the plan has one per level: x - z and its passes beside the
+        // one-launch forward.
+        const bool upper = plan->m > kRowsMaxLevel;
+        const int nup = plan->m - kRowsMaxLevel;
+        const bool par = upper && plan->nsides >= nup;
+        if (par) {
+            HIP_TRY(hipEventRecord(plan->fork_ev, stream));
+            HIP_TRY(hipStreamWaitEvent(plan->side[0], plan->fork_ev, 0));
+            HIP_TRY(launch_sub_real(x, z, plan->d_v, plan->n_in, plan->side[0]));
+            HIP_TRY(hipEventRecord(plan->join_ev[0], plan->side[0]));      // x - z ready
+            for (int k = 0; k < nup; ++k) {
+                const hipStream_t sk = plan->side[k];
+                if (k) HIP_TRY(hipStreamWaitEvent(sk, plan->join_ev[0], 0));
+                st = upper_passes(plan, plan->d_v, plan->d_Yv, sk, true, nullptr, true,
+                                  k ? plan->d_ss[k - 1] : plan->d_s, kRowsMaxLevel + 1 + k);
+                if (st) return st;
+            }
+            for (int k = 0; k < nup; ++k) HIP_TRY(hipEventRecord(plan->join_ev[k], plan->side[k]));
+        }
         HIP_TRY(launch_loss_alpha(num_den, gL, plan->d_alpha, rows, plan->m, stream));
         {
             ProfScope ps(plan, MRDFT_KERNEL_LOSS, stream);
             HIP_TRY(launch_fwd_real_scaled(x, z, plan->d_alpha, plan->m, plan->d_Yv, plan->d_rjobs, plan->nrjobs,
                                            plan->tw(), stream, true));
         }
-        if (plan->m > kRowsMaxLevel) {
-            HIP_TRY(launch_sub_real(x, z, plan->d_v, plan->n_in, stream));
-            st = upper_passes(plan, plan->d_v, plan->d_Yv, stream, true, nullptr, true);
-            if (st) return st;
+        if (upper) {
+            if (par) {
+                for (int k = 0; k < nup; ++k) HIP_TRY(hipStreamWaitEvent(stream, plan->join_ev[k], 0));
+            } else {
+                HIP_TRY(launch_sub_real(x, z, plan->d_v, plan->n_in, stream));
+                st = upper_passes(plan, plan->d_v, plan->d_Yv, stream, true, nullptr, true);
+                if (st) return st;
+            }
             HIP_TRY(launch_scale_levels(plan->d_Yv, num_den, gL, plan->m, N / 2,
                                         plan->batch * (plan->m - kRowsMaxLevel), stream, kRowsMaxLevel));
         }
