@@ -15,7 +15,7 @@ def _api():
     return api
 
 
-@pytest.mark.parametrize("m", [1, 2, 4, 5, 8, 12, 13, 15, 17])
+@pytest.mark.parametrize("m", [1, 2, 4, 5, 8, 12, 13, 15, 17, 18])
 @pytest.mark.parametrize("real", [False, True])
 def test_adjoint_vs_oracle(m, real):
     need_gpu()
@@ -204,3 +204,43 @@ def test_spectral_loss_fwd_graph_replay(m):
         torch.cuda.synchronize()
         assert torch.allclose(nd, nd0, rtol=1e-12, atol=0.0), r
         assert torch.allclose(L, L0, rtol=1e-6, atol=0.0), r
+
+
+@pytest.mark.parametrize("m", [13, 18])
+def test_spectral_loss_bwd_graph_replay(m):
+    """The loss backward captured into a HIP graph: at m = 18 the passes of
+    levels 17 and 18 and the heads of the adjoint's pass chains fork onto side
+    streams and join back inside the capture.  Every replay, with eager work
+    between, gives the eager gradient."""
+    need_gpu()
+    api = _api()
+    x, z = _loss_case(3, m, 950 + m)
+    log("loss backward graph m=%d" % m)
+    xd, zd = to_dev(x), to_dev(z)
+    plan = api.Plan(m=m, batch=3, dtype="r32")
+    nd = torch.empty(3, m, 2, dtype=torch.float64, device="cuda")
+    L = torch.empty(1, dtype=torch.float32, device="cuda")
+    gL = torch.full((1,), 0.75, dtype=torch.float32, device="cuda")
+    gx = torch.empty(3, 1 << m, dtype=torch.float32, device="cuda")
+    plan.mrdft_spectral_loss_fwd(xd, zd, nd, L)
+    plan.mrdft_spectral_loss_bwd(xd, zd, nd, gL, gx)        # eager
+    torch.cuda.synchronize()
+    g0 = gx.clone()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            plan.mrdft_spectral_loss_bwd(xd, zd, nd, gL, gx)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    junk = torch.zeros(1 << 20, device="cuda")
+    for r in range(3):
+        gx.fill_(-1.0)
+        junk.add_(float(r))                                  # eager work between the replays
+        g.replay()
+        torch.cuda.synchronize()
+        assert rel_l2(gx.cpu().numpy().astype(np.float64), g0.cpu().numpy().astype(np.float64)) <= 1e-6, r
+    # and the eager gradient itself against the oracle on one signal
+    ref = oracle.spectral_loss_grad(x[1], z[1], oracle.spectral_loss(x[1], z[1])[0], gL=0.75)
+    assert rel_l2(g0[1].cpu().numpy().astype(np.float64), ref) <= GRAD_TOL
