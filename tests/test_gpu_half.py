@@ -29,6 +29,8 @@ def _ragged_real(orders, seed):
     ([17, 12], 1, 28),                      # a pass level above 16
     ([16, 13, 17, 6], 3, 14),               # level range: tiles and pieces only
     ([17, 14], 13, 17),                     # level range: pieces and the pass level
+    ([18, 13], 1, 28),                      # two pass levels: one side stream per adjoint chain
+    ([18, 17, 12], 1, 28),                  # more pass chains than side streams: one stream
 ])
 def test_half_forward_and_adjoint_ragged(orders, lo, hi):
     need_gpu()
