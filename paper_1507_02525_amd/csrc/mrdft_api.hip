@@ -1198,17 +1198,27 @@ mrdft_status ensure_loss_workspace(mrdft_plan* p) {
     if (p->d_Yv) return MRDFT_OK;
     const int64_t rows = p->batch * p->m;
     const int64_t N = int64_t(1) << p->m;
+    // The fused path (one-launch real forward) keeps the level sums, the
+    // gradient factors, x - z and the packed half spectra of x - z; the
+    // generic path the full spectra of x - z and of z and per-chunk sums.
+    const bool fused = p->d_rjobs != nullptr;
     const int nch = loss_chunks(N);
-    if (hipMalloc(&p->d_sums, sizeof(double) * 2 * rows) != hipSuccess ||
-        hipMalloc(&p->d_alpha, sizeof(float) * rows) != hipSuccess ||
-        hipMalloc(&p->d_v, sizeof(float) * p->n_in) != hipSuccess ||
-        hipMalloc(&p->d_Yv, sizeof(float2) * p->n_out) != hipSuccess ||
-        hipMalloc(&p->d_Yz, sizeof(float2) * p->n_out) != hipSuccess ||
-        hipMalloc(&p->d_part, sizeof(double) * 2 * rows * nch) != hipSuccess) {
+    bool ok = hipMalloc(&p->d_sums, sizeof(double) * 2 * rows) == hipSuccess &&
+              hipMalloc(&p->d_alpha, sizeof(float) * rows) == hipSuccess &&
+              hipMalloc(&p->d_v, sizeof(float) * p->n_in) == hipSuccess &&
+              hipMalloc(&p->d_Yv, sizeof(float2) * (fused ? p->n_out / 2 : p->n_out)) == hipSuccess;
+    if (ok && !fused)
+        ok = hipMalloc(&p->d_Yz, sizeof(float2) * p->n_out) == hipSuccess &&
+             hipMalloc(&p->d_part, sizeof(double) * 2 * rows * nch) == hipSuccess;
+    if (!ok) {
+        dfree(p->d_sums);
+        dfree(p->d_alpha);
         dfree(p->d_v);
         dfree(p->d_Yv);
         dfree(p->d_Yz);
         dfree(p->d_part);
+        p->d_sums = nullptr;
+        p->d_alpha = nullptr;
         p->d_v = nullptr;
         p->d_Yv = p->d_Yz = nullptr;
         p->d_part = nullptr;
