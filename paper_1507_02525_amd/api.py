@@ -122,12 +122,28 @@ class Plan:
         B.check(B.lib().mrdft_adjoint(self.handle, _ptr(gY), _ptr(gx), _stream_ptr(gY)))
         return gx
 
+    def _check_buf(self, t: torch.Tensor, dtype, numel: int, what: str):
+        if t.dtype != dtype or t.device != self.device or not t.is_contiguous() or t.numel() != numel:
+            raise ValueError("%s must be a contiguous %s tensor of %d elements on %s" % (what, dtype, numel, self.device))
+
+    def _check_loss(self, x, z, num_den):
+        if self.dtype != "r32" or self.ragged:
+            raise ValueError("the spectral loss needs a uniform real (r32) plan")
+        self._check_in(x, "x")
+        self._check_in(z, "z")
+        self._check_buf(num_den, torch.float64, self.batch * self.m * 2, "num_den")
+
     def mrdft_spectral_loss_fwd(self, x, z, num_den, L):
+        self._check_loss(x, z, num_den)
+        self._check_buf(L, torch.float32, 1, "L")
         B.check(B.lib().mrdft_spectral_loss_fwd(self.handle, _ptr(x), _ptr(z), _ptr(num_den), _ptr(L),
                                                 _stream_ptr(x)))
         return num_den, L
 
     def mrdft_spectral_loss_bwd(self, x, z, num_den, gL, gx):
+        self._check_loss(x, z, num_den)
+        self._check_buf(gL, torch.float32, 1, "gL")
+        self._check_in(gx, "gx")
         B.check(B.lib().mrdft_spectral_loss_bwd(self.handle, _ptr(x), _ptr(z), _ptr(num_den), _ptr(gL), _ptr(gx),
                                                 _stream_ptr(x)))
         return gx
@@ -209,10 +225,12 @@ class Plan2D:
         return Y
 
     def mrdft_adjoint2d(self, gY: torch.Tensor, gx: torch.Tensor) -> torch.Tensor:
-        if gY.dtype != torch.complex64 or not gY.is_contiguous() or gY.numel() != self.n_out:
-            raise ValueError("gY must be a contiguous complex64 tensor of %d elements" % self.n_out)
-        if gx.dtype != self._want() or not gx.is_contiguous() or gx.numel() != self.n_in:
-            raise ValueError("gx must be a contiguous %s tensor of %d elements" % (self._want(), self.n_in))
+        if gY.dtype != torch.complex64 or not gY.is_contiguous() or gY.numel() != self.n_out \
+                or gY.device != self.device:
+            raise ValueError("gY must be a contiguous complex64 tensor of %d elements on %s" % (self.n_out, self.device))
+        if gx.dtype != self._want() or not gx.is_contiguous() or gx.numel() != self.n_in or gx.device != self.device:
+            raise ValueError("gx must be a contiguous %s tensor of %d elements on %s"
+                             % (self._want(), self.n_in, self.device))
         B.check(B.lib().mrdft_adjoint2d(self.handle, _ptr(gY), _ptr(gx), _stream_ptr(gY)))
         return gx
 
@@ -307,13 +325,21 @@ def mrdft(x: torch.Tensor) -> torch.Tensor:
     return MrDFT.apply(x)
 
 
+def _check_loss_inputs(x: torch.Tensor, z: torch.Tensor):
+    if x.dtype != torch.float32 or z.dtype != torch.float32:
+        raise TypeError("spectral_loss takes float32 x and z")
+    if x.shape != z.shape or x.dim() == 0:
+        raise ValueError("x and z must have one shape (..., N), got %s and %s" % (tuple(x.shape), tuple(z.shape)))
+    if not x.is_cuda or x.device != z.device:
+        raise ValueError("x and z must be on one GPU (there is no CPU path)")
+
+
 class SpectralLoss(torch.autograd.Function):
     """L = sum_b (1/m) sum_i ||Y^(i)(x_b) - Y^(i)(z_b)||^2 / ||Y^(i)(z_b)||^2 (z not differentiated)."""
 
     @staticmethod
     def forward(ctx, x, z):
-        if x.dtype != torch.float32 or z.dtype != torch.float32:
-            raise TypeError("spectral_loss takes float32 x and z")
+        _check_loss_inputs(x, z)
         m = _order_of(x.shape[-1])
         xb = x.reshape(-1, x.shape[-1]).contiguous()
         zb = z.reshape(-1, z.shape[-1]).contiguous()
@@ -340,6 +366,7 @@ def spectral_loss(x: torch.Tensor, z: torch.Tensor) -> torch.Tensor:
 
 def spectral_loss_terms(x: torch.Tensor, z: torch.Tensor):
     """(num_den (B, m, 2) float64, L) without autograd."""
+    _check_loss_inputs(x, z)
     m = _order_of(x.shape[-1])
     xb = x.reshape(-1, x.shape[-1]).contiguous()
     zb = z.reshape(-1, z.shape[-1]).contiguous()

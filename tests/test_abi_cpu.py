@@ -142,3 +142,21 @@ def test_2d_bogus_handles():
     assert lib.mrdft_adjoint2d(bogus, None, None, None) == b.MRDFT_E_INVALID_ARG
     assert lib.mrdft_plan2d_destroy(bogus) == b.MRDFT_E_INVALID_ARG
     assert lib.mrdft_plan2d_destroy(None) == b.MRDFT_OK
+
+
+def test_spectral_loss_rejects_bad_inputs_before_any_call():
+    """Shapes, dtypes and devices are checked in Python before the library is
+    reached, so a short z can never be read past its end."""
+    import torch
+    from paper_1507_02525_amd import api
+    x = torch.zeros(2, 64)
+    with pytest.raises(ValueError):
+        api.spectral_loss(x, torch.zeros(2, 32))                 # z shorter than x
+    with pytest.raises(ValueError):
+        api.spectral_loss(x, torch.zeros(3, 64))                 # batch mismatch
+    with pytest.raises(ValueError):
+        api.spectral_loss(x, torch.zeros(2, 64))                 # CPU tensors: no CPU path
+    with pytest.raises(TypeError):
+        api.spectral_loss(x.double(), torch.zeros(2, 64, dtype=torch.float64))
+    with pytest.raises(ValueError):
+        api.spectral_loss_terms(x, torch.zeros(2, 32))

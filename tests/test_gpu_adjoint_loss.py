@@ -244,3 +244,33 @@ def test_spectral_loss_bwd_graph_replay(m):
     # and the eager gradient itself against the oracle on one signal
     ref = oracle.spectral_loss_grad(x[1], z[1], oracle.spectral_loss(x[1], z[1])[0], gL=0.75)
     assert rel_l2(g0[1].cpu().numpy().astype(np.float64), ref) <= GRAD_TOL
+
+
+def test_loss_entry_points_check_buffers():
+    """The plan's loss calls reject buffers of the wrong size, dtype or plan
+    kind before the library is called; a valid call after them still works."""
+    need_gpu()
+    api = _api()
+    m, b = 12, 2
+    x, z = _loss_case(b, m, 77)
+    xd, zd = to_dev(x), to_dev(z)
+    plan = api.Plan(m=m, batch=b, dtype="r32")
+    nd = torch.empty(b, m, 2, dtype=torch.float64, device="cuda")
+    L = torch.empty(1, dtype=torch.float32, device="cuda")
+    gL = torch.ones(1, dtype=torch.float32, device="cuda")
+    gx = torch.empty(b, 1 << m, dtype=torch.float32, device="cuda")
+    with pytest.raises(ValueError):
+        plan.mrdft_spectral_loss_fwd(xd, zd[:1], nd, L)                    # z of one signal
+    with pytest.raises(ValueError):
+        plan.mrdft_spectral_loss_fwd(xd, zd, nd[:1], L)                    # num_den too short
+    with pytest.raises(ValueError):
+        plan.mrdft_spectral_loss_fwd(xd, zd, nd.float(), L)                # num_den not float64
+    with pytest.raises(ValueError):
+        plan.mrdft_spectral_loss_bwd(xd, zd, nd, gL, gx[:1])               # gx too short
+    with pytest.raises(ValueError):
+        api.Plan(m=m, batch=b, dtype="c64").mrdft_spectral_loss_fwd(xd, zd, nd, L)
+    plan.mrdft_spectral_loss_fwd(xd, zd, nd, L)
+    plan.mrdft_spectral_loss_bwd(xd, zd, nd, gL, gx)
+    torch.cuda.synchronize()
+    ref = oracle.spectral_loss_grad(x[1], z[1], oracle.spectral_loss(x[1], z[1])[0])
+    assert rel_l2(gx[1].cpu().numpy().astype(np.float64), ref) <= GRAD_TOL
