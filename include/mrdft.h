@@ -222,7 +222,9 @@ mrdft_status mrdft_spectral_loss_bwd(mrdft_plan_t plan, const float* x, const fl
 mrdft_status mrdft_plan_set_profiling(mrdft_plan_t plan, int enable);
 mrdft_status mrdft_plan_read_profile(mrdft_plan_t plan, int nkinds, double* total_ms, int64_t* launches);
 
-/* Destroy a plan (NULL is accepted).  The handle must not be used afterwards. */
+/* Destroy a plan (NULL is accepted).  The handle must not be used afterwards.
+ * Freeing the plan's device memory waits for the device, so work of the plan
+ * still queued on any stream completes first. */
 mrdft_status mrdft_plan_destroy(mrdft_plan_t plan);
 
 /*
