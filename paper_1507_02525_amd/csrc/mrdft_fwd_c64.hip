@@ -122,6 +122,9 @@ __global__ __launch_bounds__(kCThreads, 4) void fwd_c64_direct(const void* __res
     __shared__ FwdC64Lds S;
     const int tid = threadIdx.x;
     const RealJob jb = jobs[blockIdx.x];
+    // tile waves (single- and multi-signal) issue ahead of piece waves: they
+    // carry most of the stores (as in the real one-launch forward)
+    if (jb.lg == 0 || jb.lg >= kMultiTileLg) __builtin_amdgcn_s_setprio(1);
     float2* yj = Y + jb.out_off;
     if constexpr (REALIN) {
         const float* xj = (const float*)x + jb.in_off;
