@@ -536,9 +536,11 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
 //   rows first  : the pieces (highest level first), then the tiles;
 //   interleaved : tiles and pieces alternate in proportion;
 //   blocks      : every block of 2^16 samples (or the whole signal if shorter)
-//                 goes whole to one bucket, its tiles and the pieces of the
-//                 windows inside it alternating: the block's samples are read
-//                 from HBM about once and then served by the XCD's L2.
+//                 goes whole to one bucket, the pieces of the windows inside
+//                 it before its tiles (real input) or after them (complex
+//                 input; the faster of the two in-block orders for each, with
+//                 tile waves at raised priority): the block's samples are
+//                 read from HBM about once and then served by the XCD's L2.
 struct JobBuckets {
     static constexpr int kX = 8;
     std::vector<std::vector<RealJob>> tiles = std::vector<std::vector<RealJob>>(kX);
@@ -570,9 +572,14 @@ struct JobBuckets {
         }
     }
     std::vector<std::vector<RealJob>> blocks = std::vector<std::vector<RealJob>>(kX);
-    void add_block(const std::vector<RealJob>& t, const std::vector<RealJob>& r, int64_t cost) {
+    // a block's tiles t and pieces r, the pieces first or the tiles first
+    void add_block(const std::vector<RealJob>& t, const std::vector<RealJob>& r, int64_t cost,
+                   bool pieces_first = false) {
         const int b = lightest();
-        alternate(blocks[b], t, r);
+        const std::vector<RealJob>& a = pieces_first ? r : t;
+        const std::vector<RealJob>& c = pieces_first ? t : r;
+        blocks[b].insert(blocks[b].end(), a.begin(), a.end());
+        blocks[b].insert(blocks[b].end(), c.begin(), c.end());
         load[b] += cost;
     }
     // contiguous: the buckets one after the other, their starts in seg[0..8]
@@ -649,7 +656,7 @@ std::vector<RealJob> real_jobs(const mrdft_plan* p, int order) {
                             jb1.g = g;
                             r.push_back(jb1);
                         }
-                jb.add_block(t, r, kTileCost * (int64_t)t.size() + (int64_t)r.size());
+                jb.add_block(t, r, kTileCost * (int64_t)t.size() + (int64_t)r.size(), true);
             }
             continue;
         }
