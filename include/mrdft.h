@@ -187,8 +187,9 @@ mrdft_status mrdft_adjoint(mrdft_plan_t plan, const void* gY, void* gx, hipStrea
  * den_i = 0 (z = 0 on a whole signal) gives an infinite or NaN loss.
  * The first call of either loss entry point on a plan allocates the plan's
  * loss workspace (device memory: x - z and, for N >= 2^12, the packed half
- * spectra of x - z, about 4 m N bytes per signal; for smaller N both full
- * spectra); make that first call outside any stream capture.
+ * spectra of x - z, about 4 m N bytes per signal, and the loss launches' job
+ * table; for smaller N both full spectra); make that first call outside any
+ * stream capture.
  */
 mrdft_status mrdft_spectral_loss_fwd(mrdft_plan_t plan, const float* x, const float* z, double* num_den,
                                      float* L, hipStream_t stream);

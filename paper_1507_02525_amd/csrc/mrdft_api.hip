@@ -113,6 +113,8 @@ struct mrdft_plan {
     // real input: tiles of 4096 samples and rows pieces of levels 13..16, one launch
     RealJob* d_rjobs = nullptr;
     int64_t nrjobs = 0;
+    RealJob* d_ljobs = nullptr;             // the fused loss's own table of the same jobs
+    int64_t nljobs = 0;
     RealJob* d_sjobs = nullptr;             // real full-spectrum plans: signals below 4096 samples
     int64_t nsjobs = 0;                     // (complex-launch tiles reading real input)
     // complex input: tiles of 2048 samples (several signals of order < 11 per
@@ -204,6 +206,7 @@ void free_plan(mrdft_plan* p) {
     dfree(p->d_tw_comb);
     dfree(p->d_tw_ccomb);
     dfree(p->d_rjobs);
+    dfree(p->d_ljobs);
     dfree(p->d_sjobs);
     dfree(p->d_cjobs);
     dfree(p->d_queue);
@@ -326,7 +329,10 @@ mrdft_status upload_twiddles(mrdft_plan* p, hipStream_t s) {
     return MRDFT_OK;
 }
 
-std::vector<RealJob> real_jobs(const mrdft_plan* p, int order);
+// Order of a block's jobs in the block-major order: tiles and pieces
+// alternating in proportion, all pieces first, or all tiles first.
+enum class InBlock { kAlternate, kPiecesFirst, kTilesFirst };
+std::vector<RealJob> real_jobs(const mrdft_plan* p, int order, InBlock in = InBlock::kPiecesFirst);
 std::vector<RealJob> complex_jobs(const mrdft_plan* p, int order, std::vector<unsigned>* seg);
 std::vector<RealJob> small_real_jobs(const mrdft_plan* p);
 mrdft_status upload_cjobs(mrdft_plan* p, int order, hipStream_t s, bool direct);
@@ -536,11 +542,13 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
 //   rows first  : the pieces (highest level first), then the tiles;
 //   interleaved : tiles and pieces alternate in proportion;
 //   blocks      : every block of 2^16 samples (or the whole signal if shorter)
-//                 goes whole to one bucket, the pieces of the windows inside
-//                 it before its tiles (real input) or after them (complex
-//                 input; the faster of the two in-block orders for each, with
-//                 tile waves at raised priority): the block's samples are
-//                 read from HBM about once and then served by the XCD's L2.
+//                 goes whole to one bucket: the block's samples are read from
+//                 HBM about once and then served by the XCD's L2.  Inside a
+//                 block the pieces of its windows come before its tiles in
+//                 the real forward and after them in the complex forward; the
+//                 fused loss's norm and scaled launches alternate the two
+//                 (for each the fastest of the three, with tile waves at
+//                 raised priority).
 struct JobBuckets {
     static constexpr int kX = 8;
     std::vector<std::vector<RealJob>> tiles = std::vector<std::vector<RealJob>>(kX);
@@ -572,14 +580,18 @@ struct JobBuckets {
         }
     }
     std::vector<std::vector<RealJob>> blocks = std::vector<std::vector<RealJob>>(kX);
-    // a block's tiles t and pieces r, the pieces first or the tiles first
+    // a block's tiles t and pieces r to the lightest bucket, in the order `in`
     void add_block(const std::vector<RealJob>& t, const std::vector<RealJob>& r, int64_t cost,
-                   bool pieces_first = false) {
+                   InBlock in = InBlock::kTilesFirst) {
         const int b = lightest();
-        const std::vector<RealJob>& a = pieces_first ? r : t;
-        const std::vector<RealJob>& c = pieces_first ? t : r;
-        blocks[b].insert(blocks[b].end(), a.begin(), a.end());
-        blocks[b].insert(blocks[b].end(), c.begin(), c.end());
+        if (in == InBlock::kAlternate) {
+            alternate(blocks[b], t, r);
+        } else {
+            const std::vector<RealJob>& a = in == InBlock::kPiecesFirst ? r : t;
+            const std::vector<RealJob>& c = in == InBlock::kPiecesFirst ? t : r;
+            blocks[b].insert(blocks[b].end(), a.begin(), a.end());
+            blocks[b].insert(blocks[b].end(), c.begin(), c.end());
+        }
         load[b] += cost;
     }
     // contiguous: the buckets one after the other, their starts in seg[0..8]
@@ -627,7 +639,7 @@ struct JobBuckets {
 
 // Real signals of order >= 12: 4096-sample tiles and pieces of levels 13..16
 // (2^(lg-13) pieces per window).
-std::vector<RealJob> real_jobs(const mrdft_plan* p, int order) {
+std::vector<RealJob> real_jobs(const mrdft_plan* p, int order, InBlock in) {
     JobBuckets jb;
     constexpr int64_t kTileCost = 6;                           // 12 x 32 KB against 64 KB per piece
     for (int64_t j = 0; j < p->batch; ++j) {
@@ -656,7 +668,7 @@ std::vector<RealJob> real_jobs(const mrdft_plan* p, int order) {
                             jb1.g = g;
                             r.push_back(jb1);
                         }
-                jb.add_block(t, r, kTileCost * (int64_t)t.size() + (int64_t)r.size(), true);
+                jb.add_block(t, r, kTileCost * (int64_t)t.size() + (int64_t)r.size(), in);
             }
             continue;
         }
@@ -1201,14 +1213,20 @@ mrdft_status check_plan(mrdft_plan_t plan) {
     return MRDFT_OK;
 }
 
-mrdft_status ensure_loss_workspace(mrdft_plan* p) {
+mrdft_status ensure_loss_workspace(mrdft_plan* p, hipStream_t s) {
+    // The fused path (one-launch real forward) keeps its own job table (the
+    // forward's jobs, block-major with tiles and pieces alternating inside a
+    // block: the faster order for its norm and scaled launches), the level
+    // sums, the gradient factors, x - z and the packed half spectra of x - z;
+    // the generic path the full spectra of x - z and of z and per-chunk sums.
+    const bool fused = p->d_rjobs != nullptr;
+    if (fused && !p->d_ljobs) {
+        mrdft_status st = upload_jobs(real_jobs(p, MRDFT_ORDER_BLOCKS, InBlock::kAlternate), &p->d_ljobs, &p->nljobs, s);
+        if (st) return st;
+    }
     if (p->d_Yv) return MRDFT_OK;
     const int64_t rows = p->batch * p->m;
     const int64_t N = int64_t(1) << p->m;
-    // The fused path (one-launch real forward) keeps the level sums, the
-    // gradient factors, x - z and the packed half spectra of x - z; the
-    // generic path the full spectra of x - z and of z and per-chunk sums.
-    const bool fused = p->d_rjobs != nullptr;
     const int nch = loss_chunks(N);
     bool ok = hipMalloc(&p->d_sums, sizeof(double) * 2 * rows) == hipSuccess &&
               hipMalloc(&p->d_alpha, sizeof(float) * rows) == hipSuccess &&
@@ -1433,7 +1451,7 @@ mrdft_status mrdft_spectral_loss_fwd(mrdft_plan_t plan, const float* x, const fl
     if (!x || !z || !num_den || !L) return fail(MRDFT_E_INVALID_ARG, "x, z, num_den and L must be non-NULL");
     if (misaligned(x, 16) || misaligned(z, 16) || misaligned(num_den, 8) || misaligned(L, 4))
         return fail(MRDFT_E_INVALID_ARG, "x or z is not 16-byte aligned");
-    st = ensure_loss_workspace(plan);
+    st = ensure_loss_workspace(plan, stream);
     if (st) return st;
     const int64_t N = int64_t(1) << plan->m;
     const int64_t rows = plan->batch * plan->m;
@@ -1462,11 +1480,11 @@ mrdft_status mrdft_spectral_loss_fwd(mrdft_plan_t plan, const float* x, const fl
         }
         {
             ProfScope ps(plan, MRDFT_KERNEL_LOSS, stream);
-            HIP_TRY(launch_fwd_real_norms(x, z, snum, plan->m, plan->d_rjobs, plan->nrjobs, tw, stream));
+            HIP_TRY(launch_fwd_real_norms(x, z, snum, plan->m, plan->d_ljobs, plan->nljobs, tw, stream));
         }
         {
             ProfScope ps(plan, MRDFT_KERNEL_LOSS, s2);
-            HIP_TRY(launch_fwd_real_norms(z, nullptr, sden, plan->m, plan->d_rjobs, plan->nrjobs, tw, s2));
+            HIP_TRY(launch_fwd_real_norms(z, nullptr, sden, plan->m, plan->d_ljobs, plan->nljobs, tw, s2));
         }
         if (upper) {
             HIP_TRY(launch_sub_real(x, z, plan->d_v, plan->n_in, stream));
@@ -1507,7 +1525,7 @@ mrdft_status mrdft_spectral_loss_bwd(mrdft_plan_t plan, const float* x, const fl
     if (!x || !z || !num_den || !gL || !gx) return fail(MRDFT_E_INVALID_ARG, "null pointer argument");
     if (misaligned(x, 16) || misaligned(z, 16) || misaligned(gx, 16))
         return fail(MRDFT_E_INVALID_ARG, "x, z or gx is not 16-byte aligned");
-    st = ensure_loss_workspace(plan);
+    st = ensure_loss_workspace(plan, stream);
     if (st) return st;
     const int64_t N = int64_t(1) << plan->m;
     const int64_t rows = plan->batch * plan->m;
@@ -1539,7 +1557,7 @@ mrdft_status mrdft_spectral_loss_bwd(mrdft_plan_t plan, const float* x, const fl
         HIP_TRY(launch_loss_alpha(num_den, gL, plan->d_alpha, rows, plan->m, stream));
         {
             ProfScope ps(plan, MRDFT_KERNEL_LOSS, stream);
-            HIP_TRY(launch_fwd_real_scaled(x, z, plan->d_alpha, plan->m, plan->d_Yv, plan->d_rjobs, plan->nrjobs,
+            HIP_TRY(launch_fwd_real_scaled(x, z, plan->d_alpha, plan->m, plan->d_Yv, plan->d_ljobs, plan->nljobs,
                                            plan->tw(), stream, true));
         }
         if (upper) {
