@@ -661,13 +661,17 @@ std::vector<RealJob> real_jobs(const mrdft_plan* p, int order, InBlock in) {
             for (int64_t u0 = 0; u0 < N; u0 += U) {
                 std::vector<RealJob> t, r;
                 for (int64_t tau = u0 >> kRealTileLog; tiles && tau < (u0 + U) >> kRealTileLog; ++tau) t.push_back(tile(tau));
-                for (int lg = phi; lg >= plo; --lg)            // highest level first
+                // pieces from the highest level down (full spectra) or from
+                // the lowest up (half spectra): the faster order for each
+                for (int q = 0; q <= phi - plo; ++q) {
+                    const int lg = p->hs ? plo + q : phi - q;
                     for (int64_t w = u0 >> lg; w < (u0 + U) >> lg; ++w)
                         for (int g = 0; g < (1 << (lg - kRowsMinLevel)); ++g) {
                             RealJob jb1 = window(lg, w);
                             jb1.g = g;
                             r.push_back(jb1);
                         }
+                }
                 jb.add_block(t, r, kTileCost * (int64_t)t.size() + (int64_t)r.size(), in);
             }
             continue;
