@@ -51,7 +51,8 @@ __global__ __launch_bounds__(kRThreads, 4) void fwd_real_kernel(const float* __r
     // Tile waves issue ahead of piece waves on a SIMD: the tiles carry most of
     // the launch's stores, and keeping that stream steady while the pieces'
     // arithmetic takes the remaining issue slots shortens the mixed launch.
-    if (jb.lg == 0) __builtin_amdgcn_s_setprio(1);
+    // The norm mode stores nothing and keeps one priority.
+    if (MODE != kModeNorms && jb.lg == 0) __builtin_amdgcn_s_setprio(1);
     const int tid = threadIdx.x;
     const float* xj = x + jb.in_off;
     const float* zj = (MODE != kModeStore && xsub) ? xsub + jb.in_off : nullptr;
