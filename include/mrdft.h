@@ -64,9 +64,22 @@ typedef enum {
 
 /* Plan flags */
 #define MRDFT_FLAG_NONE 0u
-/* Time the candidate schedules (tile depth, job order, persistent grid) on
+/* Time the candidate schedules (tile depth, job order, persistent grid, and
+ * for the winner whether the levels above the tile run on side streams) on
  * scratch buffers at plan creation and keep the fastest; without it the
- * defaults are used.  Costs a few forward calls at creation. */
+ * defaults are used.  Costs a few forward calls at creation.
+ *
+ * Environment, read at plan creation:
+ *   MRDFT_TUNE=0|1        overrides MRDFT_FLAG_TUNE (off / on).
+ *   MRDFT_TUNE_CACHE=path a tuning cache file (include/mrdft_tune.h): a
+ *                         tuned plan whose key is in the file takes the stored
+ *                         schedule without timing; otherwise the result of
+ *                         timing is stored.  A corrupt file is ignored.
+ *   MRDFT_TILE_T=11|12    pins the tile depth after tuning (12 only for
+ *                         real plans).
+ *   MRDFT_GRAPH=0|1       overrides MRDFT_FLAG_GRAPH.
+ *   MRDFT_SERIAL=1        no side streams at all.
+ * A malformed value makes plan creation fail with MRDFT_E_INVALID_ARG. */
 #define MRDFT_FLAG_TUNE 1u
 /* Capture mrdft_forward into a HIP graph on first use for a given (x, Y) pair
  * and replay it afterwards (one graph launch per call); a call with other
@@ -126,10 +139,17 @@ mrdft_status mrdft_plan_create_levels(mrdft_plan_t* plan, int m, int64_t batch, 
 /*
  * Output offsets of a plan, in complex elements: host int64[batch+1],
  * out[j] = O_j (start of signal j's levels in Y), out[batch] = total outputs.
+ * Section 2 stacks the m levels of one signal into one mN-vector (eq. (1));
+ * these offsets place the stacked vector of every signal of a batch.
+ *   out : host memory of batch+1 int64, written.
+ * Errors: MRDFT_E_INVALID_ARG for a handle that is not live or out = NULL.
  */
 mrdft_status mrdft_plan_output_offsets(mrdft_plan_t plan, int64_t* out);
 
-/* Total number of input samples and of complex outputs of the plan. */
+/* Total number of input samples (the N of Section 2 summed over the batch)
+ * and of complex outputs (the mN of eq. (1), summed; shrunk by level ranges
+ * and half-spectrum output) of the plan, written to host int64s.
+ * Errors: MRDFT_E_INVALID_ARG for a handle that is not live or a NULL pointer. */
 mrdft_status mrdft_plan_sizes(mrdft_plan_t plan, int64_t* n_in, int64_t* n_out);
 
 /*
@@ -147,6 +167,9 @@ mrdft_status mrdft_plan_sizes(mrdft_plan_t plan, int64_t* n_in, int64_t* n_out);
 #define MRDFT_ORDER_ROWS_FIRST 1  /* upper-level pieces (highest level first), then tiles */
 #define MRDFT_ORDER_INTERLEAVED 2 /* tiles and pieces alternate in proportion */
 #define MRDFT_ORDER_BLOCKS 3      /* per block of 2^16 samples: its tiles and the pieces inside it, together */
+/* OR-ed into `order`: every forward launch on the caller's stream (the levels
+ * above the tile do not run on the plan's side streams). */
+#define MRDFT_SCHED_SERIAL 0x100
 mrdft_status mrdft_plan_schedule(mrdft_plan_t plan, int* tile_log, int* grid, int* order);
 
 /*
@@ -154,7 +177,8 @@ mrdft_status mrdft_plan_schedule(mrdft_plan_t plan, int* tile_log, int* grid, in
  * of tuning again.  tile_log: 11 or 12 for complex plans, 12 for real plans;
  * grid: workgroups of the persistent complex launch (>= 1; 0: one workgroup
  * per job; ignored for real plans and tile_log 12);
- * order: MRDFT_ORDER_*.  Drops a captured forward graph.  Synchronises
+ * order: MRDFT_ORDER_*, optionally OR MRDFT_SCHED_SERIAL.  Drops a captured
+ * forward graph.  Synchronises
  * `stream` (the job table is re-uploaded).
  * Errors: MRDFT_E_INVALID_ARG for values outside these sets.
  */
@@ -178,7 +202,12 @@ mrdft_status mrdft_forward(mrdft_plan_t plan, const void* x, void* Y, hipStream_
 mrdft_status mrdft_adjoint(mrdft_plan_t plan, const void* gY, void* gx, hipStream_t stream);
 
 /*
- * Multi-resolution spectral loss, uniform real (MRDFT_R32) plans only:
+ * Multi-resolution spectral loss.  NOT part of the paper: a training loss
+ * built on the level spectra of eq. (1) (Section 2); the paper defines the
+ * transform only.  Readings this library takes: the batch loss is the SUM of
+ * the per-signal losses (so a signal's gradient does not depend on the batch
+ * size), and z is a constant (not differentiated).
+ * Uniform real (MRDFT_R32) plans only:
  *   num_i = || Y^(i)(x) - Y^(i)(z) ||^2,  den_i = || Y^(i)(z) ||^2,
  *   L_b = (1/m) sum_i num_i / den_i,  L = sum_b L_b.
  *   x, z    : device float32 [batch][N].
@@ -195,7 +224,8 @@ mrdft_status mrdft_spectral_loss_fwd(mrdft_plan_t plan, const float* x, const fl
                                      float* L, hipStream_t stream);
 
 /*
- * Gradient of the spectral loss with respect to x, scaled by *gL:
+ * Gradient of the spectral loss with respect to x (NOT part of the paper: the
+ * adjoint of eq. (1) applied to the loss's level gradients), scaled by *gL:
  *   gx = Re( sum_i A_i^H [ gL * 2 (Y^(i)(x) - Y^(i)(z)) / (m * den_i) ] ),
  * with A_i^H the level-i adjoint above.  The level spectra are recomputed from
  * x and z (nothing of the forward is stored).
@@ -223,9 +253,12 @@ mrdft_status mrdft_spectral_loss_bwd(mrdft_plan_t plan, const float* x, const fl
 mrdft_status mrdft_plan_set_profiling(mrdft_plan_t plan, int enable);
 mrdft_status mrdft_plan_read_profile(mrdft_plan_t plan, int nkinds, double* total_ms, int64_t* launches);
 
-/* Destroy a plan (NULL is accepted).  The handle must not be used afterwards.
+/* Destroy a plan (NULL is accepted): releases what mrdft_plan_create
+ * allocated for the transform of Section 2 (twiddle tables, job tables,
+ * workspace, captured graph).  The handle must not be used afterwards.
  * Freeing the plan's device memory waits for the device, so work of the plan
- * still queued on any stream completes first. */
+ * still queued on any stream completes first.
+ * Errors: MRDFT_E_INVALID_ARG for a handle that is not live (destroyed twice). */
 mrdft_status mrdft_plan_destroy(mrdft_plan_t plan);
 
 /*
@@ -267,7 +300,18 @@ mrdft_status mrdft_forward2d(mrdft_plan2d_t plan, const void* x, void* Y, hipStr
 mrdft_status mrdft_adjoint2d(mrdft_plan2d_t plan, const void* gY, void* gx, hipStream_t stream);
 mrdft_status mrdft_plan2d_destroy(mrdft_plan2d_t plan);    /* NULL is accepted */
 
-/* Thread-local message of the last failing call on this thread ("" if none). */
+/* Number of device allocations the library currently holds, over all plans
+ * of the process (diagnostics: a plan whose creation fails holds none, and
+ * destroying every plan brings the count back).  The library's error paths
+ * can be exercised by setting MRDFT_FAIL_ALLOC_AT=k in the environment: the
+ * k-th device allocation of each subsequent plan creation (or first loss
+ * call) then fails with MRDFT_E_ALLOC. */
+int64_t mrdft_live_device_allocations(void);
+
+/* Thread-local message of the last failing call on this thread ("" if none).
+ * Error reporting of the library itself (the paper defines no interface);
+ * the string is owned by the library and valid until the thread's next
+ * failing call. */
 const char* mrdft_last_error(void);
 
 #ifdef __cplusplus

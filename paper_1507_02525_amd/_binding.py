@@ -1,4 +1,5 @@
-"""ctypes binding of the C ABI in include/mrdft.h (argument marshalling only).
+"""ctypes binding of the C ABI in include/mrdft.h and include/mrdft_tune.h
+(argument marshalling only).
 
 Every computation runs in the HIP library ``libmrdft.so``; there is no CPU or
 PyTorch fallback.  If the library is missing or cannot be loaded, importing a
@@ -25,6 +26,7 @@ MRDFT_FLAG_TUNE = 1
 MRDFT_FLAG_GRAPH = 2
 MRDFT_FLAG_HALF = 4
 ORDERS = ("tiles_first", "rows_first", "interleaved", "blocks")
+MRDFT_SCHED_SERIAL = 0x100
 KERNEL_KINDS = ("tile_fwd", "pass_fwd", "tile_adj", "pass_adj", "fused_fwd", "loss")
 
 # Every symbol the header declares, with (restype, argtypes).
@@ -54,6 +56,12 @@ SIGNATURES = {
     "mrdft_adjoint2d": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "mrdft_plan2d_destroy": (ctypes.c_int, [_vp]),
     "mrdft_last_error": (ctypes.c_char_p, []),
+    "mrdft_live_device_allocations": (ctypes.c_int64, []),
+    "mrdft_tune_cache_lookup": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int),
+                                               ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                               ctypes.POINTER(ctypes.c_int)]),
+    "mrdft_tune_cache_store": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_char_p, ctypes.c_int, ctypes.c_int,
+                                              ctypes.c_int, ctypes.c_int]),
 }
 
 _lib = None

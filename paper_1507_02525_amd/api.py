@@ -13,6 +13,7 @@ with thin tensor helpers on top:
 """
 from __future__ import annotations
 
+import collections
 import ctypes
 import threading
 
@@ -79,17 +80,18 @@ class Plan:
 
     # -- C ABI mirrors -------------------------------------------------------
     def schedule(self) -> dict:
-        """Forward schedule chosen at creation: tile_log, grid, order."""
+        """Forward schedule chosen at creation: tile_log, grid, order, serial."""
         t, g, o = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         B.check(B.lib().mrdft_plan_schedule(self.handle, ctypes.byref(t), ctypes.byref(g), ctypes.byref(o)))
-        return {"tile_log": t.value, "grid": g.value, "order": B.ORDERS[o.value]}
+        return {"tile_log": t.value, "grid": g.value, "order": B.ORDERS[o.value & 0xff],
+                "serial": bool(o.value & B.MRDFT_SCHED_SERIAL)}
 
-    def set_schedule(self, tile_log: int, grid: int, order: str):
+    def set_schedule(self, tile_log: int, grid: int, order: str, serial: bool = False):
         """Pin the forward schedule (values as returned by schedule())."""
+        code = B.ORDERS.index(order) | (B.MRDFT_SCHED_SERIAL if serial else 0)
         with torch.cuda.device(self.device):
             stream = ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
-            B.check(B.lib().mrdft_plan_set_schedule(self.handle, int(tile_log), int(grid), B.ORDERS.index(order),
-                                                    stream))
+            B.check(B.lib().mrdft_plan_set_schedule(self.handle, int(tile_log), int(grid), code, stream))
 
     def output_offsets(self) -> np.ndarray:
         out = np.empty(self.batch + 1, dtype=np.int64)
@@ -256,18 +258,37 @@ class Plan2D:
             pass
 
 
-_cache: dict = {}
+# Plans of the tensor helpers, least recently used first.  A plan's workspace
+# (pass scratch, adjoint scratch, loss buffers) is single, so two calls on one
+# plan must not overlap: the key holds the stream the call is queued on (calls
+# on one stream run in order) and the calling thread (a plan's host state is
+# not shared between threads).  At most CACHE_SIZE plans are kept; an evicted
+# plan is destroyed when its last user (e.g. an autograd context) drops it,
+# and destruction waits for its queued work.
+CACHE_SIZE = 8
+_cache: "collections.OrderedDict" = collections.OrderedDict()
 _cache_lock = threading.Lock()
 
 
 def get_plan(m: int, batch: int, dtype: str, device) -> Plan:
-    key = (int(m), int(batch), dtype, str(device))
+    device = torch.device(device)
+    stream = torch.cuda.current_stream(device).cuda_stream
+    key = (int(m), int(batch), dtype, str(device), int(stream), threading.get_ident())
     with _cache_lock:
         p = _cache.get(key)
         if p is None:
             p = Plan(m=m, batch=batch, dtype=dtype, device=device)
             _cache[key] = p
+        _cache.move_to_end(key)
+        while len(_cache) > CACHE_SIZE:
+            _cache.popitem(last=False)
         return p
+
+
+def clear_plan_cache():
+    """Drop every cached plan (each is destroyed once no caller holds it)."""
+    with _cache_lock:
+        _cache.clear()
 
 
 def _order_of(n: int) -> int:

@@ -1,6 +1,7 @@
 """Build libmrdft.so (HIP, gfx950) in-tree with hipcc.
 
-Every .hip source under csrc/ is compiled for gfx950 and linked into
+Every .hip source under csrc/ is compiled for gfx950 (and every host-only
+.cpp source with the host compiler) and linked into
 paper_1507_02525_amd/libmrdft.so.  Packed-FP32 instruction selection is turned
 off (it has produced silent wrong results on this hardware class).
 """
@@ -27,9 +28,16 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
           "-Wall", "-Wno-unused-function"]
 
 
+HOSTCXX = shutil.which("g++") or "g++"
+HOST_COMMON = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-I" + os.path.join(ROOT, "include")]
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *COMMON, "-c", src, "-o", obj]
+    if src.endswith(".cpp"):          # host-only sources (no device code)
+        cmd = [HOSTCXX, *HOST_COMMON, "-c", src, "-o", obj]
+    else:
+        cmd = [HIPCC, *COMMON, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
@@ -44,7 +52,7 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD_DIR, exist_ok=True)
-    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp%d" % os.getpid()

@@ -106,9 +106,9 @@ void free2d(mrdft_plan2d* p) {
     if (!p) return;
     if (p->cols) mrdft_plan_destroy(p->cols);
     if (p->rows) mrdft_plan_destroy(p->rows);
-    if (p->xt) (void)hipFree(p->xt);
-    if (p->c) (void)hipFree(p->c);
-    if (p->d) (void)hipFree(p->d);
+    dev_free(p->xt);
+    dev_free(p->c);
+    dev_free(p->d);
     delete p;
 }
 
@@ -154,6 +154,7 @@ mrdft_status mrdft_plan2d_create(mrdft_plan2d_t* plan, int m1, int m2, int64_t b
     if (batch > (int64_t(1) << 46) / (N1 * N2 * m1 * m2))
         return fail2(MRDFT_E_INVALID_ARG, "2-D transform of %lld images of 2^%d x 2^%d is too large",
                      (long long)batch, m1, m2);
+    AllocScope alloc_scope;
     mrdft_plan2d* p = new (std::nothrow) mrdft_plan2d();
     if (!p) return fail2(MRDFT_E_ALLOC, "host allocation failed");
     p->m1 = m1;
@@ -172,8 +173,8 @@ mrdft_status mrdft_plan2d_create(mrdft_plan2d_t* plan, int m1, int m2, int64_t b
     }
     const size_t esz = dtype == MRDFT_R32 ? sizeof(float) : sizeof(float2);
     const size_t cbytes = sizeof(float2) * (size_t)(p->n_in * m1);
-    if (hipMalloc(&p->xt, esz * (size_t)p->n_in) != hipSuccess || hipMalloc(&p->c, cbytes) != hipSuccess ||
-        hipMalloc(&p->d, cbytes) != hipSuccess) {
+    if (dev_malloc(&p->xt, esz * (size_t)p->n_in) != hipSuccess || dev_malloc(&p->c, cbytes) != hipSuccess ||
+        dev_malloc(&p->d, cbytes) != hipSuccess) {
         free2d(p);
         return fail2(MRDFT_E_ALLOC, "2-D workspace allocation failed (%zu bytes)", esz * (size_t)p->n_in + 2 * cbytes);
     }

@@ -1,6 +1,7 @@
 // Host side of the C ABI declared in include/mrdft.h: plan creation and
 // validation, FP64 twiddle generation, tile tables, launch sequencing.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -13,6 +14,7 @@
 #include <vector>
 
 #include "../../include/mrdft.h"
+#include "../../include/mrdft_tune.h"
 #include "mrdft_device.h"
 #include "mrdft_internal.h"
 #include "mrdft_loss.h"
@@ -163,6 +165,7 @@ struct mrdft_plan {
     hipEvent_t fork_ev = nullptr;
     hipEvent_t join_ev[kSides] = {nullptr, nullptr, nullptr, nullptr};
     int nsides = 0;
+    bool serial = false;                    // forward: every launch on the caller's stream (tuned choice)
     // opt-in kernel timing: events recorded around every launch on its stream
     bool profiling = false;
     struct Rec {
@@ -177,9 +180,7 @@ struct mrdft_plan {
 
 namespace {
 
-void dfree(void* ptr) {
-    if (ptr) (void)hipFree(ptr);
-}
+void dfree(void* ptr) { dev_free(ptr); }
 
 void free_plan(mrdft_plan* p) {
     if (!p) return;
@@ -262,7 +263,7 @@ mrdft_status upload_twiddles(mrdft_plan* p, hipStream_t s) {
                 rt[off + k2 * 1024 + n1] = make_float2((float)std::cos(a), (float)(-std::sin(a)));
             }
     }
-    if (hipMalloc(&p->d_tw16, sizeof(float2) * nrow) != hipSuccess)
+    if (dev_malloc(&p->d_tw16, sizeof(float2) * nrow) != hipSuccess)
         return fail(MRDFT_E_ALLOC, "twiddle table allocation failed");
     HIP_TRY(hipMemcpyAsync(p->d_tw16, rt.data(), sizeof(float2) * nrow, hipMemcpyHostToDevice, s));
     // Row twiddles w_L^{n1*k2} (n1 < 256, k2 < L/256) of the real levels 13..16, [k2][n1].
@@ -277,7 +278,7 @@ mrdft_status upload_twiddles(mrdft_plan* p, hipStream_t s) {
                 rr[off + k2 * kRowsN + n1] = make_float2((float)std::cos(a), (float)(-std::sin(a)));
             }
     }
-    if (hipMalloc(&p->d_tw_rows, sizeof(float2) * nrows) != hipSuccess)
+    if (dev_malloc(&p->d_tw_rows, sizeof(float2) * nrows) != hipSuccess)
         return fail(MRDFT_E_ALLOC, "twiddle table allocation failed");
     HIP_TRY(hipMemcpyAsync(p->d_tw_rows, rr.data(), sizeof(float2) * nrows, hipMemcpyHostToDevice, s));
     // Column-combine factors of those levels: for piece g, pair s, row q (k = 16 g + q),
@@ -299,7 +300,7 @@ mrdft_status upload_twiddles(mrdft_plan* p, hipStream_t s) {
                                     (float)(0.5 * (wax - wby)), (float)(0.5 * (way + wbx)));
                 }
     }
-    if (hipMalloc(&p->d_tw_comb, sizeof(float4) * ncomb) != hipSuccess)
+    if (dev_malloc(&p->d_tw_comb, sizeof(float4) * ncomb) != hipSuccess)
         return fail(MRDFT_E_ALLOC, "twiddle table allocation failed");
     HIP_TRY(hipMemcpyAsync(p->d_tw_comb, cv.data(), sizeof(float4) * ncomb, hipMemcpyHostToDevice, s));
     // Combine factors of the complex levels 12..16: w_R^{r (16 g + q)}, index ((g * P + r) * 16 + q).
@@ -315,12 +316,12 @@ mrdft_status upload_twiddles(mrdft_plan* p, hipStream_t s) {
                         make_float2((float)std::cos(a), (float)(-std::sin(a)));
                 }
     }
-    if (hipMalloc(&p->d_tw_ccomb, sizeof(float2) * nccomb) != hipSuccess)
+    if (dev_malloc(&p->d_tw_ccomb, sizeof(float2) * nccomb) != hipSuccess)
         return fail(MRDFT_E_ALLOC, "twiddle table allocation failed");
     HIP_TRY(hipMemcpyAsync(p->d_tw_ccomb, cc.data(), sizeof(float2) * nccomb, hipMemcpyHostToDevice, s));
-    if (hipMalloc(&p->d_tw_tile, sizeof(float2) * kTileMax) != hipSuccess ||
-        hipMalloc(&p->d_tw_hi, sizeof(double2) * nf) != hipSuccess ||
-        hipMalloc(&p->d_tw_lo, sizeof(double2) * nf) != hipSuccess)
+    if (dev_malloc(&p->d_tw_tile, sizeof(float2) * kTileMax) != hipSuccess ||
+        dev_malloc(&p->d_tw_hi, sizeof(double2) * nf) != hipSuccess ||
+        dev_malloc(&p->d_tw_lo, sizeof(double2) * nf) != hipSuccess)
         return fail(MRDFT_E_ALLOC, "twiddle table allocation failed");
     HIP_TRY(hipMemcpyAsync(p->d_tw_tile, tile.data(), sizeof(float2) * kTileMax, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(p->d_tw_hi, hi.data(), sizeof(double2) * nf, hipMemcpyHostToDevice, s));
@@ -370,7 +371,7 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
         if (q >= p->njobs_full) p->tail_tmax = std::max(p->tail_tmax, (int)jobs[q].t);
     }
     if (!jobs.empty()) {
-        if (hipMalloc(&p->d_jobs, sizeof(TileJob) * jobs.size()) != hipSuccess)
+        if (dev_malloc(&p->d_jobs, sizeof(TileJob) * jobs.size()) != hipSuccess)
             return fail(MRDFT_E_ALLOC, "tile table allocation failed (%zu bytes)", sizeof(TileJob) * jobs.size());
         HIP_TRY(hipMemcpyAsync(p->d_jobs, jobs.data(), sizeof(TileJob) * jobs.size(), hipMemcpyHostToDevice, s));
     }
@@ -385,7 +386,7 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
         mrdft_status st = upload_cjobs(p, p->order, s, true);   // default: one workgroup per job
         if (st) return st;
         if (p->ncjobs > 0) {
-            if (!p->d_queue && hipMalloc(&p->d_queue, kC64Queues * sizeof(unsigned)) != hipSuccess)
+            if (!p->d_queue && dev_malloc(&p->d_queue, kC64Queues * sizeof(unsigned)) != hipSuccess)
                 return fail(MRDFT_E_ALLOC, "queue allocation failed");
             HIP_TRY(hipMemsetAsync(p->d_queue, 0, kC64Queues * sizeof(unsigned), s));   // once; kernels restore it
             p->tile_log = kC64TileLog;
@@ -445,10 +446,10 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
         p->nacols = (int64_t)cj.size();
         p->nasmall = (int64_t)sm.size();
         for (const TileJob& t : sm) p->asmall_tmax = std::max(p->asmall_tmax, (int)t.t);
-        if ((!aj.empty() && hipMalloc(&p->d_ajobs, sizeof(RealJob) * aj.size()) != hipSuccess) ||
-            (!cj.empty() && hipMalloc(&p->d_acols, sizeof(AdjColJob) * cj.size()) != hipSuccess) ||
-            (!sm.empty() && hipMalloc(&p->d_asmall, sizeof(TileJob) * sm.size()) != hipSuccess) ||
-            (scr > 0 && hipMalloc(&p->d_ascratch, sizeof(float2) * scr) != hipSuccess))
+        if ((!aj.empty() && dev_malloc(&p->d_ajobs, sizeof(RealJob) * aj.size()) != hipSuccess) ||
+            (!cj.empty() && dev_malloc(&p->d_acols, sizeof(AdjColJob) * cj.size()) != hipSuccess) ||
+            (!sm.empty() && dev_malloc(&p->d_asmall, sizeof(TileJob) * sm.size()) != hipSuccess) ||
+            (scr > 0 && dev_malloc(&p->d_ascratch, sizeof(float2) * scr) != hipSuccess))
             return fail(MRDFT_E_ALLOC, "adjoint tables or scratch allocation failed (%lld complex)", (long long)scr);
         if (!aj.empty()) HIP_TRY(hipMemcpyAsync(p->d_ajobs, aj.data(), sizeof(RealJob) * aj.size(), hipMemcpyHostToDevice, s));
         if (!cj.empty())
@@ -472,8 +473,8 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
         }
         p->nhjobs = (int64_t)hj.size();
         if (!hj.empty()) {
-            if (hipMalloc(&p->d_hjobs, sizeof(HalfJob) * hj.size()) != hipSuccess ||
-                hipMalloc(&p->d_gfull, sizeof(float2) * p->n_fout) != hipSuccess)
+            if (dev_malloc(&p->d_hjobs, sizeof(HalfJob) * hj.size()) != hipSuccess ||
+                dev_malloc(&p->d_gfull, sizeof(float2) * p->n_fout) != hipSuccess)
                 return fail(MRDFT_E_ALLOC, "half-spectrum gradient workspace allocation failed (%lld complex)",
                             (long long)p->n_fout);
             HIP_TRY(hipMemcpyAsync(p->d_hjobs, hj.data(), sizeof(HalfJob) * hj.size(), hipMemcpyHostToDevice, s));
@@ -486,8 +487,8 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
         g.order = o;
         g.count = (int64_t)gin[o].size();
         if (p->ragged) {
-            if (hipMalloc(&g.d_in_sig, sizeof(int64_t) * g.count) != hipSuccess ||
-                hipMalloc(&g.d_out_sig, sizeof(int64_t) * g.count) != hipSuccess) {
+            if (dev_malloc(&g.d_in_sig, sizeof(int64_t) * g.count) != hipSuccess ||
+                dev_malloc(&g.d_out_sig, sizeof(int64_t) * g.count) != hipSuccess) {
                 p->groups.push_back(g);
                 return fail(MRDFT_E_ALLOC, "signal table allocation failed");
             }
@@ -519,12 +520,12 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
     if (scratch > 0) {
         // one ping-pong pair per side stream: chains of passes of different
         // levels run concurrently
-        if (hipMalloc(&p->d_s[0], sizeof(float2) * scratch) != hipSuccess ||
-            hipMalloc(&p->d_s[1], sizeof(float2) * scratch) != hipSuccess)
+        if (dev_malloc(&p->d_s[0], sizeof(float2) * scratch) != hipSuccess ||
+            dev_malloc(&p->d_s[1], sizeof(float2) * scratch) != hipSuccess)
             return fail(MRDFT_E_ALLOC, "pass workspace allocation failed (2 x %lld complex)", (long long)scratch);
         for (int k = 1; k < p->nsides; ++k)
-            if (hipMalloc(&p->d_ss[k - 1][0], sizeof(float2) * scratch) != hipSuccess ||
-                hipMalloc(&p->d_ss[k - 1][1], sizeof(float2) * scratch) != hipSuccess)
+            if (dev_malloc(&p->d_ss[k - 1][0], sizeof(float2) * scratch) != hipSuccess ||
+                dev_malloc(&p->d_ss[k - 1][1], sizeof(float2) * scratch) != hipSuccess)
                 return fail(MRDFT_E_ALLOC, "pass workspace allocation failed (%d x 2 x %lld complex)", p->nsides,
                             (long long)scratch);
     }
@@ -775,7 +776,7 @@ mrdft_status upload_cjobs(mrdft_plan* p, int order, hipStream_t s, bool direct) 
     if (st) return st;
     p->cjobs_direct = direct;
     if (direct) return MRDFT_OK;
-    if (!p->d_cseg && hipMalloc(&p->d_cseg, sizeof(unsigned) * seg.size()) != hipSuccess)
+    if (!p->d_cseg && dev_malloc(&p->d_cseg, sizeof(unsigned) * seg.size()) != hipSuccess)
         return fail(MRDFT_E_ALLOC, "segment table allocation failed");
     HIP_TRY(hipMemcpyAsync(p->d_cseg, seg.data(), sizeof(unsigned) * seg.size(), hipMemcpyHostToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -788,7 +789,7 @@ mrdft_status upload_jobs(const std::vector<RealJob>& v, RealJob** dst, int64_t* 
     *dst = nullptr;
     *n = (int64_t)v.size();
     if (v.empty()) return MRDFT_OK;
-    if (hipMalloc(dst, sizeof(RealJob) * v.size()) != hipSuccess)
+    if (dev_malloc(dst, sizeof(RealJob) * v.size()) != hipSuccess)
         return fail(MRDFT_E_ALLOC, "job table allocation failed (%zu bytes)", sizeof(RealJob) * v.size());
     HIP_TRY(hipMemcpyAsync(*dst, v.data(), sizeof(RealJob) * v.size(), hipMemcpyHostToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -841,11 +842,13 @@ float2* level_ptr(const mrdft_plan* p, float2* Y, int i, int64_t N) {
 // explicit override of kind `in_kind`).
 mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, hipStream_t s0) {
     const Twiddles tw = p->tw();
-    // Levels above the tile go to the side stream, which first waits for
-    // everything already queued on the caller's stream.
-    if (p->nsides) {
+    // Levels above the tile go to the side streams (unless the schedule is
+    // serial), which first wait for everything already queued on the caller's
+    // stream.
+    const int nsides = p->serial ? 0 : p->nsides;
+    if (nsides) {
         HIP_TRY(hipEventRecord(p->fork_ev, s0));
-        for (int k = 0; k < p->nsides; ++k) HIP_TRY(hipStreamWaitEvent(p->side[k], p->fork_ev, 0));
+        for (int k = 0; k < nsides; ++k) HIP_TRY(hipStreamWaitEvent(p->side[k], p->fork_ev, 0));
     }
     const bool real_jobs_cover = in_kind == IN_R32 && p->d_rjobs;
     const bool cjobs_cover = in_kind == IN_C64 && p->d_cjobs && p->tile_log == kC64TileLog;
@@ -858,8 +861,8 @@ mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, h
             // levels spread over the side streams; the passes of one level run
             // in order on one stream with that stream's scratch pair
             const int si = (i <= kUpperMaxLevel) ? (i - kTileMaxLog - 1) : chain++;
-            const int k = p->nsides ? si % p->nsides : 0;
-            const hipStream_t s = p->nsides ? p->side[k] : s0;
+            const int k = nsides ? si % nsides : 0;
+            const hipStream_t s = nsides ? p->side[k] : s0;
             float2* const* ds = k == 0 ? p->d_s : p->d_ss[k - 1];
             if (i <= kUpperMaxLevel) {
                 if (p->hs) return fail(MRDFT_E_UNSUPPORTED, "half-spectrum output of level %d without the real launch", i);
@@ -932,7 +935,7 @@ mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, h
             HIP_TRY(launch_tile_fwd(false, x, Y, p->d_jobs, p->njobs, p->jobs_tmax, tw, s0));
         }
     }
-    for (int k = 0; k < p->nsides; ++k) {
+    for (int k = 0; k < nsides; ++k) {
         HIP_TRY(hipEventRecord(p->join_ev[k], p->side[k]));
         HIP_TRY(hipStreamWaitEvent(s0, p->join_ev[k], 0));
     }
@@ -1125,7 +1128,7 @@ mrdft_status tune(mrdft_plan* p, hipStream_t s) {
     void* x = nullptr;
     float2* Y = nullptr;
     const size_t xbytes = (size_t)p->n_in * (real ? sizeof(float) : sizeof(float2));
-    if (hipMalloc(&x, xbytes) != hipSuccess || hipMalloc(&Y, sizeof(float2) * (size_t)p->n_out) != hipSuccess) {
+    if (dev_malloc(&x, xbytes) != hipSuccess || dev_malloc(&Y, sizeof(float2) * (size_t)p->n_out) != hipSuccess) {
         dfree(x);
         return fail(MRDFT_E_ALLOC, "tuning buffers allocation failed");
     }
@@ -1172,10 +1175,113 @@ mrdft_status tune(mrdft_plan* p, hipStream_t s) {
     p->tile_log = best.tile_log;
     p->order = best.tile_log == kTileMaxLog && !real ? cur_order : best.order;
     p->grid = best.grid;
+    // the winner once more with every launch on the caller's stream: pass
+    // chains beside the one-launch kernel share the GPU with it, which can
+    // cost more than it overlaps
+    if (!st && p->nsides > 0) {
+        p->serial = true;
+        float ms = 0.0f;
+        st = time_forward(p, x, Y, s, &ms);
+        if (st || !(ms < best_ms)) p->serial = false;
+    }
     if (hipStreamSynchronize(s) != hipSuccess && !st) st = fail(MRDFT_E_HIP, "tuning failed");
     dfree(x);
     dfree(Y);
     return st;
+}
+
+// Pin a forward schedule (validated; job tables re-uploaded when needed; a
+// captured graph is dropped).
+mrdft_status apply_schedule(mrdft_plan* plan, int tile_log, int grid, int order, bool serial, hipStream_t stream) {
+    const bool real = plan->dtype == MRDFT_R32;
+    if (order < MRDFT_ORDER_TILES_FIRST || order > MRDFT_ORDER_BLOCKS)
+        return fail(MRDFT_E_INVALID_ARG, "unknown job order %d", order);
+    if (real ? tile_log != kRealTileLog : (tile_log != kC64TileLog && tile_log != kTileMaxLog))
+        return fail(MRDFT_E_INVALID_ARG, "tile_log %d is not available for this plan", tile_log);
+    if (!real && tile_log == kC64TileLog && grid < 0) return fail(MRDFT_E_INVALID_ARG, "grid must be >= 0");
+    const bool direct = !real && tile_log == kC64TileLog && grid == 0;
+    if (order != plan->order || (!real && plan->ncjobs > 0 && direct != plan->cjobs_direct)) {
+        mrdft_status st = real ? upload_jobs(real_jobs(plan, order), &plan->d_rjobs, &plan->nrjobs, stream)
+                               : upload_cjobs(plan, order, stream, direct);
+        if (st) return st;
+        plan->order = order;
+    }
+    if (!real) {
+        plan->tile_log = plan->ncjobs > 0 ? tile_log : kTileMaxLog;
+        plan->grid = grid;
+    }
+    plan->serial = serial;
+    if (plan->gexec) (void)hipGraphExecDestroy(plan->gexec);
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    plan->gexec = nullptr;
+    plan->graph = nullptr;
+    return MRDFT_OK;
+}
+
+// Key of a plan in the tuning cache: device architecture, input type, output
+// form, level range and the exact batch shape (orders and their counts).
+std::string tune_key(const mrdft_plan* p) {
+    std::string arch = "unknown";
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        arch = prop.gcnArchName;
+        for (char& c : arch)
+            if (c == '"' || c == '\\' || (unsigned char)c < 0x20) c = '_';
+    }
+    std::string k = arch + (p->dtype == MRDFT_R32 ? "|r32" : "|c64") + (p->hs ? "|half" : "|full") + "|levels" +
+                    std::to_string(p->lo) + "-" + std::to_string(std::min(p->hi, p->max_order)) +
+                    (p->ragged ? "|ragged" : "|uniform");
+    int64_t count[kMaxOrder + 1] = {};
+    for (int o : p->orders) ++count[o];
+    for (int o = 1; o <= kMaxOrder; ++o)
+        if (count[o]) k += "|" + std::to_string(count[o]) + "x2^" + std::to_string(o);
+    return k;
+}
+
+// Integer value of an environment variable (def if unset; -1 if not a number).
+int env_int(const char* name, int def) {
+    const char* v = std::getenv(name);
+    if (!v || !*v) return def;
+    char* end = nullptr;
+    const long r = std::strtol(v, &end, 10);
+    if (*end || r < 0 || r > 1000000) return -1;
+    return (int)r;
+}
+
+// Tuning at plan creation: MRDFT_TUNE (0/1) overrides the flag; with
+// MRDFT_TUNE_CACHE set, a cached schedule is applied without timing and a
+// fresh result is stored.  MRDFT_TILE_T then pins the tile depth.
+mrdft_status tune_with_cache(mrdft_plan* p, hipStream_t s) {
+    const int env_tune = env_int("MRDFT_TUNE", -2);
+    if (env_tune == -1 || env_tune > 1) return fail(MRDFT_E_INVALID_ARG, "MRDFT_TUNE must be 0 or 1");
+    const bool want = env_tune == -2 ? (p->flags & MRDFT_FLAG_TUNE) != 0 : env_tune == 1;
+    mrdft_status st = MRDFT_OK;
+    if (want) {
+        const char* path = std::getenv("MRDFT_TUNE_CACHE");
+        const std::string key = tune_key(p);
+        int t = 0, g = 0, o = 0, se = 0;
+        bool hit = false;
+        if (path && *path && mrdft_tune_cache_lookup(path, key.c_str(), &t, &g, &o, &se) == 1) {
+            const bool sides = p->nsides > 0;
+            hit = apply_schedule(p, t, g, o, se != 0 && sides, s) == MRDFT_OK;   // an unusable entry is re-tuned
+        }
+        if (!hit) {
+            st = tune(p, s);
+            if (!st && path && *path) {
+                // a cache that cannot be written does not fail the plan
+                (void)mrdft_tune_cache_store(path, key.c_str(), p->tile_log, p->grid, p->order, p->serial ? 1 : 0);
+            }
+        }
+    }
+    if (st) return st;
+    const int tt = env_int("MRDFT_TILE_T", 0);
+    if (tt != 0) {
+        if (tt < 0) return fail(MRDFT_E_INVALID_ARG, "MRDFT_TILE_T must be a tile depth (11 or 12)");
+        st = apply_schedule(p, tt, p->dtype == MRDFT_R32 ? 0 : p->grid, p->order, p->serial, s);
+        if (st) return fail(st, "MRDFT_TILE_T=%d: %s", tt, g_last_error.c_str());
+    }
+    return MRDFT_OK;
 }
 
 // Graph replay of the forward: capture once per (x, Y) pair on the plan's own
@@ -1232,14 +1338,18 @@ mrdft_status ensure_loss_workspace(mrdft_plan* p, hipStream_t s) {
     const int64_t rows = p->batch * p->m;
     const int64_t N = int64_t(1) << p->m;
     const int nch = loss_chunks(N);
-    bool ok = hipMalloc(&p->d_sums, sizeof(double) * 2 * rows) == hipSuccess &&
-              hipMalloc(&p->d_alpha, sizeof(float) * rows) == hipSuccess &&
-              hipMalloc(&p->d_v, sizeof(float) * p->n_in) == hipSuccess &&
-              hipMalloc(&p->d_Yv, sizeof(float2) * (fused ? p->n_out / 2 : p->n_out)) == hipSuccess;
+    bool ok = dev_malloc(&p->d_sums, sizeof(double) * 2 * rows) == hipSuccess &&
+              dev_malloc(&p->d_alpha, sizeof(float) * rows) == hipSuccess &&
+              dev_malloc(&p->d_v, sizeof(float) * p->n_in) == hipSuccess &&
+              dev_malloc(&p->d_Yv, sizeof(float2) * (fused ? p->n_out / 2 : p->n_out)) == hipSuccess;
     if (ok && !fused)
-        ok = hipMalloc(&p->d_Yz, sizeof(float2) * p->n_out) == hipSuccess &&
-             hipMalloc(&p->d_part, sizeof(double) * 2 * rows * nch) == hipSuccess;
+        ok = dev_malloc(&p->d_Yz, sizeof(float2) * p->n_out) == hipSuccess &&
+             dev_malloc(&p->d_part, sizeof(double) * 2 * rows * nch) == hipSuccess;
     if (!ok) {
+        // all or nothing: a failed first call leaves the plan as it was
+        dfree(p->d_ljobs);
+        p->d_ljobs = nullptr;
+        p->nljobs = 0;
         dfree(p->d_sums);
         dfree(p->d_alpha);
         dfree(p->d_v);
@@ -1262,11 +1372,48 @@ namespace mrdft {
 // Error reporting for the other host files of the library (thread-local
 // message returned by mrdft_last_error).
 mrdft_status report_error(mrdft_status st, const char* msg) { return fail(st, "%s", msg); }
+
+namespace {
+std::atomic<int64_t> g_live_allocs{0};
+thread_local int g_scope_depth = 0;
+thread_local int64_t g_scope_allocs = 0;
+thread_local int64_t g_fail_at = 0;         // 0: no injected failure
+}  // namespace
+
+AllocScope::AllocScope() {
+    if (g_scope_depth++ == 0) {
+        g_scope_allocs = 0;
+        const char* v = std::getenv("MRDFT_FAIL_ALLOC_AT");
+        g_fail_at = (v && *v) ? std::strtoll(v, nullptr, 10) : 0;
+    }
+}
+
+AllocScope::~AllocScope() {
+    if (--g_scope_depth == 0) g_fail_at = 0;
+}
+
+hipError_t dev_malloc_raw(void** ptr, size_t bytes) {
+    *ptr = nullptr;
+    ++g_scope_allocs;
+    if (g_scope_depth > 0 && g_fail_at > 0 && g_scope_allocs == g_fail_at) return hipErrorOutOfMemory;
+    const hipError_t e = hipMalloc(ptr, bytes);
+    if (e == hipSuccess) g_live_allocs.fetch_add(1);
+    else *ptr = nullptr;
+    return e;
+}
+
+void dev_free(void* ptr) {
+    if (!ptr) return;
+    (void)hipFree(ptr);
+    g_live_allocs.fetch_sub(1);
+}
 }  // namespace mrdft
 
 extern "C" {
 
 const char* mrdft_last_error(void) { return g_last_error.c_str(); }
+
+int64_t mrdft_live_device_allocations(void) { return g_live_allocs.load(); }
 
 mrdft_status mrdft_plan_create(mrdft_plan_t* plan, int m, int64_t batch, const int64_t* offsets, mrdft_dtype dtype,
                                unsigned flags, hipStream_t stream) {
@@ -1277,6 +1424,7 @@ mrdft_status mrdft_plan_create_levels(mrdft_plan_t* plan, int m, int64_t batch, 
                                       mrdft_dtype dtype, unsigned flags, int lo, int hi, hipStream_t stream) {
     if (!plan) return fail(MRDFT_E_INVALID_ARG, "plan output pointer is NULL");
     *plan = nullptr;
+    AllocScope alloc_scope;
     if (lo < 1 || hi < lo || hi > MRDFT_MAX_ORDER)
         return fail(MRDFT_E_INVALID_ARG, "level range [%d, %d] must satisfy 1 <= lo <= hi <= %d", lo, hi,
                     MRDFT_MAX_ORDER);
@@ -1356,9 +1504,18 @@ mrdft_status mrdft_plan_create_levels(mrdft_plan_t* plan, int m, int64_t batch, 
             return fail(MRDFT_E_HIP, "no usable HIP device");
         }
     }
+    {
+        const int g = env_int("MRDFT_GRAPH", -2);          // 0/1 overrides MRDFT_FLAG_GRAPH
+        if (g == -1 || g > 1) {
+            delete p;
+            return fail(MRDFT_E_INVALID_ARG, "MRDFT_GRAPH must be 0 or 1");
+        }
+        if (g == 0) p->flags &= ~MRDFT_FLAG_GRAPH;
+        if (g == 1) p->flags |= MRDFT_FLAG_GRAPH;
+    }
     mrdft_status st = upload_twiddles(p, stream);
     if (st == MRDFT_OK) st = build_tables(p, stream);
-    if (st == MRDFT_OK && (flags & MRDFT_FLAG_TUNE)) st = tune(p, stream);
+    if (st == MRDFT_OK) st = tune_with_cache(p, stream);
     if (st != MRDFT_OK) {
         free_plan(p);
         return st;
@@ -1401,28 +1558,8 @@ mrdft_status mrdft_forward(mrdft_plan_t plan, const void* x, void* Y, hipStream_
 mrdft_status mrdft_plan_set_schedule(mrdft_plan_t plan, int tile_log, int grid, int order, hipStream_t stream) {
     mrdft_status st = check_plan(plan);
     if (st) return st;
-    const bool real = plan->dtype == MRDFT_R32;
-    if (order < MRDFT_ORDER_TILES_FIRST || order > MRDFT_ORDER_BLOCKS)
-        return fail(MRDFT_E_INVALID_ARG, "unknown job order %d", order);
-    if (real ? tile_log != kRealTileLog : (tile_log != kC64TileLog && tile_log != kTileMaxLog))
-        return fail(MRDFT_E_INVALID_ARG, "tile_log %d is not available for this plan", tile_log);
-    if (!real && tile_log == kC64TileLog && grid < 0) return fail(MRDFT_E_INVALID_ARG, "grid must be >= 0");
-    const bool direct = !real && tile_log == kC64TileLog && grid == 0;
-    if (order != plan->order || (!real && plan->ncjobs > 0 && direct != plan->cjobs_direct)) {
-        st = real ? upload_jobs(real_jobs(plan, order), &plan->d_rjobs, &plan->nrjobs, stream)
-                  : upload_cjobs(plan, order, stream, direct);
-        if (st) return st;
-        plan->order = order;
-    }
-    if (!real) {
-        plan->tile_log = plan->ncjobs > 0 ? tile_log : kTileMaxLog;
-        plan->grid = grid;
-    }
-    if (plan->gexec) (void)hipGraphExecDestroy(plan->gexec);
-    if (plan->graph) (void)hipGraphDestroy(plan->graph);
-    plan->gexec = nullptr;
-    plan->graph = nullptr;
-    return MRDFT_OK;
+    if (order & ~(MRDFT_SCHED_SERIAL | 0xff)) return fail(MRDFT_E_INVALID_ARG, "unknown schedule bits in order 0x%x", order);
+    return apply_schedule(plan, tile_log, grid, order & 0xff, (order & MRDFT_SCHED_SERIAL) != 0, stream);
 }
 
 mrdft_status mrdft_plan_schedule(mrdft_plan_t plan, int* tile_log, int* grid, int* order) {
@@ -1430,7 +1567,7 @@ mrdft_status mrdft_plan_schedule(mrdft_plan_t plan, int* tile_log, int* grid, in
     if (st) return st;
     if (tile_log) *tile_log = plan->dtype == MRDFT_R32 ? kRealTileLog : plan->tile_log;
     if (grid) *grid = (plan->dtype == MRDFT_C64 && plan->tile_log == kC64TileLog) ? plan->grid : 0;
-    if (order) *order = plan->order;
+    if (order) *order = plan->order | (plan->serial ? MRDFT_SCHED_SERIAL : 0);
     return MRDFT_OK;
 }
 
@@ -1455,7 +1592,10 @@ mrdft_status mrdft_spectral_loss_fwd(mrdft_plan_t plan, const float* x, const fl
     if (!x || !z || !num_den || !L) return fail(MRDFT_E_INVALID_ARG, "x, z, num_den and L must be non-NULL");
     if (misaligned(x, 16) || misaligned(z, 16) || misaligned(num_den, 8) || misaligned(L, 4))
         return fail(MRDFT_E_INVALID_ARG, "x or z is not 16-byte aligned");
-    st = ensure_loss_workspace(plan, stream);
+    {
+        AllocScope alloc_scope;
+        st = ensure_loss_workspace(plan, stream);
+    }
     if (st) return st;
     const int64_t N = int64_t(1) << plan->m;
     const int64_t rows = plan->batch * plan->m;
@@ -1529,7 +1669,10 @@ mrdft_status mrdft_spectral_loss_bwd(mrdft_plan_t plan, const float* x, const fl
     if (!x || !z || !num_den || !gL || !gx) return fail(MRDFT_E_INVALID_ARG, "null pointer argument");
     if (misaligned(x, 16) || misaligned(z, 16) || misaligned(gx, 16))
         return fail(MRDFT_E_INVALID_ARG, "x, z or gx is not 16-byte aligned");
-    st = ensure_loss_workspace(plan, stream);
+    {
+        AllocScope alloc_scope;
+        st = ensure_loss_workspace(plan, stream);
+    }
     if (st) return st;
     const int64_t N = int64_t(1) << plan->m;
     const int64_t rows = plan->batch * plan->m;

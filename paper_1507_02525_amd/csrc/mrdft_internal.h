@@ -5,6 +5,25 @@
 
 namespace mrdft {
 
+// Every device allocation and free of the library goes through these two.
+// They count the library's live allocations (mrdft_live_device_allocations)
+// and implement failure injection: with MRDFT_FAIL_ALLOC_AT=k in the
+// environment, the k-th allocation inside the outermost AllocScope of the
+// calling thread fails as if the device were out of memory (tests of the
+// error paths).
+hipError_t dev_malloc_raw(void** p, size_t bytes);
+void dev_free(void* p);
+template <class T>
+hipError_t dev_malloc(T** p, size_t bytes) {
+    return dev_malloc_raw(reinterpret_cast<void**>(p), bytes);
+}
+// Outermost allocating entry point of a call: restarts the allocation count
+// (nested calls, e.g. a 2-D plan creating its 1-D plans, share the count).
+struct AllocScope {
+    AllocScope();
+    ~AllocScope();
+};
+
 // Levels kept by a plan: [lo, hi] (1-based).  Outputs of other levels are not
 // stored and their gradients read as zero; packed into one job field.
 struct LevelRange {

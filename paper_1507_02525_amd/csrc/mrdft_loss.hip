@@ -2,8 +2,11 @@
 // num_i = ||Y^(i)(x) - Y^(i)(z)||^2 and den_i = ||Y^(i)(z)||^2, the loss
 // L = sum_b (1/m) sum_i num_i / den_i, and the per-level scaling of the
 // recomputed spectra by dL/dY = gL * 2 (Y(x) - Y(z)) / (m * den_i) that feeds
-// the adjoint.  Reductions accumulate in FP64 and are deterministic (fixed
-// chunking, fixed tree order).
+// the adjoint.  Reductions accumulate in FP64.  The partial sums of the
+// generic path (sumsq_kernel, then finalize_kernel) use fixed chunks and a
+// fixed tree order, so they are bit-for-bit repeatable; the fused path adds
+// its per-level sums with FP64 atomics from workgroups that finish in no fixed
+// order, so its num_den and L can differ in the last bits between calls.
 #include "mrdft_internal.h"
 #include "mrdft_loss.h"
 
@@ -107,25 +110,6 @@ __global__ __launch_bounds__(256) void scale_levels_kernel(float2* __restrict__ 
     }
 }
 
-__global__ void add_rows_kernel(const double* __restrict__ part, int nch, double* __restrict__ sums, int64_t batch,
-                                int m, int first) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int per = m - first;
-    if (r >= batch * per) return;
-    double t = 0.0;
-    for (int c = 0; c < nch; ++c) t += part[r * nch + c];
-    const int64_t b = r / per;
-    sums[b * m + first + (r - b * per)] += t;
-}
-
-hipError_t launch_add_rows(const double* part, int nch, double* sums, int64_t batch, int m, int first, hipStream_t s) {
-    const int64_t n = batch * (m - first);
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(add_rows_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part, nch, sums, batch, m,
-                       first);
-    return hipGetLastError();
-}
-
 hipError_t launch_sub_real(const float* x, const float* z, float* v, int64_t n, hipStream_t s) {
     const int64_t nb = (n + 4 * 256 - 1) / (4 * 256);
     hipLaunchKernelGGL(sub_real_kernel, dim3((unsigned)nb), dim3(256), 0, s, x, z, v, n);
@@ -142,9 +126,9 @@ hipError_t launch_sumsq(const float2* Y, double* part, int64_t rows, int64_t N, 
 }
 
 hipError_t launch_finalize(const double* pnum, const double* pden, double* num_den, float* L, int64_t batch, int m,
-                           int64_t N, hipStream_t s) {
+                           int nchunks, hipStream_t s) {
     hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kRedThreads), 0, s, pnum, pden, num_den, L, batch, m,
-                       loss_chunks(N));
+                       nchunks);
     return hipGetLastError();
 }
 

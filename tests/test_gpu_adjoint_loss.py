@@ -95,7 +95,7 @@ def test_spectral_loss_vs_oracle(m):
     Lref = 0.0
     for b in range(3):
         ndr, lr = oracle.spectral_loss(x[b], z[b])
-        assert np.max(np.abs(nd[b] / ndr - 1)) <= FWD_TOL * 10
+        assert np.max(np.abs(nd[b] / ndr - 1)) <= FWD_TOL
         Lref += lr
     assert abs(L.item() / Lref - 1) <= 1e-6
 
@@ -165,10 +165,10 @@ def test_workload5_full_size():
         Lsum += np.sum((xd - zd) ** 2) / np.sum(zd ** 2)
     for b in (0, 31):
         ndr, _ = oracle.spectral_loss(x[b], z[b])
-        assert np.max(np.abs(nd[b] / ndr - 1)) <= FWD_TOL * 10
+        assert np.max(np.abs(nd[b] / ndr - 1)) <= FWD_TOL
         ref = oracle.spectral_loss_grad(x[b], z[b], ndr)
         assert rel_l2(g[b], ref) <= GRAD_TOL
-    assert abs(L.item() / Lsum - 1) <= 1e-5
+    assert abs(L.item() / Lsum - 1) <= FWD_TOL
 
 
 @pytest.mark.parametrize("m", [13, 18])

@@ -147,6 +147,46 @@ def test_tuned_plan_matches_oracle():
         assert err <= FWD_TOL, (j, m, err)
 
 
+
+def test_workload4_tuned_graph_full_size():
+    """The 1000-signal ragged batch (m in 8..18) through the plan the benchmark
+    times: tuned schedule and graph replay, so the levels above 16 run as pass
+    chains forked onto side streams inside the capture.  Two replays, with
+    eager work on the stream between them, equal an eager plan with the same
+    schedule bit for bit; the longest signals and one signal of every order are
+    compared with the oracle."""
+    need_gpu()
+    d = workloads.make(4)
+    x, offs, orders = d["x"], d["offsets"], d["orders"]
+    log("workload 4 tuned + graph: %d signals, %d samples" % (len(orders), offs[-1]))
+    graphed = api.Plan(offsets=offs, dtype="c64", tune=True, graph=True)
+    sch = graphed.schedule()
+    log("  tuned schedule %s" % sch)
+    eager = api.Plan(offsets=offs, dtype="c64")
+    eager.set_schedule(sch["tile_log"], sch["grid"], sch["order"], sch["serial"])
+    xd = to_dev(x)
+    Yg = torch.empty(graphed.n_out, dtype=torch.complex64, device="cuda")
+    Ye = torch.empty_like(Yg)
+    eager.mrdft_forward(xd, Ye)
+    for r in range(2):
+        Yg.fill_(float("nan"))
+        graphed.mrdft_forward(xd, Yg)                  # first call captures, the second replays
+        junk = torch.randn(1 << 22, device="cuda") * 3.0   # eager work between the replays
+        torch.cuda.synchronize()
+        assert torch.equal(Yg, Ye), "graph call %d differs from the eager plan" % r
+        del junk
+    oo = graphed.output_offsets()
+    pick = set(int(j) for j in np.nonzero(orders == 18)[0][:3]) | set(int(j) for j in np.nonzero(orders == 17)[0][:2])
+    for o in np.unique(orders):
+        pick.add(int(np.nonzero(orders == o)[0][-1]))
+    Yh = Yg.cpu().numpy()
+    for j in sorted(pick):
+        mj = int(orders[j])
+        ref = oracle.forward(x[offs[j]:offs[j + 1]].astype(np.complex128))
+        err = worst_level_err(Yh[oo[j]:oo[j + 1]].reshape(mj, 1 << mj), ref)
+        assert err <= FWD_TOL, (j, mj, err)
+
+
 # ---------------------------------------------------------------------------
 # Level-range plans: only levels lo..hi are stored (compact layout).
 
