@@ -56,7 +56,8 @@ def test_complex_schedules_match_oracle(tile_log, grid, order):
     x, offs = _ragged(C_ORDERS, 41)
     plan = api.Plan(offsets=offs, dtype="c64")
     plan.set_schedule(tile_log, grid, order)
-    assert plan.schedule() == {"tile_log": tile_log, "grid": grid if tile_log == 11 else 0, "order": order}
+    assert plan.schedule() == {"tile_log": tile_log, "grid": grid if tile_log == 11 else 0, "order": order,
+                               "serial": False}
     Y = torch.empty(plan.n_out, dtype=torch.complex64, device="cuda")
     plan.mrdft_forward(to_dev(x), Y)
     err = _check_ragged(Y, x, offs, C_ORDERS, plan)
