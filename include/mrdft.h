@@ -224,6 +224,23 @@ mrdft_status mrdft_spectral_loss_fwd(mrdft_plan_t plan, const float* x, const fl
                                      float* L, hipStream_t stream);
 
 /*
+ * mrdft_spectral_loss_fwd without any device allocation, for callers that
+ * cannot allocate (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, results and errors as
+ * mrdft_spectral_loss_fwd, for uniform real full-spectrum plans of order
+ * 12 <= m <= 16 and batch * m <= 32768; other plans give MRDFT_E_UNSUPPORTED
+ * with a message (nothing is enqueued).  The per-level sums live in a
+ * workspace inside the library (512 KiB per device, held until the process
+ * ends; found once per device at the first call on it), not in the plan:
+ * every call on one device shares it, so calls that overlap in time on one
+ * device (on different streams, or from different threads) race and must
+ * be serialised by the caller.  The call clears the workspace itself, in a
+ * kernel, before using it.
+ */
+mrdft_status mrdft_spectral_loss_fwd_noalloc(mrdft_plan_t plan, const float* x, const float* z, double* num_den,
+                                             float* L, hipStream_t stream);
+
+/*
  * Gradient of the spectral loss with respect to x (NOT part of the paper: the
  * adjoint of eq. (1) applied to the loss's level gradients), scaled by *gL:
  *   gx = Re( sum_i A_i^H [ gL * 2 (Y^(i)(x) - Y^(i)(z)) / (m * den_i) ] ),

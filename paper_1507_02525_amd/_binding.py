@@ -47,6 +47,7 @@ SIGNATURES = {
     "mrdft_adjoint": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "mrdft_spectral_loss_fwd": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "mrdft_spectral_loss_bwd": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "mrdft_spectral_loss_fwd_noalloc": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "mrdft_plan_set_profiling": (ctypes.c_int, [_vp, ctypes.c_int]),
     "mrdft_plan_read_profile": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), _i64p]),
     "mrdft_plan_destroy": (ctypes.c_int, [_vp]),

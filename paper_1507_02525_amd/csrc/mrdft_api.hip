@@ -1409,6 +1409,36 @@ void dev_free(void* ptr) {
 }
 }  // namespace mrdft
 
+namespace {
+
+// Workspace of mrdft_spectral_loss_fwd_noalloc: the per-level (num, den)
+// sums, FP64.  One copy per device, held until the process ends.
+constexpr int64_t kNoallocMaxSums = int64_t(1) << 16;             // 512 KiB of doubles
+static __device__ __align__(256) double scratch[kNoallocMaxSums];
+
+std::mutex g_scratch_mu;
+std::vector<double*> g_scratch_ptr;                                // device address per device (null: not yet)
+
+// Device address of `scratch` on the current device, looked up once per
+// device (the host-side name of the array is not a device address).
+mrdft_status scratch_address(double** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(MRDFT_E_HIP, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_ptr[dev] = (double*)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return MRDFT_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* mrdft_last_error(void) { return g_last_error.c_str(); }
@@ -1654,6 +1684,36 @@ mrdft_status mrdft_spectral_loss_fwd(mrdft_plan_t plan, const float* x, const fl
     HIP_TRY(launch_sumsq(plan->d_Yv, plan->d_part, rows, N, stream));
     HIP_TRY(launch_sumsq(plan->d_Yz, plan->d_part + rows * nch, rows, N, stream));
     HIP_TRY(launch_finalize(plan->d_part, plan->d_part + rows * nch, num_den, L, plan->batch, plan->m, nch, stream));
+    return MRDFT_OK;
+}
+
+mrdft_status mrdft_spectral_loss_fwd_noalloc(mrdft_plan_t plan, const float* x, const float* z, double* num_den,
+                                             float* L, hipStream_t stream) {
+    mrdft_status st = check_plan(plan);
+    if (st) return st;
+    if (plan->ragged || plan->dtype != MRDFT_R32 || plan->hs || !plan->full_range(plan->m))
+        return fail(MRDFT_E_UNSUPPORTED, "the spectral loss needs a uniform real full-spectrum plan of every level");
+    if (plan->m < kRealTileLog || plan->m > kRowsMaxLevel || !plan->d_rjobs)
+        return fail(MRDFT_E_UNSUPPORTED,
+                    "mrdft_spectral_loss_fwd_noalloc handles orders %d..%d (one launch per input, no passes); "
+                    "the plan has order %d", kRealTileLog, kRowsMaxLevel, plan->m);
+    const int64_t rows = plan->batch * plan->m;
+    if (2 * rows > kNoallocMaxSums)
+        return fail(MRDFT_E_UNSUPPORTED,
+                    "mrdft_spectral_loss_fwd_noalloc: batch * m = %lld exceeds its workspace of %lld levels",
+                    (long long)rows, (long long)(kNoallocMaxSums / 2));
+    if (!x || !z || !num_den || !L) return fail(MRDFT_E_INVALID_ARG, "x, z, num_den and L must be non-NULL");
+    if (misaligned(x, 16) || misaligned(z, 16) || misaligned(num_den, 8) || misaligned(L, 4))
+        return fail(MRDFT_E_INVALID_ARG, "x or z is not 16-byte aligned");
+    double* sums = nullptr;
+    st = scratch_address(&sums);
+    if (st) return st;
+    const Twiddles tw = plan->tw();
+    // the sums start at zero (a fill kernel: the call may be captured)
+    HIP_TRY(launch_zero(sums, (int64_t)sizeof(double) * 2 * rows, stream));
+    HIP_TRY(launch_fwd_real_norms(x, z, sums, plan->m, plan->d_rjobs, plan->nrjobs, tw, stream));
+    HIP_TRY(launch_fwd_real_norms(z, nullptr, sums + rows, plan->m, plan->d_rjobs, plan->nrjobs, tw, stream));
+    HIP_TRY(launch_finalize(sums, sums + rows, num_den, L, plan->batch, plan->m, 1, stream));
     return MRDFT_OK;
 }
 
