@@ -50,6 +50,15 @@ __device__ __forceinline__ float2 twiddle_small(float2 a, int q, int n) {
     return make_float2(a.x * c - a.y * s, a.x * s + a.y * c);
 }
 
+// Output store with the non-temporal hint: the level spectra are written once
+// and not read again by the launch, so they should not displace the input
+// samples that other workgroups of the launch re-read from L2.
+typedef float ntf4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void store_out(float2* p, float4 v) {
+    const ntf4 t = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(t, (ntf4*)p);
+}
+
 __host__ __device__ constexpr int bitrev_ct(int v, int bits) {
     int r = 0;
     for (int b = 0; b < bits; ++b) r |= ((v >> b) & 1) << (bits - 1 - b);

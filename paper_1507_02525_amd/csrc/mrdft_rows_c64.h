@@ -118,7 +118,7 @@ __device__ __forceinline__ void rows_c64_body(CRowsLds& S, const float2* __restr
         const int k1 = e >> 3, kp = (e & 7) * 2;
         const float2 a = S.C[kp * kRowsStride + rpad(k1)];
         const float2 c = S.C[(kp + 1) * kRowsStride + rpad(k1)];
-        *(float4*)(yw + k0 + kp + (int64_t)R * k1) = make_float4(a.x, a.y, c.x, c.y);
+        store_out(yw + k0 + kp + (int64_t)R * k1, make_float4(a.x, a.y, c.x, c.y));
     }
 }
 
@@ -183,7 +183,7 @@ __device__ __forceinline__ void rows_c64_body2(CRowsLds& S, const float2* __rest
             const int k1 = e >> 3, kp = (e & 7) * 2;
             const float2 a = S.C[kp * kRowsStride + rpad(k1)];
             const float2 c = S.C[(kp + 1) * kRowsStride + rpad(k1)];
-            *(float4*)(yw + kh + kp + (int64_t)R * k1) = make_float4(a.x, a.y, c.x, c.y);
+            store_out(yw + kh + kp + (int64_t)R * k1, make_float4(a.x, a.y, c.x, c.y));
         }
     }
 }

@@ -180,7 +180,7 @@ __device__ __forceinline__ void ct_level(CTileLds& S, float2* __restrict__ y, in
         const int J = tid + c * kCThreads;          // = w * M + k: the pair (2k, 2k+1) of window w
         const float4 pr = make_float4(u[c].x, u[c].y, d[c].x, d[c].y);
         *(float4*)(S.P + 2 * J) = pr;
-        if (store && (!MULTI || 2 * J < sm.vlen)) *(float4*)(y + sm.off<MULTI>(2 * J)) = pr;
+        if (store && (!MULTI || 2 * J < sm.vlen)) store_out(y + sm.off<MULTI>(2 * J), pr);
     }
     __syncthreads();
 }
@@ -212,7 +212,7 @@ __device__ __forceinline__ void ct_stage(const float2* pv, float4* st, float2* _
     for (int r = 0; r < 4; ++r) {
         const int p = 64 * r + lane, wl = p >> 2, e = p & 3;
         const int t = t0 + 2 * p;
-        if (!MULTI || t < sm.vlen) *(float4*)(yl + sm.off<MULTI>(t)) = st[4 * wl + (e ^ (wl & 3))];
+        if (!MULTI || t < sm.vlen) store_out(yl + sm.off<MULTI>(t), st[4 * wl + (e ^ (wl & 3))]);
     }
     ct_wave_sync();
 }
