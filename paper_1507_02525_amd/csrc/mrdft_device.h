@@ -25,6 +25,12 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 __device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+// acc + a * b as four fused multiply-adds (cadd(acc, cmul(a, b)) compiles to
+// six instructions: the product is rounded before the sum)
+__device__ __forceinline__ float2 cmac(float2 acc, float2 a, float2 b) {
+    return make_float2(__builtin_fmaf(a.x, b.x, __builtin_fmaf(-a.y, b.y, acc.x)),
+                       __builtin_fmaf(a.x, b.y, __builtin_fmaf(a.y, b.x, acc.y)));
+}
 // a * conj(b)
 __device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
     return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);

@@ -99,7 +99,7 @@ __device__ __forceinline__ void rows_c64_body(CRowsLds& S, const float2* __restr
                 acc[q] = z[q];                                      // r = 0: factor 1
             } else {
                 const float2 w = cb[r * 16 + q];                    // wave-uniform: scalar loads
-                acc[q] = cadd(acc[q], cmul(z[q], w));
+                acc[q] = cmac(acc[q], z[q], w);
             }
         }
     };
@@ -161,8 +161,8 @@ __device__ __forceinline__ void rows_c64_body2(CRowsLds& S, const float2* __rest
         } else {
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
-                acc[q] = cadd(acc[q], cmul(z[q], cb0[r * 16 + q]));    // wave-uniform: scalar loads
-                acc[16 + q] = cadd(acc[16 + q], cmul(z[q], cb1[r * 16 + q]));
+                acc[q] = cmac(acc[q], z[q], cb0[r * 16 + q]);    // wave-uniform: scalar loads
+                acc[16 + q] = cmac(acc[16 + q], z[q], cb1[r * 16 + q]);
             }
         }
     }

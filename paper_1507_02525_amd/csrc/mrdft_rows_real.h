@@ -166,10 +166,11 @@ __device__ __forceinline__ void rows_real_body(RowsLds& S, const float* __restri
             const int kk = q & 15, kc = (16 - kk) & 15;
             const float2 Z = z[kk], Zm = z[kc];                     // Zc = conj(Zm)
             const float4 uv = cb[s * kRowsMax + q];                 // wave-uniform: scalar loads
-            float2 t;
-            t.x = Z.x * uv.x - Z.y * uv.y + Zm.x * uv.z + Zm.y * uv.w;
-            t.y = Z.x * uv.y + Z.y * uv.x + Zm.x * uv.w - Zm.y * uv.z;
-            acc[q] = first ? t : cadd(acc[q], t);
+            // acc += Z u + conj(Zm) v as a chain of fused multiply-adds
+            const float2 a0 = first ? make_float2(0.0f, 0.0f) : acc[q];
+            acc[q] = make_float2(
+                __builtin_fmaf(Z.x, uv.x, __builtin_fmaf(-Z.y, uv.y, __builtin_fmaf(Zm.x, uv.z, __builtin_fmaf(Zm.y, uv.w, a0.x)))),
+                __builtin_fmaf(Z.x, uv.y, __builtin_fmaf(Z.y, uv.x, __builtin_fmaf(Zm.x, uv.w, __builtin_fmaf(-Zm.y, uv.z, a0.y)))));
         }
     };
     pair(0, true);

@@ -63,7 +63,7 @@ __device__ __forceinline__ void column_from_complex(const float2* v, int g, cons
 #pragma unroll
             for (int kap = 0; kap < 16; ++kap) {
                 if (r == 0) out[kap] = f[kap];
-                else out[kap] = cadd(out[kap], cmul(f[kap], tw_tile(tab, RL, (r * (16 * g + kap)) & (R - 1))));
+                else out[kap] = cmac(out[kap], f[kap], tw_tile(tab, RL, (r * (16 * g + kap)) & (R - 1)));
             }
         }
     }
@@ -96,8 +96,8 @@ __device__ __forceinline__ void column_from_real_pair(const float* va, const flo
                     ob[kap] = fb[kap];
                 } else {
                     const float2 w = tw_tile(tab, RL, (r * (16 * g + kap)) & (R - 1));
-                    oa[kap] = cadd(oa[kap], cmul(fa[kap], w));
-                    ob[kap] = cadd(ob[kap], cmul(fb[kap], w));
+                    oa[kap] = cmac(oa[kap], fa[kap], w);
+                    ob[kap] = cmac(ob[kap], fb[kap], w);
                 }
             }
         }
