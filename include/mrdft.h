@@ -170,6 +170,10 @@ mrdft_status mrdft_plan_sizes(mrdft_plan_t plan, int64_t* n_in, int64_t* n_out);
 /* OR-ed into `order`: every forward launch on the caller's stream (the levels
  * above the tile do not run on the plan's side streams). */
 #define MRDFT_SCHED_SERIAL 0x100
+/* OR-ed into `order`: the levels above the one-launch kernel's levels start
+ * when that kernel has finished, on the plan's side streams (concurrently
+ * with each other).  Excludes MRDFT_SCHED_SERIAL. */
+#define MRDFT_SCHED_AFTER 0x200
 mrdft_status mrdft_plan_schedule(mrdft_plan_t plan, int* tile_log, int* grid, int* order);
 
 /*
@@ -177,7 +181,7 @@ mrdft_status mrdft_plan_schedule(mrdft_plan_t plan, int* tile_log, int* grid, in
  * of tuning again.  tile_log: 11 or 12 for complex plans, 12 for real plans;
  * grid: workgroups of the persistent complex launch (>= 1; 0: one workgroup
  * per job; ignored for real plans and tile_log 12);
- * order: MRDFT_ORDER_*, optionally OR MRDFT_SCHED_SERIAL.  Drops a captured
+ * order: MRDFT_ORDER_*, optionally OR MRDFT_SCHED_SERIAL or MRDFT_SCHED_AFTER.  Drops a captured
  * forward graph.  Synchronises
  * `stream` (the job table is re-uploaded).
  * Errors: MRDFT_E_INVALID_ARG for values outside these sets.

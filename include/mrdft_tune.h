@@ -12,7 +12,8 @@
  * File format: one JSON object, versioned,
  *   {"format": "mrdft-tune", "version": 1,
  *    "entries": {"<key>": {"tile_log": T, "grid": G, "order": O, "serial": S}, ...}}
- * with non-negative integers T, G, O, S.  A file that does not parse, has
+ * with non-negative integers T, G, O, S (S: 0 side streams beside the main
+ * launch, 1 every launch on the caller's stream, 2 side streams after it).  A file that does not parse, has
  * another format name or version, or holds an entry with a missing or
  * negative field is treated as empty (never an error): lookups miss and the
  * next store replaces it with a valid file.

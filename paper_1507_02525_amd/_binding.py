@@ -27,6 +27,7 @@ MRDFT_FLAG_GRAPH = 2
 MRDFT_FLAG_HALF = 4
 ORDERS = ("tiles_first", "rows_first", "interleaved", "blocks")
 MRDFT_SCHED_SERIAL = 0x100
+MRDFT_SCHED_AFTER = 0x200
 KERNEL_KINDS = ("tile_fwd", "pass_fwd", "tile_adj", "pass_adj", "fused_fwd", "loss")
 
 # Every symbol the header declares, with (restype, argtypes).

@@ -84,11 +84,11 @@ class Plan:
         t, g, o = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         B.check(B.lib().mrdft_plan_schedule(self.handle, ctypes.byref(t), ctypes.byref(g), ctypes.byref(o)))
         return {"tile_log": t.value, "grid": g.value, "order": B.ORDERS[o.value & 0xff],
-                "serial": bool(o.value & B.MRDFT_SCHED_SERIAL)}
+                "serial": bool(o.value & B.MRDFT_SCHED_SERIAL), "after": bool(o.value & B.MRDFT_SCHED_AFTER)}
 
-    def set_schedule(self, tile_log: int, grid: int, order: str, serial: bool = False):
+    def set_schedule(self, tile_log: int, grid: int, order: str, serial: bool = False, after: bool = False):
         """Pin the forward schedule (values as returned by schedule())."""
-        code = B.ORDERS.index(order) | (B.MRDFT_SCHED_SERIAL if serial else 0)
+        code = B.ORDERS.index(order) | (B.MRDFT_SCHED_SERIAL if serial else 0) | (B.MRDFT_SCHED_AFTER if after else 0)
         with torch.cuda.device(self.device):
             stream = ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
             B.check(B.lib().mrdft_plan_set_schedule(self.handle, int(tile_log), int(grid), code, stream))

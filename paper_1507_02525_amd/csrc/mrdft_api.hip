@@ -166,6 +166,7 @@ struct mrdft_plan {
     hipEvent_t join_ev[kSides] = {nullptr, nullptr, nullptr, nullptr};
     int nsides = 0;
     bool serial = false;                    // forward: every launch on the caller's stream (tuned choice)
+    bool after = false;                     // forward: side-stream levels start after the main launch (tuned choice)
     // opt-in kernel timing: events recorded around every launch on its stream
     bool profiling = false;
     struct Rec {
@@ -842,16 +843,23 @@ float2* level_ptr(const mrdft_plan* p, float2* Y, int i, int64_t N) {
 // explicit override of kind `in_kind`).
 mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, hipStream_t s0) {
     const Twiddles tw = p->tw();
-    // Levels above the tile go to the side streams (unless the schedule is
-    // serial), which first wait for everything already queued on the caller's
-    // stream.
+    // Levels above the tile go to the side streams, which first wait for
+    // everything already queued on the caller's stream: with the default
+    // schedule they run beside the tile / one-launch kernel, with
+    // MRDFT_SCHED_AFTER they start when it has finished (still concurrently
+    // with each other), with MRDFT_SCHED_SERIAL everything runs in order on the
+    // caller's stream.
     const int nsides = p->serial ? 0 : p->nsides;
-    if (nsides) {
-        HIP_TRY(hipEventRecord(p->fork_ev, s0));
-        for (int k = 0; k < nsides; ++k) HIP_TRY(hipStreamWaitEvent(p->side[k], p->fork_ev, 0));
-    }
     const bool real_jobs_cover = in_kind == IN_R32 && p->d_rjobs;
     const bool cjobs_cover = in_kind == IN_C64 && p->d_cjobs && p->tile_log == kC64TileLog;
+    auto fork = [&]() -> mrdft_status {
+        if (nsides) {
+            HIP_TRY(hipEventRecord(p->fork_ev, s0));
+            for (int k = 0; k < nsides; ++k) HIP_TRY(hipStreamWaitEvent(p->side[k], p->fork_ev, 0));
+        }
+        return MRDFT_OK;
+    };
+    auto upper = [&]() -> mrdft_status {
     int chain = 0;                                    // multi-pass levels, dealt over the side streams
     for (const Group& g : p->groups) {
         const int64_t N = int64_t(1) << g.order;
@@ -903,7 +911,9 @@ mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, h
             }
         }
     }
-    {
+    return MRDFT_OK;
+    };
+    auto main_launch = [&]() -> mrdft_status {
         if (real_jobs_cover) {
             {
                 ProfScope ps(p, MRDFT_KERNEL_FUSED_FWD, s0);
@@ -934,7 +944,19 @@ mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, h
             ProfScope ps(p, MRDFT_KERNEL_TILE_FWD, s0);
             HIP_TRY(launch_tile_fwd(false, x, Y, p->d_jobs, p->njobs, p->jobs_tmax, tw, s0));
         }
+        return MRDFT_OK;
+    };
+    mrdft_status st = MRDFT_OK;
+    if (p->after) {
+        st = main_launch();
+        if (!st) st = fork();
+        if (!st) st = upper();
+    } else {
+        st = fork();
+        if (!st) st = upper();
+        if (!st) st = main_launch();
     }
+    if (st) return st;
     for (int k = 0; k < nsides; ++k) {
         HIP_TRY(hipEventRecord(p->join_ev[k], p->side[k]));
         HIP_TRY(hipStreamWaitEvent(s0, p->join_ev[k], 0));
@@ -1179,10 +1201,19 @@ mrdft_status tune(mrdft_plan* p, hipStream_t s) {
     // chains beside the one-launch kernel share the GPU with it, which can
     // cost more than it overlaps
     if (!st && p->nsides > 0) {
-        p->serial = true;
+        p->after = true;
         float ms = 0.0f;
         st = time_forward(p, x, Y, s, &ms);
-        if (st || !(ms < best_ms)) p->serial = false;
+        if (!st && ms < best_ms) best_ms = ms;
+        else p->after = false;
+        const bool keep_after = p->after;
+        p->after = false;
+        p->serial = true;
+        if (!st) st = time_forward(p, x, Y, s, &ms);
+        if (st || !(ms < best_ms)) {
+            p->serial = false;
+            p->after = keep_after;
+        }
     }
     if (hipStreamSynchronize(s) != hipSuccess && !st) st = fail(MRDFT_E_HIP, "tuning failed");
     dfree(x);
@@ -1192,7 +1223,8 @@ mrdft_status tune(mrdft_plan* p, hipStream_t s) {
 
 // Pin a forward schedule (validated; job tables re-uploaded when needed; a
 // captured graph is dropped).
-mrdft_status apply_schedule(mrdft_plan* plan, int tile_log, int grid, int order, bool serial, hipStream_t stream) {
+mrdft_status apply_schedule(mrdft_plan* plan, int tile_log, int grid, int order, bool serial, bool after,
+                            hipStream_t stream) {
     const bool real = plan->dtype == MRDFT_R32;
     if (order < MRDFT_ORDER_TILES_FIRST || order > MRDFT_ORDER_BLOCKS)
         return fail(MRDFT_E_INVALID_ARG, "unknown job order %d", order);
@@ -1211,6 +1243,7 @@ mrdft_status apply_schedule(mrdft_plan* plan, int tile_log, int grid, int order,
         plan->grid = grid;
     }
     plan->serial = serial;
+    plan->after = after && !serial;
     if (plan->gexec) (void)hipGraphExecDestroy(plan->gexec);
     if (plan->graph) (void)hipGraphDestroy(plan->graph);
     plan->gexec = nullptr;
@@ -1264,13 +1297,14 @@ mrdft_status tune_with_cache(mrdft_plan* p, hipStream_t s) {
         bool hit = false;
         if (path && *path && mrdft_tune_cache_lookup(path, key.c_str(), &t, &g, &o, &se) == 1) {
             const bool sides = p->nsides > 0;
-            hit = apply_schedule(p, t, g, o, se != 0 && sides, s) == MRDFT_OK;   // an unusable entry is re-tuned
+            hit = apply_schedule(p, t, g, o, se == 1 && sides, se == 2 && sides, s) == MRDFT_OK;   // an unusable entry is re-tuned
         }
         if (!hit) {
             st = tune(p, s);
             if (!st && path && *path) {
                 // a cache that cannot be written does not fail the plan
-                (void)mrdft_tune_cache_store(path, key.c_str(), p->tile_log, p->grid, p->order, p->serial ? 1 : 0);
+                (void)mrdft_tune_cache_store(path, key.c_str(), p->tile_log, p->grid, p->order,
+                                             p->serial ? 1 : (p->after ? 2 : 0));
             }
         }
     }
@@ -1278,7 +1312,7 @@ mrdft_status tune_with_cache(mrdft_plan* p, hipStream_t s) {
     const int tt = env_int("MRDFT_TILE_T", 0);
     if (tt != 0) {
         if (tt < 0) return fail(MRDFT_E_INVALID_ARG, "MRDFT_TILE_T must be a tile depth (11 or 12)");
-        st = apply_schedule(p, tt, p->dtype == MRDFT_R32 ? 0 : p->grid, p->order, p->serial, s);
+        st = apply_schedule(p, tt, p->dtype == MRDFT_R32 ? 0 : p->grid, p->order, p->serial, p->after, s);
         if (st) return fail(st, "MRDFT_TILE_T=%d: %s", tt, g_last_error.c_str());
     }
     return MRDFT_OK;
@@ -1588,8 +1622,12 @@ mrdft_status mrdft_forward(mrdft_plan_t plan, const void* x, void* Y, hipStream_
 mrdft_status mrdft_plan_set_schedule(mrdft_plan_t plan, int tile_log, int grid, int order, hipStream_t stream) {
     mrdft_status st = check_plan(plan);
     if (st) return st;
-    if (order & ~(MRDFT_SCHED_SERIAL | 0xff)) return fail(MRDFT_E_INVALID_ARG, "unknown schedule bits in order 0x%x", order);
-    return apply_schedule(plan, tile_log, grid, order & 0xff, (order & MRDFT_SCHED_SERIAL) != 0, stream);
+    if (order & ~(MRDFT_SCHED_SERIAL | MRDFT_SCHED_AFTER | 0xff))
+        return fail(MRDFT_E_INVALID_ARG, "unknown schedule bits in order 0x%x", order);
+    if ((order & MRDFT_SCHED_SERIAL) && (order & MRDFT_SCHED_AFTER))
+        return fail(MRDFT_E_INVALID_ARG, "MRDFT_SCHED_SERIAL and MRDFT_SCHED_AFTER exclude each other");
+    return apply_schedule(plan, tile_log, grid, order & 0xff, (order & MRDFT_SCHED_SERIAL) != 0,
+                          (order & MRDFT_SCHED_AFTER) != 0, stream);
 }
 
 mrdft_status mrdft_plan_schedule(mrdft_plan_t plan, int* tile_log, int* grid, int* order) {
@@ -1597,7 +1635,7 @@ mrdft_status mrdft_plan_schedule(mrdft_plan_t plan, int* tile_log, int* grid, in
     if (st) return st;
     if (tile_log) *tile_log = plan->dtype == MRDFT_R32 ? kRealTileLog : plan->tile_log;
     if (grid) *grid = (plan->dtype == MRDFT_C64 && plan->tile_log == kC64TileLog) ? plan->grid : 0;
-    if (order) *order = plan->order | (plan->serial ? MRDFT_SCHED_SERIAL : 0);
+    if (order) *order = plan->order | (plan->serial ? MRDFT_SCHED_SERIAL : 0) | (plan->after ? MRDFT_SCHED_AFTER : 0);
     return MRDFT_OK;
 }
 

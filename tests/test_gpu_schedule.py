@@ -57,7 +57,7 @@ def test_complex_schedules_match_oracle(tile_log, grid, order):
     plan = api.Plan(offsets=offs, dtype="c64")
     plan.set_schedule(tile_log, grid, order)
     assert plan.schedule() == {"tile_log": tile_log, "grid": grid if tile_log == 11 else 0, "order": order,
-                               "serial": False}
+                               "serial": False, "after": False}
     Y = torch.empty(plan.n_out, dtype=torch.complex64, device="cuda")
     plan.mrdft_forward(to_dev(x), Y)
     err = _check_ragged(Y, x, offs, C_ORDERS, plan)
@@ -149,6 +149,32 @@ def test_tuned_plan_matches_oracle():
 
 
 
+
+@pytest.mark.parametrize("mode", ["beside", "serial", "after"])
+def test_stream_modes_match_oracle(mode):
+    """The levels above the one-launch kernel on side streams beside it, all
+    on the caller's stream, or on side streams after it: the same result
+    (bit for bit) and the oracle's, eager and under graph replay."""
+    need_gpu()
+    orders = [17, 12, 18, 9, 17, 16]
+    x, offs = _ragged(orders, 61)
+    ref = api.Plan(offsets=offs, dtype="c64")
+    Yr = torch.empty(ref.n_out, dtype=torch.complex64, device="cuda")
+    xd = to_dev(x)
+    ref.mrdft_forward(xd, Yr)
+    for graph in (False, True):
+        plan = api.Plan(offsets=offs, dtype="c64", graph=graph)
+        plan.set_schedule(11, 0, "blocks", mode == "serial", mode == "after")
+        sch = plan.schedule()
+        assert sch["serial"] == (mode == "serial") and sch["after"] == (mode == "after")
+        Y = torch.empty_like(Yr)
+        for _ in range(2):
+            Y.fill_(float("nan"))
+            plan.mrdft_forward(xd, Y)
+            torch.cuda.synchronize()
+            assert torch.equal(Y, Yr), (mode, graph)
+    assert _check_ragged(Yr, x, offs, orders, ref) <= FWD_TOL
+
 def test_workload4_tuned_graph_full_size():
     """The 1000-signal ragged batch (m in 8..18) through the plan the benchmark
     times: tuned schedule and graph replay, so the levels above 16 run as pass
@@ -164,7 +190,7 @@ def test_workload4_tuned_graph_full_size():
     sch = graphed.schedule()
     log("  tuned schedule %s" % sch)
     eager = api.Plan(offsets=offs, dtype="c64")
-    eager.set_schedule(sch["tile_log"], sch["grid"], sch["order"], sch["serial"])
+    eager.set_schedule(sch["tile_log"], sch["grid"], sch["order"], sch["serial"], sch["after"])
     xd = to_dev(x)
     Yg = torch.empty(graphed.n_out, dtype=torch.complex64, device="cuda")
     Ye = torch.empty_like(Yg)
