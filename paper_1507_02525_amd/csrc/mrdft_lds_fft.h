@@ -22,6 +22,11 @@ struct Log2 {
 constexpr int kPadShift = 5;
 __device__ __forceinline__ int pad(int i) { return i + (i >> kPadShift); }
 constexpr int padded_size(int n) { return n + (n >> kPadShift); }
+// Padding inside each FFT instead (PADC): element q of FFT f at
+// f * fst + q + (q >> 5); with a suitable fst the Stockham steps' strided
+// accesses and the column-wise accesses of the global passes both spread
+// over the banks.
+__device__ __forceinline__ int padc(int q) { return q + (q >> kPadShift); }
 
 // Twiddles w_{2^lg}^e (lg <= kTileMaxLog) read from a global FP32 table.
 struct TwGlobal {
@@ -55,7 +60,7 @@ __device__ __forceinline__ void load_quarter(float2* q, const float2* __restrict
 
 // Load the inputs of this thread's jobs, apply the step twiddles and the
 // R-point DFT.  Results stay in v[c*R + s].
-template <int R, int JPT, bool INV, bool PAD = false, class TW = TwGlobal>
+template <int R, int JPT, bool INV, bool PAD = false, bool PADC = false, class TW = TwGlobal>
 __device__ __forceinline__ void step_load(const float2* buf, int lgM, int lgNs, int fst, int est, int nfft,
                                           const TW& tw, float2* v, int tid, int nthr) {
     constexpr int lgR = Log2<R>::v;
@@ -70,7 +75,7 @@ __device__ __forceinline__ void step_load(const float2* buf, int lgM, int lgNs, 
             const int j = J & (per - 1);
 #pragma unroll
             for (int s = 0; s < R; ++s) {
-                const int li = f * fst + (j + s * per) * est;
+                const int li = PADC ? f * fst + padc(j + s * per) : f * fst + (j + s * per) * est;
                 v[c * R + s] = buf[PAD ? pad(li) : li];
             }
             if (lgNs > 0) {
@@ -87,7 +92,7 @@ __device__ __forceinline__ void step_load(const float2* buf, int lgM, int lgNs, 
 }
 
 // Write the results of step_load to their Stockham output positions.
-template <int R, int JPT, bool PAD = false>
+template <int R, int JPT, bool PAD = false, bool PADC = false>
 __device__ __forceinline__ void step_store(float2* buf, int lgM, int lgNs, int fst, int est, int nfft,
                                            const float2* v, int tid, int nthr) {
     constexpr int lgR = Log2<R>::v;
@@ -104,7 +109,7 @@ __device__ __forceinline__ void step_store(float2* buf, int lgM, int lgNs, int f
             const int base = ((j >> lgNs) << (lgNs + lgR)) + jm;
 #pragma unroll
             for (int s = 0; s < R; ++s) {
-                const int li = f * fst + (base + (s << lgNs)) * est;
+                const int li = PADC ? f * fst + padc(base + (s << lgNs)) : f * fst + (base + (s << lgNs)) * est;
                 buf[PAD ? pad(li) : li] = v[c * R + s];
             }
         }
@@ -112,13 +117,13 @@ __device__ __forceinline__ void step_store(float2* buf, int lgM, int lgNs, int f
 }
 
 // A full in-place Stockham step: load, barrier, store, barrier.
-template <int R, int JPT, bool INV, bool PAD = false, class TW = TwGlobal>
+template <int R, int JPT, bool INV, bool PAD = false, bool PADC = false, class TW = TwGlobal>
 __device__ __forceinline__ void lds_step(float2* buf, int lgM, int lgNs, int fst, int est, int nfft,
                                          const TW& tw, int tid, int nthr) {
     float2 v[JPT * R];
-    step_load<R, JPT, INV, PAD>(buf, lgM, lgNs, fst, est, nfft, tw, v, tid, nthr);
+    step_load<R, JPT, INV, PAD, PADC>(buf, lgM, lgNs, fst, est, nfft, tw, v, tid, nthr);
     __syncthreads();
-    step_store<R, JPT, PAD>(buf, lgM, lgNs, fst, est, nfft, v, tid, nthr);
+    step_store<R, JPT, PAD, PADC>(buf, lgM, lgNs, fst, est, nfft, v, tid, nthr);
     __syncthreads();
 }
 
