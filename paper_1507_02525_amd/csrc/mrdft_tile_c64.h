@@ -21,6 +21,7 @@
 #include "mrdft_device.h"
 #include "mrdft_internal.h"
 #include "mrdft_lds_fft.h"
+#include "mrdft_xlane.h"
 
 namespace mrdft {
 
@@ -190,107 +191,15 @@ __device__ __forceinline__ void ct_level_lds(CTileLds& S, float2* __restrict__ y
 //
 // Wave v owns X[512 v, 512 v + 512) and P[512 v, 512 v + 512) (its pairs
 // 256 v .. 256 v + 255 of every level), so these levels need no workgroup
-// barrier.  Of level I (FFTs of M = 2^n points, n = I - 1, 256 / M windows
-// per wave) lane l, register r holds the point whose 8-bit wave index has
-// the two top FFT-index bits in r and the other six bits ("content" bits
-// c0..c5, low FFT-index bits first, then window bits) in the lane, with
-// c0 = l0^l2, c1 = l1^l2, c2 = l2^l3, c3 = l3, c4 = l4, c5 = l5.  The lane
-// permutations that DPP offers inside a row of 16 lanes (swap neighbours,
-// swap pairs, mirror 8, mirror 16) then each flip exactly one content bit
-// (c0, c1, c2, c3 in that order), so each is one radix-2 butterfly stage.
+// barrier.  The wave's 256 odd-bin points of level I (FFTs of 2^(I-1)
+// points) are transformed by xl_fft (mrdft_xlane.h).
 constexpr int kCtWaveMaxLog = 9;
-
-struct CtLane {
-    int c;                 // content bits of this lane
-    float s[4];            // +1 / -1: content bit b clear / set
-    float2 tw[4];          // stage b >= 1: 1, or -w_{2^(b+1)}^{c mod 2^b} where bit b is set
-};
-
-__device__ __forceinline__ CtLane ct_lane(const float2* Q, int lane) {
-    const int l2 = (lane >> 2) & 1, l3 = (lane >> 3) & 1;
-    CtLane ln;
-    ln.c = (lane & 0x30) | (l3 << 3) | ((l2 ^ l3) << 2) | ((((lane >> 1) & 1) ^ l2) << 1) | ((lane & 1) ^ l2);
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const bool hi = (ln.c >> b) & 1;
-        ln.s[b] = hi ? -1.0f : 1.0f;
-        if (b > 0) {
-            const float2 t = TwQ2048{Q}(b + 1, ln.c & ((1 << b) - 1));
-            ln.tw[b] = hi ? make_float2(-t.x, -t.y) : make_float2(1.0f, 0.0f);
-        }
-    }
-    return ln;
-}
-
-// Value of lane l ^ 1, l ^ 2, l ^ 7 (within 8) or l ^ 15 (within 16): the
-// lane whose content differs in bit B only.
-template <int B>
-__device__ __forceinline__ float ct_dpp(float x) {
-    constexpr int ctrl = B == 0 ? 0xB1 : B == 1 ? 0x4E : B == 2 ? 0x141 : 0x140;
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), ctrl, 0xF, 0xF, false));
-}
-
-// Radix-2 decimation-in-frequency stage over content bit B: the lane with
-// the bit clear ends with a + b, the other with (a - b) w (B > 0) or a - b
-// (B = 0), written as (partner * s + self) * tw with s = -1 and the sign of
-// tw flipped on the second lane.
-template <int B>
-__device__ __forceinline__ float2 ct_xbfly(float2 v, const CtLane& ln) {
-    const float px = ct_dpp<B>(v.x), py = ct_dpp<B>(v.y);
-    const float2 t = make_float2(__builtin_fmaf(px, ln.s[B], v.x), __builtin_fmaf(py, ln.s[B], v.y));
-    if constexpr (B == 0) return make_float2(t.x * ln.s[0], t.y * ln.s[0]);
-    else return cmul(t, ln.tw[B]);
-}
-
-template <int B>
-struct CtXStages {
-    static __device__ __forceinline__ void run(float2* a, const CtLane& ln) {
-        if constexpr (B >= 0) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) a[r] = ct_xbfly<B>(a[r], ln);
-            CtXStages<B - 1>::run(a, ln);
-        }
-    }
-};
-
-// Exchange register bit 1 with lane bit 5 and register bit 0 with lane bit 4
-// (lane halves and rows of 16 swapped by permlane).
-__device__ __forceinline__ void ct_swap_bits(float& lo_reg_hi_lane, float& hi_reg_lo_lane, bool rows) {
-    const unsigned a = __builtin_bit_cast(unsigned, lo_reg_hi_lane), b = __builtin_bit_cast(unsigned, hi_reg_lo_lane);
-    if (rows) {
-        const auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);
-        lo_reg_hi_lane = __builtin_bit_cast(float, (unsigned)r[0]);
-        hi_reg_lo_lane = __builtin_bit_cast(float, (unsigned)r[1]);
-    } else {
-        const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
-        lo_reg_hi_lane = __builtin_bit_cast(float, (unsigned)r[0]);
-        hi_reg_lo_lane = __builtin_bit_cast(float, (unsigned)r[1]);
-    }
-}
-__device__ __forceinline__ void ct_transpose45(float2* a) {
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {             // register pairs (0, 2), (1, 3): bit 1 <-> lane bit 5
-        ct_swap_bits(a[r].x, a[r + 2].x, false);
-        ct_swap_bits(a[r].y, a[r + 2].y, false);
-    }
-#pragma unroll
-    for (int r = 0; r < 4; r += 2) {          // register pairs (0, 1), (2, 3): bit 0 <-> lane bit 4
-        ct_swap_bits(a[r].x, a[r + 1].x, true);
-        ct_swap_bits(a[r].y, a[r + 1].y, true);
-    }
-}
-
-// Odd-bin scratch index (wave-local point p = window * M + k): bits 4..7
-// folded into bits 0..3, so that both the lane-scattered writes and the
-// natural-order reads fall on distinct banks.
-__device__ __forceinline__ int cfsw(int p) { return p ^ ((p >> 4) & 15); }
 
 template <int I, bool MULTI>
 __device__ __forceinline__ void ct_level_wave(CTileLds& S, float2* __restrict__ y, int tid, bool store,
-                                              const SubMap& sm, const CtLane& ln) {
+                                              const SubMap& sm, const XLane& ln) {
     constexpr int L = 1 << I, M = L / 2, n = I - 1;
     constexpr int NQ = n - 2;                            // FFT-index bits held by the lane
-    constexpr int NB = NQ < 4 ? NQ : 4;                  // DPP stages (content bits 0..NB-1)
     const int v = tid >> 6, lane = tid & 63;
     float2* Pb = S.P + 512 * v;
     // ---- U^(i): even bins of the wave's pairs J = 64 c + lane ----
@@ -311,49 +220,14 @@ __device__ __forceinline__ void ct_level_wave(CTileLds& S, float2* __restrict__ 
         const int e = 512 * v + wl * L + q;
         a[r] = cmul(csub(S.X[cx(e)], S.X[cx(e + M)]), TwQ2048{S.Q}(I, q));
     }
-    // ---- radix-4 over the top two index bits (registers), twiddles w_M^(qlow f) ----
-    dft_reg<4, false>(a);
-#pragma unroll
-    for (int f = 1; f < 4; ++f) a[f] = cmul(a[f], TwQ2048{S.Q}(n, qlow * f));
-    if constexpr (n == 8) {
-        // index bits 5, 4 into the registers, then radix-4 over them (64-point sub-FFTs)
-        ct_transpose45(a);
-        dft_reg<4, false>(a);
-        const int q4 = ln.c & 15;
-#pragma unroll
-        for (int f = 1; f < 4; ++f) a[f] = cmul(a[f], TwQ2048{S.Q}(6, q4 * f));
-    } else if constexpr (n == 7) {
-        // register bit 1 <- window bit, register bit 0 <- index bit 4: radix 2
-        ct_transpose45(a);
-        const float2 t = TwQ2048{S.Q}(5, ln.c & 15);
-#pragma unroll
-        for (int h = 0; h < 4; h += 2) {
-            const float2 p0 = a[h], p1 = a[h + 1];
-            a[h] = cadd(p0, p1);
-            a[h + 1] = cmul(csub(p0, p1), t);
-        }
-    }
-    // ---- radix-2 stages across lanes: content bit b gives bin bit n-1-b ----
-    CtXStages<NB - 1>::run(a, ln);
-    // ---- bins to natural order through the wave's LDS (F overlays P) ----
-    int pl = 0;                                          // lane part of the position
-#pragma unroll
-    for (int b = 0; b < NB; ++b) pl |= ((ln.c >> b) & 1) << (n - 1 - b);
-    if constexpr (n >= 7) pl |= (ln.c >> 4) & 3;        // the first radix-4 digit went to lanes 4, 5
-    else pl |= (ln.c >> NQ) << n;                        // window bits
+    xl_fft<n>(a, ln, TwQ2048{S.Q});
     ct_wave_sync();                                      // U reads before the overlaying writes
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        int p = pl;
-        if constexpr (n == 8) p |= (r & 1) << 2 | (r >> 1) << 3;
-        else if constexpr (n == 7) p |= (r & 1) << 2 | (r >> 1) << 7;
-        else p |= r;
-        Pb[cfsw(p)] = a[r];
-    }
+    for (int r = 0; r < 4; ++r) Pb[xl_fsw(xl_pos<n>(ln.c, r))] = a[r];
     ct_wave_sync();
     float2 d[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) d[c] = Pb[cfsw(64 * c + lane)];
+    for (int c = 0; c < 4; ++c) d[c] = Pb[xl_fsw(64 * c + lane)];
     ct_wave_sync();
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
@@ -371,7 +245,7 @@ __device__ __forceinline__ void ct_level_wave(CTileLds& S, float2* __restrict__ 
 template <int I, bool MULTI>
 struct CtLevels {
     static __device__ __forceinline__ void run(CTileLds& S, float2* __restrict__ y, int64_t ls, int tid,
-                                               LevelRange lv, const SubMap& sm, const CtLane& ln) {
+                                               LevelRange lv, const SubMap& sm, const XLane& ln) {
         if constexpr (I <= kCTLog) {
             if (I > lv.hi) return;                    // levels above the range are not computed
             if constexpr (I <= kCtWaveMaxLog)
@@ -483,7 +357,7 @@ __device__ __forceinline__ void c64_tile_body(CTileLds& S, const void* __restric
     for (int e = 0; e < C / 2; ++e)
         *(float4*)(S.P + C * tid + 2 * e) = make_float4(pv[2 * e].x, pv[2 * e].y, pv[2 * e + 1].x, pv[2 * e + 1].y);
     __syncthreads();
-    const CtLane ln = ct_lane(S.Q, lane);
+    const XLane ln = xl_lane(lane, TwQ2048{S.Q});
     CtLevels<4, MULTI>::run(S, y, ls, tid, lv, sm, ln);
 }
 

@@ -26,6 +26,7 @@
 
 #include "mrdft_internal.h"
 #include "mrdft_lds_fft.h"
+#include "mrdft_xlane.h"
 
 namespace mrdft {
 
@@ -47,6 +48,14 @@ static_assert(sizeof(float) * kRT + sizeof(float2) * kRT / 2 == (kRThreads / 64)
 // wait for every earlier store.  All twiddles therefore come from LDS.
 
 __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+
+// Orders LDS accesses of lanes of one wave (LDS executes a wave's
+// instructions in issue order; this only stops the compiler from moving them).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // Where the level spectra go: stored to Y, or (spectral loss) only their
 // squared magnitudes summed per level in FP64, Y never written.
@@ -94,20 +103,25 @@ struct NormOut {
 // 32 or more (the twiddles of one Stockham step) fall on different banks.
 __device__ __forceinline__ int qswz(int E) { return E ^ ((E >> 5) & 31); }
 
-// w_{2^LG}^e (LG <= 12, 0 <= e < 2^LG) from the LDS quarter table:
-// w^{r + 1024 c} = (-j)^c w^r.
+// w_{2^lg}^e (lg <= 12) from the LDS quarter table: w^{r + 1024 c} = (-j)^c w^r.
+struct RtTw {
+    const float2* Q;
+    __device__ __forceinline__ float2 operator()(int lg, int e) const {
+        const int E = (e << (kRTLog - lg)) & (kRT - 1);
+        const float2 a = Q[qswz(E & (kRT / 4 - 1))];
+        const int c = E >> (kRTLog - 2);
+        float re = (c & 1) ? a.y : a.x;
+        float im = (c & 1) ? -a.x : a.y;
+        if (c & 2) {
+            re = -re;
+            im = -im;
+        }
+        return make_float2(re, im);
+    }
+};
 template <int LG>
 __device__ __forceinline__ float2 wl(const float2* Q, int e) {
-    const int E = (e << (kRTLog - LG)) & (kRT - 1);
-    const float2 a = Q[qswz(E & (kRT / 4 - 1))];
-    const int c = E >> (kRTLog - 2);
-    float re = (c & 1) ? a.y : a.x;
-    float im = (c & 1) ? -a.x : a.y;
-    if (c & 2) {
-        re = -re;
-        im = -im;
-    }
-    return make_float2(re, im);
+    return RtTw{Q}(LG, e);
 }
 // Same for exponents known to lie in the first quadrant (e < 2^LG / 4).
 template <int LG>
@@ -181,7 +195,41 @@ struct RSteps {
     }
 };
 
-// Level I >= 5 of the tile.
+// A level's outputs of post job (w, k) (j = H - 1 - k): the full spectrum
+// (bins 2k, 2k+1, 2j, 2j+1 and their mirrored upper pairs), the packed slots
+// (half-spectrum output) or only their squared magnitudes (norm).
+template <int I, class O>
+__device__ __forceinline__ void real_level_out(float2* __restrict__ y, int w, int k, int j, float2 uk, float2 uj,
+                                               float2 uk1, float2 uj1, float2 ok, float2 oj, float& nrm, O& out) {
+    constexpr int L = 1 << I, M = L / 2;
+    // Full spectrum: bins 2k, 2k+1 (lower half) and the aligned upper pairs
+    // (L/2 + 2t, L/2 + 2t + 1) = (conj u[H-t], conj o[H-1-t]), t = j and t = k;
+    // bin 0 is real, bin L/2 (Nyquist) is the second half of slot 0.
+    float2* yw = y + (int64_t)w * L;
+    const float2 u0 = (k == 0) ? make_float2(uk.x, 0.0f) : uk;
+    const float2 ua = cconj(uk1);
+    const float2 ub = (k == 0) ? make_float2(uj1.y, 0.0f) : cconj(uj1);
+    const float2 oka = cconj(ok), oja = cconj(oj);
+    if constexpr (O::kReduce) {
+        nrm += norm2(u0) + norm2(ok) + norm2(uj) + norm2(oj) + norm2(ua) + norm2(oka) + norm2(ub) + norm2(oja);
+    } else if (O::kHalf) {
+        if (out.keep(I)) {                          // the packed slots themselves (slot 0 = uk at k = 0)
+            float2* yh = y + (int64_t)w * M;
+            const float2 s0 = out.sc(I, uk), s1 = out.sc(I, ok), s2 = out.sc(I, uj), s3 = out.sc(I, oj);
+            *(float4*)(yh + 2 * k) = make_float4(s0.x, s0.y, s1.x, s1.y);
+            *(float4*)(yh + 2 * j) = make_float4(s2.x, s2.y, s3.x, s3.y);
+        }
+    } else if (out.keep(I)) {
+        const float2 s0 = out.sc(I, u0), s1 = out.sc(I, ok), s2 = out.sc(I, uj), s3 = out.sc(I, oj);
+        const float2 s4 = out.sc(I, ua), s5 = out.sc(I, oka), s6 = out.sc(I, ub), s7 = out.sc(I, oja);
+        *(float4*)(yw + 2 * k) = make_float4(s0.x, s0.y, s1.x, s1.y);
+        *(float4*)(yw + 2 * j) = make_float4(s2.x, s2.y, s3.x, s3.y);
+        *(float4*)(yw + M + 2 * j) = make_float4(s4.x, s4.y, s5.x, s5.y);
+        *(float4*)(yw + M + 2 * k) = make_float4(s6.x, s6.y, s7.x, s7.y);
+    }
+}
+
+// Level I = 11 or 12 of the tile (windows spanning several waves).
 template <int I, class O>
 __device__ __forceinline__ void real_level(RealTileLds& S, float2* __restrict__ y, int tid, O& out) {
     constexpr int L = 1 << I, M = L / 2, H = M / 2, LH = I - 2;
@@ -265,54 +313,104 @@ __device__ __forceinline__ void real_level(RealTileLds& S, float2* __restrict__ 
         float2* pw = S.P + w * M;
         *(float4*)(pw + 2 * k) = make_float4(uk[c].x, uk[c].y, ok[c].x, ok[c].y);
         *(float4*)(pw + 2 * j) = make_float4(uj[c].x, uj[c].y, oj[c].x, oj[c].y);
-        // Full spectrum: bins 2k, 2k+1 (lower half) and the aligned upper pairs
-        // (L/2 + 2t, L/2 + 2t + 1) = (conj u[H-t], conj o[H-1-t]), t = j and t = k;
-        // bin 0 is real, bin L/2 (Nyquist) is the second half of slot 0.
-        float2* yw = y + (int64_t)w * L;
-        const float2 u0 = (k == 0) ? make_float2(uk[c].x, 0.0f) : uk[c];
-        const float2 ua = cconj(uk1[c]);
-        const float2 ub = (k == 0) ? make_float2(uj1[c].y, 0.0f) : cconj(uj1[c]);
-        const float2 oka = cconj(ok[c]), oja = cconj(oj[c]);
-        if constexpr (O::kReduce) {
-            nrm += norm2(u0) + norm2(ok[c]) + norm2(uj[c]) + norm2(oj[c]) + norm2(ua) + norm2(oka) + norm2(ub) +
-                   norm2(oja);
-        } else if (O::kHalf) {
-            if (out.keep(I)) {                          // the packed slots themselves (slot 0 = uk at k = 0)
-                float2* yh = y + (int64_t)w * M;
-                const float2 s0 = out.sc(I, uk[c]), s1 = out.sc(I, ok[c]), s2 = out.sc(I, uj[c]), s3 = out.sc(I, oj[c]);
-                *(float4*)(yh + 2 * k) = make_float4(s0.x, s0.y, s1.x, s1.y);
-                *(float4*)(yh + 2 * j) = make_float4(s2.x, s2.y, s3.x, s3.y);
-            }
-        } else if (out.keep(I)) {
-            const float2 s0 = out.sc(I, u0), s1 = out.sc(I, ok[c]), s2 = out.sc(I, uj[c]), s3 = out.sc(I, oj[c]);
-            const float2 s4 = out.sc(I, ua), s5 = out.sc(I, oka), s6 = out.sc(I, ub), s7 = out.sc(I, oja);
-            *(float4*)(yw + 2 * k) = make_float4(s0.x, s0.y, s1.x, s1.y);
-            *(float4*)(yw + 2 * j) = make_float4(s2.x, s2.y, s3.x, s3.y);
-            *(float4*)(yw + M + 2 * j) = make_float4(s4.x, s4.y, s5.x, s5.y);
-            *(float4*)(yw + M + 2 * k) = make_float4(s6.x, s6.y, s7.x, s7.y);
-        }
+        real_level_out<I, O>(y, w, k, j, uk[c], uj[c], uk1[c], uj1[c], ok[c], oj[c], nrm, out);
     }
     if constexpr (O::kReduce) out.add(I, nrm);
     __syncthreads();
 }
 
+// ---- levels 5..10: windows inside one wave's 1024 samples ----
+//
+// Wave v owns samples [1024 v, 1024 v + 1024) and half-spectrum slots
+// [512 v, 512 v + 512); its 256 points of the packed odd-bin FFTs (FFTs of
+// H = 2^(I-2) points) are transformed across lanes by xl_fft, then put in
+// natural order through the wave's slots; no workgroup barrier is needed.
+constexpr int kRtWaveMaxLog = 10;
+
+template <int I, class O>
+__device__ __forceinline__ void real_level_wave(RealTileLds& S, float2* __restrict__ y, int tid, O& out,
+                                                const XLane& ln) {
+    constexpr int L = 1 << I, M = L / 2, H = M / 2, n = I - 2;
+    constexpr int NQ = n - 2;                   // FFT-index bits held by the lane
+    constexpr int HJ = H / 2;                   // post jobs per window
+    const int v = tid >> 6, lane = tid & 63;
+    float2* Pb = S.P + 512 * v;
+    // ---- U^(i) of the wave's post jobs J = 64 c + lane (window J / HJ, k = J mod HJ) ----
+    float2 uk[2], uj[2], uk1[2], uj1[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const int J = 64 * c + lane;
+        const int w = J / HJ, k = J % HJ;
+        const int j = H - 1 - k;
+        const float2* c0 = Pb + (2 * w) * H;
+        uk[c] = cadd(c0[k], c0[H + k]);
+        uj[c] = cadd(c0[j], c0[H + j]);
+        uk1[c] = cadd(c0[k + 1], c0[H + k + 1]);
+        const int jn = (k == 0) ? 0 : j + 1;
+        uj1[c] = cadd(c0[jn], c0[H + jn]);
+    }
+    // ---- packed real window differences, pre-twiddled by w_M^p, p = plow + 2^NQ r ----
+    const int plow = ln.c & ((1 << (NQ < 6 ? NQ : 6)) - 1);
+    const int wl_ = NQ < 6 ? ln.c >> NQ : 0;
+    float2 a[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int p = plow + (r << NQ);
+        const int base = 1024 * v + wl_ * L;
+        const float2 lo = *(const float2*)(S.X + xsw(base + 2 * p));
+        const float2 hi = *(const float2*)(S.X + xsw(base + M + 2 * p));
+        a[r] = cmul(make_float2(lo.x - hi.x, lo.y - hi.y), wq2<I - 1>(S.Q, p));
+    }
+    xl_fft<n>(a, ln, RtTw{S.Q});
+    wave_sync();                                // U reads before the overlaying writes
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Pb[xl_fsw(xl_pos<n>(ln.c, r))] = a[r];
+    wave_sync();
+    // ---- post-processing, new half spectra and the level's output ----
+    float2 ok[2], oj[2];
+    float nrm = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const int J = 64 * c + lane;
+        const int w = J / HJ, k = J % HJ;
+        const int j = H - 1 - k;
+        const float2 zk = Pb[xl_fsw(w * H + k)], zj = Pb[xl_fsw(w * H + j)];
+        const float2 zjc = cconj(zj);
+        const float2 A = cscale(cadd(zk, zjc), 0.5f);
+        const float2 B = mul_mj(cscale(csub(zk, zjc), 0.5f));
+        const float2 T = cmul(wq1<I>(S.Q, 2 * k + 1), B);              // w_L^{2k+1}, 2k+1 < L/4
+        ok[c] = cadd(A, T);
+        oj[c] = cconj(csub(A, T));
+    }
+    wave_sync();
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const int J = 64 * c + lane;
+        const int w = J / HJ, k = J % HJ;
+        const int j = H - 1 - k;
+        const int wg = (1024 / L) * v + w;      // the window's index in the tile
+        float2* pw = Pb + w * M;
+        *(float4*)(pw + 2 * k) = make_float4(uk[c].x, uk[c].y, ok[c].x, ok[c].y);
+        *(float4*)(pw + 2 * j) = make_float4(uj[c].x, uj[c].y, oj[c].x, oj[c].y);
+        real_level_out<I, O>(y, wg, k, j, uk[c], uj[c], uk1[c], uj1[c], ok[c], oj[c], nrm, out);
+    }
+    if constexpr (O::kReduce) out.add(I, nrm);
+    if constexpr (I == kRtWaveMaxLog) __syncthreads();
+    else wave_sync();
+}
+
 template <int I, class O>
 struct RealLevels {
-    static __device__ __forceinline__ void run(RealTileLds& S, float2* __restrict__ y, int64_t ls, int tid, O& out) {
+    static __device__ __forceinline__ void run(RealTileLds& S, float2* __restrict__ y, int64_t ls, int tid, O& out,
+                                               const XLane& ln) {
         if constexpr (I <= kRTLog) {
-            real_level<I, O>(S, y + (int64_t)(I - 1) * ls, tid, out);
-            RealLevels<I + 1, O>::run(S, y, ls, tid, out);
+            if constexpr (I <= kRtWaveMaxLog) real_level_wave<I, O>(S, y + (int64_t)(I - 1) * ls, tid, out, ln);
+            else real_level<I, O>(S, y + (int64_t)(I - 1) * ls, tid, out);
+            RealLevels<I + 1, O>::run(S, y, ls, tid, out, ln);
         }
     }
 };
 
-// Orders LDS accesses of lanes of one wave (LDS executes a wave's
-// instructions in issue order; this only stops the compiler from moving them).
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // Writes one register-phase level (16 complex values per thread, one window
 // each) through the wave's private LDS region, so that every global store
@@ -478,7 +576,8 @@ __device__ __forceinline__ void real_tile_body(RealTileLds& S, const float* __re
     for (int e = tid; e < kRT / 4; e += kRThreads) S.Q[qswz(e)] = t4096[e];   // before any store
     real_local<O>(x, xsub, y, ls, S, tid, out);
     __syncthreads();
-    RealLevels<5, O>::run(S, y, ls, tid, out);
+    const XLane ln = xl_lane(tid & 63, RtTw{S.Q});
+    RealLevels<5, O>::run(S, y, ls, tid, out, ln);
 }
 
 }  // namespace mrdft
