@@ -145,9 +145,9 @@ def measured_traffic(profile, key, sources):
 
 
 C64_SOURCES = ["mrdft_fwd_c64.hip", "mrdft_tile_c64.h", "mrdft_rows_c64.h", "mrdft_device.h", "mrdft_lds_fft.h",
-               "mrdft_internal.h", "mrdft_api.hip"]
+               "mrdft_internal.h", "mrdft_api.hip", "mrdft_xlane.h"]
 R32_SOURCES = ["mrdft_fwd_real.hip", "mrdft_tile_real.h", "mrdft_rows_real.h", "mrdft_device.h", "mrdft_lds_fft.h",
-               "mrdft_internal.h", "mrdft_api.hip"]
+               "mrdft_internal.h", "mrdft_api.hip", "mrdft_xlane.h"]
 TRAFFIC = {
     ("workload4", "fused_fwd"): ("profiles/fused_c64_ragged1000.md", "fused_c64_ragged", C64_SOURCES),
     ("workload2", "fused_fwd"): ("profiles/fused_fwd_r32_b64_m16.md", "fused_fwd", R32_SOURCES),
