@@ -9,13 +9,18 @@
 // * even bins (transpose of U^(i), eq. (2)): G_i[w][2k] is added to bin k of
 //   both child windows, G_{i-1} = gY^(i-1) + U^T G_i;
 // * level 1: gx[2w] += g0 + g1, gx[2w+1] += g0 - g1.
-// The conjugate DFTs run as Stockham steps on the natural-order bins.  Only
-// Re(gx) is accumulated for a real signal (the real part is linear).  256
-// threads; 28 KB of LDS (real gx) or 36 KB (complex gx).
+// Levels 4..9 (windows inside one wave's 512 samples) run wave by wave: the
+// conjugate DFT of the odd bins goes through the cross-lane FFT of
+// mrdft_xlane.h (conjugated in and out) and one LDS pass back to natural
+// order, with no workgroup barrier; the other levels run as Stockham steps
+// on the natural-order bins.  Only Re(gx) is accumulated for a real signal
+// (the real part is linear).  256 threads; 28 KB of LDS (real gx) or 36 KB
+// (complex gx).
 #pragma once
 #include "mrdft_device.h"
 #include "mrdft_internal.h"
 #include "mrdft_tile_c64.h"
+#include "mrdft_xlane.h"
 
 namespace mrdft {
 
@@ -72,6 +77,9 @@ struct AdjSteps {
         }
     }
 };
+
+// Orders one wave's LDS accesses (the compiler may not move them across).
+__device__ __forceinline__ void wave_sync_c() { ct_wave_sync(); }
 
 template <bool REAL>
 __device__ __forceinline__ void adj_acc(AdjTileLds<REAL>& S, int i, float2 v, bool add) {
@@ -148,13 +156,92 @@ __device__ __forceinline__ void adj_level(AdjTileLds<REAL>& S, const float2* __r
     __syncthreads();
 }
 
+// Level I (4 <= I <= 9), wave by wave: wave v owns samples and A entries
+// [512 v, 512 v + 512), pairs [256 v, 256 v + 256) of P (P[512 v, 512 v +
+// 512)), bins [512 v, 512 v + 512) of gY at every level and (HALF) packed
+// slots [256 v, 256 v + 256) of H.  P holds G_I on entry and G_{I-1} on exit.
+template <int I, bool REAL, bool HALF>
+__device__ __forceinline__ void adj_level_wave(AdjTileLds<REAL>& S, const float2* __restrict__ gyl, int tid,
+                                               bool have, float hsc, const XLane& ln) {
+    constexpr int L = 1 << I, M = L / 2, n = I - 1;
+    constexpr int NQ = n - 2;                        // FFT-index bits held by the lane
+    const int v = tid >> 6, lane = tid & 63;
+    float2* Pb = S.P + 512 * v;
+    if constexpr (HALF) {
+        // the wave's packed slots of level I-1 into H (coalesced), read back
+        // through half_bin below
+        float2* Hb = S.H + 256 * v;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int p = 64 * c + lane;
+            *(float4*)(Hb + 2 * p) = have ? ((const float4*)(gyl + 256 * v))[p] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        }
+    }
+    // even bins of the wave's pairs J = 64 c + lane (window J / M, bin 2k) and
+    // the children's gradient inputs of level I-1
+    float2 e[4], nxt0[4], nxt1[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int J = 64 * c + lane;
+        const int w = J / M, k = J % M;
+        if constexpr (!HALF) {
+            nxt0[c] = have ? gyl[512 * v + 2 * w * M + k] : make_float2(0.0f, 0.0f);
+            nxt1[c] = have ? gyl[512 * v + (2 * w + 1) * M + k] : make_float2(0.0f, 0.0f);
+        }
+        e[c] = Pb[2 * J];
+    }
+    // odd bins in the cross-lane input layout (bin plow + 2^NQ r of window wl),
+    // conjugated: conj(DFT(conj(d))) is the conjugate DFT of d
+    const int plow = ln.c & ((1 << (NQ < 6 ? NQ : 6)) - 1);
+    const int wl = NQ < 6 ? ln.c >> NQ : 0;
+    float2 a[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) a[r] = cconj(Pb[2 * (wl * M + plow + (r << NQ)) + 1]);
+    xl_fft<n>(a, ln, TwQ2048{S.Q});
+    wave_sync_c();                                   // P reads before the overlaying writes
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Pb[xl_fsw(xl_pos<n>(ln.c, r))] = cconj(a[r]);
+    wave_sync_c();
+    float2 t[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) t[c] = Pb[xl_fsw(64 * c + lane)];
+    // untwiddle and scatter: +d w_L^{-q} at wL + q, - at wL + q + M
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int pq = 64 * c + lane;
+        const int w = pq / M, q = pq % M;
+        const float2 tt = cmul(t[c], adj_tw(S.Q, I, q));
+        adj_acc<REAL>(S, 512 * v + w * L + q, tt, true);
+        adj_acc<REAL>(S, 512 * v + w * L + q + M, make_float2(-tt.x, -tt.y), true);
+    }
+    wave_sync_c();                                   // scratch reads before the new G
+    // G_{I-1} = gY^(I-1) + even bins of G_I on both children
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int J = 64 * c + lane;
+        const int w = J / M, k = J % M;
+        if constexpr (HALF) {
+            nxt0[c] = half_bin(S.H + 256 * v + 2 * w * (M / 2), k, M, hsc);
+            nxt1[c] = half_bin(S.H + 256 * v + (2 * w + 1) * (M / 2), k, M, hsc);
+        }
+        Pb[2 * w * M + k] = cadd(nxt0[c], e[c]);
+        Pb[(2 * w + 1) * M + k] = cadd(nxt1[c], e[c]);
+    }
+    // the next level reads its own quarter (wave levels), or all of P
+    if constexpr (I == 4) __syncthreads();
+    else wave_sync_c();
+}
+
 template <int I, bool REAL, bool HALF>
 struct AdjLevels {
     static __device__ __forceinline__ void run(AdjTileLds<REAL>& S, const float2* __restrict__ gy, int64_t ls,
-                                               int tid, LevelRange lv, float hsc) {
+                                               int tid, LevelRange lv, float hsc, const XLane& ln) {
         if constexpr (I >= 2) {
-            adj_level<I, REAL, HALF>(S, gy + (int64_t)(I - 2) * ls, tid, lv.in(I - 1), hsc);
-            AdjLevels<I - 1, REAL, HALF>::run(S, gy, ls, tid, lv, hsc);
+            if constexpr (I >= 4 && I <= kCtWaveMaxLog)
+                adj_level_wave<I, REAL, HALF>(S, gy + (int64_t)(I - 2) * ls, tid, lv.in(I - 1), hsc, ln);
+            else
+                adj_level<I, REAL, HALF>(S, gy + (int64_t)(I - 2) * ls, tid, lv.in(I - 1), hsc);
+            AdjLevels<I - 1, REAL, HALF>::run(S, gy, ls, tid, lv, hsc, ln);
         }
     }
 };
@@ -194,7 +281,8 @@ __device__ __forceinline__ void adj_tile_body(AdjTileLds<REAL>& S, const float2*
         }
     }
     __syncthreads();
-    AdjLevels<kCTLog, REAL, HALF>::run(S, gy, ls, tid, lv, hsc);
+    const XLane ln = xl_lane(tid & 63, TwQ2048{S.Q});
+    AdjLevels<kCTLog, REAL, HALF>::run(S, gy, ls, tid, lv, hsc, ln);
     // level 1: windows of two
 #pragma unroll
     for (int r = 0; r < kCT / 2 / kCThreads; ++r) {
