@@ -1073,7 +1073,7 @@ mrdft_status run_adjoint(mrdft_plan* p, const float2* gY, void* gx, bool real_ou
 // the plan's own); only: that one level (0: every level).
 mrdft_status upper_passes(mrdft_plan* p, const float* x, float2* W, hipStream_t s, bool full_layout = false,
                           double* norms = nullptr, bool half = false, float2* const* scr = nullptr,
-                          int only = 0) {
+                          int only = 0, const float* out_scale = nullptr) {
     float2* const* ds = scr ? scr : p->d_s;           // ping-pong scratch of the stream s
     const Twiddles tw = p->tw();
     const int64_t N = int64_t(1) << p->m;
@@ -1106,7 +1106,11 @@ mrdft_status upper_passes(mrdft_plan* p, const float* x, float2* W, hipStream_t 
                     ok = OUT_NORM;
                 } else if (last) {
                     out = (void*)(W + (int64_t)slot * (N >> (half ? 1 : 0)));
-                    if (half) ok = OUT_HALF;
+                    if (half) {
+                        ok = OUT_HALF;
+                        geo.out_scale = out_scale;              // uniform batches only (one group)
+                        geo.out_scale_m = p->m;
+                    }
                 }
                 ProfScope ps(p, MRDFT_KERNEL_PASS_FWD, s);
                 HIP_TRY(launch_pass(false, first ? IN_R32 : IN_C64, ok, in, out, geo, tw, s));
@@ -1779,12 +1783,13 @@ mrdft_status mrdft_spectral_loss_bwd(mrdft_plan_t plan, const float* x, const fl
         // gradient factor (levels 1..16 in the one-launch forward), as packed
         // half spectra (x - z is real: its level spectra are Hermitian, and
         // the real adjoint of the packed values is the gradient), then the adjoint.
-        // Levels above 16 (unscaled, scaled afterwards) run on side streams
-        // when the plan has one per level: x - z and its passes beside the
-        // one-launch forward.
+        // Levels above 16 run on side streams when the plan has one per
+        // level: x - z and its passes beside the one-launch forward, the last
+        // pass of each level storing its packed spectra already scaled.
         const bool upper = plan->m > kRowsMaxLevel;
         const int nup = plan->m - kRowsMaxLevel;
         const bool par = upper && plan->nsides >= nup;
+        HIP_TRY(launch_loss_alpha(num_den, gL, plan->d_alpha, rows, plan->m, stream));
         if (par) {
             HIP_TRY(hipEventRecord(plan->fork_ev, stream));
             HIP_TRY(hipStreamWaitEvent(plan->side[0], plan->fork_ev, 0));
@@ -1794,12 +1799,11 @@ mrdft_status mrdft_spectral_loss_bwd(mrdft_plan_t plan, const float* x, const fl
                 const hipStream_t sk = plan->side[k];
                 if (k) HIP_TRY(hipStreamWaitEvent(sk, plan->join_ev[0], 0));
                 st = upper_passes(plan, plan->d_v, plan->d_Yv, sk, true, nullptr, true,
-                                  k ? plan->d_ss[k - 1] : plan->d_s, kRowsMaxLevel + 1 + k);
+                                  k ? plan->d_ss[k - 1] : plan->d_s, kRowsMaxLevel + 1 + k, plan->d_alpha);
                 if (st) return st;
             }
             for (int k = 0; k < nup; ++k) HIP_TRY(hipEventRecord(plan->join_ev[k], plan->side[k]));
         }
-        HIP_TRY(launch_loss_alpha(num_den, gL, plan->d_alpha, rows, plan->m, stream));
         {
             ProfScope ps(plan, MRDFT_KERNEL_LOSS, stream);
             HIP_TRY(launch_fwd_real_scaled(x, z, plan->d_alpha, plan->m, plan->d_Yv, plan->d_ljobs, plan->nljobs,
@@ -1810,11 +1814,9 @@ mrdft_status mrdft_spectral_loss_bwd(mrdft_plan_t plan, const float* x, const fl
                 for (int k = 0; k < nup; ++k) HIP_TRY(hipStreamWaitEvent(stream, plan->join_ev[k], 0));
             } else {
                 HIP_TRY(launch_sub_real(x, z, plan->d_v, plan->n_in, stream));
-                st = upper_passes(plan, plan->d_v, plan->d_Yv, stream, true, nullptr, true);
+                st = upper_passes(plan, plan->d_v, plan->d_Yv, stream, true, nullptr, true, nullptr, 0, plan->d_alpha);
                 if (st) return st;
             }
-            HIP_TRY(launch_scale_levels(plan->d_Yv, num_den, gL, plan->m, N / 2,
-                                        plan->batch * (plan->m - kRowsMaxLevel), stream, kRowsMaxLevel));
         }
         return run_adjoint(plan, plan->d_Yv, gx, true, stream, true);
     }

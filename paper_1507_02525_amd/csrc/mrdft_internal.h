@@ -55,6 +55,11 @@ struct PassGeom {
     const int64_t* out_sig;
     int64_t out_stride;
     float half_scale = 0.5f;   // IN_HALF: scale of half_bin
+    // OUT_HALF, if set: the outputs of signal b (of a uniform batch) are
+    // multiplied by out_scale[b * out_scale_m + lg - 1] (the loss gradient's
+    // per-level factors)
+    const float* out_scale = nullptr;
+    int out_scale_m = 0;
 };
 
 // IN_HALF: a real plan's packed half-spectrum gradient (window W at W * L/2),

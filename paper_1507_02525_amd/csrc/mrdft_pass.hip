@@ -158,6 +158,7 @@ __global__ __launch_bounds__(PassShape<LP>::kThreads) void pass_kernel(const voi
     column_fft<LP, INV>(B, rl, T, tid);
 
     double nacc = 0.0;                                 // OUT_NORM: this thread's squared magnitudes
+    const float osc = (OUT_KIND == OUT_HALF && g.out_scale) ? g.out_scale[b * g.out_scale_m + g.lg - 1] : 1.0f;
     for (int e = tid; e < nval; e += kPassThreads) {
         int jj, s;
         int64_t o;
@@ -182,9 +183,10 @@ __global__ __launch_bounds__(PassShape<LP>::kThreads) void pass_kernel(const voi
             // Nyquist real parts share slot 0, the upper half is dropped
             const int64_t k = o - ob;
             float* sl = (float*)((float2*)out + ob);
-            if (k == 0) sl[0] = v.x;
-            else if (k == L / 2) sl[1] = v.x;
-            else if (k < L / 2) ((float2*)out)[o] = v;
+            const float2 w = g.out_scale ? make_float2(v.x * osc, v.y * osc) : v;
+            if (k == 0) sl[0] = w.x;
+            else if (k == L / 2) sl[1] = w.x;
+            else if (k < L / 2) ((float2*)out)[o] = w;
         } else if constexpr (OUT_KIND == OUT_ADD_C64) {
             float2* p = (float2*)out + o;
             *p = cadd(*p, v);
