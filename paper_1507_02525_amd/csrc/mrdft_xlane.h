@@ -1,8 +1,10 @@
 // In-wave FFTs of 256 points (4 per lane) with butterflies across lanes.
 //
-// Shared by the forward tiles: at each level of the recurrence (Section 3,
-// eq. (4)) the odd bins of every window are the DFT of a twiddled window
-// difference (eq. (3), D^(i), F^(i)).  For windows that fit in one wave the
+// Shared by the forward tiles and the adjoint tile: at each level of the
+// recurrence (Section 3, eq. (4)) the odd bins of every window are the DFT of
+// a twiddled window difference (eq. (3), D^(i), F^(i)); the adjoint takes the
+// conjugate DFT of the odd-bin gradient (conjugating input and output).  For
+// windows that fit in one wave the
 // wave's 256 FFT points (256 / 2^n windows of 2^n points, 3 <= n <= 8) are
 // transformed in registers:
 //
