@@ -1789,12 +1789,21 @@ mrdft_status mrdft_spectral_loss_bwd(mrdft_plan_t plan, const float* x, const fl
         // half spectra (x - z is real: its level spectra are Hermitian, and
         // the real adjoint of the packed values is the gradient), then the adjoint.
         // Levels above 16 run on side streams when the plan has one per
-        // level: x - z and its passes beside the one-launch forward, the last
-        // pass of each level storing its packed spectra already scaled.
+        // level, after the one-launch forward was issued (passes started
+        // beside it were starved; this order saved ~20 us per forward +
+        // backward on 32 x 2^18): x - z and its passes, the last pass of each
+        // level storing its packed spectra already scaled.  The adjoint's
+        // chain of each level follows on the same side stream, so the
+        // caller's stream does not wait for these passes.
         const bool upper = plan->m > kRowsMaxLevel;
         const int nup = plan->m - kRowsMaxLevel;
         const bool par = upper && plan->nsides >= nup;
         HIP_TRY(launch_loss_alpha(num_den, gL, plan->d_alpha, rows, plan->m, stream));
+        {
+            ProfScope ps(plan, MRDFT_KERNEL_LOSS, stream);
+            HIP_TRY(launch_fwd_real_scaled(x, z, plan->d_alpha, plan->m, plan->d_Yv, plan->d_ljobs, plan->nljobs,
+                                           plan->tw(), stream, true));
+        }
         if (par) {
             HIP_TRY(hipEventRecord(plan->fork_ev, stream));
             HIP_TRY(hipStreamWaitEvent(plan->side[0], plan->fork_ev, 0));
@@ -1809,14 +1818,9 @@ mrdft_status mrdft_spectral_loss_bwd(mrdft_plan_t plan, const float* x, const fl
             }
             for (int k = 0; k < nup; ++k) HIP_TRY(hipEventRecord(plan->join_ev[k], plan->side[k]));
         }
-        {
-            ProfScope ps(plan, MRDFT_KERNEL_LOSS, stream);
-            HIP_TRY(launch_fwd_real_scaled(x, z, plan->d_alpha, plan->m, plan->d_Yv, plan->d_ljobs, plan->nljobs,
-                                           plan->tw(), stream, true));
-        }
         if (upper) {
             if (par) {
-                for (int k = 0; k < nup; ++k) HIP_TRY(hipStreamWaitEvent(stream, plan->join_ev[k], 0));
+                // read only by the adjoint's chains on the same side streams
             } else {
                 HIP_TRY(launch_sub_real(x, z, plan->d_v, plan->n_in, stream));
                 st = upper_passes(plan, plan->d_v, plan->d_Yv, stream, true, nullptr, true, nullptr, 0, plan->d_alpha);
