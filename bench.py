@@ -53,6 +53,9 @@ def parse():
     ap.add_argument("--extra", default=",".join(SIDE_NAMES),
                     help="comma-separated side workloads (%s)" % ",".join(SIDE_NAMES))
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-level comparators")
+    ap.add_argument("--side-only", action="store_true",
+                    help="profiling aid: run only the --extra side workloads (no headline, no CPU baseline) "
+                         "and print their JSON object")
     ap.add_argument("--tune-cache", default="",
                     help="tuning cache file (MRDFT_TUNE_CACHE): a second run reuses the schedules")
     return ap.parse_args()
@@ -553,6 +556,13 @@ def side_workload2d(args, sync):
     return r
 
 
+SIDE_FN = {"workload2": lambda args, sync: side_workload2(args, sync),
+           "workload2_half": lambda args, sync: side_workload2(args, sync, half=True),
+           "workload3": side_workload3,
+           "workload5": side_workload5,
+           "workload2d": side_workload2d}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -571,7 +581,7 @@ def main():
 
     # the host oracle first: its worker processes are forked before the GPU is touched
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not args.side_only:
         workers = args.cpu_workers or min(16, os.cpu_count() or 1)
         cpu = cpu_baseline(workloads.make(4), workers)
 
@@ -584,6 +594,11 @@ def main():
             dst.copy_(src)
         sync()
         del src, dst
+
+    if args.side_only:
+        side = {n: SIDE_FN[n](args, sync) for n in names}
+        print(json.dumps({"side_only": True, "steps": args.steps, "side_workloads": side}), flush=True)
+        return
 
     h, _ = headline(args, sync)
 
@@ -602,14 +617,7 @@ def main():
     del big, big2
     torch.cuda.empty_cache()
 
-    side = {}
-    for n in names:
-        fn = {"workload2": lambda: side_workload2(args, sync),
-              "workload2_half": lambda: side_workload2(args, sync, half=True),
-              "workload3": lambda: side_workload3(args, sync),
-              "workload5": lambda: side_workload5(args, sync),
-              "workload2d": lambda: side_workload2d(args, sync)}[n]
-        side[n] = fn()
+    side = {n: SIDE_FN[n](args, sync) for n in names}
 
     out = {
         "metric": "MrDFT Gsamples/s & % HBM peak, fwd and fwd+bwd, vs per-level form, rel err<=1e-6",
