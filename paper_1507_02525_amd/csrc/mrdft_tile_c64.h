@@ -5,8 +5,8 @@
 // * even bins: U^(i) (eq. (2)), Y^(i)[w][2k] = Y^(i-1)[2w][k] + Y^(i-1)[2w+1][k];
 // * odd bins: V^(i), D^(i), F^(i) (eq. (3)): the L/2-point DFT of the window
 //   difference d[q] = x[wL + q] - x[wL + q + L/2] twiddled by w_L^q,
-//   Y^(i)[w][2k+1] = DFT(d)[k].  The DFT runs as Stockham steps (natural
-//   order out, so the bit reversal of Section 3 is never executed).
+//   Y^(i)[w][2k+1] = DFT(d)[k].  The bins are put in natural order in LDS
+//   (the bit reversal of Section 3 is never executed).
 // Levels 1..3 run in registers (one 8-sample window per thread) and are
 // written through wave-private LDS staging, so that every store instruction
 // covers 1 KB of consecutive output.  Levels 4..9 (windows inside one wave's
@@ -14,9 +14,10 @@
 // registers (4 per lane), the first radix-4 stage runs in registers and the
 // others as cross-lane butterflies (DPP within rows of 16 lanes, permlane
 // swaps across them), with one pass through LDS to put the bins in natural
-// order.  Levels 10 and 11 run as radix-4 Stockham steps in LDS.  U^(i) is
-// formed first and kept in registers, which lets the FFT work space overlay
-// the level spectra.
+// order.  Levels 10 and 11 take one radix-4 stage in registers and one
+// exchange between waves through LDS, after which the same cross-lane FFT
+// finishes each wave's sub-FFTs.  U^(i) is formed first and kept in
+// registers, which lets the FFT work space overlay the level spectra.
 #pragma once
 #include "mrdft_device.h"
 #include "mrdft_internal.h"
@@ -37,8 +38,8 @@ struct CTileLds {
 static_assert(sizeof(CTileLds) <= 40 * 1024 - 256, "four workgroups per CU");
 
 // w_{2^lg}^e (lg <= 11) from the quarter table q[r] = w_2048^r, r < 512:
-// w^{r + 512 c} = (-j)^c w^r.  Entry r sits at r ^ ((r >> 5) & 15): the
-// twiddles of one Stockham step (a power-of-two stride) spread over the banks.
+// w^{r + 512 c} = (-j)^c w^r.  Entry r sits at r ^ ((r >> 5) & 15): twiddles
+// at a power-of-two stride (one FFT stage) spread over the banks.
 __device__ __forceinline__ int cqswz(int r) { return r ^ ((r >> 5) & 15); }
 struct TwQ2048 {
     const float2* q;
@@ -56,8 +57,9 @@ struct TwQ2048 {
     }
 };
 
-// FFT work space index: one spare element after every 32 (bank spread of the
-// strided Stockham accesses); 1024 points need 1056 slots of P.
+// FFT work space index of the adjoint tile's Stockham steps: one spare
+// element after every 32 (bank spread of the strided accesses); 1024 points
+// need 1056 slots of P.
 __device__ __forceinline__ int cfpad(int i) { return i + (i >> 5); }
 
 // Sample index in X: bits 4..6 folded into bits 1..3 (bit 0 kept, so sample
@@ -85,106 +87,6 @@ __device__ __forceinline__ void ct_wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// One radix-4 Stockham step over the tile's 1024 FFT points (FFTs of M
-// points stored contiguously per window in F, padded), span 2^LNS before the
-// step; one job per thread.
-template <int M, int LNS>
-__device__ __forceinline__ void ct_step(float2* F, const float2* Q, int tid) {
-    constexpr int PER = M / 4;
-    constexpr int NS = 1 << LNS;
-    static_assert(kCT / 2 / 4 == kCThreads, "one job per thread");
-    const int w = tid / PER, j = tid % PER;
-    float2 v[4];
-#pragma unroll
-    for (int s = 0; s < 4; ++s) v[s] = F[cfpad(w * M + j + s * PER)];
-    if constexpr (LNS > 0) {
-        const int jm = j & (NS - 1);
-#pragma unroll
-        for (int s = 1; s < 4; ++s) v[s] = cmul(v[s], TwQ2048{Q}(LNS + 2, jm * s));
-    }
-    dft_reg<4, false>(v);
-    __syncthreads();
-    const int base = w * M + ((j >> LNS) << (LNS + 2)) + (j & (NS - 1));
-#pragma unroll
-    for (int s = 0; s < 4; ++s) F[cfpad(base + s * NS)] = v[s];
-    __syncthreads();
-}
-
-template <int M, int LNS, int LM>
-struct CtSteps {
-    static __device__ __forceinline__ void run(float2* F, const float2* Q, int tid) {
-        if constexpr (LNS < LM) {
-            ct_step<M, LNS>(F, Q, tid);
-            CtSteps<M, LNS + 2, LM>::run(F, Q, tid);
-        }
-    }
-};
-
-// Level I = 10 or 11 of the tile (windows spanning several waves): radix-4
-// Stockham steps through LDS; y points at this level's output.
-template <int I, bool MULTI>
-__device__ __forceinline__ void ct_level_lds(CTileLds& S, float2* __restrict__ y, int tid, bool store,
-                                             const SubMap& sm) {
-    constexpr int L = 1 << I, M = L / 2, LM = I - 1;
-    constexpr int NW = kCT / L;
-    constexpr int PPT = NW * M / kCThreads;              // (w, k) jobs per thread
-    constexpr int R1 = (LM & 1) ? 2 : 4;                 // first FFT step radix
-    constexpr int LR1 = (R1 == 2) ? 1 : 2;
-    float2* F = S.P;
-    // ---- U^(i): even bins from the two child windows (length M each) ----
-    float2 u[PPT];
-#pragma unroll
-    for (int c = 0; c < PPT; ++c) {
-        const int J = tid + c * kCThreads;
-        const int w = J / M, k = J % M;
-        u[c] = cadd(S.P[2 * w * M + k], S.P[(2 * w + 1) * M + k]);
-    }
-    __syncthreads();
-    // ---- first FFT step fused with the twiddled difference d[q] w_L^q ----
-    {
-        constexpr int PER = M / R1;
-        constexpr int JPT = NW * PER / kCThreads;
-        float2 v[JPT][R1];
-#pragma unroll
-        for (int c = 0; c < JPT; ++c) {
-            const int J = tid + c * kCThreads;
-            const int w = J / PER, j = J % PER;
-#pragma unroll
-            for (int s = 0; s < R1; ++s) {
-                const int q = j + s * PER;
-                v[c][s] = cmul(csub(S.X[cx(w * L + q)], S.X[cx(w * L + q + M)]), TwQ2048{S.Q}(I, q));
-            }
-            dft_reg<R1, false>(v[c]);
-        }
-#pragma unroll
-        for (int c = 0; c < JPT; ++c) {
-            const int J = tid + c * kCThreads;
-            const int w = J / PER, j = J % PER;
-#pragma unroll
-            for (int s = 0; s < R1; ++s) F[cfpad(w * M + j * R1 + s)] = v[c][s];
-        }
-        __syncthreads();
-    }
-    CtSteps<M, LR1, LM>::run(F, S.Q, tid);
-    // ---- odd bins, new spectra, output (u, D) pairs ----
-    float2 d[PPT];
-#pragma unroll
-    for (int c = 0; c < PPT; ++c) {
-        const int J = tid + c * kCThreads;
-        const int w = J / M, k = J % M;
-        d[c] = F[cfpad(w * M + k)];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < PPT; ++c) {
-        const int J = tid + c * kCThreads;          // = w * M + k: the pair (2k, 2k+1) of window w
-        const float4 pr = make_float4(u[c].x, u[c].y, d[c].x, d[c].y);
-        *(float4*)(S.P + 2 * J) = pr;
-        if (store && (!MULTI || 2 * J < sm.vlen)) store_out(y + sm.off<MULTI>(2 * J), pr);
-    }
-    __syncthreads();
 }
 
 // ---- levels 4..9: one wave per 512 samples, butterflies across lanes ----
@@ -242,6 +144,86 @@ __device__ __forceinline__ void ct_level_wave(CTileLds& S, float2* __restrict__ 
     else ct_wave_sync();
 }
 
+// Level I = 10 or 11 (windows spanning two or four waves).  The odd-bin FFT
+// of M = 2^n points (n = I - 1) per window: a radix-4 stage over the two top
+// index bits (lane l, register r holding point qlow + (M/4) r, qlow from the
+// lane's content bits and the wave), one exchange through LDS after which
+// each wave holds whole sub-FFTs of M/4 points (one of 256 at level 11, two of
+// 128 at level 10: sub-FFT s = window * 4 + first-stage digit), xl_fft on
+// them, and one pass through LDS back to natural order (index p ^ ((p >>
+// (n-4)) & 15): the bins a 16-lane row scatters then differ in their low bits).
+template <int I, bool MULTI>
+__device__ __forceinline__ void ct_level_x(CTileLds& S, float2* __restrict__ y, int tid, bool store,
+                                           const SubMap& sm, const XLane& ln) {
+    constexpr int L = 1 << I, M = L / 2, n = I - 1;
+    constexpr int Q4 = M / 4;                           // sub-FFT size
+    constexpr int NS = n - 2;                           // its index bits: 8 or 7
+    constexpr int SH = n - 4;                           // natural-order swizzle shift
+    static_assert(I == 10 || I == 11, "levels whose windows span several waves");
+    const int v = tid >> 6;
+    float2* F = S.P;
+    // ---- U^(i): even bins from the two child windows (pairs J = tid + 256 c) ----
+    float2 u[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int J = tid + c * kCThreads;
+        const int w = J / M, k = J % M;
+        u[c] = cadd(S.P[2 * w * M + k], S.P[(2 * w + 1) * M + k]);
+    }
+    __syncthreads();
+    // ---- radix 4 over the top two index bits of the twiddled differences ----
+    const int qb = I == 11 ? v : (v & 1);               // index bits above the lane's six
+    const int wb = I == 11 ? 0 : (v >> 1);              // window (level 10)
+    const int qlow = ln.c + 64 * qb;                    // < M/4
+    float2 a[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int q = qlow + Q4 * r;
+        const int e = wb * L + q;
+        a[r] = cmul(csub(S.X[cx(e)], S.X[cx(e + M)]), TwQ2048{S.Q}(I, q));
+    }
+    dft_reg<4, false>(a);
+#pragma unroll
+    for (int f = 1; f < 4; ++f) a[f] = cmul(a[f], TwQ2048{S.Q}(n, qlow * f));
+    // ---- exchange: sub-FFT s = window * 4 + digit, point qlow ----
+#pragma unroll
+    for (int r = 0; r < 4; ++r) F[(wb * 4 + r) * Q4 + qlow] = a[r];
+    __syncthreads();
+    // the wave's sub-FFT(s) in the xl_fft<NS> layout: point plow + 2^(NS-2) r'
+    // of sub-FFT s (level 11: s = v; level 10: s = 2 v + content bit 5)
+    const int plow = ln.c & ((1 << (NS - 2)) - 1);
+    const int s0 = I == 11 ? v : 2 * v + (ln.c >> 5);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) a[r] = F[s0 * Q4 + plow + (r << (NS - 2))];
+    xl_fft<NS>(a, ln, TwQ2048{S.Q});
+    __syncthreads();                                    // every wave's exchange reads before the writes
+    // ---- bins to natural order: window s >> 2, bin (s & 3) + 4 k' ----
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int pos = xl_pos<NS>(ln.c, r);
+        const int s = I == 11 ? v : 2 * v + (pos >> 7);
+        const int kp = I == 11 ? pos : (pos & 127);
+        const int P = (s >> 2) * M + (s & 3) + 4 * kp;
+        F[P ^ ((P >> SH) & 15)] = a[r];
+    }
+    __syncthreads();
+    float2 d[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int J = tid + c * kCThreads;
+        d[c] = F[J ^ ((J >> SH) & 15)];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int J = tid + c * kCThreads;          // = w * M + k: the pair (2k, 2k+1) of window w
+        const float4 pr = make_float4(u[c].x, u[c].y, d[c].x, d[c].y);
+        *(float4*)(S.P + 2 * J) = pr;
+        if (store && (!MULTI || 2 * J < sm.vlen)) store_out(y + sm.off<MULTI>(2 * J), pr);
+    }
+    __syncthreads();
+}
+
 template <int I, bool MULTI>
 struct CtLevels {
     static __device__ __forceinline__ void run(CTileLds& S, float2* __restrict__ y, int64_t ls, int tid,
@@ -251,7 +233,7 @@ struct CtLevels {
             if constexpr (I <= kCtWaveMaxLog)
                 ct_level_wave<I, MULTI>(S, y + (int64_t)(I - 1) * ls, tid, lv.in(I), sm, ln);
             else
-                ct_level_lds<I, MULTI>(S, y + (int64_t)(I - 1) * ls, tid, lv.in(I), sm);
+                ct_level_x<I, MULTI>(S, y + (int64_t)(I - 1) * ls, tid, lv.in(I), sm, ln);
             CtLevels<I + 1, MULTI>::run(S, y, ls, tid, lv, sm, ln);
         }
     }
