@@ -72,6 +72,12 @@ std::vector<int> pass_bits(int lg) {
     return b;
 }
 
+// Lowest level of a forward recurrence chain: levels whose direct chain needs
+// three passes are built from the level below (even bins, eq. (2)) and the
+// half-length DFT of the twiddled difference (odd bins, eq. (3)): per level
+// the passes move 4 (level 19) or 5 units of 8N bytes instead of 6.
+constexpr int kRecMinLevel = 2 * kPassMaxLog + 1;
+
 }  // namespace
 
 struct mrdft_plan {
@@ -164,6 +170,10 @@ struct mrdft_plan {
     hipStream_t side[kSides] = {nullptr, nullptr, nullptr, nullptr};
     hipEvent_t fork_ev = nullptr;
     hipEvent_t join_ev[kSides] = {nullptr, nullptr, nullptr, nullptr};
+    // forward: end of level i's chain, awaited by the recurrence chain of
+    // level i + 1 on another side stream (created with the side streams when
+    // some signal has a level >= kRecMinLevel)
+    hipEvent_t lvl_ev[MRDFT_MAX_ORDER + 1] = {};
     int nsides = 0;
     bool serial = false;                    // forward: every launch on the caller's stream (tuned choice)
     bool after = false;                     // forward: side-stream levels start after the main launch (tuned choice)
@@ -191,6 +201,8 @@ void free_plan(mrdft_plan* p) {
     }
     for (auto e : p->event_pool) (void)hipEventDestroy(e);
     if (p->fork_ev) (void)hipEventDestroy(p->fork_ev);
+    for (auto e : p->lvl_ev)
+        if (e) (void)hipEventDestroy(e);
     for (int k = 0; k < p->nsides; ++k) {
         if (p->join_ev[k]) (void)hipEventDestroy(p->join_ev[k]);
         if (p->side[k]) (void)hipStreamDestroy(p->side[k]);
@@ -517,6 +529,9 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
             HIP_TRY(hipEventCreateWithFlags(&p->join_ev[k], hipEventDisableTiming));
             p->nsides = k + 1;
         }
+        if (p->max_order >= kRecMinLevel)
+            for (int i = kRecMinLevel - 1; i < p->max_order; ++i)
+                HIP_TRY(hipEventCreateWithFlags(&p->lvl_ev[i], hipEventDisableTiming));
     }
     if (scratch > 0) {
         // one ping-pong pair per side stream: chains of passes of different
@@ -888,27 +903,39 @@ mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, h
                 HIP_TRY(launch_upper_fwd(in_kind == IN_R32, x, level_ptr(p, Y, i, N), geo, tw, s));
                 continue;
             }
-            const std::vector<int> bits = pass_bits(i);
+            // recurrence chain: level i - 1 is stored by this plan (a chain
+            // of this loop, ended by lvl_ev[i - 1] on the side streams)
+            const bool rec = i >= kRecMinLevel && i - 1 >= p->lo && !p->hs;
+            const int dl = rec ? i - 1 : i;            // order of the DFTs of the chain
+            const std::vector<int> bits = pass_bits(dl);
+            const int64_t wlen = rec ? N / 2 : N;      // scratch points per signal
             int ns = 0;
             for (size_t q = 0; q < bits.size(); ++q) {
                 const bool first = q == 0, last = q + 1 == bits.size();
                 PassGeom geo;
-                geo.lg = i;
+                geo.lg = dl;
                 geo.r_log = bits[q];
                 geo.ns_log = ns;
                 geo.nwin = g.count * (N >> i);
                 geo.wps = N >> i;
                 geo.in_sig = first ? g.d_in_sig : nullptr;
-                geo.in_stride = N;
+                geo.in_stride = first ? N : wlen;
                 geo.out_sig = last ? g.d_out_sig : nullptr;
-                geo.out_stride = last ? (int64_t)p->kept(g.order) * (N >> p->hs) : N;
+                geo.out_stride = last ? (int64_t)p->kept(g.order) * (N >> p->hs) : wlen;
+                geo.rec_prev = (rec && last) ? N : 0;
                 const void* in = first ? x : (const void*)ds[(q - 1) & 1];
                 void* out = last ? (void*)level_ptr(p, Y, i, N >> p->hs) : (void*)ds[q & 1];
-                const int ok = (last && p->hs) ? OUT_HALF : OUT_STORE;
+                const int ik = !first ? IN_C64 : !rec ? in_kind : in_kind == IN_R32 ? IN_DIFF_R32 : IN_DIFF;
+                const int ok = (last && p->hs) ? OUT_HALF : (last && rec) ? OUT_REC : OUT_STORE;
+                if (last && rec && nsides) {
+                    if (!p->lvl_ev[i - 1]) return fail(MRDFT_E_HIP, "no event for level %d", i - 1);
+                    HIP_TRY(hipStreamWaitEvent(s, p->lvl_ev[i - 1], 0));
+                }
                 ProfScope ps(p, MRDFT_KERNEL_PASS_FWD, s);
-                HIP_TRY(launch_pass(false, first ? in_kind : IN_C64, ok, in, out, geo, tw, s));
+                HIP_TRY(launch_pass(false, ik, ok, in, out, geo, tw, s));
                 ns += bits[q];
             }
+            if (i < g.order && p->lvl_ev[i] && nsides) HIP_TRY(hipEventRecord(p->lvl_ev[i], s));
         }
     }
     return MRDFT_OK;

@@ -60,15 +60,25 @@ struct PassGeom {
     // per-level factors)
     const float* out_scale = nullptr;
     int out_scale_m = 0;
+    // OUT_REC: elements from a window of level lg + 1 back to the same
+    // position of level lg in the output (the signal length N)
+    int64_t rec_prev = 0;
 };
 
 // IN_HALF: a real plan's packed half-spectrum gradient (window W at W * L/2),
 // read through half_bin; first passes of the adjoint only (OUT_STORE).
-enum InKind { IN_C64 = 0, IN_R32 = 1, IN_HALF = 2 };
+// IN_DIFF, IN_DIFF_R32: odd bins of level lg + 1 (Section 3, eq. (3)): the
+// L-point sequence of window W (L = 2^lg) is (x[n] - x[n + L]) w_{2L}^n, with
+// x[n] the n-th sample of window W of level lg + 1 (at W * 2L); first passes
+// only (OUT_STORE).
+enum InKind { IN_C64 = 0, IN_R32 = 1, IN_HALF = 2, IN_DIFF = 3, IN_DIFF_R32 = 4 };
 // OUT_HALF: store packed half spectra (window W at W * L/2, slot 0 = (Y[0], Y[L/2])).
 // OUT_NORM: nothing stored; the squared magnitudes of signal b's level lg are
 // added (FP64) to ((double*)out)[b * out_stride + lg - 1].
-enum OutKind { OUT_STORE = 0, OUT_ADD_C64 = 1, OUT_ADD_R32 = 2, OUT_HALF = 3, OUT_NORM = 4 };
+// OUT_REC: the last pass of an IN_DIFF chain stores window W of level lg + 1
+// (at W * 2L): bin 2k + 1 is the pass output k, bin 2k the sum of bin k of
+// the two child windows of level lg, read rec_prev elements back (eq. (2)).
+enum OutKind { OUT_STORE = 0, OUT_ADD_C64 = 1, OUT_ADD_R32 = 2, OUT_HALF = 3, OUT_NORM = 4, OUT_REC = 5 };
 
 struct Twiddles {
     const float2* tile;   // w_{4096}^e, e < 4096 (FP32, rounded once from FP64)

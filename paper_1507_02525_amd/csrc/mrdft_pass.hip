@@ -22,6 +22,15 @@
 // first row s0 and forms its further rows s0 + 16 i by FP64 multiplication
 // (no scattered table reads per element).  With INV the conjugate kernel is used (adjoint), and the last
 // pass can accumulate into the gradient instead of storing.
+//
+// Recurrence chains (the levels whose window of L = 2^lg points needs three
+// passes): level lg is built from level lg - 1 as Section 3 does on chip.
+// The odd bins are the L/2-point DFT of the twiddled difference of the
+// window's halves (eq. (3)): the first pass forms it while loading x
+// (IN_DIFF), so the chain moves half the points.  The even bins are the sums
+// of the child windows' bins at level lg - 1 (eq. (2)): the last pass
+// (OUT_REC) loads those with its data and stores both bins of each k side by
+// side.
 #include "mrdft_internal.h"
 #include "mrdft_lds_fft.h"
 
@@ -100,18 +109,19 @@ __global__ __launch_bounds__(PassShape<LP>::kThreads) void pass_kernel(const voi
     const int64_t gwin = blk / jblocks;
     const int64_t j0 = (blk - gwin * jblocks) << lnc;
     const int64_t b = gwin / g.wps, W = gwin - b * g.wps;
-    const int64_t ib = (g.in_sig ? g.in_sig[b] : b * g.in_stride) + W * (IN_KIND == IN_HALF ? L / 2 : L);
-    const int64_t ob = (g.out_sig ? g.out_sig[b] : b * g.out_stride) + W * (OUT_KIND == OUT_HALF ? L / 2 : L);
+    constexpr bool kDiff = IN_KIND == IN_DIFF || IN_KIND == IN_DIFF_R32;
+    const int64_t ib = (g.in_sig ? g.in_sig[b] : b * g.in_stride) + W * (IN_KIND == IN_HALF ? L / 2 : kDiff ? 2 * L : L);
+    const int64_t ob =
+        (g.out_sig ? g.out_sig[b] : b * g.out_stride) + W * (OUT_KIND == OUT_HALF ? L / 2 : OUT_KIND == OUT_REC ? 2 * L : L);
     const int tid = threadIdx.x;
     const int ns_log = g.ns_log;
     const int64_t nsm = ((int64_t)1 << ns_log) - 1;
-    const int nval = kPassPoints;
+    constexpr int kRowsPerThread = kPassPoints / kPassThreads;
 
     {
         // thread: column jj = tid mod nc, rows s = s0 + (256 / nc) i (s0 = tid / nc),
         // 16 rows per thread; all of the thread's loads are issued before the
         // first one is used
-        constexpr int kRowsPerThread = kPassPoints / kPassThreads;
         const int jj = tid & (nc - 1), s0 = tid >> lnc;
         const int rstep = kPassThreads >> lnc;
         const int64_t j = j0 + jj;
@@ -129,6 +139,13 @@ __global__ __launch_bounds__(PassShape<LP>::kThreads) void pass_kernel(const voi
             const int64_t idx = ib + j + (int64_t)s * cols;
             if constexpr (IN_KIND == IN_R32) {
                 v[i] = make_float2(__builtin_nontemporal_load((const float*)in + idx), 0.0f);
+            } else if constexpr (IN_KIND == IN_DIFF_R32) {
+                const float* xr = (const float*)in + idx;
+                v[i] = make_float2(__builtin_nontemporal_load(xr) - __builtin_nontemporal_load(xr + L), 0.0f);
+            } else if constexpr (IN_KIND == IN_DIFF) {
+                const f2v a = __builtin_nontemporal_load((const f2v*)((const float2*)in + idx));
+                const f2v c = __builtin_nontemporal_load((const f2v*)((const float2*)in + idx + L));
+                v[i] = make_float2(a.x - c.x, a.y - c.y);
             } else if constexpr (IN_KIND == IN_HALF) {
                 v[i] = half_bin((const float2*)in + ib, idx - ib, L, g.half_scale);   // first pass: bin idx - ib
             } else {
@@ -141,12 +158,15 @@ __global__ __launch_bounds__(PassShape<LP>::kThreads) void pass_kernel(const voi
         if (ns_log > 0) {
             w = tw_big64(hi, lo, tlg, (j & nsm) * s0);
             step = tw_big64(hi, lo, tlg, (j & nsm) * rstep);
+        } else if constexpr (kDiff) {                   // w_{2L}^n, n = j + s cols
+            w = tw_big64(hi, lo, g.lg + 1, j + (int64_t)s0 * cols);
+            step = tw_big64(hi, lo, g.lg + 1, (int64_t)rstep * cols);
         }
 #pragma unroll
         for (int i = 0; i < kRowsPerThread; ++i) {
             const int s = s0 + rstep * i;
             float2 u = v[i];
-            if (ns_log > 0) {
+            if (ns_log > 0 || kDiff) {
                 const float2 wf = make_float2((float)w.x, (float)w.y);
                 u = INV ? cmulc(u, wf) : cmul(u, wf);
                 w = make_double2(w.x * step.x - w.y * step.y, w.x * step.y + w.y * step.x);
@@ -157,9 +177,31 @@ __global__ __launch_bounds__(PassShape<LP>::kThreads) void pass_kernel(const voi
     __syncthreads();
     column_fft<LP, INV>(B, rl, T, tid);
 
+    typedef float f2v __attribute__((ext_vector_type(2)));
+    float2 ev[OUT_KIND == OUT_REC ? kRowsPerThread : 1];
+    if constexpr (OUT_KIND == OUT_REC) {
+        // even bins 2k of the thread's outputs k (the store loop's mapping:
+        // column j0 + tid mod nc, rows tid / nc + i kPassThreads / nc): bin k
+        // of the two child windows, all loads in flight before the first sum
+        const int64_t jo = j0 + (tid & (nc - 1));
+        const float2* pv = (const float2*)out + (ob - g.rec_prev + ((jo >> ns_log) << (ns_log + rl)) + (jo & nsm) +
+                                                 ((int64_t)(tid >> lnc) << ns_log));
+        const int64_t dk = (int64_t)(kPassThreads >> lnc) << ns_log;
+        f2v p0[kRowsPerThread], p1[kRowsPerThread];
+#pragma unroll
+        for (int i = 0; i < kRowsPerThread; ++i) {
+            p0[i] = __builtin_nontemporal_load((const f2v*)(pv + i * dk));
+            p1[i] = __builtin_nontemporal_load((const f2v*)(pv + i * dk + L));
+        }
+#pragma unroll
+        for (int i = 0; i < kRowsPerThread; ++i) ev[i] = make_float2(p0[i].x + p1[i].x, p0[i].y + p1[i].y);
+    }
+
     double nacc = 0.0;                                 // OUT_NORM: this thread's squared magnitudes
     const float osc = (OUT_KIND == OUT_HALF && g.out_scale) ? g.out_scale[b * g.out_scale_m + g.lg - 1] : 1.0f;
-    for (int e = tid; e < nval; e += kPassThreads) {
+#pragma unroll
+    for (int ie = 0; ie < kRowsPerThread; ++ie) {
+        const int e = tid + ie * kPassThreads;
         int jj, s;
         int64_t o;
         if (ns_log == 0) {          // outputs of column j are the r consecutive values j*r + s
@@ -187,6 +229,10 @@ __global__ __launch_bounds__(PassShape<LP>::kThreads) void pass_kernel(const voi
             if (k == 0) sl[0] = w.x;
             else if (k == L / 2) sl[1] = w.x;
             else if (k < L / 2) ((float2*)out)[o] = w;
+        } else if constexpr (OUT_KIND == OUT_REC) {
+            float2* q = (float2*)out + ob + 2 * (o - ob);
+            q[0] = ev[ie];
+            q[1] = v;
         } else if constexpr (OUT_KIND == OUT_ADD_C64) {
             float2* p = (float2*)out + o;
             *p = cadd(*p, v);
@@ -227,6 +273,12 @@ struct PassLdsInit {
         allow_pass_lds<kPassBigLog, true, IN_C64>();
         (void)hipFuncSetAttribute((const void*)pass_kernel<kPassBigLog, true, IN_HALF, OUT_STORE>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, PassShape<kPassBigLog>::kLdsBytes);
+        (void)hipFuncSetAttribute((const void*)pass_kernel<kPassBigLog, false, IN_DIFF, OUT_STORE>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, PassShape<kPassBigLog>::kLdsBytes);
+        (void)hipFuncSetAttribute((const void*)pass_kernel<kPassBigLog, false, IN_DIFF_R32, OUT_STORE>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, PassShape<kPassBigLog>::kLdsBytes);
+        (void)hipFuncSetAttribute((const void*)pass_kernel<kPassBigLog, false, IN_C64, OUT_REC>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, PassShape<kPassBigLog>::kLdsBytes);
     }
 };
 
@@ -247,6 +299,21 @@ static hipError_t launch_pass_t(int in_kind, int out_kind, const void* in, void*
             MRDFT_PASS(IN_HALF, OUT_STORE);
         } else {
             return hipErrorInvalidValue;
+        }
+    } else if (in_kind == IN_DIFF || in_kind == IN_DIFF_R32 || out_kind == OUT_REC) {
+        // the recurrence chains of the forward: IN_DIFF first passes, OUT_REC last passes
+        if constexpr (INV) {
+            return hipErrorInvalidValue;
+        } else {
+            if (out_kind == OUT_REC) {
+                if (in_kind != IN_C64 || g.ns_log == 0 || g.rec_prev < 2 * ((int64_t)1 << g.lg))
+                    return hipErrorInvalidValue;
+                MRDFT_PASS(IN_C64, OUT_REC);
+            } else {
+                if (out_kind != OUT_STORE || g.ns_log != 0 || g.lg + 1 > kMaxOrder) return hipErrorInvalidValue;
+                if (in_kind == IN_DIFF) MRDFT_PASS(IN_DIFF, OUT_STORE);
+                else MRDFT_PASS(IN_DIFF_R32, OUT_STORE);
+            }
         }
     } else if (in_kind == IN_R32) {
         if (out_kind == OUT_STORE) MRDFT_PASS(IN_R32, OUT_STORE);
