@@ -4,6 +4,9 @@
 // 256-point rows, see mrdft_rows_real.h).  Both kinds use 256 threads and at
 // most 40 KB of LDS, so four workgroups of either kind share a CU and the
 // store streams of the levels overlap instead of running one after another.
+// The level spectra are stored with the non-temporal hint, so that the
+// pieces' re-reads of their windows' samples stay in L2 (64 x 2^16 samples:
+// 118 -> 115 us; the loss's scaled launch reads x and z and gains more).
 #include "mrdft_internal.h"
 #include "mrdft_rows_real.h"
 #include "mrdft_tile_real.h"

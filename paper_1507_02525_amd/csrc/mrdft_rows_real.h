@@ -208,7 +208,7 @@ __device__ __forceinline__ void rows_real_body(RowsLds& S, const float* __restri
         float2 a = S.C[kp * kRowsStride + rpad(k1)];
         const float2 c = S.C[(kp + 1) * kRowsStride + rpad(k1)];
         if (HALF && u == 0 && tid == 0 && g == 0) a.y = S.C[rpad(kRowsN / 2)].x;   // (DC, Nyquist)
-        *(float4*)(yw + k0 + kp + (int64_t)R * k1) = make_float4(scale * a.x, scale * a.y, scale * c.x, scale * c.y);
+        store_out(yw + k0 + kp + (int64_t)R * k1, make_float4(scale * a.x, scale * a.y, scale * c.x, scale * c.y));
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -217,8 +217,8 @@ __device__ __forceinline__ void rows_real_body(RowsLds& S, const float* __restri
         // bin 16 gm + kp (+1) at k1 = conj(row 16 - kp (15 - kp) at 255 - k1)
         const float2 a = S.C[(16 - kp) * kRowsStride + rpad(kRowsN - 1 - k1)];
         const float2 c = S.C[(15 - kp) * kRowsStride + rpad(kRowsN - 1 - k1)];
-        *(float4*)(yw + 16 * gm + kp + (int64_t)R * k1) = make_float4(scale * a.x, -scale * a.y, scale * c.x,
-                                                                       -scale * c.y);
+        store_out(yw + 16 * gm + kp + (int64_t)R * k1, make_float4(scale * a.x, -scale * a.y, scale * c.x,
+                                                                       -scale * c.y));
     }
 }
 

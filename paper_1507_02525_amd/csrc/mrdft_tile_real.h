@@ -216,16 +216,16 @@ __device__ __forceinline__ void real_level_out(float2* __restrict__ y, int w, in
         if (out.keep(I)) {                          // the packed slots themselves (slot 0 = uk at k = 0)
             float2* yh = y + (int64_t)w * M;
             const float2 s0 = out.sc(I, uk), s1 = out.sc(I, ok), s2 = out.sc(I, uj), s3 = out.sc(I, oj);
-            *(float4*)(yh + 2 * k) = make_float4(s0.x, s0.y, s1.x, s1.y);
-            *(float4*)(yh + 2 * j) = make_float4(s2.x, s2.y, s3.x, s3.y);
+            store_out(yh + 2 * k, make_float4(s0.x, s0.y, s1.x, s1.y));
+            store_out(yh + 2 * j, make_float4(s2.x, s2.y, s3.x, s3.y));
         }
     } else if (out.keep(I)) {
         const float2 s0 = out.sc(I, u0), s1 = out.sc(I, ok), s2 = out.sc(I, uj), s3 = out.sc(I, oj);
         const float2 s4 = out.sc(I, ua), s5 = out.sc(I, oka), s6 = out.sc(I, ub), s7 = out.sc(I, oja);
-        *(float4*)(yw + 2 * k) = make_float4(s0.x, s0.y, s1.x, s1.y);
-        *(float4*)(yw + 2 * j) = make_float4(s2.x, s2.y, s3.x, s3.y);
-        *(float4*)(yw + M + 2 * j) = make_float4(s4.x, s4.y, s5.x, s5.y);
-        *(float4*)(yw + M + 2 * k) = make_float4(s6.x, s6.y, s7.x, s7.y);
+        store_out(yw + 2 * k, make_float4(s0.x, s0.y, s1.x, s1.y));
+        store_out(yw + 2 * j, make_float4(s2.x, s2.y, s3.x, s3.y));
+        store_out(yw + M + 2 * j, make_float4(s4.x, s4.y, s5.x, s5.y));
+        store_out(yw + M + 2 * k, make_float4(s6.x, s6.y, s7.x, s7.y));
     }
 }
 
@@ -447,7 +447,7 @@ __device__ __forceinline__ void stage_level(const float2* pv, float4* st, float2
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int p = 64 * r + lane, wl = p >> 2, e = p & 3;
-            *(float4*)(yl + 2 * p) = st[4 * wl + (e ^ ((wl >> 2) & 3))];
+            store_out(yl + 2 * p, st[4 * wl + (e ^ ((wl >> 2) & 3))]);
         }
         wave_sync();
         return;
@@ -461,7 +461,7 @@ __device__ __forceinline__ void stage_level(const float2* pv, float4* st, float2
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
         const int p = 64 * r + lane, wl = p >> 3, e = p & 7;
-        *(float4*)(yl + 2 * p) = st[8 * wl + (e ^ ((wl >> 1) & 7))];
+        store_out(yl + 2 * p, st[8 * wl + (e ^ ((wl >> 1) & 7))]);
     }
     wave_sync();
 }
