@@ -113,7 +113,8 @@ __device__ __forceinline__ void adj_rows_real_body(RowsLds& S, const float2* __r
             S.C[kp * kRowsStride + rpad(c)] = half_bin(gyw, k0 + kp + (int64_t)R * c, L, hsc);
             S.C[(kp + 1) * kRowsStride + rpad(c)] = half_bin(gyw, k0 + kp + 1 + (int64_t)R * c, L, hsc);
         }
-        S.C[16 * kRowsStride + rpad(tid)] = half_bin(gyw, k0 + 16 + (int64_t)R * tid, L, hsc);
+        S.C[16 * kRowsStride + rpad(tid)] =
+            g == NG / 2 - 1 ? half_bin(gyw, k0 + 16 + (int64_t)R * tid, L, hsc) : make_float2(0.0f, 0.0f);
         __syncthreads();
     } else {
         const int gm = NG - 1 - g;
@@ -126,7 +127,9 @@ __device__ __forceinline__ void adj_rows_real_body(RowsLds& S, const float2* __r
             pv[u] = *(const float4*)(gyw + 16 * gm + kp + (int64_t)R * k1);     // rows 16 gm + kp, +1 at k1
         }
         const int k1 = tid;
-        const float2 d16 = gyw[k0 + 16 + (int64_t)R * k1];                         // row k0 + 16
+        // row k0 + 16 (stored by the last piece only: the others skip its
+        // 256 scattered loads and transform zeros there)
+        const float2 d16 = g == NG / 2 - 1 ? gyw[k0 + 16 + (int64_t)R * k1] : make_float2(0.0f, 0.0f);
         const float2 p0 = gyw[((R - k0) & (R - 1)) + (int64_t)R * k1];              // partner of row k0
 #pragma unroll
         for (int u = 0; u < 8; ++u) {

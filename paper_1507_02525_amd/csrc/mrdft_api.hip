@@ -347,6 +347,11 @@ mrdft_status upload_twiddles(mrdft_plan* p, hipStream_t s) {
 // alternating in proportion, all pieces first, or all tiles first.
 enum class InBlock { kAlternate, kPiecesFirst, kTilesFirst };
 std::vector<RealJob> real_jobs(const mrdft_plan* p, int order, InBlock in = InBlock::kPiecesFirst);
+struct JobBlock {
+    std::vector<RealJob> tiles, pieces;
+    int64_t cost;
+};
+std::vector<RealJob> deal_blocks(const std::vector<JobBlock>& blocks);
 std::vector<RealJob> complex_jobs(const mrdft_plan* p, int order, std::vector<unsigned>* seg);
 std::vector<RealJob> small_real_jobs(const mrdft_plan* p);
 mrdft_status upload_cjobs(mrdft_plan* p, int order, hipStream_t s, bool direct);
@@ -409,7 +414,7 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
     {
         // adjoint tables: 2048-sample tiles and rows pieces of levels 12..16 (launch a),
         // columns jobs per region of up to 2^16 samples (launch b), scratch B per signal
-        std::vector<RealJob> aj;
+        std::vector<JobBlock> ablocks;
         std::vector<AdjColJob> cj;
         std::vector<TileJob> sm;
         int64_t scr = 0;
@@ -428,25 +433,34 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
             // half_bin), the full layout otherwise
             const int64_t gb = p->hs ? p->base(j) : p->basef(j);
             const int hs = p->hs;
-            for (int64_t tau = 0; !p->adj_zero && tau < (N >> kC64TileLog); ++tau)
-                aj.push_back(RealJob{gb + ((tau << kC64TileLog) >> hs), p->in_off[j] + (tau << kC64TileLog), N >> hs, 0,
-                                     p->range()});
             const int top = std::min(mj, kRowsMaxLevel);
             bool any_upper = false;
-            for (int lg = kCRowsMinLevel; lg <= top; ++lg) {
-                if (lg < p->lo || lg > p->hi) continue;
-                any_upper = true;
-                const int64_t L = int64_t(1) << lg;
-                // real plans: 17-row Hermitian pieces above level 12 (half as many)
-                const int pieces = (p->dtype == MRDFT_R32 && lg > kCRowsMinLevel) ? 1 << (lg - kCRowsMinLevel - 1)
-                                                                                   : 1 << (lg - kCRowsMinLevel);
-                for (int64_t w = 0; w < N / L; ++w)
-                    for (int g = 0; g < pieces; ++g)
-                        aj.push_back(RealJob{gb + (((int64_t)(lg - 1) * N + w * L) >> hs),
-                                             scr + (int64_t)(lg - kCRowsMinLevel) * N + w * L, 0, lg, g});
+            // one block per region of 2^top samples: its tiles and the rows
+            // pieces of its windows (a real piece reads rows that its
+            // neighbours read too, so a region's jobs share one XCD's L2)
+            const int64_t region = int64_t(1) << top;
+            for (int64_t u0 = 0; u0 < N; u0 += region) {
+                JobBlock blk;
+                for (int64_t tau = u0 >> kC64TileLog; !p->adj_zero && tau < (u0 + region) >> kC64TileLog; ++tau)
+                    blk.tiles.push_back(RealJob{gb + ((tau << kC64TileLog) >> hs), p->in_off[j] + (tau << kC64TileLog),
+                                                N >> hs, 0, p->range()});
+                for (int lg = kCRowsMinLevel; lg <= top; ++lg) {
+                    if (lg < p->lo || lg > p->hi) continue;
+                    any_upper = true;
+                    const int64_t L = int64_t(1) << lg;
+                    // real plans: 17-row Hermitian pieces above level 12 (half as many)
+                    const int pieces = (p->dtype == MRDFT_R32 && lg > kCRowsMinLevel) ? 1 << (lg - kCRowsMinLevel - 1)
+                                                                                       : 1 << (lg - kCRowsMinLevel);
+                    for (int64_t w = u0 / L; w < (u0 + region) / L; ++w)
+                        for (int g = 0; g < pieces; ++g)
+                            blk.pieces.push_back(RealJob{gb + (((int64_t)(lg - 1) * N + w * L) >> hs),
+                                                         scr + (int64_t)(lg - kCRowsMinLevel) * N + w * L, 0, lg, g});
+                }
+                // cost ~ gradient bytes read: 11 levels of a tile, ~2 x 17 rows of a piece
+                blk.cost = 11 * (int64_t)blk.tiles.size() + 6 * (int64_t)blk.pieces.size();
+                if (blk.cost) ablocks.push_back(std::move(blk));
             }
             if (top >= kCRowsMinLevel) {
-                const int64_t region = int64_t(1) << top;
                 if (any_upper)
                     for (int64_t r = 0; r < N / region; ++r)
                         for (int c = 0; c < 16; ++c)
@@ -455,6 +469,7 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
                 scr += (int64_t)(top - kCRowsMinLevel + 1) * N;
             }
         }
+        const std::vector<RealJob> aj = deal_blocks(ablocks);
         p->najobs = (int64_t)aj.size();
         p->nacols = (int64_t)cj.size();
         p->nasmall = (int64_t)sm.size();
@@ -653,6 +668,14 @@ struct JobBuckets {
         return out;
     }
 };
+
+// Blocks of jobs (tiles first), each whole to the least loaded of the 8
+// buckets, interleaved so that bucket b runs on XCD b.
+std::vector<RealJob> deal_blocks(const std::vector<JobBlock>& blocks) {
+    JobBuckets jb;
+    for (const JobBlock& b : blocks) jb.add_block(b.tiles, b.pieces, b.cost, InBlock::kTilesFirst);
+    return jb.deal(MRDFT_ORDER_BLOCKS);
+}
 
 // Real signals of order >= 12: 4096-sample tiles and pieces of levels 13..16
 // (2^(lg-13) pieces per window).
