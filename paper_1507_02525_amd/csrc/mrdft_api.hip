@@ -170,10 +170,6 @@ struct mrdft_plan {
     hipStream_t side[kSides] = {nullptr, nullptr, nullptr, nullptr};
     hipEvent_t fork_ev = nullptr;
     hipEvent_t join_ev[kSides] = {nullptr, nullptr, nullptr, nullptr};
-    // forward: end of level i's chain, awaited by the recurrence chain of
-    // level i + 1 on another side stream (created with the side streams when
-    // some signal has a level >= kRecMinLevel)
-    hipEvent_t lvl_ev[MRDFT_MAX_ORDER + 1] = {};
     int nsides = 0;
     bool serial = false;                    // forward: every launch on the caller's stream (tuned choice)
     bool after = false;                     // forward: side-stream levels start after the main launch (tuned choice)
@@ -201,8 +197,6 @@ void free_plan(mrdft_plan* p) {
     }
     for (auto e : p->event_pool) (void)hipEventDestroy(e);
     if (p->fork_ev) (void)hipEventDestroy(p->fork_ev);
-    for (auto e : p->lvl_ev)
-        if (e) (void)hipEventDestroy(e);
     for (int k = 0; k < p->nsides; ++k) {
         if (p->join_ev[k]) (void)hipEventDestroy(p->join_ev[k]);
         if (p->side[k]) (void)hipStreamDestroy(p->side[k]);
@@ -544,9 +538,7 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
             HIP_TRY(hipEventCreateWithFlags(&p->join_ev[k], hipEventDisableTiming));
             p->nsides = k + 1;
         }
-        if (p->max_order >= kRecMinLevel)
-            for (int i = kRecMinLevel - 1; i < p->max_order; ++i)
-                HIP_TRY(hipEventCreateWithFlags(&p->lvl_ev[i], hipEventDisableTiming));
+
     }
     if (scratch > 0) {
         // one ping-pong pair per side stream: chains of passes of different
@@ -901,13 +893,19 @@ mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, h
     int chain = 0;                                    // multi-pass levels, dealt over the side streams
     for (const Group& g : p->groups) {
         const int64_t N = int64_t(1) << g.order;
+        int kprev = 0;                                // stream of level i - 1
         for (int i = kTileMaxLog + 1; i <= g.order; ++i) {
             if ((real_jobs_cover || cjobs_cover) && i <= kRowsMaxLevel) continue;     // in the one launch
             if (i < p->lo || i > p->hi) continue;                                      // level not kept
+            // recurrence chain: level i - 1 is stored by this plan, by the
+            // chain just before on the same stream
+            const bool rec = i >= kRecMinLevel && i - 1 >= p->lo && !p->hs;
             // levels spread over the side streams; the passes of one level run
-            // in order on one stream with that stream's scratch pair
+            // in order on one stream with that stream's scratch pair, and a
+            // recurrence chain follows the level below on its stream
             const int si = (i <= kUpperMaxLevel) ? (i - kTileMaxLog - 1) : chain++;
-            const int k = nsides ? si % nsides : 0;
+            const int k = !nsides ? 0 : rec ? kprev : si % nsides;
+            kprev = k;
             const hipStream_t s = nsides ? p->side[k] : s0;
             float2* const* ds = k == 0 ? p->d_s : p->d_ss[k - 1];
             if (i <= kUpperMaxLevel) {
@@ -926,9 +924,6 @@ mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, h
                 HIP_TRY(launch_upper_fwd(in_kind == IN_R32, x, level_ptr(p, Y, i, N), geo, tw, s));
                 continue;
             }
-            // recurrence chain: level i - 1 is stored by this plan (a chain
-            // of this loop, ended by lvl_ev[i - 1] on the side streams)
-            const bool rec = i >= kRecMinLevel && i - 1 >= p->lo && !p->hs;
             const int dl = rec ? i - 1 : i;            // order of the DFTs of the chain
             const std::vector<int> bits = pass_bits(dl);
             const int64_t wlen = rec ? N / 2 : N;      // scratch points per signal
@@ -950,15 +945,10 @@ mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, h
                 void* out = last ? (void*)level_ptr(p, Y, i, N >> p->hs) : (void*)ds[q & 1];
                 const int ik = !first ? IN_C64 : !rec ? in_kind : in_kind == IN_R32 ? IN_DIFF_R32 : IN_DIFF;
                 const int ok = (last && p->hs) ? OUT_HALF : (last && rec) ? OUT_REC : OUT_STORE;
-                if (last && rec && nsides) {
-                    if (!p->lvl_ev[i - 1]) return fail(MRDFT_E_HIP, "no event for level %d", i - 1);
-                    HIP_TRY(hipStreamWaitEvent(s, p->lvl_ev[i - 1], 0));
-                }
                 ProfScope ps(p, MRDFT_KERNEL_PASS_FWD, s);
                 HIP_TRY(launch_pass(false, ik, ok, in, out, geo, tw, s));
                 ns += bits[q];
             }
-            if (i < g.order && p->lvl_ev[i] && nsides) HIP_TRY(hipEventRecord(p->lvl_ev[i], s));
         }
     }
     return MRDFT_OK;
