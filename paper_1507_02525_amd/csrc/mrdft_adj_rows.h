@@ -181,18 +181,20 @@ struct AdjColsLds {
 
 __device__ __forceinline__ int cpad(int i) { return i + (i >> 4); }
 
-// One conjugate Stockham step of radix RR over the 4096 points of V (NF FFTs
-// of R points, FFT f at f * R), span 2^LNS; 4096 / RR jobs over 256 threads.
-template <int RR, int R, int LNS>
+// One conjugate Stockham step of radix RR over the first NP points of V (NP / R
+// FFTs of R points, FFT f at f * R), span 2^LNS; NP / RR jobs over 256 threads.
+template <int RR, int R, int LNS, int NP = kAdjColsPoints>
 __device__ __forceinline__ void adj_cols_step(AdjColsLds& S, int tid) {
     constexpr int LR = (RR == 2) ? 1 : (RR == 4) ? 2 : (RR == 8) ? 3 : 4;
     constexpr int PER = R / RR;
-    constexpr int JPT = kAdjColsPoints / RR / kRowsThreads;
+    constexpr int JOBS = NP / RR;
+    constexpr int JPT = (JOBS + kRowsThreads - 1) / kRowsThreads;
     constexpr int NS = 1 << LNS;
     float2 v[JPT][RR];
 #pragma unroll
     for (int c = 0; c < JPT; ++c) {
         const int J = tid + c * kRowsThreads;
+        if (JOBS % kRowsThreads && J >= JOBS) break;
         const int f = J / PER, j = J % PER;
 #pragma unroll
         for (int s = 0; s < RR; ++s) v[c][s] = S.V[cpad(f * R + j + s * PER)];
@@ -207,6 +209,7 @@ __device__ __forceinline__ void adj_cols_step(AdjColsLds& S, int tid) {
 #pragma unroll
     for (int c = 0; c < JPT; ++c) {
         const int J = tid + c * kRowsThreads;
+        if (JOBS % kRowsThreads && J >= JOBS) break;
         const int f = J / PER, j = J % PER;
         const int base = f * R + ((j >> LNS) << (LNS + LR)) + (j & (NS - 1));
 #pragma unroll
@@ -217,15 +220,15 @@ __device__ __forceinline__ void adj_cols_step(AdjColsLds& S, int tid) {
 
 // R-point conjugate DFTs (R = 16 .. 256): a first step of radix R/16 (if R > 16),
 // then radix 16.
-template <int R>
+template <int R, int NP = kAdjColsPoints>
 __device__ __forceinline__ void adj_cols_fft(AdjColsLds& S, int tid) {
     if constexpr (R == 16) {
-        adj_cols_step<16, R, 0>(S, tid);
+        adj_cols_step<16, R, 0, NP>(S, tid);
     } else {
         constexpr int R0 = R / 16;
         constexpr int L0 = (R0 == 2) ? 1 : (R0 == 4) ? 2 : (R0 == 8) ? 3 : 4;
-        adj_cols_step<R0, R, 0>(S, tid);
-        adj_cols_step<16, R, L0>(S, tid);
+        adj_cols_step<R0, R, 0, NP>(S, tid);
+        adj_cols_step<16, R, L0, NP>(S, tid);
     }
 }
 
@@ -234,7 +237,10 @@ __device__ __forceinline__ void adj_cols_fft(AdjColsLds& S, int tid) {
 // thread's gx values at region row rho = (tid >> 4) + 16 s, column tid & 15.
 //   scr : the scratch block of this level at the region's first sample
 // HERM (real output, levels 13..16): only the rows k2 <= R/2 are in the
-// scratch; the others are their conjugates (B[R - k2] = conj(B[k2])).
+// scratch; the others are their conjugates (B[R - k2] = conj(B[k2])).  The
+// conjugate DFT of such a column is real, so columns c and c + 8 share one
+// complex FFT of Z = B_c + i B_{c+8}: its real part is the first column's
+// result, its imaginary part the second's (half the FFTs).
 template <int RL, bool REAL, class ACC>
 __device__ __forceinline__ void adj_cols_level(AdjColsLds& S, const float2* __restrict__ scr, int region_log, int c0,
                                                ACC* acc, int tid) {
@@ -242,6 +248,55 @@ __device__ __forceinline__ void adj_cols_level(AdjColsLds& S, const float2* __re
     constexpr bool HERM = REAL && RL >= 5;
     const int nwin = 1 << (region_log - RL - kRowsLog);          // windows of this level in the region
     const int rows = nwin * R;                                    // = region / 256
+    if constexpr (HERM) {
+        // FFT f = w * 8 + pc holds Z[k2] = B[w][k2][c0 + pc] + i B[w][k2][c0 + pc + 8]
+        typedef float nt2 __attribute__((ext_vector_type(2)));
+        constexpr int kPer = kAdjColsPoints / 2 / kRowsThreads;  // (pair, row) items per thread
+        float2 va[kPer], vb[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int e = tid + u * kRowsThreads;
+            const int pc = e & 7, rr = e >> 3;                    // rr = w * R + k2
+            const int w = rr / R, k2 = rr % R;
+            if (e < rows * 8 && k2 <= R / 2) {
+                const float2* q = scr + (int64_t)w * L + k2 * kRowsN + c0 + pc;
+                const nt2 a = __builtin_nontemporal_load((const nt2*)q);
+                const nt2 b = __builtin_nontemporal_load((const nt2*)(q + 8));
+                va[u] = make_float2(a.x, a.y);
+                vb[u] = make_float2(b.x, b.y);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int e = tid + u * kRowsThreads;
+            const int pc = e & 7, rr = e >> 3;
+            const int w = rr / R, k2 = rr % R;
+            if (e < rows * 8 && k2 <= R / 2) {
+                const float2 a = va[u], b = vb[u];
+                const int f0 = (w * 8 + pc) * R;
+                if (k2 == 0 || k2 == R / 2) {
+                    S.V[cpad(f0 + k2)] = make_float2(a.x, b.x);   // real rows: their real parts
+                } else {
+                    S.V[cpad(f0 + k2)] = make_float2(a.x - b.y, a.y + b.x);
+                    S.V[cpad(f0 + R - k2)] = make_float2(a.x + b.y, b.x - a.y);   // conj(B_c) + i conj(B_c+8)
+                }
+            }
+        }
+        __syncthreads();
+        adj_cols_fft<R, kAdjColsPoints / 2>(S, tid);
+        const int col = tid & 15;
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            const int rho = (tid >> 4) + 16 * s;
+            if (rho < rows) {
+                const int w = rho / R, n2 = rho % R;
+                const float2 o = S.V[cpad((w * 8 + (col & 7)) * R + n2)];
+                acc[s] += col < 8 ? o.x : o.y;
+            }
+        }
+        __syncthreads();
+        return;
+    }
     // load B[w][k2][c0 + col] (128-byte chunks) into FFT f = w * 16 + col, point
     // k2; all of a thread's loads are issued before the first LDS store.  The
     // scratch is read once: non-temporal loads (complex gradients of
