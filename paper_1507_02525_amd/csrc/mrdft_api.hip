@@ -1015,6 +1015,10 @@ mrdft_status adj_chain(mrdft_plan* p, const Group& g, int i, const float2* gY, v
     const Twiddles tw = p->tw();
     const int64_t N = int64_t(1) << g.order;
     const std::vector<int> bits = pass_bits(i);
+    // real output from packed (Hermitian) gradients: the windows go through
+    // the chain in pairs, h1 + i h2, so half the transforms run
+    const bool pair = real_out && half;
+    const int64_t nwin = g.count * (N >> i);
     int ns = 0;
     for (size_t q = 0; q < q0; ++q) ns += bits[q];
     for (size_t q = q0; q < q1; ++q) {
@@ -1023,7 +1027,8 @@ mrdft_status adj_chain(mrdft_plan* p, const Group& g, int i, const float2* gY, v
         geo.lg = i;
         geo.r_log = bits[q];
         geo.ns_log = ns;
-        geo.nwin = g.count * (N >> i);
+        geo.nwin = pair ? (nwin + 1) / 2 : nwin;
+        geo.pair_nwin = pair && (first || last) ? nwin : 0;
         geo.wps = N >> i;
         geo.in_sig = first ? g.d_out_sig : nullptr;
         geo.in_stride = first ? (int64_t)p->kept(g.order) * (N >> half) : N;
@@ -1032,9 +1037,10 @@ mrdft_status adj_chain(mrdft_plan* p, const Group& g, int i, const float2* gY, v
         geo.half_scale = packed_from_full ? 1.0f : 0.5f;
         const void* in = first ? (const void*)level_ptr(p, (float2*)gY, i, N >> half) : (const void*)ds[(q - 1) & 1];
         void* out = last ? gx : (void*)ds[q & 1];
-        const int ok = last ? (real_out ? OUT_ADD_R32 : OUT_ADD_C64) : OUT_STORE;
+        const int ok = !last ? OUT_STORE : pair ? OUT_ADD_R32_PAIR : real_out ? OUT_ADD_R32 : OUT_ADD_C64;
+        const int ik = !(first && half) ? IN_C64 : pair ? IN_HALF_PAIR : IN_HALF;
         ProfScope ps(p, MRDFT_KERNEL_PASS_ADJ, s);
-        HIP_TRY(launch_pass(true, (first && half) ? IN_HALF : IN_C64, ok, in, out, geo, tw, s));
+        HIP_TRY(launch_pass(true, ik, ok, in, out, geo, tw, s));
         ns += bits[q];
     }
     return MRDFT_OK;

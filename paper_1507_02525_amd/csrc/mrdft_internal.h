@@ -63,6 +63,10 @@ struct PassGeom {
     // OUT_REC: elements from a window of level lg + 1 back to the same
     // position of level lg in the output (the signal length N)
     int64_t rec_prev = 0;
+    // IN_HALF_PAIR / OUT_ADD_R32_PAIR: the chain runs over pairs of windows;
+    // window w (< pair_nwin) of the (wps, in_sig/out_sig, strides) geometry
+    // is half of pair w / 2
+    int64_t pair_nwin = 0;
 };
 
 // IN_HALF: a real plan's packed half-spectrum gradient (window W at W * L/2),
@@ -71,14 +75,21 @@ struct PassGeom {
 // L-point sequence of window W (L = 2^lg) is (x[n] - x[n + L]) w_{2L}^n, with
 // x[n] the n-th sample of window W of level lg + 1 (at W * 2L); first passes
 // only (OUT_STORE).
-enum InKind { IN_C64 = 0, IN_R32 = 1, IN_HALF = 2, IN_DIFF = 3, IN_DIFF_R32 = 4 };
+// IN_HALF_PAIR: two windows' packed gradients h1, h2 (read as IN_HALF reads
+// one) enter as h1 + i h2; since both are Hermitian, the conjugate DFT of the
+// sum is G1 + i G2 with G1, G2 real (adjoint with real output).
+enum InKind { IN_C64 = 0, IN_R32 = 1, IN_HALF = 2, IN_DIFF = 3, IN_DIFF_R32 = 4, IN_HALF_PAIR = 5 };
 // OUT_HALF: store packed half spectra (window W at W * L/2, slot 0 = (Y[0], Y[L/2])).
 // OUT_NORM: nothing stored; the squared magnitudes of signal b's level lg are
 // added (FP64) to ((double*)out)[b * out_stride + lg - 1].
 // OUT_REC: the last pass of an IN_DIFF chain stores window W of level lg + 1
 // (at W * 2L): bin 2k + 1 is the pass output k, bin 2k the sum of bin k of
 // the two child windows of level lg, read rec_prev elements back (eq. (2)).
-enum OutKind { OUT_STORE = 0, OUT_ADD_C64 = 1, OUT_ADD_R32 = 2, OUT_HALF = 3, OUT_NORM = 4, OUT_REC = 5 };
+// OUT_ADD_R32_PAIR: the last pass of an IN_HALF_PAIR chain adds the real
+// part of its output to the first window's samples and the imaginary part
+// to the second's.
+enum OutKind { OUT_STORE = 0, OUT_ADD_C64 = 1, OUT_ADD_R32 = 2, OUT_HALF = 3, OUT_NORM = 4, OUT_REC = 5,
+               OUT_ADD_R32_PAIR = 6 };
 
 struct Twiddles {
     const float2* tile;   // w_{4096}^e, e < 4096 (FP32, rounded once from FP64)

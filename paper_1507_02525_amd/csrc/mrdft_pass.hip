@@ -110,9 +110,26 @@ __global__ __launch_bounds__(PassShape<LP>::kThreads) void pass_kernel(const voi
     const int64_t j0 = (blk - gwin * jblocks) << lnc;
     const int64_t b = gwin / g.wps, W = gwin - b * g.wps;
     constexpr bool kDiff = IN_KIND == IN_DIFF || IN_KIND == IN_DIFF_R32;
-    const int64_t ib = (g.in_sig ? g.in_sig[b] : b * g.in_stride) + W * (IN_KIND == IN_HALF ? L / 2 : kDiff ? 2 * L : L);
-    const int64_t ob =
-        (g.out_sig ? g.out_sig[b] : b * g.out_stride) + W * (OUT_KIND == OUT_HALF ? L / 2 : OUT_KIND == OUT_REC ? 2 * L : L);
+    constexpr bool kPairIn = IN_KIND == IN_HALF_PAIR, kPairOut = OUT_KIND == OUT_ADD_R32_PAIR;
+    // paired chains: block window gwin is the pair of windows 2 gwin, 2 gwin + 1
+    // of the (wps, signal tables, strides) geometry; the second may be absent
+    const bool has2 = (kPairIn || kPairOut) && 2 * gwin + 1 < g.pair_nwin;
+    auto in_base = [&](int64_t w) {
+        const int64_t bw = w / g.wps;
+        return (g.in_sig ? g.in_sig[bw] : bw * g.in_stride) + (w - bw * g.wps) * (L / 2);
+    };
+    auto out_base = [&](int64_t w) {
+        const int64_t bw = w / g.wps;
+        return (g.out_sig ? g.out_sig[bw] : bw * g.out_stride) + (w - bw * g.wps) * L;
+    };
+    const int64_t ib = kPairIn ? in_base(2 * gwin)
+                               : (g.in_sig ? g.in_sig[b] : b * g.in_stride) +
+                                     W * (IN_KIND == IN_HALF ? L / 2 : kDiff ? 2 * L : L);
+    const int64_t ib2 = kPairIn && has2 ? in_base(2 * gwin + 1) : ib;
+    const int64_t ob = kPairOut ? out_base(2 * gwin)
+                                : (g.out_sig ? g.out_sig[b] : b * g.out_stride) +
+                                      W * (OUT_KIND == OUT_HALF ? L / 2 : OUT_KIND == OUT_REC ? 2 * L : L);
+    const int64_t ob2 = kPairOut && has2 ? out_base(2 * gwin + 1) : ob;
     const int tid = threadIdx.x;
     const int ns_log = g.ns_log;
     const int64_t nsm = ((int64_t)1 << ns_log) - 1;
@@ -148,6 +165,11 @@ __global__ __launch_bounds__(PassShape<LP>::kThreads) void pass_kernel(const voi
                 v[i] = make_float2(a.x - c.x, a.y - c.y);
             } else if constexpr (IN_KIND == IN_HALF) {
                 v[i] = half_bin((const float2*)in + ib, idx - ib, L, g.half_scale);   // first pass: bin idx - ib
+            } else if constexpr (kPairIn) {
+                const int64_t n = idx - ib;             // bin n of both windows
+                const float2 h1 = half_bin((const float2*)in + ib, n, L, g.half_scale);
+                const float2 h2 = has2 ? half_bin((const float2*)in + ib2, n, L, g.half_scale) : make_float2(0.0f, 0.0f);
+                v[i] = make_float2(h1.x - h2.y, h1.y + h2.x);
             } else {
                 const f2v t = __builtin_nontemporal_load((const f2v*)((const float2*)in + idx));
                 v[i] = make_float2(t.x, t.y);
@@ -233,6 +255,14 @@ __global__ __launch_bounds__(PassShape<LP>::kThreads) void pass_kernel(const voi
             float2* q = (float2*)out + ob + 2 * (o - ob);
             q[0] = ev[ie];
             q[1] = v;
+        } else if constexpr (kPairOut) {
+            const int64_t k = o - ob;
+            float* p1 = (float*)out + o;
+            *p1 += v.x;
+            if (has2) {
+                float* p2 = (float*)out + ob2 + k;
+                *p2 += v.y;
+            }
         } else if constexpr (OUT_KIND == OUT_ADD_C64) {
             float2* p = (float2*)out + o;
             *p = cadd(*p, v);
@@ -273,6 +303,10 @@ struct PassLdsInit {
         allow_pass_lds<kPassBigLog, true, IN_C64>();
         (void)hipFuncSetAttribute((const void*)pass_kernel<kPassBigLog, true, IN_HALF, OUT_STORE>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, PassShape<kPassBigLog>::kLdsBytes);
+        (void)hipFuncSetAttribute((const void*)pass_kernel<kPassBigLog, true, IN_HALF_PAIR, OUT_STORE>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, PassShape<kPassBigLog>::kLdsBytes);
+        (void)hipFuncSetAttribute((const void*)pass_kernel<kPassBigLog, true, IN_C64, OUT_ADD_R32_PAIR>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, PassShape<kPassBigLog>::kLdsBytes);
         (void)hipFuncSetAttribute((const void*)pass_kernel<kPassBigLog, false, IN_DIFF, OUT_STORE>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, PassShape<kPassBigLog>::kLdsBytes);
         (void)hipFuncSetAttribute((const void*)pass_kernel<kPassBigLog, false, IN_DIFF_R32, OUT_STORE>,
@@ -293,7 +327,22 @@ static hipError_t launch_pass_t(int in_kind, int out_kind, const void* in, void*
 #define MRDFT_PASS(IK, OK)                                                                                      \
     hipLaunchKernelGGL((pass_kernel<LP, INV, IK, OK>), grid, block, Sh::kLdsBytes, s, in, out, g, tw.tile, tw.hi, \
                        tw.lo)
-    if (in_kind == IN_HALF) {
+    if (in_kind == IN_HALF_PAIR || out_kind == OUT_ADD_R32_PAIR) {
+        // paired chains of the real adjoint: first passes read two packed
+        // windows, last passes add into two real windows
+        if constexpr (!INV) {
+            return hipErrorInvalidValue;
+        } else {
+            if (g.pair_nwin <= 0 || g.nwin != (g.pair_nwin + 1) / 2) return hipErrorInvalidValue;
+            if (in_kind == IN_HALF_PAIR) {
+                if (out_kind != OUT_STORE) return hipErrorInvalidValue;
+                MRDFT_PASS(IN_HALF_PAIR, OUT_STORE);
+            } else {
+                if (in_kind != IN_C64 || g.ns_log == 0) return hipErrorInvalidValue;
+                MRDFT_PASS(IN_C64, OUT_ADD_R32_PAIR);
+            }
+        }
+    } else if (in_kind == IN_HALF) {
         if constexpr (INV) {                          // first adjoint passes only
             if (out_kind != OUT_STORE) return hipErrorInvalidValue;
             MRDFT_PASS(IN_HALF, OUT_STORE);

@@ -31,6 +31,7 @@ def _ragged_real(orders, seed):
     ([17, 14], 13, 17),                     # level range: pieces and the pass level
     ([18, 13], 1, 28),                      # two pass levels: one side stream per adjoint chain
     ([18, 17, 12], 1, 28),                  # more pass chains than side streams: one stream
+    ([18, 18, 18], 1, 28),                  # adjoint pass chains over window pairs: 3 windows at 18, 6 at 17
 ])
 def test_half_forward_and_adjoint_ragged(orders, lo, hi):
     need_gpu()
