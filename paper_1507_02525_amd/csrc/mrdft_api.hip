@@ -1129,6 +1129,10 @@ mrdft_status upper_passes(mrdft_plan* p, const float* x, float2* W, hipStream_t 
             if (i < p->lo || i > p->hi) continue;                                      // level not kept
             if (only && i != only) continue;                                           // one level asked for
             const std::vector<int> bits = pass_bits(i);
+            // norms of a level with an even number of windows per signal: the
+            // windows go through the chain in pairs, x1 + i x2
+            const bool pair = norms && ((N >> i) & 1) == 0;
+            const int64_t nwin = g.count * (N >> i);
             int ns = 0;
             for (size_t q = 0; q < bits.size(); ++q) {
                 const bool first = q == 0, last = q + 1 == bits.size();
@@ -1136,7 +1140,8 @@ mrdft_status upper_passes(mrdft_plan* p, const float* x, float2* W, hipStream_t 
                 geo.lg = i;
                 geo.r_log = bits[q];
                 geo.ns_log = ns;
-                geo.nwin = g.count * (N >> i);
+                geo.nwin = pair ? nwin / 2 : nwin;
+                geo.pair_nwin = pair && (first || last) ? nwin : 0;
                 geo.wps = N >> i;
                 geo.in_sig = nullptr;
                 geo.in_stride = N;
@@ -1159,7 +1164,7 @@ mrdft_status upper_passes(mrdft_plan* p, const float* x, float2* W, hipStream_t 
                     }
                 }
                 ProfScope ps(p, MRDFT_KERNEL_PASS_FWD, s);
-                HIP_TRY(launch_pass(false, first ? IN_R32 : IN_C64, ok, in, out, geo, tw, s));
+                HIP_TRY(launch_pass(false, !first ? IN_C64 : pair ? IN_R32_PAIR : IN_R32, ok, in, out, geo, tw, s));
                 ns += bits[q];
             }
         }

@@ -78,7 +78,11 @@ struct PassGeom {
 // IN_HALF_PAIR: two windows' packed gradients h1, h2 (read as IN_HALF reads
 // one) enter as h1 + i h2; since both are Hermitian, the conjugate DFT of the
 // sum is G1 + i G2 with G1, G2 real (adjoint with real output).
-enum InKind { IN_C64 = 0, IN_R32 = 1, IN_HALF = 2, IN_DIFF = 3, IN_DIFF_R32 = 4, IN_HALF_PAIR = 5 };
+// IN_R32_PAIR: two real windows x1, x2 of one signal enter as x1 + i x2; the
+// spectrum Z = X1 + i X2 has sum_k |Z[k]|^2 = sum_k |X1[k]|^2 + |X2[k]|^2
+// (X1, X2 are Hermitian), so an OUT_NORM chain over such pairs adds the two
+// windows' squared magnitudes (first passes only).
+enum InKind { IN_C64 = 0, IN_R32 = 1, IN_HALF = 2, IN_DIFF = 3, IN_DIFF_R32 = 4, IN_HALF_PAIR = 5, IN_R32_PAIR = 6 };
 // OUT_HALF: store packed half spectra (window W at W * L/2, slot 0 = (Y[0], Y[L/2])).
 // OUT_NORM: nothing stored; the squared magnitudes of signal b's level lg are
 // added (FP64) to ((double*)out)[b * out_stride + lg - 1].

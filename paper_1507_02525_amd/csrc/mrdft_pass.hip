@@ -110,13 +110,13 @@ __global__ __launch_bounds__(PassShape<LP>::kThreads) void pass_kernel(const voi
     const int64_t j0 = (blk - gwin * jblocks) << lnc;
     const int64_t b = gwin / g.wps, W = gwin - b * g.wps;
     constexpr bool kDiff = IN_KIND == IN_DIFF || IN_KIND == IN_DIFF_R32;
-    constexpr bool kPairIn = IN_KIND == IN_HALF_PAIR, kPairOut = OUT_KIND == OUT_ADD_R32_PAIR;
+    constexpr bool kPairIn = IN_KIND == IN_HALF_PAIR || IN_KIND == IN_R32_PAIR, kPairOut = OUT_KIND == OUT_ADD_R32_PAIR;
     // paired chains: block window gwin is the pair of windows 2 gwin, 2 gwin + 1
     // of the (wps, signal tables, strides) geometry; the second may be absent
     const bool has2 = (kPairIn || kPairOut) && 2 * gwin + 1 < g.pair_nwin;
     auto in_base = [&](int64_t w) {
         const int64_t bw = w / g.wps;
-        return (g.in_sig ? g.in_sig[bw] : bw * g.in_stride) + (w - bw * g.wps) * (L / 2);
+        return (g.in_sig ? g.in_sig[bw] : bw * g.in_stride) + (w - bw * g.wps) * (IN_KIND == IN_HALF_PAIR ? L / 2 : L);
     };
     auto out_base = [&](int64_t w) {
         const int64_t bw = w / g.wps;
@@ -165,6 +165,10 @@ __global__ __launch_bounds__(PassShape<LP>::kThreads) void pass_kernel(const voi
                 v[i] = make_float2(a.x - c.x, a.y - c.y);
             } else if constexpr (IN_KIND == IN_HALF) {
                 v[i] = half_bin((const float2*)in + ib, idx - ib, L, g.half_scale);   // first pass: bin idx - ib
+            } else if constexpr (IN_KIND == IN_R32_PAIR) {
+                const int64_t n = idx - ib;             // sample n of both windows
+                v[i] = make_float2(__builtin_nontemporal_load((const float*)in + idx),
+                                   has2 ? __builtin_nontemporal_load((const float*)in + ib2 + n) : 0.0f);
             } else if constexpr (kPairIn) {
                 const int64_t n = idx - ib;             // bin n of both windows
                 const float2 h1 = half_bin((const float2*)in + ib, n, L, g.half_scale);
@@ -281,7 +285,9 @@ __global__ __launch_bounds__(PassShape<LP>::kThreads) void pass_kernel(const voi
             if (tid < h) red[tid] += red[tid + h];
             __syncthreads();
         }
-        if (tid == 0) atomicAdd((double*)out + b * g.out_stride + g.lg - 1, red[0]);
+        // a pair chain (windows 2 gwin, 2 gwin + 1 of one signal) adds to that signal's sum
+        const int64_t bn = g.pair_nwin > 0 ? (2 * gwin) / g.wps : b;
+        if (tid == 0) atomicAdd((double*)out + bn * g.out_stride + g.lg - 1, red[0]);
     }
 }
 
@@ -302,6 +308,8 @@ struct PassLdsInit {
         allow_pass_lds<kPassBigLog, true, IN_R32>();
         allow_pass_lds<kPassBigLog, true, IN_C64>();
         (void)hipFuncSetAttribute((const void*)pass_kernel<kPassBigLog, true, IN_HALF, OUT_STORE>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, PassShape<kPassBigLog>::kLdsBytes);
+        (void)hipFuncSetAttribute((const void*)pass_kernel<kPassBigLog, false, IN_R32_PAIR, OUT_STORE>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, PassShape<kPassBigLog>::kLdsBytes);
         (void)hipFuncSetAttribute((const void*)pass_kernel<kPassBigLog, true, IN_HALF_PAIR, OUT_STORE>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, PassShape<kPassBigLog>::kLdsBytes);
@@ -327,7 +335,16 @@ static hipError_t launch_pass_t(int in_kind, int out_kind, const void* in, void*
 #define MRDFT_PASS(IK, OK)                                                                                      \
     hipLaunchKernelGGL((pass_kernel<LP, INV, IK, OK>), grid, block, Sh::kLdsBytes, s, in, out, g, tw.tile, tw.hi, \
                        tw.lo)
-    if (in_kind == IN_HALF_PAIR || out_kind == OUT_ADD_R32_PAIR) {
+    if (in_kind == IN_R32_PAIR) {
+        // the norm chains of the loss: pairs of windows of one signal
+        if constexpr (INV) {
+            return hipErrorInvalidValue;
+        } else {
+            if (out_kind != OUT_STORE || g.pair_nwin <= 0 || g.nwin * 2 != g.pair_nwin || g.wps % 2 || g.ns_log != 0)
+                return hipErrorInvalidValue;
+            MRDFT_PASS(IN_R32_PAIR, OUT_STORE);
+        }
+    } else if (in_kind == IN_HALF_PAIR || out_kind == OUT_ADD_R32_PAIR) {
         // paired chains of the real adjoint: first passes read two packed
         // windows, last passes add into two real windows
         if constexpr (!INV) {
