@@ -72,11 +72,13 @@ std::vector<int> pass_bits(int lg) {
     return b;
 }
 
-// Lowest level of a forward recurrence chain: levels whose direct chain needs
-// three passes are built from the level below (even bins, eq. (2)) and the
-// half-length DFT of the twiddled difference (odd bins, eq. (3)): per level
-// the passes move 4 (level 19) or 5 units of 8N bytes instead of 6.
-constexpr int kRecMinLevel = 2 * kPassMaxLog + 1;
+// Lowest level of a forward recurrence chain: from level 18 up a level is
+// built from the level below (even bins, eq. (2)) and the half-length DFT of
+// the twiddled difference (odd bins, eq. (3)).  Level 18's chain head shares
+// its read of x with level 17's (launch_pass_head2): the two levels move 7
+// units of 8N bytes instead of 8; each level whose direct chain needs three
+// passes moves 4 (level 19) or 5 instead of 6.
+constexpr int kRecMinLevel = 2 * kPassMaxLog;
 
 }  // namespace
 
@@ -894,6 +896,7 @@ mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, h
     for (const Group& g : p->groups) {
         const int64_t N = int64_t(1) << g.order;
         int kprev = 0;                                // stream of level i - 1
+        bool head_done = false;                       // level kRecMinLevel's first pass ran with level i - 1's
         for (int i = kTileMaxLog + 1; i <= g.order; ++i) {
             if ((real_jobs_cover || cjobs_cover) && i <= kRowsMaxLevel) continue;     // in the one launch
             if (i < p->lo || i > p->hi) continue;                                      // level not kept
@@ -927,9 +930,33 @@ mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, h
             const int dl = rec ? i - 1 : i;            // order of the DFTs of the chain
             const std::vector<int> bits = pass_bits(dl);
             const int64_t wlen = rec ? N / 2 : N;      // scratch points per signal
+            // level kRecMinLevel - 1 with the next level built from it: one
+            // head for both chains (this level's scratch ds[0], the next's ds[1])
+            const bool head2 = !rec && i + 1 == kRecMinLevel && i + 1 <= g.order && i + 1 <= p->hi && !p->hs &&
+                               bits.size() == 2 && bits[0] == kPassMaxLog;
+            const bool skip_head = rec && i == kRecMinLevel && head_done;
             int ns = 0;
             for (size_t q = 0; q < bits.size(); ++q) {
                 const bool first = q == 0, last = q + 1 == bits.size();
+                if (first && head2) {
+                    PassGeom geo;
+                    geo.lg = i;
+                    geo.r_log = bits[0];
+                    geo.ns_log = 0;
+                    geo.nwin = g.count * (N >> (i + 1));
+                    geo.wps = N >> (i + 1);
+                    geo.in_sig = g.d_in_sig;
+                    geo.in_stride = N;
+                    ProfScope ps(p, MRDFT_KERNEL_PASS_FWD, s);
+                    HIP_TRY(launch_pass_head2(in_kind, x, ds[0], ds[1], geo, tw, s));
+                    head_done = true;
+                    ns += bits[q];
+                    continue;
+                }
+                if (first && skip_head) {              // ran with the level below
+                    ns += bits[q];
+                    continue;
+                }
                 PassGeom geo;
                 geo.lg = dl;
                 geo.r_log = bits[q];
@@ -941,7 +968,7 @@ mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, h
                 geo.out_sig = last ? g.d_out_sig : nullptr;
                 geo.out_stride = last ? (int64_t)p->kept(g.order) * (N >> p->hs) : wlen;
                 geo.rec_prev = (rec && last) ? N : 0;
-                const void* in = first ? x : (const void*)ds[(q - 1) & 1];
+                const void* in = first ? x : (const void*)ds[((q - 1) & 1) ^ (skip_head ? 1 : 0)];
                 void* out = last ? (void*)level_ptr(p, Y, i, N >> p->hs) : (void*)ds[q & 1];
                 const int ik = !first ? IN_C64 : !rec ? in_kind : in_kind == IN_R32 ? IN_DIFF_R32 : IN_DIFF;
                 const int ok = (last && p->hs) ? OUT_HALF : (last && rec) ? OUT_REC : OUT_STORE;

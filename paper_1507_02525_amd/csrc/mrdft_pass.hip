@@ -291,6 +291,131 @@ __global__ __launch_bounds__(PassShape<LP>::kThreads) void pass_kernel(const voi
     }
 }
 
+// Heads of two chains from one read of x: the first passes of level lg (its
+// two windows inside a window of level lg + 1) and of the recurrence chain
+// of level lg + 1 (the twiddled difference of those two windows, eq. (3))
+// use the same columns j + s L / r of the same samples (L = 2^lg, radix r).
+// A workgroup loads its 16 columns of both halves once and runs three column
+// FFTs through LDS: the first half (level lg, window 2 W), the second half
+// (window 2 W + 1), both written to out_lo in the lower chain's dense
+// layout, and (x0 - x1) w_{2L}^n, written to out_hi in the upper chain's.
+// g: lg, r_log (the first radix), nwin / wps / in_sig / in_stride of the
+// windows of level lg + 1; outputs dense (window index x L).
+template <int LP, int IN_KIND>
+__global__ __launch_bounds__(PassShape<LP>::kThreads, 4) void pass_head2_kernel(const void* __restrict__ in,
+                                                                             float2* __restrict__ out_lo,
+                                                                             float2* __restrict__ out_hi, PassGeom g,
+                                                                             const float2* __restrict__ tab,
+                                                                             const double2* __restrict__ hi,
+                                                                             const double2* __restrict__ lo) {
+    using Sh = PassShape<LP>;
+    constexpr int kPassPoints = Sh::kPoints, kPassThreads = Sh::kThreads;
+    constexpr int kRowsPerThread = kPassPoints / kPassThreads;
+    typedef float f2v __attribute__((ext_vector_type(2)));
+    float2* const B = g_pass_lds;
+    float2* const T = g_pass_lds + kPassPoints + (kPassPoints >> 4);
+    const int rl = g.r_log;
+    const int r = 1 << rl;
+    const int fst = kColStride(r);
+    const int lnc = LP - rl;
+    const int nc = 1 << lnc;
+    const int64_t L = (int64_t)1 << g.lg;
+    const int64_t cols = L >> rl;
+    const int64_t jblocks = cols >> lnc;
+    const int64_t blk = blockIdx.x;
+    const int64_t gwin = blk / jblocks;
+    const int64_t j0 = (blk - gwin * jblocks) << lnc;
+    const int64_t b = gwin / g.wps, W = gwin - b * g.wps;
+    const int64_t ib = (g.in_sig ? g.in_sig[b] : b * g.in_stride) + W * 2 * L;
+    const int tid = threadIdx.x;
+    const int jj = tid & (nc - 1), s0 = tid >> lnc;
+    const int rstep = kPassThreads >> lnc;
+    const int64_t j = j0 + jj;
+    float2 x0[kRowsPerThread], x1[kRowsPerThread];
+#pragma unroll
+    for (int i = 0; i < kRowsPerThread; ++i) {
+        const int64_t idx = ib + j + (int64_t)(s0 + rstep * i) * cols;
+        if constexpr (IN_KIND == IN_R32) {
+            x0[i] = make_float2(__builtin_nontemporal_load((const float*)in + idx), 0.0f);
+            x1[i] = make_float2(__builtin_nontemporal_load((const float*)in + idx + L), 0.0f);
+        } else {
+            const f2v a = __builtin_nontemporal_load((const f2v*)((const float2*)in + idx));
+            const f2v c = __builtin_nontemporal_load((const f2v*)((const float2*)in + idx + L));
+            x0[i] = make_float2(a.x, a.y);
+            x1[i] = make_float2(c.x, c.y);
+        }
+    }
+    T[tid] = tab[tid << (kTileMaxLog - Sh::kTwLog)];
+    // one column-FFT phase: the data already in LDS, the FFTs, the r
+    // consecutive outputs of each column to dst (first pass: span 1).  The
+    // thread index goes through an empty asm per phase, so that the LDS
+    // addresses derived from it are formed per phase, not kept in registers
+    // across the three.
+    auto to_lds = [&](const float2* v) __attribute__((always_inline)) {
+        int t = tid;
+        asm volatile("" : "+v"(t));
+        const int tj = t & (nc - 1), ts = t >> lnc;
+#pragma unroll
+        for (int i = 0; i < kRowsPerThread; ++i) B[tj * fst + padc(ts + rstep * i)] = v[i];
+    };
+    auto fft_out = [&](float2* __restrict__ dst) __attribute__((always_inline)) {
+        int t = tid;
+        asm volatile("" : "+v"(t));
+        __syncthreads();
+        column_fft<LP, false>(B, rl, T, t);
+#pragma unroll
+        for (int ie = 0; ie < kRowsPerThread; ++ie) {
+            const int e = t + ie * kPassThreads;
+            const int jo = e >> rl, s = e & (r - 1);
+            dst[(j0 + jo) * r + s] = B[jo * fst + padc(s)];
+        }
+        __syncthreads();                               // B read before the next phase writes it
+    };
+    // first half into LDS; its registers then take the twiddled difference
+    // (x0 - x1) w_{2L}^n, n = j + s cols (FP64 recurrence), before the FFTs
+    to_lds(x0);
+    {
+        double2 w = tw_big64(hi, lo, g.lg + 1, j + (int64_t)s0 * cols);
+        const double2 step = tw_big64(hi, lo, g.lg + 1, (int64_t)rstep * cols);
+#pragma unroll
+        for (int i = 0; i < kRowsPerThread; ++i) {
+            x0[i] = cmul(make_float2(x0[i].x - x1[i].x, x0[i].y - x1[i].y), make_float2((float)w.x, (float)w.y));
+            w = make_double2(w.x * step.x - w.y * step.y, w.x * step.y + w.y * step.x);
+        }
+    }
+    fft_out(out_lo + (2 * gwin) * L);
+    to_lds(x1);
+    fft_out(out_lo + (2 * gwin + 1) * L);
+    to_lds(x0);
+    fft_out(out_hi + gwin * L);
+}
+
+hipError_t launch_pass_head2(int in_kind, const void* in, float2* out_lo, float2* out_hi, const PassGeom& g,
+                             const Twiddles& tw, hipStream_t s) {
+    if (g.r_log != kPassMaxLog || g.lg + 1 > kMaxOrder || (in_kind != IN_C64 && in_kind != IN_R32))
+        return hipErrorInvalidValue;
+    using Sh = PassShape<kPassBigLog>;
+    if (g.lg < kPassBigLog) return hipErrorInvalidValue;
+    const int64_t nblk = g.nwin << (g.lg - kPassBigLog);
+    if (nblk <= 0) return hipSuccess;
+    static const bool attr = [] {
+        (void)hipFuncSetAttribute((const void*)pass_head2_kernel<kPassBigLog, IN_C64>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, Sh::kLdsBytes);
+        (void)hipFuncSetAttribute((const void*)pass_head2_kernel<kPassBigLog, IN_R32>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, Sh::kLdsBytes);
+        return true;
+    }();
+    (void)attr;
+    dim3 grid((unsigned)nblk), block(Sh::kThreads);
+    if (in_kind == IN_R32)
+        hipLaunchKernelGGL((pass_head2_kernel<kPassBigLog, IN_R32>), grid, block, Sh::kLdsBytes, s, in, out_lo, out_hi,
+                           g, tw.tile, tw.hi, tw.lo);
+    else
+        hipLaunchKernelGGL((pass_head2_kernel<kPassBigLog, IN_C64>), grid, block, Sh::kLdsBytes, s, in, out_lo, out_hi,
+                           g, tw.tile, tw.hi, tw.lo);
+    return hipGetLastError();
+}
+
 // Lets every large-workgroup instantiation use its dynamic LDS (above 64 KB).
 template <int LP, bool INV, int IK>
 static void allow_pass_lds() {
