@@ -74,10 +74,11 @@ std::vector<int> pass_bits(int lg) {
 
 // Lowest level of a forward recurrence chain: from level 18 up a level is
 // built from the level below (even bins, eq. (2)) and the half-length DFT of
-// the twiddled difference (odd bins, eq. (3)).  Level 18's chain head shares
-// its read of x with level 17's (launch_pass_head2): the two levels move 7
-// units of 8N bytes instead of 8; each level whose direct chain needs three
-// passes moves 4 (level 19) or 5 instead of 6.
+// the twiddled difference (odd bins, eq. (3)).  Level 18's chain shares its
+// head with level 17's (one read of x, launch_pass_head2) and its tail (level
+// 17's spectra give the even bins without a read back, launch_pass_tail2):
+// the two levels move 6 units of 8N bytes instead of 8; each level whose
+// direct chain needs three passes moves 4 (level 19) or 5 instead of 6.
 constexpr int kRecMinLevel = 2 * kPassMaxLog;
 
 }  // namespace
@@ -954,6 +955,23 @@ mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, h
                     continue;
                 }
                 if (first && skip_head) {              // ran with the level below
+                    ns += bits[q];
+                    continue;
+                }
+                if (last && head2) continue;           // stored by the next level's tail
+                if (last && skip_head && bits.size() == 2) {
+                    // both levels' last passes: level i - 1's windows from
+                    // ds[0], this level's odd bins from ds[1]
+                    PassGeom geo;
+                    geo.lg = dl;
+                    geo.r_log = bits[q];
+                    geo.ns_log = ns;
+                    geo.nwin = g.count * (N >> i);
+                    geo.wps = N >> i;
+                    geo.out_sig = g.d_out_sig;
+                    geo.out_stride = (int64_t)p->kept(g.order) * N;
+                    ProfScope ps(p, MRDFT_KERNEL_PASS_FWD, s);
+                    HIP_TRY(launch_pass_tail2(ds[0], ds[1], level_ptr(p, Y, i - 1, N), level_ptr(p, Y, i, N), geo, tw, s));
                     ns += bits[q];
                     continue;
                 }

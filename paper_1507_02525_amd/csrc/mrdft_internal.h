@@ -202,6 +202,11 @@ hipError_t launch_upper_fwd(bool real_in, const void* x, float2* Y, const PassGe
 // level lg + 1 from one read of x (radix 2^kPassMaxLog): see mrdft_pass.hip.
 hipError_t launch_pass_head2(int in_kind, const void* in, float2* out_lo, float2* out_hi, const PassGeom& g,
                              const Twiddles& tw, hipStream_t s);
+// The last passes of level lg (two windows) and of level lg + 1's recurrence
+// chain in one launch; level lg's spectra give level lg + 1's even bins
+// without being read back (see mrdft_pass.hip).
+hipError_t launch_pass_tail2(const float2* s_lo, const float2* s_hi, float2* y_lo, float2* y_hi, const PassGeom& g,
+                             const Twiddles& tw, hipStream_t s);
 hipError_t launch_pass(bool inv, int in_kind, int out_kind, const void* in, void* out, const PassGeom& g,
                        const Twiddles& tw, hipStream_t s);
 

@@ -416,6 +416,130 @@ hipError_t launch_pass_head2(int in_kind, const void* in, float2* out_lo, float2
     return hipGetLastError();
 }
 
+// Tails of the same two chains: the last pass of level lg (windows 2 W and
+// 2 W + 1 of level lg) and the last pass of level lg + 1's recurrence chain
+// (window W) have the same radix and span, so the outputs k = j + s Ns of a
+// column block are the same positions in all three.  A workgroup runs the
+// three column FFTs one after the other: level lg's two windows are stored
+// and their sum kept in registers, which is level lg + 1's even bin 2k
+// (eq. (2)) beside the odd bin 2k + 1 of the third FFT: level lg's spectra
+// are not read back.
+// g: lg, r_log and ns_log of the last pass (ns_log + r_log = lg), nwin / wps
+// of the windows of level lg + 1, out_sig / out_stride of both levels;
+// s_lo / s_hi: the two chains' scratch (dense, window index x L).
+template <int LP>
+__global__ __launch_bounds__(PassShape<LP>::kThreads, 4) void pass_tail2_kernel(const float2* __restrict__ s_lo,
+                                                                             const float2* __restrict__ s_hi,
+                                                                             float2* __restrict__ y_lo,
+                                                                             float2* __restrict__ y_hi, PassGeom g,
+                                                                             const float2* __restrict__ tab,
+                                                                             const double2* __restrict__ hi,
+                                                                             const double2* __restrict__ lo) {
+    using Sh = PassShape<LP>;
+    constexpr int kPassPoints = Sh::kPoints, kPassThreads = Sh::kThreads;
+    constexpr int kRowsPerThread = kPassPoints / kPassThreads;
+    typedef float f2v __attribute__((ext_vector_type(2)));
+    float2* const B = g_pass_lds;
+    float2* const T = g_pass_lds + kPassPoints + (kPassPoints >> 4);
+    const int rl = g.r_log;
+    const int fst = kColStride(1 << rl);
+    const int lnc = LP - rl;
+    const int nc = 1 << lnc;
+    const int64_t L = (int64_t)1 << g.lg;
+    const int64_t cols = L >> rl;
+    const int64_t jblocks = cols >> lnc;
+    const int64_t blk = blockIdx.x;
+    const int64_t gwin = blk / jblocks;
+    const int64_t j0 = (blk - gwin * jblocks) << lnc;
+    const int64_t b = gwin / g.wps, W = gwin - b * g.wps;
+    const int64_t obase = g.out_sig ? g.out_sig[b] : b * g.out_stride;
+    const int ns_log = g.ns_log;
+    const int64_t nsm = ((int64_t)1 << ns_log) - 1;
+    const int tid = threadIdx.x;
+    T[tid] = tab[tid << (kTileMaxLog - Sh::kTwLog)];
+    // one FFT phase over the L-point window at src: load, span twiddles,
+    // column FFTs; the results stay in LDS for the caller's output loop
+    auto phase = [&](const float2* __restrict__ src) __attribute__((always_inline)) {
+        int t = tid;
+        asm volatile("" : "+v"(t));
+        const int tj = t & (nc - 1), ts = t >> lnc;
+        const int rstep = kPassThreads >> lnc;
+        const int64_t j = j0 + tj;
+        float2 v[kRowsPerThread];
+#pragma unroll
+        for (int i = 0; i < kRowsPerThread; ++i) {
+            const f2v a = __builtin_nontemporal_load((const f2v*)(src + j + (int64_t)(ts + rstep * i) * cols));
+            v[i] = make_float2(a.x, a.y);
+        }
+        double2 w = tw_big64(hi, lo, ns_log + rl, (j & nsm) * ts);
+        const double2 step = tw_big64(hi, lo, ns_log + rl, (j & nsm) * rstep);
+#pragma unroll
+        for (int i = 0; i < kRowsPerThread; ++i) {
+            B[tj * fst + padc(ts + rstep * i)] = cmul(v[i], make_float2((float)w.x, (float)w.y));
+            w = make_double2(w.x * step.x - w.y * step.y, w.x * step.y + w.y * step.x);
+        }
+        __syncthreads();
+        column_fft<LP, false>(B, rl, T, t);
+    };
+    // output ie of this thread: column j0 + (e mod nc), row e / nc, at
+    // ((j >> ns) << (ns + r)) + (j mod 2^ns) + (row << ns) of the window
+    // (offsets inside a window fit 32 bits)
+    auto out_pos = [&](int t, int ie, int& lds) __attribute__((always_inline)) {
+        const int e = t + ie * kPassThreads;
+        const int jj = e & (nc - 1), s = e >> lnc;
+        const int j = (int)j0 + jj;
+        lds = jj * fst + padc(s);
+        return ((j >> ns_log) << (ns_log + rl)) + (j & (int)nsm) + (s << ns_log);
+    };
+    float2 esum[kRowsPerThread];
+    auto lower = [&](int h) __attribute__((always_inline)) {
+        phase(s_lo + (2 * gwin + h) * L);
+        int t = tid;
+        asm volatile("" : "+v"(t));
+        float2* const yw = y_lo + obase + (2 * W + h) * L;
+#pragma unroll
+        for (int ie = 0; ie < kRowsPerThread; ++ie) {
+            int li;
+            const int o = out_pos(t, ie, li);
+            const float2 vo = B[li];
+            yw[o] = vo;
+            esum[ie] = h ? cadd(esum[ie], vo) : vo;
+        }
+        __syncthreads();
+    };
+    lower(0);
+    lower(1);
+    phase(s_hi + gwin * L);
+    {
+        int t = tid;
+        asm volatile("" : "+v"(t));
+        float2* const yh = y_hi + obase + W * 2 * L;
+#pragma unroll
+        for (int ie = 0; ie < kRowsPerThread; ++ie) {
+            int li;
+            const int o = out_pos(t, ie, li);
+            const float2 vo = B[li];
+            float2* q = yh + 2 * o;
+            q[0] = esum[ie];
+            q[1] = vo;
+        }
+    }
+}
+
+hipError_t launch_pass_tail2(const float2* s_lo, const float2* s_hi, float2* y_lo, float2* y_hi, const PassGeom& g,
+                             const Twiddles& tw, hipStream_t s) {
+    using Sh = PassShape<kPassSmallLog>;
+    if (g.r_log < 4 || g.r_log > kPassSmallMaxLog || g.ns_log <= 0 || g.ns_log + g.r_log != g.lg ||
+        g.lg < kPassSmallLog || g.lg + 1 > kMaxOrder)
+        return hipErrorInvalidValue;
+    const int64_t nblk = g.nwin << (g.lg - kPassSmallLog);
+    if (nblk <= 0) return hipSuccess;
+    dim3 grid((unsigned)nblk), block(Sh::kThreads);
+    hipLaunchKernelGGL((pass_tail2_kernel<kPassSmallLog>), grid, block, Sh::kLdsBytes, s, s_lo, s_hi, y_lo, y_hi, g,
+                       tw.tile, tw.hi, tw.lo);
+    return hipGetLastError();
+}
+
 // Lets every large-workgroup instantiation use its dynamic LDS (above 64 KB).
 template <int LP, bool INV, int IK>
 static void allow_pass_lds() {
