@@ -1,9 +1,10 @@
-"""Levels above 18 (windows of 2^19 samples and more) against the FP64 oracle.
+"""Levels above 16 computed by global passes, against the FP64 oracle.
 
-These levels are built from the level below them: the even bins are the sums
-of the child windows' bins (Section 3, eq. (2)), the odd bins the half-length
-DFT of the twiddled difference of the window's halves (eq. (3)), both over
-global passes.  Covered: ragged complex and real batches; level ranges that
+From level 18 up a level is built from the level below: the even bins are
+the sums of the child windows' bins (Section 3, eq. (2)), the odd bins the
+half-length DFT of the twiddled difference of the window's halves (eq. (3)),
+both over global passes (levels 17 and 18 sharing their first and last
+launches).  Covered: ragged complex and real batches; level ranges that
 keep the level below (recurrence) or not (direct passes); every stream
 schedule; graph replay against the eager plan bit for bit.
 """
@@ -49,6 +50,7 @@ def _check_upper(Yh, x, offs, orders, lo, hi, oo):
     ("c64", [21, 20], 19, 21),          # level 19 by direct passes (18 not kept), 20 and 21 from the level below
     ("c64", [20], 20, 20),              # a single upper level: direct passes
     ("c64", [21, 19], 18, 20),          # 19 and 20 from the level below, 21 not kept
+    ("c64", [19, 18], 17, 18),          # levels 17 and 18 only: their shared head and tail launches
     ("r32", [20, 19], 1, 28),           # real input (difference of real halves)
 ])
 def test_upper_levels_every_schedule(dtype, orders, lo, hi):
