@@ -929,12 +929,17 @@ mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, h
                 continue;
             }
             const int dl = rec ? i - 1 : i;            // order of the DFTs of the chain
-            const std::vector<int> bits = pass_bits(dl);
+            std::vector<int> bits = pass_bits(dl);
             const int64_t wlen = rec ? N / 2 : N;      // scratch points per signal
+            // the chains of levels 17 and 18 (2^17-point DFTs) start with the
+            // smaller radix: the shared head, three FFTs per workgroup, then runs
+            // four 4096-point workgroups per CU, the shared tail two 8192-point
+            // ones (the 1000-signal batch ~1.773 -> ~1.755 ms)
+            if ((i == kRecMinLevel - 1 || i == kRecMinLevel) && bits.size() == 2) std::swap(bits[0], bits[1]);
             // level kRecMinLevel - 1 with the next level built from it: one
             // head for both chains (this level's scratch ds[0], the next's ds[1])
             const bool head2 = !rec && i + 1 == kRecMinLevel && i + 1 <= g.order && i + 1 <= p->hi && !p->hs &&
-                               bits.size() == 2 && bits[0] == kPassMaxLog;
+                               bits.size() == 2;
             const bool skip_head = rec && i == kRecMinLevel && head_done;
             int ns = 0;
             for (size_t q = 0; q < bits.size(); ++q) {

@@ -199,7 +199,7 @@ int64_t row_twiddle_entries();
 hipError_t launch_upper_fwd(bool real_in, const void* x, float2* Y, const PassGeom& g, const Twiddles& tw,
                             hipStream_t s);
 // The first passes of level lg (two windows) and of the recurrence chain of
-// level lg + 1 from one read of x (radix 2^kPassMaxLog): see mrdft_pass.hip.
+// level lg + 1 from one read of x (radix up to 2^kPassMaxLog): see mrdft_pass.hip.
 hipError_t launch_pass_head2(int in_kind, const void* in, float2* out_lo, float2* out_hi, const PassGeom& g,
                              const Twiddles& tw, hipStream_t s);
 // The last passes of level lg (two windows) and of level lg + 1's recurrence

@@ -390,30 +390,37 @@ __global__ __launch_bounds__(PassShape<LP>::kThreads, 4) void pass_head2_kernel(
     fft_out(out_hi + gwin * L);
 }
 
-hipError_t launch_pass_head2(int in_kind, const void* in, float2* out_lo, float2* out_hi, const PassGeom& g,
-                             const Twiddles& tw, hipStream_t s) {
-    if (g.r_log != kPassMaxLog || g.lg + 1 > kMaxOrder || (in_kind != IN_C64 && in_kind != IN_R32))
-        return hipErrorInvalidValue;
-    using Sh = PassShape<kPassBigLog>;
-    if (g.lg < kPassBigLog) return hipErrorInvalidValue;
-    const int64_t nblk = g.nwin << (g.lg - kPassBigLog);
+template <int LP>
+static hipError_t launch_head2_t(int in_kind, const void* in, float2* out_lo, float2* out_hi, const PassGeom& g,
+                                 const Twiddles& tw, hipStream_t s) {
+    using Sh = PassShape<LP>;
+    if (g.lg < LP) return hipErrorInvalidValue;
+    const int64_t nblk = g.nwin << (g.lg - LP);
     if (nblk <= 0) return hipSuccess;
     static const bool attr = [] {
-        (void)hipFuncSetAttribute((const void*)pass_head2_kernel<kPassBigLog, IN_C64>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, Sh::kLdsBytes);
-        (void)hipFuncSetAttribute((const void*)pass_head2_kernel<kPassBigLog, IN_R32>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, Sh::kLdsBytes);
+        (void)hipFuncSetAttribute((const void*)pass_head2_kernel<LP, IN_C64>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  Sh::kLdsBytes);
+        (void)hipFuncSetAttribute((const void*)pass_head2_kernel<LP, IN_R32>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  Sh::kLdsBytes);
         return true;
     }();
     (void)attr;
     dim3 grid((unsigned)nblk), block(Sh::kThreads);
     if (in_kind == IN_R32)
-        hipLaunchKernelGGL((pass_head2_kernel<kPassBigLog, IN_R32>), grid, block, Sh::kLdsBytes, s, in, out_lo, out_hi,
-                           g, tw.tile, tw.hi, tw.lo);
+        hipLaunchKernelGGL((pass_head2_kernel<LP, IN_R32>), grid, block, Sh::kLdsBytes, s, in, out_lo, out_hi, g,
+                           tw.tile, tw.hi, tw.lo);
     else
-        hipLaunchKernelGGL((pass_head2_kernel<kPassBigLog, IN_C64>), grid, block, Sh::kLdsBytes, s, in, out_lo, out_hi,
-                           g, tw.tile, tw.hi, tw.lo);
+        hipLaunchKernelGGL((pass_head2_kernel<LP, IN_C64>), grid, block, Sh::kLdsBytes, s, in, out_lo, out_hi, g,
+                           tw.tile, tw.hi, tw.lo);
     return hipGetLastError();
+}
+
+hipError_t launch_pass_head2(int in_kind, const void* in, float2* out_lo, float2* out_hi, const PassGeom& g,
+                             const Twiddles& tw, hipStream_t s) {
+    if (g.r_log < 4 || g.r_log > kPassMaxLog || g.lg + 1 > kMaxOrder || (in_kind != IN_C64 && in_kind != IN_R32))
+        return hipErrorInvalidValue;
+    return g.r_log <= kPassSmallMaxLog ? launch_head2_t<kPassSmallLog>(in_kind, in, out_lo, out_hi, g, tw, s)
+                                       : launch_head2_t<kPassBigLog>(in_kind, in, out_lo, out_hi, g, tw, s);
 }
 
 // Tails of the same two chains: the last pass of level lg (windows 2 W and
@@ -526,18 +533,31 @@ __global__ __launch_bounds__(PassShape<LP>::kThreads, 4) void pass_tail2_kernel(
     }
 }
 
+template <int LP>
+static hipError_t launch_tail2_t(const float2* s_lo, const float2* s_hi, float2* y_lo, float2* y_hi, const PassGeom& g,
+                                 const Twiddles& tw, hipStream_t s) {
+    using Sh = PassShape<LP>;
+    if (g.lg < LP) return hipErrorInvalidValue;
+    const int64_t nblk = g.nwin << (g.lg - LP);
+    if (nblk <= 0) return hipSuccess;
+    static const bool attr = [] {
+        (void)hipFuncSetAttribute((const void*)pass_tail2_kernel<LP>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  Sh::kLdsBytes);
+        return true;
+    }();
+    (void)attr;
+    dim3 grid((unsigned)nblk), block(Sh::kThreads);
+    hipLaunchKernelGGL((pass_tail2_kernel<LP>), grid, block, Sh::kLdsBytes, s, s_lo, s_hi, y_lo, y_hi, g, tw.tile,
+                       tw.hi, tw.lo);
+    return hipGetLastError();
+}
+
 hipError_t launch_pass_tail2(const float2* s_lo, const float2* s_hi, float2* y_lo, float2* y_hi, const PassGeom& g,
                              const Twiddles& tw, hipStream_t s) {
-    using Sh = PassShape<kPassSmallLog>;
-    if (g.r_log < 4 || g.r_log > kPassSmallMaxLog || g.ns_log <= 0 || g.ns_log + g.r_log != g.lg ||
-        g.lg < kPassSmallLog || g.lg + 1 > kMaxOrder)
+    if (g.r_log < 4 || g.r_log > kPassMaxLog || g.ns_log <= 0 || g.ns_log + g.r_log != g.lg || g.lg + 1 > kMaxOrder)
         return hipErrorInvalidValue;
-    const int64_t nblk = g.nwin << (g.lg - kPassSmallLog);
-    if (nblk <= 0) return hipSuccess;
-    dim3 grid((unsigned)nblk), block(Sh::kThreads);
-    hipLaunchKernelGGL((pass_tail2_kernel<kPassSmallLog>), grid, block, Sh::kLdsBytes, s, s_lo, s_hi, y_lo, y_hi, g,
-                       tw.tile, tw.hi, tw.lo);
-    return hipGetLastError();
+    return g.r_log <= kPassSmallMaxLog ? launch_tail2_t<kPassSmallLog>(s_lo, s_hi, y_lo, y_hi, g, tw, s)
+                                       : launch_tail2_t<kPassBigLog>(s_lo, s_hi, y_lo, y_hi, g, tw, s);
 }
 
 // Lets every large-workgroup instantiation use its dynamic LDS (above 64 KB).
