@@ -160,6 +160,7 @@ struct mrdft_plan {
     void* gkey_y = nullptr;
     float2* d_s[2] = {nullptr, nullptr};    // pass ping-pong scratch of the caller's stream / side stream 0
     float2* d_ss[3][2] = {};                // ping-pong scratch of side streams 1..3
+    int64_t scratch_pts = 0;                // complex points of each of those arrays
     // spectral loss workspace
     float* d_v = nullptr;
     float2* d_Yv = nullptr;
@@ -554,6 +555,7 @@ mrdft_status build_tables(mrdft_plan* p, hipStream_t s) {
                 dev_malloc(&p->d_ss[k - 1][1], sizeof(float2) * scratch) != hipSuccess)
                 return fail(MRDFT_E_ALLOC, "pass workspace allocation failed (%d x 2 x %lld complex)", p->nsides,
                             (long long)scratch);
+        p->scratch_pts = scratch;
     }
     HIP_TRY(hipStreamSynchronize(s));
     return MRDFT_OK;
@@ -892,6 +894,24 @@ mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, h
         }
         return MRDFT_OK;
     };
+    // Signals of order kRecMinLevel - 1 (that level by a direct chain of two
+    // passes) run it inside the shared head and tail launches of the first
+    // longer group: their workgroups, shorter than the pairs', follow them and
+    // fill the pair launches' last, partly filled round of workgroups.  Their
+    // scratch follows the longer group's upper chain in ds[1].
+    const Group* g_one = nullptr;                     // the order kRecMinLevel - 1 group
+    const Group* g_two = nullptr;                     // the group whose head and tail take it along
+    {
+        const int l1 = kRecMinLevel - 1;
+        if (!p->hs && l1 >= p->lo && l1 + 1 <= p->hi && pass_bits(l1).size() == 2)
+            for (const Group& g : p->groups) {
+                if (g.order == l1) g_one = &g;
+                else if (g.order > l1 && !g_two) g_two = &g;
+            }
+        if (!g_one || !g_two ||
+            (g_two->count << (g_two->order - 1)) + (g_one->count << l1) > p->scratch_pts)
+            g_one = g_two = nullptr;
+    }
     auto upper = [&]() -> mrdft_status {
     int chain = 0;                                    // multi-pass levels, dealt over the side streams
     for (const Group& g : p->groups) {
@@ -901,6 +921,7 @@ mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, h
         for (int i = kTileMaxLog + 1; i <= g.order; ++i) {
             if ((real_jobs_cover || cjobs_cover) && i <= kRowsMaxLevel) continue;     // in the one launch
             if (i < p->lo || i > p->hi) continue;                                      // level not kept
+            if (&g == g_one && i == kRecMinLevel - 1) continue;                        // with g_two's head and tail
             // recurrence chain: level i - 1 is stored by this plan, by the
             // chain just before on the same stream
             const bool rec = i >= kRecMinLevel && i - 1 >= p->lo && !p->hs;
@@ -941,6 +962,23 @@ mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, h
             const bool head2 = !rec && i + 1 == kRecMinLevel && i + 1 <= g.order && i + 1 <= p->hi && !p->hs &&
                                bits.size() == 2;
             const bool skip_head = rec && i == kRecMinLevel && head_done;
+            // g_one's windows of level kRecMinLevel - 1 beside this group's pairs
+            const bool with_one = &g == g_two && (head2 || skip_head);
+            const int64_t N1 = g_one ? int64_t(1) << g_one->order : 0;
+            float2* const s_one = with_one ? ds[1] + (g.count << (g.order - 1)) : nullptr;
+            auto one_geo = [&](int r_log, int ns_log) {
+                PassGeom o;
+                o.lg = kRecMinLevel - 1;
+                o.r_log = r_log;
+                o.ns_log = ns_log;
+                o.nwin = g_one->count * (N1 >> o.lg);
+                o.wps = N1 >> o.lg;
+                o.in_sig = g_one->d_in_sig;
+                o.in_stride = N1;
+                o.out_sig = g_one->d_out_sig;
+                o.out_stride = (int64_t)p->kept(g_one->order) * N1;
+                return o;
+            };
             int ns = 0;
             for (size_t q = 0; q < bits.size(); ++q) {
                 const bool first = q == 0, last = q + 1 == bits.size();
@@ -953,8 +991,9 @@ mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, h
                     geo.wps = N >> (i + 1);
                     geo.in_sig = g.d_in_sig;
                     geo.in_stride = N;
+                    const PassGeom g1 = with_one ? one_geo(bits[0], 0) : geo;
                     ProfScope ps(p, MRDFT_KERNEL_PASS_FWD, s);
-                    HIP_TRY(launch_pass_head2(in_kind, x, ds[0], ds[1], geo, tw, s));
+                    HIP_TRY(launch_pass_head2(in_kind, x, ds[0], ds[1], geo, s_one, with_one ? &g1 : nullptr, tw, s));
                     head_done = true;
                     ns += bits[q];
                     continue;
@@ -975,8 +1014,11 @@ mrdft_status run_forward(mrdft_plan* p, const void* x, int in_kind, float2* Y, h
                     geo.wps = N >> i;
                     geo.out_sig = g.d_out_sig;
                     geo.out_stride = (int64_t)p->kept(g.order) * N;
+                    const PassGeom g1 = with_one ? one_geo(bits[q], ns) : geo;
+                    float2* const y_one = with_one ? level_ptr(p, Y, kRecMinLevel - 1, N1) : nullptr;
                     ProfScope ps(p, MRDFT_KERNEL_PASS_FWD, s);
-                    HIP_TRY(launch_pass_tail2(ds[0], ds[1], level_ptr(p, Y, i - 1, N), level_ptr(p, Y, i, N), geo, tw, s));
+                    HIP_TRY(launch_pass_tail2(ds[0], ds[1], level_ptr(p, Y, i - 1, N), level_ptr(p, Y, i, N), geo, s_one,
+                                              y_one, with_one ? &g1 : nullptr, tw, s));
                     ns += bits[q];
                     continue;
                 }

@@ -200,13 +200,16 @@ hipError_t launch_upper_fwd(bool real_in, const void* x, float2* Y, const PassGe
                             hipStream_t s);
 // The first passes of level lg (two windows) and of the recurrence chain of
 // level lg + 1 from one read of x (radix up to 2^kPassMaxLog): see mrdft_pass.hip.
+// gs (or null): windows of level lg of signals that end there, their plain
+// first pass (to out_s) in the same launch.
 hipError_t launch_pass_head2(int in_kind, const void* in, float2* out_lo, float2* out_hi, const PassGeom& g,
-                             const Twiddles& tw, hipStream_t s);
+                             float2* out_s, const PassGeom* gs, const Twiddles& tw, hipStream_t s);
 // The last passes of level lg (two windows) and of level lg + 1's recurrence
 // chain in one launch; level lg's spectra give level lg + 1's even bins
-// without being read back (see mrdft_pass.hip).
+// without being read back (see mrdft_pass.hip).  gs (or null): the plain
+// last pass of the windows given to the head's gs, from s_s to y_s.
 hipError_t launch_pass_tail2(const float2* s_lo, const float2* s_hi, float2* y_lo, float2* y_hi, const PassGeom& g,
-                             const Twiddles& tw, hipStream_t s);
+                             const float2* s_s, float2* y_s, const PassGeom* gs, const Twiddles& tw, hipStream_t s);
 hipError_t launch_pass(bool inv, int in_kind, int out_kind, const void* in, void* out, const PassGeom& g,
                        const Twiddles& tw, hipStream_t s);
 

@@ -301,10 +301,15 @@ __global__ __launch_bounds__(PassShape<LP>::kThreads) void pass_kernel(const voi
 // layout, and (x0 - x1) w_{2L}^n, written to out_hi in the upper chain's.
 // g: lg, r_log (the first radix), nwin / wps / in_sig / in_stride of the
 // windows of level lg + 1; outputs dense (window index x L).
+// gs (gs.nwin may be 0): windows of level lg whose signals end at that level
+// (no level lg + 1): the plain first pass of their chain (one FFT, to out_s),
+// run by the workgroups after the pairs' so that the last, partly filled
+// round of the pair workgroups is shared with this shorter work.
 template <int LP, int IN_KIND>
 __global__ __launch_bounds__(PassShape<LP>::kThreads, 4) void pass_head2_kernel(const void* __restrict__ in,
                                                                              float2* __restrict__ out_lo,
                                                                              float2* __restrict__ out_hi, PassGeom g,
+                                                                             float2* __restrict__ out_s, PassGeom gs,
                                                                              const float2* __restrict__ tab,
                                                                              const double2* __restrict__ hi,
                                                                              const double2* __restrict__ lo) {
@@ -322,29 +327,15 @@ __global__ __launch_bounds__(PassShape<LP>::kThreads, 4) void pass_head2_kernel(
     const int64_t L = (int64_t)1 << g.lg;
     const int64_t cols = L >> rl;
     const int64_t jblocks = cols >> lnc;
-    const int64_t blk = blockIdx.x;
+    const int64_t npair = g.nwin * jblocks;
+    const bool single = (int64_t)blockIdx.x >= npair;              // uniform over the workgroup
+    const int64_t blk = single ? (int64_t)blockIdx.x - npair : (int64_t)blockIdx.x;
     const int64_t gwin = blk / jblocks;
     const int64_t j0 = (blk - gwin * jblocks) << lnc;
-    const int64_t b = gwin / g.wps, W = gwin - b * g.wps;
-    const int64_t ib = (g.in_sig ? g.in_sig[b] : b * g.in_stride) + W * 2 * L;
     const int tid = threadIdx.x;
     const int jj = tid & (nc - 1), s0 = tid >> lnc;
     const int rstep = kPassThreads >> lnc;
     const int64_t j = j0 + jj;
-    float2 x0[kRowsPerThread], x1[kRowsPerThread];
-#pragma unroll
-    for (int i = 0; i < kRowsPerThread; ++i) {
-        const int64_t idx = ib + j + (int64_t)(s0 + rstep * i) * cols;
-        if constexpr (IN_KIND == IN_R32) {
-            x0[i] = make_float2(__builtin_nontemporal_load((const float*)in + idx), 0.0f);
-            x1[i] = make_float2(__builtin_nontemporal_load((const float*)in + idx + L), 0.0f);
-        } else {
-            const f2v a = __builtin_nontemporal_load((const f2v*)((const float2*)in + idx));
-            const f2v c = __builtin_nontemporal_load((const f2v*)((const float2*)in + idx + L));
-            x0[i] = make_float2(a.x, a.y);
-            x1[i] = make_float2(c.x, c.y);
-        }
-    }
     T[tid] = tab[tid << (kTileMaxLog - Sh::kTwLog)];
     // one column-FFT phase: the data already in LDS, the FFTs, the r
     // consecutive outputs of each column to dst (first pass: span 1).  The
@@ -371,6 +362,33 @@ __global__ __launch_bounds__(PassShape<LP>::kThreads, 4) void pass_head2_kernel(
         }
         __syncthreads();                               // B read before the next phase writes it
     };
+    auto load = [&](int64_t idx) __attribute__((always_inline)) {
+        if constexpr (IN_KIND == IN_R32) {
+            return make_float2(__builtin_nontemporal_load((const float*)in + idx), 0.0f);
+        } else {
+            const f2v a = __builtin_nontemporal_load((const f2v*)((const float2*)in + idx));
+            return make_float2(a.x, a.y);
+        }
+    };
+    if (single) {                                      // one window: its first pass only
+        const int64_t b = gwin / gs.wps, W = gwin - b * gs.wps;
+        const int64_t ib = (gs.in_sig ? gs.in_sig[b] : b * gs.in_stride) + W * L;
+        float2 xs[kRowsPerThread];
+#pragma unroll
+        for (int i = 0; i < kRowsPerThread; ++i) xs[i] = load(ib + j + (int64_t)(s0 + rstep * i) * cols);
+        to_lds(xs);
+        fft_out(out_s + gwin * L);
+        return;
+    }
+    const int64_t b = gwin / g.wps, W = gwin - b * g.wps;
+    const int64_t ib = (g.in_sig ? g.in_sig[b] : b * g.in_stride) + W * 2 * L;
+    float2 x0[kRowsPerThread], x1[kRowsPerThread];
+#pragma unroll
+    for (int i = 0; i < kRowsPerThread; ++i) {
+        const int64_t idx = ib + j + (int64_t)(s0 + rstep * i) * cols;
+        x0[i] = load(idx);
+        x1[i] = load(idx + L);
+    }
     // first half into LDS; its registers then take the twiddled difference
     // (x0 - x1) w_{2L}^n, n = j + s cols (FP64 recurrence), before the FFTs
     to_lds(x0);
@@ -392,11 +410,12 @@ __global__ __launch_bounds__(PassShape<LP>::kThreads, 4) void pass_head2_kernel(
 
 template <int LP>
 static hipError_t launch_head2_t(int in_kind, const void* in, float2* out_lo, float2* out_hi, const PassGeom& g,
-                                 const Twiddles& tw, hipStream_t s) {
+                                 float2* out_s, const PassGeom& gs, const Twiddles& tw, hipStream_t s) {
     using Sh = PassShape<LP>;
     if (g.lg < LP) return hipErrorInvalidValue;
-    const int64_t nblk = g.nwin << (g.lg - LP);
+    const int64_t nblk = (g.nwin + gs.nwin) << (g.lg - LP);
     if (nblk <= 0) return hipSuccess;
+    if (nblk > INT32_MAX) return hipErrorInvalidValue;
     static const bool attr = [] {
         (void)hipFuncSetAttribute((const void*)pass_head2_kernel<LP, IN_C64>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   Sh::kLdsBytes);
@@ -408,19 +427,31 @@ static hipError_t launch_head2_t(int in_kind, const void* in, float2* out_lo, fl
     dim3 grid((unsigned)nblk), block(Sh::kThreads);
     if (in_kind == IN_R32)
         hipLaunchKernelGGL((pass_head2_kernel<LP, IN_R32>), grid, block, Sh::kLdsBytes, s, in, out_lo, out_hi, g,
-                           tw.tile, tw.hi, tw.lo);
+                           out_s, gs, tw.tile, tw.hi, tw.lo);
     else
         hipLaunchKernelGGL((pass_head2_kernel<LP, IN_C64>), grid, block, Sh::kLdsBytes, s, in, out_lo, out_hi, g,
-                           tw.tile, tw.hi, tw.lo);
+                           out_s, gs, tw.tile, tw.hi, tw.lo);
     return hipGetLastError();
 }
 
 hipError_t launch_pass_head2(int in_kind, const void* in, float2* out_lo, float2* out_hi, const PassGeom& g,
-                             const Twiddles& tw, hipStream_t s) {
-    if (g.r_log < 4 || g.r_log > kPassMaxLog || g.lg + 1 > kMaxOrder || (in_kind != IN_C64 && in_kind != IN_R32))
+                             float2* out_s, const PassGeom* gs, const Twiddles& tw, hipStream_t s) {
+    if (g.r_log < 4 || g.r_log > kPassMaxLog || g.lg + 1 > kMaxOrder || (in_kind != IN_C64 && in_kind != IN_R32) ||
+        g.nwin < 0)
         return hipErrorInvalidValue;
-    return g.r_log <= kPassSmallMaxLog ? launch_head2_t<kPassSmallLog>(in_kind, in, out_lo, out_hi, g, tw, s)
-                                       : launch_head2_t<kPassBigLog>(in_kind, in, out_lo, out_hi, g, tw, s);
+    PassGeom one = g;                                  // no single windows unless given
+    one.nwin = 0;
+    one.wps = 1;
+    one.in_sig = nullptr;
+    one.in_stride = 0;
+    if (gs) {
+        if (gs->lg != g.lg || gs->r_log != g.r_log || gs->nwin < 0 || (gs->nwin > 0 && (!out_s || gs->wps <= 0)))
+            return hipErrorInvalidValue;
+        one = *gs;
+    }
+    return g.r_log <= kPassSmallMaxLog
+               ? launch_head2_t<kPassSmallLog>(in_kind, in, out_lo, out_hi, g, out_s, one, tw, s)
+               : launch_head2_t<kPassBigLog>(in_kind, in, out_lo, out_hi, g, out_s, one, tw, s);
 }
 
 // Tails of the same two chains: the last pass of level lg (windows 2 W and
@@ -434,11 +465,16 @@ hipError_t launch_pass_head2(int in_kind, const void* in, float2* out_lo, float2
 // g: lg, r_log and ns_log of the last pass (ns_log + r_log = lg), nwin / wps
 // of the windows of level lg + 1, out_sig / out_stride of both levels;
 // s_lo / s_hi: the two chains' scratch (dense, window index x L).
+// gs (gs.nwin may be 0): level lg of signals that end at that level, the
+// plain last pass of their chain (scratch s_s, output y_s with gs's wps /
+// out_sig / out_stride), after the pair workgroups as in the head.
 template <int LP>
 __global__ __launch_bounds__(PassShape<LP>::kThreads, 4) void pass_tail2_kernel(const float2* __restrict__ s_lo,
                                                                              const float2* __restrict__ s_hi,
                                                                              float2* __restrict__ y_lo,
                                                                              float2* __restrict__ y_hi, PassGeom g,
+                                                                             const float2* __restrict__ s_s,
+                                                                             float2* __restrict__ y_s, PassGeom gs,
                                                                              const float2* __restrict__ tab,
                                                                              const double2* __restrict__ hi,
                                                                              const double2* __restrict__ lo) {
@@ -455,11 +491,11 @@ __global__ __launch_bounds__(PassShape<LP>::kThreads, 4) void pass_tail2_kernel(
     const int64_t L = (int64_t)1 << g.lg;
     const int64_t cols = L >> rl;
     const int64_t jblocks = cols >> lnc;
-    const int64_t blk = blockIdx.x;
+    const int64_t npair = g.nwin * jblocks;
+    const bool single = (int64_t)blockIdx.x >= npair;              // uniform over the workgroup
+    const int64_t blk = single ? (int64_t)blockIdx.x - npair : (int64_t)blockIdx.x;
     const int64_t gwin = blk / jblocks;
     const int64_t j0 = (blk - gwin * jblocks) << lnc;
-    const int64_t b = gwin / g.wps, W = gwin - b * g.wps;
-    const int64_t obase = g.out_sig ? g.out_sig[b] : b * g.out_stride;
     const int ns_log = g.ns_log;
     const int64_t nsm = ((int64_t)1 << ns_log) - 1;
     const int tid = threadIdx.x;
@@ -498,6 +534,23 @@ __global__ __launch_bounds__(PassShape<LP>::kThreads, 4) void pass_tail2_kernel(
         lds = jj * fst + padc(s);
         return ((j >> ns_log) << (ns_log + rl)) + (j & (int)nsm) + (s << ns_log);
     };
+    if (single) {                                      // one window: its last pass only
+        const int64_t b = gwin / gs.wps, W = gwin - b * gs.wps;
+        const int64_t obase = gs.out_sig ? gs.out_sig[b] : b * gs.out_stride;
+        phase(s_s + gwin * L);
+        int t = tid;
+        asm volatile("" : "+v"(t));
+        float2* const yw = y_s + obase + W * L;
+#pragma unroll
+        for (int ie = 0; ie < kRowsPerThread; ++ie) {
+            int li;
+            const int o = out_pos(t, ie, li);
+            yw[o] = B[li];
+        }
+        return;
+    }
+    const int64_t b = gwin / g.wps, W = gwin - b * g.wps;
+    const int64_t obase = g.out_sig ? g.out_sig[b] : b * g.out_stride;
     float2 esum[kRowsPerThread];
     auto lower = [&](int h) __attribute__((always_inline)) {
         phase(s_lo + (2 * gwin + h) * L);
@@ -535,11 +588,13 @@ __global__ __launch_bounds__(PassShape<LP>::kThreads, 4) void pass_tail2_kernel(
 
 template <int LP>
 static hipError_t launch_tail2_t(const float2* s_lo, const float2* s_hi, float2* y_lo, float2* y_hi, const PassGeom& g,
-                                 const Twiddles& tw, hipStream_t s) {
+                                 const float2* s_s, float2* y_s, const PassGeom& gs, const Twiddles& tw,
+                                 hipStream_t s) {
     using Sh = PassShape<LP>;
     if (g.lg < LP) return hipErrorInvalidValue;
-    const int64_t nblk = g.nwin << (g.lg - LP);
+    const int64_t nblk = (g.nwin + gs.nwin) << (g.lg - LP);
     if (nblk <= 0) return hipSuccess;
+    if (nblk > INT32_MAX) return hipErrorInvalidValue;
     static const bool attr = [] {
         (void)hipFuncSetAttribute((const void*)pass_tail2_kernel<LP>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   Sh::kLdsBytes);
@@ -547,17 +602,30 @@ static hipError_t launch_tail2_t(const float2* s_lo, const float2* s_hi, float2*
     }();
     (void)attr;
     dim3 grid((unsigned)nblk), block(Sh::kThreads);
-    hipLaunchKernelGGL((pass_tail2_kernel<LP>), grid, block, Sh::kLdsBytes, s, s_lo, s_hi, y_lo, y_hi, g, tw.tile,
-                       tw.hi, tw.lo);
+    hipLaunchKernelGGL((pass_tail2_kernel<LP>), grid, block, Sh::kLdsBytes, s, s_lo, s_hi, y_lo, y_hi, g, s_s, y_s,
+                       gs, tw.tile, tw.hi, tw.lo);
     return hipGetLastError();
 }
 
 hipError_t launch_pass_tail2(const float2* s_lo, const float2* s_hi, float2* y_lo, float2* y_hi, const PassGeom& g,
-                             const Twiddles& tw, hipStream_t s) {
-    if (g.r_log < 4 || g.r_log > kPassMaxLog || g.ns_log <= 0 || g.ns_log + g.r_log != g.lg || g.lg + 1 > kMaxOrder)
+                             const float2* s_s, float2* y_s, const PassGeom* gs, const Twiddles& tw, hipStream_t s) {
+    if (g.r_log < 4 || g.r_log > kPassMaxLog || g.ns_log <= 0 || g.ns_log + g.r_log != g.lg || g.lg + 1 > kMaxOrder ||
+        g.nwin < 0)
         return hipErrorInvalidValue;
-    return g.r_log <= kPassSmallMaxLog ? launch_tail2_t<kPassSmallLog>(s_lo, s_hi, y_lo, y_hi, g, tw, s)
-                                       : launch_tail2_t<kPassBigLog>(s_lo, s_hi, y_lo, y_hi, g, tw, s);
+    PassGeom one = g;                                  // no single windows unless given
+    one.nwin = 0;
+    one.wps = 1;
+    one.out_sig = nullptr;
+    one.out_stride = 0;
+    if (gs) {
+        if (gs->lg != g.lg || gs->r_log != g.r_log || gs->ns_log != g.ns_log || gs->nwin < 0 ||
+            (gs->nwin > 0 && (!s_s || !y_s || gs->wps <= 0)))
+            return hipErrorInvalidValue;
+        one = *gs;
+    }
+    return g.r_log <= kPassSmallMaxLog
+               ? launch_tail2_t<kPassSmallLog>(s_lo, s_hi, y_lo, y_hi, g, s_s, y_s, one, tw, s)
+               : launch_tail2_t<kPassBigLog>(s_lo, s_hi, y_lo, y_hi, g, s_s, y_s, one, tw, s);
 }
 
 // Lets every large-workgroup instantiation use its dynamic LDS (above 64 KB).

@@ -4,9 +4,10 @@ From level 18 up a level is built from the level below: the even bins are
 the sums of the child windows' bins (Section 3, eq. (2)), the odd bins the
 half-length DFT of the twiddled difference of the window's halves (eq. (3)),
 both over global passes (levels 17 and 18 sharing their first and last
-launches).  Covered: ragged complex and real batches; level ranges that
-keep the level below (recurrence) or not (direct passes); every stream
-schedule; graph replay against the eager plan bit for bit.
+launches, which also take level 17 of the signals of order 17 when the
+pass scratch holds it).  Covered: ragged complex and real batches; level
+ranges that keep the level below (recurrence) or not (direct passes); every
+stream schedule; graph replay against the eager plan bit for bit.
 """
 import numpy as np
 import pytest
@@ -52,6 +53,13 @@ def _check_upper(Yh, x, offs, orders, lo, hi, oo):
     ("c64", [21, 19], 18, 20),          # 19 and 20 from the level below, 21 not kept
     ("c64", [19, 18], 17, 18),          # levels 17 and 18 only: their shared head and tail launches
     ("r32", [20, 19], 1, 28),           # real input (difference of real halves)
+    # signals of order 17 run their level 17 inside the shared head and tail
+    # launches of the first longer group when the scratch holds both
+    ("c64", [17, 18, 17, 19], 1, 28),   # with the order-18 group's head and tail
+    ("r32", [17, 19, 17], 1, 28),       # with an order-19 group's; the scratch exactly full
+    ("c64", [17, 17, 17, 18], 1, 28),   # scratch too small: separate passes
+    ("c64", [18, 17], 17, 18),          # levels 17 and 18 only
+    ("c64", [18, 17], 17, 17),          # level 17 only: no shared launches
 ])
 def test_upper_levels_every_schedule(dtype, orders, lo, hi):
     need_gpu()
