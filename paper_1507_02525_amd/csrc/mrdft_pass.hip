@@ -23,14 +23,18 @@
 // (no scattered table reads per element).  With INV the conjugate kernel is used (adjoint), and the last
 // pass can accumulate into the gradient instead of storing.
 //
-// Recurrence chains (the levels whose window of L = 2^lg points needs three
-// passes): level lg is built from level lg - 1 as Section 3 does on chip.
-// The odd bins are the L/2-point DFT of the twiddled difference of the
-// window's halves (eq. (3)): the first pass forms it while loading x
-// (IN_DIFF), so the chain moves half the points.  The even bins are the sums
-// of the child windows' bins at level lg - 1 (eq. (2)): the last pass
-// (OUT_REC) loads those with its data and stores both bins of each k side by
-// side.
+// Recurrence chains (levels 18 and up, when the level below is kept): level
+// lg is built from level lg - 1 as Section 3 does on chip.  The odd bins are
+// the L/2-point DFT of the twiddled difference of the window's halves
+// (eq. (3)): the first pass forms it while loading x (IN_DIFF), so the chain
+// moves half the points.  The even bins are the sums of the child windows'
+// bins at level lg - 1 (eq. (2)): the last pass (OUT_REC) loads those with
+// its data and stores both bins of each k side by side.  Level 18 and level
+// 17 share their first pass (pass_head2_kernel: both halves and their
+// twiddled difference from one read of x) and their last pass
+// (pass_tail2_kernel: level 17's two windows give level 18's even bins in
+// registers); those two launches also carry level 17 of the signals of
+// order 17, whose workgroups follow the pairs'.
 #include "mrdft_internal.h"
 #include "mrdft_lds_fft.h"
 
