@@ -24,13 +24,6 @@ static_assert(kRThreads == kRowsThreads, "one block size for both job kinds");
 
 constexpr int kModeStore = 0, kModeNorms = 1, kModeScaled = 2, kModeHalf = 3, kModeScaledHalf = 4;
 
-// Sum of v over the 64 lanes of a wave (all lanes receive it).
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
 // MODE kModeStore: the level spectra are stored to Y (kModeHalf: as packed
 // half spectra, the job offsets and level stride in half-spectrum units).  kModeScaled
 // (spectral-loss gradient): the input is x - xsub and level i of signal b is
@@ -114,7 +107,7 @@ __global__ __launch_bounds__(kRThreads, 4) void fwd_real_kernel(const float* __r
                                                  comb + rows_combine_offset(16), tid, zj, &acc); break;
                 default: break;
             }
-            const double t = wave_sum(acc);
+            const double t = xl_wave_sum(acc);
             if (lane == 0) atomicAdd(sb + jb.lg - 1, t);
         }
     }

@@ -91,9 +91,7 @@ struct NormOut {
     __device__ __forceinline__ bool keep(int) const { return true; }
     // Adds the wave's partial sums of one level (every lane must call it).
     __device__ __forceinline__ void add(int level, float t) {
-        double v = (double)t;
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+        const double v = xl_wave_sum((double)t);
         if ((threadIdx.x & 63) == 0) atomicAdd(sums + level - 1, v);
     }
 };

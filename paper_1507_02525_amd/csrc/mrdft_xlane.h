@@ -85,6 +85,41 @@ struct XStages {
     }
 };
 
+// Sum of v over the 64 lanes of a wave, every lane receiving it, in FP64:
+// the four DPP permutations pair lanes that differ in one of bits 0..3 of
+// the lane index (within a row of 16 any pairing across the bit will do,
+// all lanes of a group hold the same partial sum by then), the permlane
+// swaps pair rows and wave halves.  Each 64-bit value moves as two 32-bit
+// halves; nothing goes through LDS.
+template <int B>
+__device__ __forceinline__ double xl_dpp64(double v) {
+    constexpr int ctrl = B == 0 ? 0xB1 : B == 1 ? 0x4E : B == 2 ? 0x141 : 0x140;
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)u, ctrl, 0xF, 0xF, false);
+    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), ctrl, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ double xl_wave_sum(double v) {
+    v += xl_dpp64<0>(v);
+    v += xl_dpp64<1>(v);
+    v += xl_dpp64<2>(v);
+    v += xl_dpp64<3>(v);
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)u, hi = (unsigned)(u >> 32);
+    // rows of 16: a = [r0, r0, r2, r2], b = [r1, r1, r3, r3] per 32-bit half
+    const auto rl = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto rh = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    v = __builtin_bit_cast(double, ((unsigned long long)(unsigned)rh[0] << 32) | (unsigned)rl[0]) +
+        __builtin_bit_cast(double, ((unsigned long long)(unsigned)rh[1] << 32) | (unsigned)rl[1]);
+    // wave halves
+    const unsigned long long w = __builtin_bit_cast(unsigned long long, v);
+    const unsigned wl = (unsigned)w, wh = (unsigned)(w >> 32);
+    const auto hl = __builtin_amdgcn_permlane32_swap(wl, wl, false, false);
+    const auto hh = __builtin_amdgcn_permlane32_swap(wh, wh, false, false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hh[0] << 32) | (unsigned)hl[0]) +
+           __builtin_bit_cast(double, ((unsigned long long)(unsigned)hh[1] << 32) | (unsigned)hl[1]);
+}
+
 // Exchange register bit 1 with lane bit 5 and register bit 0 with lane bit 4.
 __device__ __forceinline__ void xl_swap(float& a, float& b, bool rows) {
     const unsigned ua = __builtin_bit_cast(unsigned, a), ub = __builtin_bit_cast(unsigned, b);
