@@ -102,3 +102,41 @@ def test_upper_levels_graph_replay():
         assert torch.equal(Yg, Ye), "graph call %d differs from the eager plan" % r
         del junk
     _check_upper(Ye.cpu().numpy(), x, offs, orders, 1, 28, eager.output_offsets())
+
+
+@pytest.mark.parametrize("seed", [6, 7, 4, 0])      # shared launches; scratch too small; real with an
+def test_upper_levels_random_mixes(seed):              # order-19 partner only; level 17 the top kept level
+    """Random ragged mixes of orders 16..19 (shuffled, 1..3 signals of each
+    order present) and random level ranges: whether the signals of order 17
+    ride in the shared launches depends on the mix and on the scratch size,
+    so these cover both outcomes and the ranges that switch the shared
+    launches off; every kept upper level against the oracle, every schedule
+    bit for bit."""
+    need_gpu()
+    rng = np.random.default_rng(4200 + seed)
+    orders = []
+    for o in (16, 17, 18, 19):
+        orders += [o] * int(rng.integers(0 if o != 17 else 1, 4))
+    rng.shuffle(orders)
+    dtype = "r32" if seed == 4 else "c64"
+    lo = int(rng.choice([1, 12, 16, 17]))
+    hi = int(rng.choice([17, 18, 28]))
+    log("upper levels random mix %s %s [%d, %d]" % (dtype, orders, lo, hi))
+    x, offs = _ragged(orders, 4300 + seed, dtype)
+    plan = api.Plan(offsets=offs, dtype=dtype, levels=(lo, hi))
+    sch = plan.schedule()
+    xd = to_dev(x)
+    oo = plan.output_offsets()
+    first = None
+    for serial, after in ((False, False), (True, False), (False, True)):
+        plan.set_schedule(sch["tile_log"], sch["grid"], sch["order"], serial, after)
+        Y = torch.full((plan.n_out,), float("nan"), dtype=torch.complex64, device="cuda")
+        plan.mrdft_forward(xd, Y)
+        torch.cuda.synchronize()
+        Yh = Y.cpu().numpy()
+        if first is None:
+            first = Yh
+            worst = _check_upper(Yh, x, offs, orders, lo, hi, oo)
+            log("  worst relative L2 of the upper levels %.2e" % worst)
+        else:
+            assert np.array_equal(Yh, first), (serial, after)
