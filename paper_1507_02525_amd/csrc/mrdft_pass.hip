@@ -549,7 +549,8 @@ __global__ __launch_bounds__(PassShape<LP>::kThreads, 4) void pass_tail2_kernel(
         for (int ie = 0; ie < kRowsPerThread; ++ie) {
             int li;
             const int o = out_pos(t, ie, li);
-            yw[o] = B[li];
+            const float2 vo = B[li];
+            __builtin_nontemporal_store(f2v{vo.x, vo.y}, (f2v*)(yw + o));
         }
         return;
     }
@@ -566,7 +567,7 @@ __global__ __launch_bounds__(PassShape<LP>::kThreads, 4) void pass_tail2_kernel(
             int li;
             const int o = out_pos(t, ie, li);
             const float2 vo = B[li];
-            yw[o] = vo;
+            __builtin_nontemporal_store(f2v{vo.x, vo.y}, (f2v*)(yw + o));
             esum[ie] = h ? cadd(esum[ie], vo) : vo;
         }
         __syncthreads();
@@ -583,9 +584,8 @@ __global__ __launch_bounds__(PassShape<LP>::kThreads, 4) void pass_tail2_kernel(
             int li;
             const int o = out_pos(t, ie, li);
             const float2 vo = B[li];
-            float2* q = yh + 2 * o;
-            q[0] = esum[ie];
-            q[1] = vo;
+            typedef float f4v __attribute__((ext_vector_type(4)));
+            __builtin_nontemporal_store(f4v{esum[ie].x, esum[ie].y, vo.x, vo.y}, (f4v*)(yh + 2 * o));
         }
     }
 }
